@@ -1,0 +1,160 @@
+"""CPU oracle for randomized graph propagation -- TEST INFRASTRUCTURE ONLY.
+
+A plain sequential reference of Algorithm 2 (Section 4 of "Approximate Graph
+Propagation", KDD'21) written in C (``agp_oracle.c``) plus dense FP64 closed
+forms (``dense.py``).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package; the product library
+never calls it and shares no code with it.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "agp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, IEEE binary64)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(
+            ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+             "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp, "-lm"],
+            check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ct.CDLL(_LIB)
+        i64p = ct.POINTER(ct.c_int64)
+        i32p = ct.POINTER(ct.c_int32)
+        u32p = ct.POINTER(ct.c_uint32)
+        u64p = ct.POINTER(ct.c_uint64)
+        dp = ct.POINTER(ct.c_double)
+        L.orc_degree_sort.argtypes = [ct.c_int64, i64p, i32p, i32p, i32p]
+        L.orc_level_tables.argtypes = [dp, ct.c_int32, dp, dp, dp, dp]
+        L.orc_theta.argtypes = [dp, ct.c_int64, ct.c_double]
+        L.orc_theta.restype = ct.c_double
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_skip.argtypes = [ct.c_double, ct.c_double]
+        L.orc_skip.restype = ct.c_int32
+        L.orc_splitmix64.argtypes = [ct.c_uint64]
+        L.orc_splitmix64.restype = ct.c_uint64
+        L.orc_exact_sum.argtypes = [dp, ct.c_int64, ct.c_int32]
+        L.orc_exact_sum.restype = ct.c_double
+        L.orc_propagate_many.argtypes = [ct.c_int64, i64p, i32p, i32p, ct.c_double, ct.c_double,
+                                         dp, ct.c_int32, dp, ct.c_int32, ct.c_double, ct.c_uint64,
+                                         u32p, ct.c_int32, dp, u64p, ct.c_int32]
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(ct.POINTER(t))
+
+
+@dataclass
+class SortedGraph:
+    """Graph whose adjacency lists are sorted by (neighbour degree, id)."""
+
+    n: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    deg: np.ndarray
+
+
+def degree_sort(g) -> SortedGraph:
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    out = np.empty_like(col)
+    deg = np.empty(g.n, dtype=np.int32)
+    rc = lib().orc_degree_sort(g.n, _p(rp, ct.c_int64), _p(col, ct.c_int32),
+                               _p(out, ct.c_int32), _p(deg, ct.c_int32))
+    assert rc == 0
+    return SortedGraph(g.n, rp, out, deg)
+
+
+def level_tables(w):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    L = w.size - 1
+    S = ct.c_double()
+    Y = np.empty(L + 2)
+    rho = np.empty(L + 1)
+    kappa = np.empty(L + 1)
+    lib().orc_level_tables(_p(w, ct.c_double), L, ct.byref(S), _p(Y, ct.c_double),
+                           _p(rho, ct.c_double), _p(kappa, ct.c_double))
+    return S.value, Y, rho, kappa
+
+
+def theta(x, eps: float) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return lib().orc_theta(_p(x, ct.c_double), x.size, eps)
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.empty(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c, ct.c_uint32), _p(k, ct.c_uint32), _p(o, ct.c_uint32))
+    return o
+
+
+def skip(p: float, V: float) -> int:
+    return lib().orc_skip(p, V)
+
+
+def splitmix64(x: int) -> int:
+    return lib().orc_splitmix64(x)
+
+
+def exact_sum(vals, wp: int) -> float:
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    return lib().orc_exact_sum(_p(v, ct.c_double), v.size, wp)
+
+
+COUNTER_NAMES = ("frontier", "hash", "det", "cand", "acc")
+
+
+def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, *,
+              wp: int = 32, qids=None, threads: int | None = None):
+    """Run Algorithm 2 on every column of x (n x C, or a length-n vector).
+
+    Returns (out, counters): out has the shape of x (float64 values that are
+    binary32 values when wp == 32); counters maps each counter name to a
+    C x (L + 1) uint64 array.
+    """
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    L = w.size - 1
+    x = np.asarray(x)
+    vec = x.ndim == 1
+    X = x.reshape(sg.n, -1)
+    C = X.shape[1]
+    xc = np.ascontiguousarray(X.T, dtype=np.float64)  # column-major
+    out = np.empty_like(xc)
+    cnt = np.zeros((C, 5, L + 1), dtype=np.uint64)
+    q = None if qids is None else np.ascontiguousarray(qids, dtype=np.uint32)
+    if threads is None:
+        threads = min(C, os.cpu_count() or 1)
+    rc = lib().orc_propagate_many(
+        sg.n, _p(sg.row_ptr, ct.c_int64), _p(sg.col, ct.c_int32), _p(sg.deg, ct.c_int32),
+        float(a), float(b), _p(w, ct.c_double), L, _p(xc, ct.c_double), C, float(eps),
+        ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), None if q is None else _p(q, ct.c_uint32), wp,
+        _p(out, ct.c_double), _p(cnt, ct.c_uint64), max(1, int(threads)))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    res = out.T
+    counters = {name: cnt[:, k, :] for k, name in enumerate(COUNTER_NAMES)}
+    return (res[:, 0].copy() if vec else np.ascontiguousarray(res)), counters

@@ -1,0 +1,526 @@
+/*
+ * agp_oracle.c -- TEST INFRASTRUCTURE ONLY (see agp_oracle.h).
+ *
+ * A deliberately plain implementation of randomized graph propagation
+ * (Approximate Graph Propagation, KDD'21, Section 4, Algorithm 2):
+ *
+ *   pi = sum_{i=0}^{L} w_i (D^-a A D^-b)^i x
+ *
+ * is estimated level by level through residue vectors r^(i) and reserves
+ * q^(i) (Definition 3.2 and the recursion that follows it).  A push from u to
+ * a neighbour v carries inc = (Y_{i+1}/Y_i) r(u) / (d_v^a d_u^b); it is added
+ * exactly when inc >= theta and otherwise v is sampled with probability
+ * inc/theta and receives theta.
+ *
+ * Readings of points the paper leaves open (each is also listed in the design
+ * notes of the repository):
+ *  - weights are normalised by S = sum w_k and the result rescaled by S
+ *    (Section 3, assumptions on w_i); Y_i = sum_{k=i..L} w_k, so the estimand
+ *    is the truncated sum and the last level keeps all of r^(L);
+ *  - theta = eps * ||x||_1 per column (Section 3 assumes ||x||_1 = 1; running
+ *    unscaled with this absolute threshold is the same as normalise, run at
+ *    eps, rescale);
+ *  - signed signals are pushed in one pass: decisions use |r|, contributions
+ *    carry the sign of r (Section 3 splits x into x+ and x-);
+ *  - adjacency lists are sorted by (d_v, v), so every correct sort agrees;
+ *  - subset sampling (after Algorithm 2): the sampled suffix of N_u is cut
+ *    into runs of equal degree group floor(log2 d_v) (only when a > 0) inside
+ *    aligned windows of 64 positions.  In a run starting at position s the
+ *    scheme draws Bernoulli(p*) per position, p* = p_{v_s} (the largest in the
+ *    run), and keeps a drawn position j with probability p_{v_j}/p*.  The
+ *    Bernoulli(p*) positions are produced by geometric skips, which has the
+ *    same distribution as the paper's Binomial count plus uniform choice;
+ *  - randomness: Philox4x32-10 keyed by the 64-bit seed, counter
+ *    (t, s, u, (qid << 8) | level), t = draw index in the run;
+ *  - the residue of a node at the next level is the exact sum of all
+ *    contributions it receives in the level, rounded once to the working
+ *    precision (binary32 or binary64).  The paper visits the nodes of a level
+ *    in no fixed order; the exact sum is the value every visiting order
+ *    agrees on;
+ *  - the reserve pi(u) is accumulated level after level in the working
+ *    precision: pi(u) <- fl(pi(u) + fl(kappa_i r(u))).
+ */
+#include "agp_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------ degree sort */
+
+static const int32_t* g_sort_deg; /* degree table used by the comparator */
+
+static int cmp_deg_id(const void* pa, const void* pb) {
+  int32_t va = *(const int32_t*)pa, vb = *(const int32_t*)pb;
+  int32_t da = g_sort_deg[va], db = g_sort_deg[vb];
+  if (da != db) return da < db ? -1 : 1;
+  if (va != vb) return va < vb ? -1 : 1;
+  return 0;
+}
+
+static pthread_mutex_t g_sort_lock = PTHREAD_MUTEX_INITIALIZER;
+
+/* Pre-sorting adjacency lists by degree (Section 4): N_u ascending in d_v. */
+int orc_degree_sort(int64_t n, const int64_t* rp, const int32_t* col,
+                    int32_t* out_col, int32_t* deg) {
+  if (n < 0) return -1;
+  for (int64_t u = 0; u < n; ++u) deg[u] = (int32_t)(rp[u + 1] - rp[u]);
+  memcpy(out_col, col, (size_t)rp[n] * sizeof(int32_t));
+  pthread_mutex_lock(&g_sort_lock);
+  g_sort_deg = deg;
+  for (int64_t u = 0; u < n; ++u)
+    qsort(out_col + rp[u], (size_t)(rp[u + 1] - rp[u]), sizeof(int32_t), cmp_deg_id);
+  pthread_mutex_unlock(&g_sort_lock);
+  return 0;
+}
+
+/* ------------------------------------------------------- weights, theta */
+
+/* Partial sums Y_i = sum_{k>=i} w_k (Definition 3.2), with w_k = 0 for k > L,
+ * added from k = L downwards; rho_i = Y_{i+1}/Y_i (recursion for r^(i+1));
+ * kappa_i = (S * w_i) / Y_i (reserve q^(i) = (w_i/Y_i) r^(i), rescaled by S). */
+int orc_level_tables(const double* w, int32_t L, double* S, double* Y,
+                     double* rho, double* kappa) {
+  if (L < 0) return -1;
+  Y[L + 1] = 0.0;
+  for (int32_t k = L; k >= 0; --k) Y[k] = Y[k + 1] + w[k];
+  *S = Y[0];
+  for (int32_t i = 0; i <= L; ++i) {
+    rho[i] = (Y[i] == 0.0) ? 0.0 : Y[i + 1] / Y[i];
+    kappa[i] = (Y[i] == 0.0) ? 0.0 : ((*S) * w[i]) / Y[i];
+  }
+  return 0;
+}
+
+/* ||x||_1 summed in binary64: sequentially inside blocks of 4096 consecutive
+ * rows, then sequentially over the block sums; theta = eps * ||x||_1. */
+double orc_theta(const double* x, int64_t n, double eps) {
+  double total = 0.0;
+  for (int64_t lo = 0; lo < n; lo += 4096) {
+    double part = 0.0;
+    int64_t hi = lo + 4096 < n ? lo + 4096 : n;
+    for (int64_t i = lo; i < hi; ++i) part += fabs(x[i]);
+    total += part;
+  }
+  return eps * total;
+}
+
+/* ------------------------------------------------------------ randomness */
+
+/* Philox4x32 with 10 rounds: each round multiplies counter words 0 and 2 by
+ * the two published multipliers, swaps and xors with the key, and the key is
+ * bumped by the two Weyl constants between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* 53-bit uniform in [0, 1) from two 32-bit words. */
+static double uniform53(uint32_t hi, uint32_t lo) {
+  uint64_t bits = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
+  return (double)bits * (1.0 / 9007199254740992.0);
+}
+
+/* Number K of failures before the next success of Bernoulli(p) trials:
+ * the largest K with 1 - (1-p)^K <= V.  With s_h = 1 - (1-p)^(2^h)
+ * (s_0 = p, s_{h+1} = s_h * (2 - s_h)) the value 1-(1-p)^K is built by
+ * binary lifting: sigma' = (sigma + s_h) - sigma * s_h.  K stays below 128,
+ * which is more than any run of 64 positions needs. */
+int32_t orc_skip(double p, double V) {
+  double s[7];
+  s[0] = p;
+  for (int h = 0; h < 6; ++h) {
+    double t = 2.0 - s[h];
+    s[h + 1] = s[h] * t;
+  }
+  double sigma = 0.0;
+  int32_t K = 0;
+  for (int h = 6; h >= 0; --h) {
+    double sum = sigma + s[h];
+    double prod = sigma * s[h];
+    double cand = sum - prod;
+    if (cand <= V) {
+      sigma = cand;
+      K += (int32_t)1 << h;
+    }
+  }
+  return K;
+}
+
+uint64_t orc_splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* ------------------------------------------------- exact accumulation */
+
+/* A binary32 value is an integer multiple of 2^-149 below 2^128 and a
+ * binary64 value a multiple of 2^-1074 below 2^1024.  Sums are kept as
+ * two's-complement integers in those units, wide enough for 2^32 terms. */
+#define W32 5
+#define W64 34
+
+typedef struct exact_acc {
+  int words;
+  int unit_exp;
+  int prec;
+} exact_fmt;
+
+static exact_fmt fmt_for(int wp) {
+  exact_fmt f;
+  if (wp == 32) {
+    f.words = W32;
+    f.unit_exp = -149;
+    f.prec = 24;
+  } else {
+    f.words = W64;
+    f.unit_exp = -1074;
+    f.prec = 53;
+  }
+  return f;
+}
+
+/* acc += v exactly (v must be a finite value of the working format). */
+static void exact_add(uint64_t* acc, const exact_fmt* f, double v) {
+  if (v == 0.0) return;
+  int e;
+  double fr = frexp(fabs(v), &e); /* |v| = fr * 2^e, fr in [0.5, 1) */
+  uint64_t m = (uint64_t)ldexp(fr, 53);
+  int pos = e - 53 - f->unit_exp;
+  while (pos < 0) {
+    if (m & 1u) abort(); /* not on the grid of the working format */
+    m >>= 1;
+    ++pos;
+  }
+  int wi = pos / 64, sh = pos % 64;
+  uint64_t part[2];
+  part[0] = m << sh;
+  part[1] = sh ? (m >> (64 - sh)) : 0;
+  if (v > 0) {
+    uint64_t carry = 0;
+    for (int k = wi; k < f->words; ++k) {
+      uint64_t add = (k == wi) ? part[0] : (k == wi + 1) ? part[1] : 0;
+      uint64_t s1 = acc[k] + add;
+      uint64_t c1 = s1 < add;
+      uint64_t s2 = s1 + carry;
+      uint64_t c2 = s2 < carry;
+      acc[k] = s2;
+      carry = c1 | c2;
+      if (k > wi && carry == 0) break;
+    }
+  } else {
+    uint64_t borrow = 0;
+    for (int k = wi; k < f->words; ++k) {
+      uint64_t sub = (k == wi) ? part[0] : (k == wi + 1) ? part[1] : 0;
+      uint64_t b1 = acc[k] < sub;
+      uint64_t d1 = acc[k] - sub;
+      uint64_t b2 = d1 < borrow;
+      uint64_t d2 = d1 - borrow;
+      acc[k] = d2;
+      borrow = b1 | b2;
+      if (k > wi && borrow == 0) break;
+    }
+  }
+}
+
+static int bit_of(const uint64_t* t, int k) { return (int)((t[k / 64] >> (k % 64)) & 1u); }
+
+/* Round the integer in acc (units 2^unit_exp) to the working format,
+ * round-to-nearest-even; a zero sum gives +0. */
+static double exact_round(const uint64_t* acc, const exact_fmt* f) {
+  uint64_t t[W64];
+  int W = f->words;
+  memcpy(t, acc, (size_t)W * sizeof(uint64_t));
+  int neg = (int)(t[W - 1] >> 63);
+  if (neg) { /* two's complement negate */
+    uint64_t carry = 1;
+    for (int k = 0; k < W; ++k) {
+      t[k] = ~t[k] + carry;
+      carry = (carry && t[k] == 0) ? 1 : 0;
+    }
+  }
+  int nb = 0;
+  for (int k = W - 1; k >= 0; --k) {
+    if (t[k]) {
+      nb = 64 * k + (64 - __builtin_clzll(t[k]));
+      break;
+    }
+  }
+  if (nb == 0) return 0.0;
+  double r;
+  if (nb <= f->prec) {
+    uint64_t q = 0;
+    for (int k = nb - 1; k >= 0; --k) q = (q << 1) | (uint64_t)bit_of(t, k);
+    r = ldexp((double)q, f->unit_exp);
+  } else {
+    int shift = nb - f->prec;
+    uint64_t q = 0;
+    for (int k = nb - 1; k >= shift; --k) q = (q << 1) | (uint64_t)bit_of(t, k);
+    int round_bit = bit_of(t, shift - 1);
+    int sticky = 0;
+    for (int k = shift - 2; k >= 0 && !sticky; --k) sticky = bit_of(t, k);
+    if (round_bit && (sticky || (q & 1u))) {
+      ++q;
+      if (q == ((uint64_t)1 << f->prec)) {
+        q >>= 1;
+        ++shift;
+      }
+    }
+    r = ldexp((double)q, f->unit_exp + shift);
+  }
+  if (f->prec == 24) r = (double)(float)r; /* exact, or +inf past FLT_MAX */
+  return neg ? -r : r;
+}
+
+double orc_exact_sum(const double* vals, int64_t k, int32_t wp) {
+  exact_fmt f = fmt_for(wp);
+  uint64_t acc[W64];
+  memset(acc, 0, sizeof(acc));
+  for (int64_t i = 0; i < k; ++i) exact_add(acc, &f, vals[i]);
+  return exact_round(acc, &f);
+}
+
+/* --------------------------------------------------------- propagation */
+
+/* Round to the working precision. */
+static double fl_w(double v, int wp) { return wp == 32 ? (double)(float)v : v; }
+
+/* d^-e for d >= 1: exact forms 1, 1/sqrt(d), 1/d for e = 0, 1/2, 1. */
+static double deg_pow(int32_t d, double e) {
+  if (d <= 0) return 0.0;
+  if (e == 0.0) return 1.0;
+  if (e == 0.5) return 1.0 / sqrt((double)d);
+  if (e == 1.0) return 1.0 / (double)d;
+  return pow((double)d, -e);
+}
+
+static int group_of(int32_t d) { return 31 - __builtin_clz((unsigned)d); }
+
+int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
+                  const int32_t* deg, double a, double b, const double* w,
+                  int32_t L, const double* x, double eps, uint64_t seed,
+                  uint32_t qid, int32_t wp, double* out, orc_counters* cnt) {
+  if (n < 0 || L < 0 || L > 255 || !(a >= 0.0 && a <= 1.0) || !(b >= 0.0 && b <= 1.0) ||
+      !(eps >= 0.0) || (wp != 32 && wp != 64))
+    return -1;
+  for (int32_t k = 0; k <= L; ++k)
+    if (!(w[k] >= 0.0) || isinf(w[k])) return -1;
+
+  int32_t maxdeg = 0;
+  for (int64_t u = 0; u < n; ++u)
+    if (deg[u] > maxdeg) maxdeg = deg[u];
+  double* da = malloc(sizeof(double) * ((size_t)maxdeg + 1));
+  double* db = malloc(sizeof(double) * ((size_t)maxdeg + 1));
+  for (int32_t d = 0; d <= maxdeg; ++d) {
+    da[d] = deg_pow(d, a);
+    db[d] = deg_pow(d, b);
+  }
+  double S;
+  double* Y = malloc(sizeof(double) * ((size_t)L + 2));
+  double* rho = malloc(sizeof(double) * ((size_t)L + 1));
+  double* kappa = malloc(sizeof(double) * ((size_t)L + 1));
+  orc_level_tables(w, L, &S, Y, &rho[0], &kappa[0]);
+
+  const double theta = orc_theta(x, n, eps);
+  const double theta_w = fl_w(theta, wp);
+  exact_fmt f = fmt_for(wp);
+  double* r = malloc(sizeof(double) * (size_t)(n ? n : 1));
+  uint64_t* acc = calloc((size_t)(n ? n : 1) * (size_t)f.words, sizeof(uint64_t));
+  unsigned char* touched = calloc((size_t)(n ? n : 1), 1);
+  int64_t* touched_list = malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  const int64_t seg = (int64_t)1 << ORC_SEG_LOG2;
+
+  for (int64_t u = 0; u < n; ++u) {
+    r[u] = x[u]; /* r^(0) = x */
+    out[u] = 0.0;
+  }
+
+  for (int32_t i = 0; i <= L; ++i) {
+    uint64_t nf = 0, hs = 0, ndet = 0, ncand = 0, nacc = 0;
+    int64_t ntouched = 0;
+    for (int64_t u = 0; u < n; ++u) { /* each u with non-zero residue */
+      double ru = r[u];
+      if (ru == 0.0) continue;
+      ++nf;
+      hs += orc_splitmix64((uint64_t)u);
+      /* reserve: pi(u) += (w_i / Y_i) r(u), rescaled by S */
+      out[u] = fl_w(out[u] + fl_w(kappa[i] * ru, wp), wp);
+      if (i == L || rho[i] == 0.0 || deg[u] == 0) continue;
+      const double sgn = ru < 0.0 ? -1.0 : 1.0;
+      const double c = (rho[i] * fabs(ru)) * db[deg[u]];
+      const int32_t* nb = col_sorted + rp[u];
+      const int64_t du = deg[u];
+      /* deterministic pushes to the prefix whose increment reaches theta */
+      int64_t j = 0;
+      while (j < du) {
+        int32_t v = nb[j];
+        double inc = c * da[deg[v]];
+        if (!(inc >= theta)) break;
+        if (!touched[v]) {
+          touched[v] = 1;
+          touched_list[ntouched++] = v;
+        }
+        exact_add(acc + (size_t)v * f.words, &f, fl_w(sgn * inc, wp));
+        ++j;
+      }
+      ndet += (uint64_t)j;
+      /* subset sampling over the rest, run by run */
+      int64_t s = j;
+      while (s < du) {
+        int64_t e = s + 1;
+        while (e < du && (e % seg) != 0 &&
+               (a == 0.0 || group_of(deg[nb[e]]) == group_of(deg[nb[s]])))
+          ++e;
+        const double dstart = da[deg[nb[s]]];
+        const double pstar = (c * dstart) / theta;
+        int64_t pos = s;
+        uint32_t t = 0;
+        for (;;) {
+          uint32_t ctr[4] = {t, (uint32_t)s, (uint32_t)u, (qid << 8) | (uint32_t)i};
+          uint32_t o[4];
+          orc_philox4x32_10(ctr, key, o);
+          double V = uniform53(o[0], o[1]);
+          double V2 = uniform53(o[2], o[3]);
+          int64_t cnd = pos + orc_skip(pstar, V);
+          if (cnd >= e) break;
+          ++ncand;
+          int32_t v = nb[cnd];
+          double ratio = da[deg[v]] / dstart;
+          if (V2 < ratio) {
+            ++nacc;
+            if (!touched[v]) {
+              touched[v] = 1;
+              touched_list[ntouched++] = v;
+            }
+            exact_add(acc + (size_t)v * f.words, &f, fl_w(sgn * theta_w, wp));
+          }
+          pos = cnd + 1;
+          ++t;
+        }
+        s = e;
+      }
+    }
+    if (cnt) {
+      cnt->frontier[i] = nf;
+      cnt->hash[i] = hs;
+      if (i < L) {
+        cnt->det[i] = ndet;
+        cnt->cand[i] = ncand;
+        cnt->acc[i] = nacc;
+      }
+    }
+    if (i == L) break;
+    /* empty level i; r^(i+1) is the rounded exact sum of what arrived */
+    for (int64_t u = 0; u < n; ++u) r[u] = 0.0;
+    for (int64_t k = 0; k < ntouched; ++k) {
+      int64_t v = touched_list[k];
+      r[v] = exact_round(acc + (size_t)v * f.words, &f);
+      memset(acc + (size_t)v * f.words, 0, sizeof(uint64_t) * (size_t)f.words);
+      touched[v] = 0;
+    }
+  }
+  free(da);
+  free(db);
+  free(Y);
+  free(rho);
+  free(kappa);
+  free(r);
+  free(acc);
+  free(touched);
+  free(touched_list);
+  return 0;
+}
+
+/* ------------------------------------------------ many columns, threads */
+
+typedef struct many_job {
+  int64_t n;
+  const int64_t* rp;
+  const int32_t* col;
+  const int32_t* deg;
+  double a, b;
+  const double* w;
+  int32_t L;
+  const double* x;
+  int32_t C;
+  double eps;
+  uint64_t seed;
+  const uint32_t* qids;
+  int32_t wp;
+  double* out;
+  uint64_t* counters;
+  int next;
+  int status;
+  pthread_mutex_t lock;
+} many_job;
+
+static void* many_worker(void* arg) {
+  many_job* jb = (many_job*)arg;
+  const size_t L1 = (size_t)jb->L + 1;
+  for (;;) {
+    pthread_mutex_lock(&jb->lock);
+    int c = jb->next++;
+    pthread_mutex_unlock(&jb->lock);
+    if (c >= jb->C) break;
+    orc_counters cn, *pc = NULL;
+    if (jb->counters) {
+      uint64_t* base = jb->counters + (size_t)c * 5 * L1;
+      cn.frontier = base;
+      cn.hash = base + L1;
+      cn.det = base + 2 * L1;
+      cn.cand = base + 3 * L1;
+      cn.acc = base + 4 * L1;
+      memset(base, 0, sizeof(uint64_t) * 5 * L1);
+      pc = &cn;
+    }
+    uint32_t qid = jb->qids ? jb->qids[c] : (uint32_t)c;
+    int rc = orc_propagate(jb->n, jb->rp, jb->col, jb->deg, jb->a, jb->b, jb->w, jb->L,
+                           jb->x + (size_t)c * (size_t)jb->n, jb->eps, jb->seed, qid, jb->wp,
+                           jb->out + (size_t)c * (size_t)jb->n, pc);
+    if (rc) {
+      pthread_mutex_lock(&jb->lock);
+      jb->status = rc;
+      pthread_mutex_unlock(&jb->lock);
+    }
+  }
+  return NULL;
+}
+
+int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
+                       const int32_t* deg, double a, double b, const double* w,
+                       int32_t L, const double* x, int32_t C, double eps,
+                       uint64_t seed, const uint32_t* qids, int32_t wp,
+                       double* out, uint64_t* counters, int32_t nthreads) {
+  if (C < 0 || nthreads < 1) return -1;
+  many_job jb = {n, rp, col_sorted, deg, a, b, w, L, x, C, eps, seed, qids, wp, out, counters, 0, 0};
+  pthread_mutex_init(&jb.lock, NULL);
+  if (nthreads > C) nthreads = C > 0 ? C : 1;
+  pthread_t* th = malloc(sizeof(pthread_t) * (size_t)nthreads);
+  for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, many_worker, &jb);
+  for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+  free(th);
+  pthread_mutex_destroy(&jb.lock);
+  return jb.status;
+}

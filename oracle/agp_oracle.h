@@ -1,0 +1,81 @@
+/*
+ * agp_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain sequential CPU reference for randomized graph propagation
+ * (Wang, He, Wei, Wang, Yuan, Du, Wen: "Approximate Graph Propagation",
+ * KDD'21; Algorithm 2 of Section 4 with the degree-sorted adjacency lists and
+ * the degree-group subset sampling described after it).  Only the tests, the
+ * package smoke check and the benchmark's CPU-baseline leg may load it; the
+ * product library never links or calls it, and it shares no code with the
+ * HIP path.
+ *
+ * Every floating point decision is taken in IEEE binary64 in the operation
+ * order written in the comments of agp_oracle.c; this file must be compiled
+ * with -ffp-contract=off so that no multiply-add is fused.
+ */
+#ifndef AGP_ORACLE_H
+#define AGP_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Subset sampling splits every sampled suffix at multiples of 2^6 positions. */
+#define ORC_SEG_LOG2 6
+
+/* Per-level counters of one propagation (one column). Arrays have L + 1
+ * entries; det/cand/acc use entries 0..L-1, frontier/hash use 0..L. */
+typedef struct orc_counters {
+  uint64_t* frontier; /* |{u : r^(i)(u) != 0}|                        */
+  uint64_t* hash;     /* sum of splitmix64(u) over that set, mod 2^64 */
+  uint64_t* det;      /* deterministic pushes                         */
+  uint64_t* cand;     /* sampled candidates                           */
+  uint64_t* acc;      /* accepted sampled pushes                      */
+} orc_counters;
+
+/* Sort every adjacency list ascending by (degree of neighbour, neighbour id).
+ * rp/col: symmetric CSR; out_col gets the sorted lists, deg the degrees. */
+int orc_degree_sort(int64_t n, const int64_t* rp, const int32_t* col,
+                    int32_t* out_col, int32_t* deg);
+
+/* S, Y_0..Y_{L+1}, rho_0..rho_L, kappa_0..kappa_L from w_0..w_L. */
+int orc_level_tables(const double* w, int32_t L, double* S, double* Y,
+                     double* rho, double* kappa);
+
+/* theta = eps * ||x||_1 with the fixed blocked summation order. */
+double orc_theta(const double* x, int64_t n, double eps);
+
+/* Philox4x32-10 block function (Salmon et al., SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Geometric skip for success probability p from the uniform V. */
+int32_t orc_skip(double p, double V);
+
+/* splitmix64 finaliser of x. */
+uint64_t orc_splitmix64(uint64_t x);
+
+/* Exact sum of vals[0..k) rounded once to binary32 (wp = 32) or binary64. */
+double orc_exact_sum(const double* vals, int64_t k, int32_t wp);
+
+/* One column of Algorithm 2. x and out hold n values; with wp = 32 every x
+ * must be a binary32 value. Returns 0, or -1 on invalid arguments. */
+int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
+                  const int32_t* deg, double a, double b, const double* w,
+                  int32_t L, const double* x, double eps, uint64_t seed,
+                  uint32_t qid, int32_t wp, double* out, orc_counters* cnt);
+
+/* Columns c = 0..C-1 of column-major x/out (x + c*n), spread over nthreads
+ * host threads; qids may be NULL (qid = c).  counters, if not NULL, is a
+ * C x 5 x (L+1) uint64 array (frontier, hash, det, cand, acc per column). */
+int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
+                       const int32_t* deg, double a, double b, const double* w,
+                       int32_t L, const double* x, int32_t C, double eps,
+                       uint64_t seed, const uint32_t* qids, int32_t wp,
+                       double* out, uint64_t* counters, int32_t nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

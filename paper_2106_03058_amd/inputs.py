@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs: graphs, signals, query sources and weight sequences.
+
+This module produces *data* only. It holds none of the propagation method's
+arithmetic (no residues, thresholds, sampling or sums), so both the HIP path and
+the CPU oracle can be fed from it without sharing any code of the method.
+
+Graphs are simple undirected graphs stored as CSR with every row sorted by
+neighbour id and no duplicate entries (the problem statement of the paper,
+Section 2, takes G undirected).  Stand-ins for the paper's datasets (Tables 3
+and 4) are power-law graphs of the same shape:
+
+* Chung-Lu graphs with expected degrees w_i ~ (i+1)^(-1/(gamma-1)), scaled to a
+  mean degree and capped at sqrt(n * mean), endpoints drawn proportional to w.
+* R-MAT graphs (Chakrabarti et al.) with quadrant probabilities (a, b, c, d).
+
+Both are symmetrised, lose generator self-loops and duplicates, and may get
+exactly one self-loop per node (the GNN convention of Section 2).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Graph:
+    """Undirected simple graph in CSR form (rows sorted by neighbour id)."""
+
+    n: int
+    row_ptr: np.ndarray  # int64, n + 1
+    col: np.ndarray  # int32, row_ptr[-1]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    @property
+    def degree(self) -> np.ndarray:
+        return np.diff(self.row_ptr).astype(np.int64)
+
+    def describe(self) -> dict:
+        d = self.degree
+        return {
+            "n": self.n,
+            "arcs": self.nnz,
+            "mean_degree": float(d.mean()) if self.n else 0.0,
+            "max_degree": int(d.max()) if self.n else 0,
+            "isolated": int((d == 0).sum()),
+        }
+
+
+def csr_from_pairs(n: int, src: np.ndarray, dst: np.ndarray, *,
+                   self_loops: bool = False) -> Graph:
+    """Symmetrise (src, dst) pairs, drop loops and duplicates, build CSR.
+
+    With ``self_loops`` one loop (u, u) is added to every row afterwards.
+    """
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    key = np.concatenate([src * n + dst, dst * n + src])
+    if self_loops:
+        ids = np.arange(n, dtype=np.int64)
+        key = np.concatenate([key, ids * n + ids])
+    key = np.unique(key)
+    rows = key // n
+    col = (key - rows * n).astype(np.int32)
+    counts = np.bincount(rows, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    return Graph(n, row_ptr, col)
+
+
+def chung_lu(n: int, mean_degree: float, gamma: float, seed: int, *,
+             pair_factor: float = 1.0, self_loops: bool = False) -> Graph:
+    """Chung-Lu power-law graph; node 0 carries the largest expected degree.
+
+    ``n * mean_degree / 2 * pair_factor`` endpoint pairs are drawn, each
+    endpoint independently with probability proportional to its weight.
+    ``pair_factor > 1`` offsets the pairs lost to loops and duplicates.
+    """
+    rng = np.random.default_rng(seed)
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (gamma - 1.0))
+    w *= mean_degree * n / w.sum()
+    np.minimum(w, math.sqrt(n * mean_degree), out=w)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    m = int(round(n * mean_degree / 2.0 * pair_factor))
+    src = np.empty(m, dtype=np.int64)
+    dst = np.empty(m, dtype=np.int64)
+    chunk = 1 << 24
+    for lo in range(0, m, chunk):
+        hi = min(m, lo + chunk)
+        src[lo:hi] = np.searchsorted(cdf, rng.random(hi - lo), side="right")
+        dst[lo:hi] = np.searchsorted(cdf, rng.random(hi - lo), side="right")
+    np.minimum(src, n - 1, out=src)
+    np.minimum(dst, n - 1, out=dst)
+    return csr_from_pairs(n, src, dst, self_loops=self_loops)
+
+
+def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
+         *, permute: bool = True, self_loops: bool = False) -> Graph:
+    """R-MAT graph with 2^scale nodes and edge_factor * 2^scale generated edges.
+
+    Node labels are shuffled by a seeded permutation so that hubs are not
+    clustered at small ids.
+    """
+    rng = np.random.default_rng(seed)
+    n = 1 << scale
+    m = n * edge_factor
+    t_a = np.uint32(min(int(a * 2**32), 2**32 - 1))
+    t_ab = np.uint32(min(int((a + b) * 2**32), 2**32 - 1))
+    t_abc = np.uint32(min(int((a + b + c) * 2**32), 2**32 - 1))
+    src = np.zeros(m, dtype=np.int64)
+    dst = np.zeros(m, dtype=np.int64)
+    chunk = 1 << 24
+    for lo in range(0, m, chunk):
+        hi = min(m, lo + chunk)
+        s = np.zeros(hi - lo, dtype=np.int64)
+        d = np.zeros(hi - lo, dtype=np.int64)
+        for _ in range(scale):
+            u = rng.integers(0, 2**32, size=hi - lo, dtype=np.uint32)
+            bit_src = u >= t_ab  # quadrants c and d
+            bit_dst = ((u >= t_a) & (u < t_ab)) | (u >= t_abc)  # b and d
+            s = (s << 1) | bit_src
+            d = (d << 1) | bit_dst
+        src[lo:hi] = s
+        dst[lo:hi] = d
+    if permute:
+        perm = rng.permutation(n).astype(np.int64)
+        src = perm[src]
+        dst = perm[dst]
+    return csr_from_pairs(n, src, dst, self_loops=self_loops)
+
+
+def erdos_renyi(n: int, p: float, seed: int, *, self_loops: bool = False) -> Graph:
+    """G(n, p) on a small node count (used for closed-form checks)."""
+    rng = np.random.default_rng(seed)
+    iu, ju = np.triu_indices(n, k=1)
+    keep = rng.random(iu.size) < p
+    return csr_from_pairs(n, iu[keep], ju[keep], self_loops=self_loops)
+
+
+def toy_graph(k: int) -> Graph:
+    """The bad case for pruned propagation in Section 4 (Figure 1).
+
+    Node 0 is s, nodes 1..k are u_1..u_k and node k+1 is v; every u_i is joined
+    to s and to v.  A 2-step walk from s ends at s or v with probability 1/2
+    each and never at a u_i.
+    """
+    u = np.arange(1, k + 1, dtype=np.int64)
+    src = np.concatenate([np.zeros(k, dtype=np.int64), u])
+    dst = np.concatenate([u, np.full(k, k + 1, dtype=np.int64)])
+    return csr_from_pairs(k + 2, src, dst)
+
+
+def path_graph(n: int) -> Graph:
+    i = np.arange(n - 1, dtype=np.int64)
+    return csr_from_pairs(n, i, i + 1)
+
+
+def star_graph(k: int) -> Graph:
+    return csr_from_pairs(k + 1, np.zeros(k, dtype=np.int64),
+                          np.arange(1, k + 1, dtype=np.int64))
+
+
+# ----------------------------------------------------------------- signals
+
+def one_hot(n: int, sources, dtype=np.float32) -> np.ndarray:
+    """n x C matrix whose column c is the indicator of node sources[c]."""
+    sources = np.asarray(sources, dtype=np.int64)
+    x = np.zeros((n, sources.size), dtype=dtype)
+    x[sources, np.arange(sources.size)] = 1
+    return x
+
+
+def features_normal(n: int, cols: int, seed: int) -> np.ndarray:
+    """n x cols float32 matrix with i.i.d. N(0, 1) entries."""
+    return np.random.default_rng(seed).standard_normal((n, cols), dtype=np.float32)
+
+
+def features_uniform(n: int, cols: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    """n x cols float32 matrix with i.i.d. U[lo, hi) entries."""
+    r = np.random.default_rng(seed).random((n, cols), dtype=np.float32)
+    return (lo + (hi - lo) * r).astype(np.float32)
+
+
+def sources_uniform(g: Graph, k: int, seed: int) -> np.ndarray:
+    """k distinct-when-possible sources, uniform over nodes with degree >= 1."""
+    rng = np.random.default_rng(seed)
+    cand = np.flatnonzero(g.degree >= 1)
+    return rng.choice(cand, size=k, replace=k > cand.size).astype(np.int64)
+
+
+def sources_by_degree(g: Graph, k: int, seed: int) -> np.ndarray:
+    """k sources drawn with probability proportional to degree."""
+    rng = np.random.default_rng(seed)
+    d = g.degree.astype(np.float64)
+    return rng.choice(g.n, size=k, p=d / d.sum()).astype(np.int64)
+
+
+# ------------------------------------------------- weight sequences (Table 1)
+
+def weights_ppr(alpha: float, L: int) -> np.ndarray:
+    """w_i = alpha (1 - alpha)^i, i = 0..L (PageRank / PPR / APPNP)."""
+    w = np.empty(L + 1)
+    v = alpha
+    for i in range(L + 1):
+        w[i] = v
+        v *= 1.0 - alpha
+    return w
+
+
+def weights_hkpr(t: float, L: int) -> np.ndarray:
+    """w_i = e^-t t^i / i!, i = 0..L (heat kernel PageRank / GDC)."""
+    w = np.empty(L + 1)
+    v = math.exp(-t)
+    for i in range(L + 1):
+        w[i] = v
+        v = v * t / (i + 1)
+    return w
+
+
+def weights_katz(beta: float, L: int, scale: float = 1.0) -> np.ndarray:
+    """w_i = scale * beta^i, i = 0..L (Katz)."""
+    w = np.empty(L + 1)
+    v = scale
+    for i in range(L + 1):
+        w[i] = v
+        v *= beta
+    return w
+
+
+def weights_tp(L: int) -> np.ndarray:
+    """w_L = 1 and w_i = 0 otherwise (L-hop transition probability)."""
+    w = np.zeros(L + 1)
+    w[L] = 1.0
+    return w
+
+
+def lambda_max(g: Graph, *, tol: float = 1e-10, max_iter: int = 1000) -> float:
+    """Largest adjacency eigenvalue by FP64 power iteration from all-ones.
+
+    Stops when the Rayleigh estimate changes by less than ``tol`` relative.
+    """
+    import scipy.sparse as sp
+
+    a = sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
+    v = np.ones(g.n)
+    v /= np.linalg.norm(v)
+    lam = 0.0
+    for _ in range(max_iter):
+        y = a @ v
+        new = float(v @ y)
+        nrm = np.linalg.norm(y)
+        if nrm == 0.0:
+            return 0.0
+        v = y / nrm
+        if lam and abs(new - lam) <= tol * abs(new):
+            return new
+        lam = new
+    return lam

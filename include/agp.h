@@ -1,0 +1,168 @@
+/*
+ * agp.h -- C ABI of the MI355X (gfx950) randomized graph propagation library.
+ *
+ * The library estimates, for an undirected graph G with adjacency matrix A and
+ * degree matrix D, the graph propagation vector of Eq. (1) of "Approximate
+ * Graph Propagation" (Wang et al., KDD'21):
+ *
+ *     pi = sum_{i=0}^{L} w_i (D^-a A D^-b)^i x,      a, b in [0, 1],
+ *
+ * with the randomized level-by-level residue push of Algorithm 2 (Section 4):
+ * at level i a node u with residue r(u) pushes inc = (Y_{i+1}/Y_i) r(u) /
+ * (d_v^a d_u^b) to each neighbour v whose increment reaches the threshold, and
+ * samples the remaining neighbours with probability inc/theta, adding theta to
+ * each sampled one.  Adjacency lists are kept sorted by neighbour degree
+ * (Section 4, pre-sorting) so the exact part is a prefix and the sampled part
+ * is visited in degree groups (Section 4, subset sampling).
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: AGP_OK (0) or a positive AGP_E* code; agp_last_error()
+ *    returns a thread-local message for the last failure.  No C++ exception
+ *    crosses this boundary.
+ *  - "device" pointers are HIP device allocations on the current device;
+ *    "host" pointers are ordinary host memory.  The library never frees
+ *    caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on it; calls documented as synchronous wait for it.
+ *  - Results depend only on (graph, a, b, w, L, x, eps, seed, column query
+ *    id), never on launch shapes, tile sizes, batch composition or timing.
+ */
+#ifndef AGP_H
+#define AGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define AGP_OK 0
+#define AGP_EINVAL 1   /* invalid argument (sizes, ranges, NaN, asymmetric graph) */
+#define AGP_ENOMEM 2   /* device or host allocation failed                       */
+#define AGP_EDEVICE 3  /* a HIP runtime call failed                              */
+#define AGP_ERANGE 4   /* a residue left the range of the exact accumulators     */
+#define AGP_ENOTSUP 5  /* valid but unsupported request                          */
+#define AGP_PENDING 6  /* agp_poll: the query has not finished                   */
+#define AGP_ENOENT 7   /* agp_poll: unknown ticket                               */
+#define AGP_EBUSY 8    /* agp_submit: the submission queue is full               */
+
+/* ---------------------------------------------------- graph creation flags */
+#define AGP_HOST_PTRS 1u      /* row_ptr / col_idx are host pointers (else device)   */
+#define AGP_VALIDATE 2u       /* check ids, no duplicates, no loops unless added, symmetry */
+#define AGP_ADD_SELF_LOOPS 4u /* give every node exactly one self-loop (GNN convention) */
+
+/* Largest supported number of levels L (the level index is 8 bits of the
+ * random stream counter). */
+#define AGP_MAX_LEVELS 255
+
+typedef struct agp_graph agp_graph_t;
+
+/* Per-call counters (Theorem 3.3 counts one unit of cost per edge push).
+ * Entries are summed over all columns of the call; index = level.
+ *  frontier[i]  number of (node, column) pairs with non-zero residue at level i
+ *  hash[i]      sum over those pairs of splitmix64(node), mod 2^64
+ *  det[i]       deterministic pushes made at level i           (i < L)
+ *  cand[i]      sampled candidate positions drawn at level i    (i < L)
+ *  acc[i]       accepted sampled pushes at level i              (i < L)
+ * An edge push is det + acc. */
+typedef struct agp_stats {
+  int32_t levels;  /* L of the call */
+  int32_t columns; /* C of the call */
+  uint64_t frontier[AGP_MAX_LEVELS + 1];
+  uint64_t hash[AGP_MAX_LEVELS + 1];
+  uint64_t det[AGP_MAX_LEVELS + 1];
+  uint64_t cand[AGP_MAX_LEVELS + 1];
+  uint64_t acc[AGP_MAX_LEVELS + 1];
+  double device_ms; /* time between the first and last enqueued kernel */
+} agp_stats_t;
+
+/* Thread-local description of the last error raised on this thread. */
+const char* agp_last_error(void);
+
+/* ------------------------------------------------------------------ graphs */
+
+/* Build the library's graph from a CSR matrix (Section 2: G = (V, E)
+ * undirected; Section 4: adjacency lists pre-sorted by degree).
+ *  n        number of nodes, 0 <= n < 2^31
+ *  nnz      number of stored arcs, row_ptr[n]; an undirected edge is stored
+ *           in both rows
+ *  row_ptr  int64[n + 1], non-decreasing, row_ptr[0] = 0
+ *  col_idx  int32[nnz], neighbour ids in [0, n)
+ *  flags    AGP_HOST_PTRS | AGP_VALIDATE | AGP_ADD_SELF_LOOPS
+ *  stream   stream for the build; the call is synchronous on it
+ *  out      receives the graph handle
+ * The library copies the arrays; the caller may free them on return.  Inside
+ * the handle every row is sorted ascending by (degree of neighbour, id).
+ * Errors: AGP_EINVAL for bad sizes, ids out of range, or (with AGP_VALIDATE)
+ * duplicate arcs, self-loops when AGP_ADD_SELF_LOOPS is not given, or an
+ * asymmetric matrix; AGP_ENOMEM; AGP_EDEVICE. */
+int agp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr,
+                     const int32_t* col_idx, uint32_t flags, void* stream,
+                     agp_graph_t** out);
+
+/* Sizes of a graph (any pointer may be NULL). */
+int agp_graph_info(const agp_graph_t* g, int64_t* n, int64_t* nnz, int32_t* max_degree);
+
+/* Copy the library's CSR to host buffers (any may be NULL):
+ * row_ptr int64[n+1], col_sorted int32[nnz] (rows sorted by (degree, id)),
+ * degree int32[n]. Synchronous. */
+int agp_graph_export(const agp_graph_t* g, int64_t* row_ptr, int32_t* col_sorted,
+                     int32_t* degree);
+
+/* Release a graph and every buffer the library cached for it. */
+int agp_graph_destroy(agp_graph_t* g);
+
+/* ------------------------------------------------------------- propagation */
+
+/* Randomized propagation of C signal columns at once (Algorithm 2).
+ *  g       graph handle
+ *  a, b    exponents of D^-a A D^-b, each in [0, 1]
+ *  w       host double[L + 1], w_i >= 0 and finite, not all zero
+ *  L       number of levels, 0 <= L <= AGP_MAX_LEVELS
+ *  x       device float[n * C], row-major (x[u * C + c]); finite values
+ *  C       number of columns, C >= 1
+ *  eps     error parameter, eps > 0.  Column c uses the absolute threshold
+ *          theta_c = eps * ||x[:, c]||_1 (Section 3 assumes ||x||_1 = 1)
+ *  seed    64-bit key of the random streams
+ *  qids    host uint32[C] query id per column, or NULL for qid = column
+ *          index; each column's random decisions depend on (seed, qid) only,
+ *          qid < 2^24
+ *  out     device float[n * C], row-major, written with pi_hat (overwritten)
+ *  stream  work is enqueued on this stream; the call waits for it before
+ *          returning so that errors can be reported
+ *  stats   optional host counters (NULL to skip)
+ * Weights are normalised by S = sum w_i and the result rescaled by S
+ * (Section 3).  Signed signals are pushed in one pass (decisions on |r|,
+ * contributions carry the sign of r).  Each next-level residue is the exact
+ * sum of what a node receives in the level, rounded once to binary32.
+ * Errors: AGP_EINVAL (bad sizes/ranges, non-finite x), AGP_ERANGE (a
+ * residue outgrew the exact accumulators: contributions larger than about
+ * 2^39 theta), AGP_ENOMEM, AGP_EDEVICE.  On AGP_EINVAL nothing is written; on
+ * AGP_ERANGE the contents of out are unspecified. */
+int agp_propagate(const agp_graph_t* g, double a, double b, const double* w, int32_t L,
+                  const float* x, int32_t C, double eps, uint64_t seed,
+                  const uint32_t* qids, float* out, void* stream, agp_stats_t* stats);
+
+/* The same in binary64 working precision (x and out are device double[n*C]);
+ * each next-level residue is the exact sum rounded once to binary64. */
+int agp_propagate_f64(const agp_graph_t* g, double a, double b, const double* w, int32_t L,
+                      const double* x, int32_t C, double eps, uint64_t seed,
+                      const uint32_t* qids, double* out, void* stream, agp_stats_t* stats);
+
+/* ------------------------------------------- weight sequences (Table 1) */
+
+/* w_i = alpha (1 - alpha)^i, i = 0..L (PageRank, PPR, APPNP). */
+int agp_weights_ppr(double alpha, int32_t L, double* w);
+/* w_i = e^-t t^i / i!, i = 0..L (heat kernel PageRank, GDC). */
+int agp_weights_hkpr(double t, int32_t L, double* w);
+/* w_i = beta^i, i = 0..L (Katz). */
+int agp_weights_katz(double beta, int32_t L, double* w);
+/* w_L = 1, w_i = 0 otherwise (L-hop transition probability, SGC). */
+int agp_weights_tp(int32_t L, double* w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

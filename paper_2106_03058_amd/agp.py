@@ -1,0 +1,212 @@
+"""Python binding of libagp: argument marshalling only.
+
+Every step of the propagation runs in the HIP kernels behind the C ABI of
+``include/agp.h``; PyTorch is used for device memory and streams.  Importing
+this module does not need a GPU, but every call does, and a missing
+``libagp.so`` is an error (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libagp.so")
+
+AGP_OK, AGP_EINVAL, AGP_ENOMEM, AGP_EDEVICE, AGP_ERANGE, AGP_ENOTSUP = 0, 1, 2, 3, 4, 5
+AGP_PENDING, AGP_ENOENT, AGP_EBUSY = 6, 7, 8
+AGP_HOST_PTRS, AGP_VALIDATE, AGP_ADD_SELF_LOOPS = 1, 2, 4
+MAX_LEVELS = 255
+
+EXPORTED = [
+    "agp_last_error", "agp_graph_create", "agp_graph_info", "agp_graph_export",
+    "agp_graph_destroy", "agp_propagate", "agp_propagate_f64", "agp_weights_ppr",
+    "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp",
+]
+
+
+class AGPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Stats(ct.Structure):
+    _fields_ = [
+        ("levels", ct.c_int32), ("columns", ct.c_int32),
+        ("frontier", ct.c_uint64 * (MAX_LEVELS + 1)),
+        ("hash", ct.c_uint64 * (MAX_LEVELS + 1)),
+        ("det", ct.c_uint64 * (MAX_LEVELS + 1)),
+        ("cand", ct.c_uint64 * (MAX_LEVELS + 1)),
+        ("acc", ct.c_uint64 * (MAX_LEVELS + 1)),
+        ("device_ms", ct.c_double),
+    ]
+
+    def to_dict(self) -> dict:
+        L = self.levels
+        d = {k: np.array(getattr(self, k)[: L + 1], dtype=np.uint64)
+             for k in ("frontier", "hash", "det", "cand", "acc")}
+        d["levels"] = L
+        d["columns"] = self.columns
+        d["device_ms"] = float(self.device_ms)
+        d["pushes"] = int(d["det"].sum() + d["acc"].sum())
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load libagp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ct.CDLL(LIB_PATH)
+        vp, dp = ct.c_void_p, ct.POINTER(ct.c_double)
+        i64p, i32p, u32p = ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_uint32)
+        L.agp_last_error.restype = ct.c_char_p
+        L.agp_graph_create.argtypes = [ct.c_int64, ct.c_int64, vp, vp, ct.c_uint32, vp, ct.POINTER(vp)]
+        L.agp_graph_info.argtypes = [vp, i64p, i64p, i32p]
+        L.agp_graph_export.argtypes = [vp, i64p, i32p, i32p]
+        L.agp_graph_destroy.argtypes = [vp]
+        prop = [vp, ct.c_double, ct.c_double, dp, ct.c_int32, vp, ct.c_int32, ct.c_double,
+                ct.c_uint64, u32p, vp, vp, ct.POINTER(Stats)]
+        L.agp_propagate.argtypes = prop
+        L.agp_propagate_f64.argtypes = prop
+        L.agp_weights_ppr.argtypes = [ct.c_double, ct.c_int32, dp]
+        L.agp_weights_hkpr.argtypes = [ct.c_double, ct.c_int32, dp]
+        L.agp_weights_katz.argtypes = [ct.c_double, ct.c_int32, dp]
+        L.agp_weights_tp.argtypes = [ct.c_int32, dp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != AGP_OK:
+        raise AGPError(rc, lib().agp_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dptr(t) -> int:
+    return int(t.data_ptr())
+
+
+class Graph:
+    """A graph resident on the GPU with degree-sorted adjacency lists."""
+
+    def __init__(self, row_ptr, col, *, validate: bool = False, self_loops: bool = False,
+                 stream=None):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        n = rp.size - 1
+        flags = AGP_HOST_PTRS | (AGP_VALIDATE if validate else 0) | (AGP_ADD_SELF_LOOPS if self_loops else 0)
+        h = ct.c_void_p()
+        _check(lib().agp_graph_create(n, int(rp[-1]), rp.ctypes.data, cl.ctypes.data if cl.size else None,
+                                      flags, _stream_ptr(stream), ct.byref(h)))
+        self._h = h
+        n_, nnz, md = ct.c_int64(), ct.c_int64(), ct.c_int32()
+        _check(lib().agp_graph_info(h, ct.byref(n_), ct.byref(nnz), ct.byref(md)))
+        self.n, self.nnz, self.max_degree = n_.value, nnz.value, md.value
+
+    @classmethod
+    def from_inputs(cls, g, **kw) -> "Graph":
+        return cls(g.row_ptr, g.col, **kw)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("graph was destroyed")
+        return self._h
+
+    def export(self):
+        rp = np.empty(self.n + 1, dtype=np.int64)
+        col = np.empty(self.nnz, dtype=np.int32)
+        deg = np.empty(self.n, dtype=np.int32)
+        _check(lib().agp_graph_export(self.handle, rp.ctypes.data_as(ct.POINTER(ct.c_int64)),
+                                      col.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                                      deg.ctypes.data_as(ct.POINTER(ct.c_int32))))
+        return rp, col, deg
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().agp_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def propagate(graph: Graph, a: float, b: float, w, x, eps: float, seed: int, *, qids=None,
+              out=None, stream=None, stats: bool = False):
+    """Run the randomized propagation on every column of x.
+
+    x: CUDA tensor (n,) or (n, C), float32 (binary32 path) or float64.
+    Returns (out, stats) where out has the shape and dtype of x and stats is
+    a dict of per-level counters (or None).
+    """
+    import torch
+
+    if not x.is_cuda:
+        raise ValueError("x must be a device tensor")
+    vec = x.dim() == 1
+    X = x.reshape(graph.n, -1)
+    if not X.is_contiguous():
+        X = X.contiguous()
+    C = X.shape[1]
+    if out is None:
+        out = torch.empty_like(X)
+    o = out.reshape(graph.n, -1)
+    if not o.is_contiguous() or o.dtype != X.dtype or o.shape != X.shape:
+        raise ValueError("out must be a contiguous tensor of x's shape and dtype")
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    L = w.size - 1
+    q = None
+    if qids is not None:
+        q = np.ascontiguousarray(qids, dtype=np.uint32)
+        if q.size != C:
+            raise ValueError("need one qid per column")
+    st = Stats() if stats else None
+    fn = {torch.float32: lib().agp_propagate, torch.float64: lib().agp_propagate_f64}.get(X.dtype)
+    if fn is None:
+        raise ValueError("x must be float32 or float64")
+    _check(fn(graph.handle, float(a), float(b), w.ctypes.data_as(ct.POINTER(ct.c_double)), L,
+              _dptr(X), C, float(eps), ct.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF),
+              None if q is None else q.ctypes.data_as(ct.POINTER(ct.c_uint32)), _dptr(o),
+              _stream_ptr(stream), ct.byref(st) if st is not None else None))
+    res = o.reshape(-1) if vec else o
+    return res, (st.to_dict() if st is not None else None)
+
+
+def _weights(fn, *args, L: int) -> np.ndarray:
+    w = np.empty(L + 1, dtype=np.float64)
+    _check(fn(*args, L, w.ctypes.data_as(ct.POINTER(ct.c_double))))
+    return w
+
+
+def weights_ppr(alpha: float, L: int) -> np.ndarray:
+    return _weights(lib().agp_weights_ppr, float(alpha), L=L)
+
+
+def weights_hkpr(t: float, L: int) -> np.ndarray:
+    return _weights(lib().agp_weights_hkpr, float(t), L=L)
+
+
+def weights_katz(beta: float, L: int) -> np.ndarray:
+    return _weights(lib().agp_weights_katz, float(beta), L=L)
+
+
+def weights_tp(L: int) -> np.ndarray:
+    w = np.empty(L + 1, dtype=np.float64)
+    _check(lib().agp_weights_tp(L, w.ctypes.data_as(ct.POINTER(ct.c_double))))
+    return w

@@ -1,0 +1,70 @@
+// Host-side internals shared by the translation units of libagp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "../../include/agp.h"
+
+namespace agp {
+
+// Thread-local error text behind agp_last_error().
+int fail(int code, const std::string& msg);
+
+#define AGP_HIP(call)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return ::agp::fail(e_ == hipErrorOutOfMemory ? AGP_ENOMEM : AGP_EDEVICE,             \
+                         std::string(#call) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+// A device buffer that only grows.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int reserve(size_t want, bool zero, hipStream_t s);
+  void release();
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(ptr);
+  }
+};
+
+// Scratch reused across propagation calls on one graph (guarded by the
+// graph's mutex).  acc[] are kept all-zero between calls.
+struct Scratch {
+  DevBuf acc[2];
+  DevBuf frontier[2];
+  DevBuf counts;     // frontier sizes per level
+  DevBuf counters;   // 5 x (L + 1) uint64
+  DevBuf colparams;  // per-column theta / unit / qid
+  DevBuf partial;    // per-block partial norms
+  DevBuf flags;      // error and signal flags
+  void release();
+};
+
+}  // namespace agp
+
+struct agp_graph {
+  int64_t n = 0;
+  int64_t nnz = 0;
+  int32_t max_degree = 0;
+  int device = 0;
+  int64_t* row_ptr = nullptr;   // device int64[n + 1]
+  uint32_t* col = nullptr;      // device uint32[nnz], rows sorted by (degree, id)
+  uint32_t* ndeg = nullptr;     // device uint32[nnz], degree of col[j]
+  int32_t* degree = nullptr;    // device int32[n]
+  std::map<double, double*> pow_tables;  // exponent e -> device d^-e, d = 0..max_degree
+  std::mutex mu;
+  agp::Scratch scratch;
+};
+
+namespace agp {
+// Device table of d^-e for d = 0..max_degree (0 at d = 0), cached per graph.
+int pow_table(agp_graph* g, double e, const double** out);
+}  // namespace agp

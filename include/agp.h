@@ -50,7 +50,7 @@ extern "C" {
 
 /* ---------------------------------------------------- graph creation flags */
 #define AGP_HOST_PTRS 1u      /* row_ptr / col_idx are host pointers (else device)   */
-#define AGP_VALIDATE 2u       /* check ids, no duplicates, no loops unless added, symmetry */
+#define AGP_VALIDATE 2u       /* also check: no duplicate arcs, symmetric matrix          */
 #define AGP_ADD_SELF_LOOPS 4u /* give every node exactly one self-loop (GNN convention) */
 
 /* Largest supported number of levels L (the level index is 8 bits of the
@@ -75,7 +75,9 @@ typedef struct agp_stats {
   uint64_t det[AGP_MAX_LEVELS + 1];
   uint64_t cand[AGP_MAX_LEVELS + 1];
   uint64_t acc[AGP_MAX_LEVELS + 1];
-  double device_ms; /* time between the first and last enqueued kernel */
+  double device_ms; /* from the first level kernel's start to the last one's end */
+  /* HIP-event time of the level kernel launched for level i (ms) */
+  double level_ms[AGP_MAX_LEVELS + 1];
 } agp_stats_t;
 
 /* Thread-local description of the last error raised on this thread. */
@@ -96,8 +98,8 @@ const char* agp_last_error(void);
  * The library copies the arrays; the caller may free them on return.  Inside
  * the handle every row is sorted ascending by (degree of neighbour, id).
  * Errors: AGP_EINVAL for bad sizes, ids out of range, or (with AGP_VALIDATE)
- * duplicate arcs, self-loops when AGP_ADD_SELF_LOOPS is not given, or an
- * asymmetric matrix; AGP_ENOMEM; AGP_EDEVICE. */
+ * duplicate arcs or an asymmetric matrix; AGP_ENOMEM; AGP_EDEVICE.  Self-loops
+ * already in the input are kept (a loop is an ordinary neighbour). */
 int agp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr,
                      const int32_t* col_idx, uint32_t flags, void* stream,
                      agp_graph_t** out);
@@ -119,7 +121,7 @@ int agp_graph_destroy(agp_graph_t* g);
 /* Randomized propagation of C signal columns at once (Algorithm 2).
  *  g       graph handle
  *  a, b    exponents of D^-a A D^-b, each in [0, 1]
- *  w       host double[L + 1], w_i >= 0 and finite, not all zero
+ *  w       host double[L + 1], w_i >= 0 and finite
  *  L       number of levels, 0 <= L <= AGP_MAX_LEVELS
  *  x       device float[n * C], row-major (x[u * C + c]); finite values
  *  C       number of columns, C >= 1

@@ -41,6 +41,7 @@ class Stats(ct.Structure):
         ("cand", ct.c_uint64 * (MAX_LEVELS + 1)),
         ("acc", ct.c_uint64 * (MAX_LEVELS + 1)),
         ("device_ms", ct.c_double),
+        ("level_ms", ct.c_double * (MAX_LEVELS + 1)),
     ]
 
     def to_dict(self) -> dict:
@@ -50,6 +51,7 @@ class Stats(ct.Structure):
         d["levels"] = L
         d["columns"] = self.columns
         d["device_ms"] = float(self.device_ms)
+        d["level_ms"] = np.array(self.level_ms[: L + 1], dtype=np.float64)
         d["pushes"] = int(d["det"].sum() + d["acc"].sum())
         return d
 

@@ -259,6 +259,32 @@ __device__ __forceinline__ void wave_append(uint64_t* __restrict__ list,
   }
 }
 
+// Per-wave LDS staging of list entries: entries are gathered with ballots and
+// written out in chunks, one global atomic per chunk.  Every call must be
+// made by all lanes of the wave together (wave-uniform control flow).
+constexpr int kStage = 512;
+
+__device__ __forceinline__ void stage_flush(uint64_t* stage, int& staged, uint64_t* __restrict__ list,
+                                            unsigned long long* __restrict__ count) {
+  if (staged == 0) return;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(count, static_cast<unsigned long long>(staged));
+  base = __shfl(base, 0);
+  for (int i = lane_id(); i < staged; i += kWave) list[base + i] = stage[i];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  staged = 0;
+}
+
+__device__ __forceinline__ void stage_push(uint64_t* stage, int& staged, uint64_t item, bool pred,
+                                           uint64_t* __restrict__ list,
+                                           unsigned long long* __restrict__ count) {
+  const unsigned long long mask = __ballot(pred);
+  if (pred) stage[staged + __popcll(mask & ((1ull << lane_id()) - 1ull))] = item;
+  staged += __popcll(mask);
+  if (staged > kStage - kWave) stage_flush(stage, staged, list, count);
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off);

@@ -45,6 +45,9 @@ struct Scratch {
   DevBuf colparams;  // per-column theta / unit / qid
   DevBuf partial;    // per-block partial norms
   DevBuf flags;      // error and signal flags
+  DevBuf levelinfo;  // per level: contribution mass (double), frontier mode (int)
+  hipEvent_t events[2 * (AGP_MAX_LEVELS + 1)] = {};  // level timing, created on demand
+  int ensure_events();
   void release();
 };
 

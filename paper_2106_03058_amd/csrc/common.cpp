@@ -36,7 +36,18 @@ void DevBuf::release() {
   bytes = 0;
 }
 
+int Scratch::ensure_events() {
+  for (auto& e : events)
+    if (!e) AGP_HIP(hipEventCreate(&e));
+  return AGP_OK;
+}
+
 void Scratch::release() {
+  for (auto& e : events)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
   for (auto& b : acc) b.release();
   for (auto& b : frontier) b.release();
   counts.release();
@@ -44,6 +55,7 @@ void Scratch::release() {
   colparams.release();
   partial.release();
   flags.release();
+  levelinfo.release();
 }
 
 // d^-e on the host in binary64: exact IEEE forms 1, 1/sqrt(d), 1/d for the

@@ -68,39 +68,51 @@ struct LevelArgs {
   unsigned long long* cnt_out;
   unsigned long long* counters;
   int* err;
-  int positive;
+  int positive;                   // non-negative signal: sparse levels allowed
+  unsigned long long dense_cut;   // frontier size from which a level is dense
+  int* mode;                      // mode[i] = 1: level i's frontier is compacted
+  double* mass;                   // per level: sum of |contribution| in units
 };
 
 // ----------------------------------------------------- working precision
 // Binary32: int64 cells.  Binary64: 128-bit cells (lo, hi) stored adjacently.
+// `mass` collects the magnitude of every contribution in units: while a
+// level's total stays below the cell range no partial sum can wrap.
 template <typename T>
 struct Prec;
+
+__device__ __forceinline__ void atomic_add_relaxed(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long atomic_add_ret(unsigned long long* p, unsigned long long v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <>
 struct Prec<float> {
   using Cell = long long;
+  using Delta = long long;
   static __device__ __forceinline__ float take(Cell* acc, size_t cell, const ColParams& p) {
     const long long K = acc[cell];
     acc[cell] = 0;
     return units_to_f32(K, p.ue);
   }
-  // Add the binary32 contribution v; returns true if the cell was zero before.
-  static __device__ __forceinline__ bool add(Cell* acc, size_t cell, float v, const ColParams& p,
-                                             int* err) {
-    long long d;
-    if (!f32_to_units(v, p.scale, &d)) {
-      atomicOr(err, 1);
-      return false;
-    }
-    return add_units(acc, cell, d, err);
+  static __device__ __forceinline__ bool to_units(float v, const ColParams& p, Delta* d, double* mass) {
+    if (!f32_to_units(v, p.scale, d)) return false;
+    *mass += fabs(static_cast<double>(*d));
+    return true;
   }
-  static __device__ __forceinline__ bool add_units(Cell* acc, size_t cell, long long d, int* err) {
-    const long long old = static_cast<long long>(
-        atomicAdd(reinterpret_cast<unsigned long long*>(acc + cell), static_cast<unsigned long long>(d)));
-    const long long now = static_cast<long long>(static_cast<unsigned long long>(old) +
-                                                 static_cast<unsigned long long>(d));
-    if ((old > 0 && d > 0 && now < 0) || (old < 0 && d < 0 && now >= 0)) atomicOr(err, 1);
-    return old == 0;
+  static __device__ __forceinline__ Delta theta_units(const ColParams& p, bool neg, double* mass) {
+    *mass += static_cast<double>(p.dtheta);
+    return neg ? -p.dtheta : p.dtheta;
+  }
+  // returns true if the cell held zero before (first contribution)
+  static __device__ __forceinline__ bool add_ret(Cell* acc, size_t cell, Delta d) {
+    return atomic_add_ret(reinterpret_cast<unsigned long long*>(acc + cell),
+                          static_cast<unsigned long long>(d)) == 0ull;
+  }
+  static __device__ __forceinline__ void add(Cell* acc, size_t cell, Delta d) {
+    atomic_add_relaxed(reinterpret_cast<unsigned long long*>(acc + cell), static_cast<unsigned long long>(d));
   }
   static __device__ __forceinline__ bool nonzero(const Cell* acc, size_t cell) { return acc[cell] != 0; }
 };
@@ -108,31 +120,33 @@ struct Prec<float> {
 template <>
 struct Prec<double> {
   using Cell = unsigned long long;  // two words per cell
+  using Delta = U128;
   static __device__ __forceinline__ double take(Cell* acc, size_t cell, const ColParams& p) {
     U128 K{acc[2 * cell], static_cast<long long>(acc[2 * cell + 1])};
     acc[2 * cell] = 0;
     acc[2 * cell + 1] = 0;
     return units_to_f64(K, p.ue);
   }
-  static __device__ __forceinline__ void add128(Cell* acc, size_t cell, U128 d) {
-    const unsigned long long old = atomicAdd(acc + 2 * cell, d.lo);
+  static __device__ __forceinline__ bool to_units(double v, const ColParams& p, Delta* d, double* mass) {
+    if (!f64_to_units(v, p.ue, d)) return false;
+    *mass += ldexp(fabs(v), -p.ue);
+    return true;
+  }
+  static __device__ __forceinline__ Delta theta_units(const ColParams& p, bool neg, double* mass) {
+    *mass += static_cast<double>(p.dtheta);
+    const long long d = neg ? -p.dtheta : p.dtheta;
+    return U128{static_cast<unsigned long long>(d), d < 0 ? -1ll : 0ll};
+  }
+  // the carry out of the low word needs the old value
+  static __device__ __forceinline__ void add(Cell* acc, size_t cell, Delta d) {
+    const unsigned long long old = atomic_add_ret(acc + 2 * cell, d.lo);
     const unsigned long long carry = (old + d.lo < old) ? 1ull : 0ull;
     const unsigned long long h = static_cast<unsigned long long>(d.hi) + carry;
-    if (h != 0ull) atomicAdd(acc + 2 * cell + 1, h);
+    if (h != 0ull) atomic_add_relaxed(acc + 2 * cell + 1, h);
   }
-  static __device__ __forceinline__ bool add(Cell* acc, size_t cell, double v, const ColParams& p,
-                                             int* err) {
-    U128 d;
-    if (!f64_to_units(v, p.ue, &d)) {
-      atomicOr(err, 1);
-      return false;
-    }
-    add128(acc, cell, d);
+  static __device__ __forceinline__ bool add_ret(Cell* acc, size_t cell, Delta d) {
+    add(acc, cell, d);
     return false;  // binary64 calls always compact the next frontier
-  }
-  static __device__ __forceinline__ bool add_units(Cell* acc, size_t cell, long long d, int*) {
-    add128(acc, cell, U128{static_cast<unsigned long long>(d), d < 0 ? -1ll : 0ll});
-    return false;
   }
   static __device__ __forceinline__ bool nonzero(const Cell* acc, size_t cell) {
     return (acc[2 * cell] | acc[2 * cell + 1]) != 0ull;
@@ -149,6 +163,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
                                                     typename Prec<T>::Cell* __restrict__ acc_next,
                                                     T* __restrict__ out) {
   using P = Prec<T>;
+  using Delta = typename P::Delta;
   __shared__ long long s_off[kTile + 1];
   __shared__ int64_t s_rp[kTile];
   __shared__ double s_cv[kTile];
@@ -158,16 +173,25 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   __shared__ uint32_t s_J[kTile];
   __shared__ uint32_t s_neg[kTile];
   __shared__ long long s_wave[kThreads / kWave];
+  __shared__ uint64_t s_stage[kThreads / kWave][kStage];
 
   const unsigned long long count = *A.cnt_in;
+  // Sparse levels detect the first contribution to a cell from the atomic's
+  // old value and append the cell to the next frontier; dense levels use
+  // fire-and-forget atomics and a compaction pass builds the next frontier.
+  const bool sparse = !kLast && A.positive && count < A.dense_cut;
+  if (!kLast && blockIdx.x == 0 && threadIdx.x == 0) A.mode[A.level + 1] = sparse ? 0 : 1;
   unsigned long long te = (count + gridDim.x - 1) / gridDim.x;
   te = te < 1 ? 1 : (te > (unsigned long long)kTile ? (unsigned long long)kTile : te);
   const unsigned long long ntiles = (count + te - 1) / te;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / kWave;
+  uint64_t* stage = s_stage[wave];
+  int staged = 0;  // wave-uniform
 
   unsigned long long n_front = 0, n_hash = 0, n_det = 0, n_cand = 0, n_acc = 0;
+  double mass = 0.0;
 
   for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const unsigned long long e0 = tile * te;
@@ -245,97 +269,142 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
     __syncthreads();
     const long long total = s_off[kThreads];
 
-    for (long long k = tid; k < total; k += kThreads) {
-      int lo = 0, hi = ne - 1;  // largest e with s_off[e] <= k
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= k)
-          lo = mid;
-        else
-          hi = mid - 1;
+    // Every lane pulls work items k = tid, tid + 256, ...: a single push of
+    // the deterministic prefix, or a 64-position window of the sampled suffix
+    // walked one random draw per step.  The loop runs in lockstep per wave so
+    // that frontier staging can use wave-wide ballots.
+    long long k = tid;
+    int ttype = 0;  // 0 idle, 1 single push, 2 window
+    bool need_run = false;
+    uint32_t u = 0, c = 0, s = 0, wend = 0, run_end = 0, pos = 0, t = 0, ctr3 = 0;
+    int64_t rpu = 0;
+    double cv = 0.0, dstart = 1.0, th = 0.0;
+    bool neg = false;
+    long long local = 0;
+    SkipTable tab;
+    for (;;) {
+      if (ttype == 0 && k < total) {
+        int lo = 0, hi = ne - 1;  // largest e with s_off[e] <= k
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= k)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const int e = lo;
+        local = k - s_off[e];
+        k += kThreads;
+        const uint32_t J = s_J[e];
+        u = s_u[e];
+        c = s_c[e];
+        rpu = s_rp[e];
+        cv = s_cv[e];
+        neg = s_neg[e] != 0;
+        if (local < static_cast<long long>(J)) {
+          ttype = 1;
+        } else {
+          ttype = 2;
+          const uint32_t d = s_d[e];
+          const uint32_t wstart = ((J >> kSegLog2) + static_cast<uint32_t>(local - J)) << kSegLog2;
+          s = wstart > J ? wstart : J;
+          wend = (wstart + static_cast<uint32_t>(kSeg)) < d ? wstart + static_cast<uint32_t>(kSeg) : d;
+          need_run = true;
+          const ColParams& cp = A.cp[c];
+          th = cp.theta;
+          ctr3 = (cp.qid << 8) | static_cast<uint32_t>(A.level);
+        }
       }
-      const int e = lo;
-      const long long local = k - s_off[e];
-      const uint32_t J = s_J[e];
-      const uint32_t u = s_u[e];
-      const uint32_t c = s_c[e];
-      const int64_t rpu = s_rp[e];
-      const double cv = s_cv[e];
-      const bool neg = s_neg[e] != 0;
-      const ColParams& cp = A.cp[c];
-      if (local < static_cast<long long>(J)) {
-        // deterministic push: increment reaches theta
+      if (!__any(ttype != 0)) break;
+
+      bool emit = false;
+      size_t vcell = 0;
+      Delta delta{};
+      uint32_t v = 0;
+      if (ttype == 1) {
+        // deterministic push: the increment reaches theta
         const int64_t arc = rpu + local;
-        const uint32_t v = A.col[arc];
+        v = A.col[arc];
         double inc = cv;
         if (!A.a_zero) inc = cv * A.da[A.nd[arc]];
         T val = to_w(inc, T());
         if (neg) val = -val;
-        const size_t vcell = static_cast<size_t>(v) * static_cast<size_t>(A.C) + c;
-        const bool first = P::add(acc_next, vcell, val, cp, A.err);
-        if (A.positive) wave_append(A.fout, A.cnt_out, (static_cast<uint64_t>(v) << 32) | c, first);
-      } else {
-        // one 64-position window of the sampled suffix
-        const uint32_t d = s_d[e];
-        const uint32_t wstart = ((J >> kSegLog2) + static_cast<uint32_t>(local - J)) << kSegLog2;
-        uint32_t s = wstart > J ? wstart : J;
-        const uint32_t wend = (wstart + static_cast<uint32_t>(kSeg)) < d ? wstart + static_cast<uint32_t>(kSeg) : d;
-        const double th = cp.theta;
-        const long long dth = neg ? -cp.dtheta : cp.dtheta;
-        const uint32_t ctr3 = (cp.qid << 8) | static_cast<uint32_t>(A.level);
-        while (s < wend) {
-          uint32_t run_end = wend;
-          double dstart = 1.0;
-          if (!A.a_zero) {
-            const uint32_t ds = A.nd[rpu + s];
-            dstart = A.da[ds];
-            const int g = 31 - __clz(ds);
-            if (g < 31) {  // first position of a higher degree group
-              const uint32_t lim = 1u << (g + 1);
-              uint32_t blo = s + 1, bhi = wend;
-              while (blo < bhi) {
-                const uint32_t mid = (blo + bhi) >> 1;
-                if (A.nd[rpu + mid] < lim)
-                  blo = mid + 1;
-                else
-                  bhi = mid;
+        emit = true;
+        if (!P::to_units(val, A.cp[c], &delta, &mass)) {
+          atomicOr(A.err, 1);
+          emit = false;
+        }
+        ttype = 0;
+      } else if (ttype == 2) {
+        if (need_run) {
+          if (s >= wend) {
+            ttype = 0;
+          } else {  // a run: same degree group (a > 0) inside the window
+            run_end = wend;
+            dstart = 1.0;
+            if (!A.a_zero) {
+              const uint32_t ds = A.nd[rpu + s];
+              dstart = A.da[ds];
+              const int g = 31 - __clz(ds);
+              if (g < 31) {
+                const uint32_t lim = 1u << (g + 1);
+                uint32_t blo = s + 1, bhi = wend;
+                while (blo < bhi) {
+                  const uint32_t mid = (blo + bhi) >> 1;
+                  if (A.nd[rpu + mid] < lim)
+                    blo = mid + 1;
+                  else
+                    bhi = mid;
+                }
+                run_end = blo;
               }
-              run_end = blo;
             }
+            const double num = cv * dstart;
+            const double pstar = num / th;
+            tab = make_skip_table(pstar);
+            pos = s;
+            t = 0;
+            need_run = false;
           }
-          const double num = cv * dstart;
-          const double pstar = num / th;
-          const SkipTable tab = make_skip_table(pstar);
-          uint32_t pos = s;
-          uint32_t t = 0;
-          for (;;) {
-            const U4 o = philox4x32_10(t, s, u, ctr3, A.key0, A.key1);
-            const double V = unit_double(o.x, o.y);
-            const double V2 = unit_double(o.z, o.w);
-            const uint32_t cand = pos + static_cast<uint32_t>(geometric_skip(tab, V));
-            if (cand >= run_end) break;
+        }
+        if (ttype == 2 && !need_run) {
+          const U4 o = philox4x32_10(t, s, u, ctr3, A.key0, A.key1);
+          const double V = unit_double(o.x, o.y);
+          const double V2 = unit_double(o.z, o.w);
+          const uint32_t cand = pos + static_cast<uint32_t>(geometric_skip(tab, V));
+          if (cand >= run_end) {
+            s = run_end;
+            need_run = true;
+          } else {
             ++n_cand;
             const int64_t arc = rpu + cand;
             double ratio = 1.0;
             if (!A.a_zero) ratio = A.da[A.nd[arc]] / dstart;
-            bool first = false;
-            uint32_t v = 0;
             if (V2 < ratio) {
               ++n_acc;
               v = A.col[arc];
-              const size_t vcell = static_cast<size_t>(v) * static_cast<size_t>(A.C) + c;
-              first = P::add_units(acc_next, vcell, dth, A.err);
+              emit = true;
+              delta = P::theta_units(A.cp[c], neg, &mass);
             }
-            if (A.positive) wave_append(A.fout, A.cnt_out, (static_cast<uint64_t>(v) << 32) | c, first);
             pos = cand + 1;
             ++t;
           }
-          s = run_end;
         }
       }
+      bool first = false;
+      if (emit) {
+        vcell = static_cast<size_t>(v) * static_cast<size_t>(A.C) + c;
+        if (sparse)
+          first = P::add_ret(acc_next, vcell, delta);
+        else
+          P::add(acc_next, vcell, delta);
+      }
+      if (sparse)  // wave-uniform: stage first-touched cells, flush in chunks
+        stage_push(stage, staged, (static_cast<uint64_t>(v) << 32) | c, first, A.fout, A.cnt_out);
     }
     __syncthreads();
   }
+  if (sparse) stage_flush(stage, staged, A.fout, A.cnt_out);
   // per-level counters: one atomic per wave
   unsigned long long* cnt = A.counters + static_cast<size_t>(A.level) * kNumCounters;
   const unsigned long long v0 = wave_sum_u64(n_front);
@@ -343,12 +412,16 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   const unsigned long long v2 = wave_sum_u64(n_det);
   const unsigned long long v3 = wave_sum_u64(n_cand);
   const unsigned long long v4 = wave_sum_u64(n_acc);
+  double m = mass;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) m += __shfl_down(m, off);
   if (lane == 0) {
     if (v0) atomicAdd(cnt + 0, v0);
     if (v1) atomicAdd(cnt + 1, v1);
     if (v2) atomicAdd(cnt + 2, v2);
     if (v3) atomicAdd(cnt + 3, v3);
     if (v4) atomicAdd(cnt + 4, v4);
+    if (m != 0.0) atomicAdd(A.mass + A.level, m);
   }
 }
 
@@ -358,8 +431,13 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
 template <typename Pred>
 __global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int C,
                                                       uint64_t* __restrict__ F,
-                                                      unsigned long long* __restrict__ cnt) {
+                                                      unsigned long long* __restrict__ cnt,
+                                                      const int* __restrict__ mode) {
+  if (mode && *mode == 0) return;  // this level's frontier was appended directly
+  __shared__ uint64_t s_stage[kThreads / kWave][kStage];
   const int lane = lane_id();
+  uint64_t* stage = s_stage[threadIdx.x / kWave];
+  int staged = 0;
   if (C >= kWave) {
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -367,7 +445,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int 
       for (int c0 = 0; c0 < C; c0 += kWave) {
         const int c = c0 + lane;
         const bool p = (c < C) && pred(static_cast<size_t>(u) * C + c);
-        wave_append(F, cnt, (static_cast<uint64_t>(u) << 32) | static_cast<uint32_t>(c), p);
+        stage_push(stage, staged, (static_cast<uint64_t>(u) << 32) | static_cast<uint32_t>(c), p, F, cnt);
       }
     }
   } else {
@@ -386,9 +464,10 @@ __global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int 
         p = pred(static_cast<size_t>(i));
         item = (static_cast<uint64_t>(u) << 32) | static_cast<uint32_t>(c);
       }
-      wave_append(F, cnt, item, p);
+      stage_push(stage, staged, item, p, F, cnt);
     }
   }
+  stage_flush(stage, staged, F, cnt);
 }
 
 template <typename T>
@@ -518,7 +597,8 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
       (rc = sc.counters.reserve(sizeof(unsigned long long) * kNumCounters * (AGP_MAX_LEVELS + 1), false, s)) ||
       (rc = sc.colparams.reserve(sizeof(ColParams) * C + sizeof(uint32_t) * C, false, s)) ||
       (rc = sc.partial.reserve(sizeof(double) * (size_t)std::max<int64_t>(tblocks, 1) * C, false, s)) ||
-      (rc = sc.flags.reserve(sizeof(int) * 4, false, s)))
+      (rc = sc.flags.reserve(sizeof(int) * 4, false, s)) ||
+      (rc = sc.levelinfo.reserve((sizeof(double) + sizeof(int)) * (AGP_MAX_LEVELS + 2), false, s)))
     return rc;
 
   ColParams* cp = sc.colparams.as<ColParams>();
@@ -526,6 +606,9 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   unsigned long long* counts = sc.counts.as<unsigned long long>();
   unsigned long long* counters = sc.counters.as<unsigned long long>();
   int* flags = sc.flags.as<int>();
+  double* mass = sc.levelinfo.as<double>();
+  int* mode = reinterpret_cast<int*>(mass + AGP_MAX_LEVELS + 2);
+  AGP_HIP(hipMemsetAsync(sc.levelinfo.ptr, 0, sc.levelinfo.bytes, s));
   AGP_HIP(hipMemsetAsync(counts, 0, sc.counts.bytes, s));
   AGP_HIP(hipMemsetAsync(counters, 0, sc.counters.bytes, s));
   AGP_HIP(hipMemsetAsync(flags, 0, sc.flags.bytes, s));
@@ -546,16 +629,12 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   const bool positive = sizeof(T) == 4 && !(hflags[1] & 2);
 
   AGP_HIP(hipMemsetAsync(out, 0, cells * sizeof(T), s));
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (stats) {
-    AGP_HIP(hipEventCreate(&ev0));
-    AGP_HIP(hipEventCreate(&ev1));
-    AGP_HIP(hipEventRecord(ev0, s));
-  }
+  hipEvent_t* ev = sc.events;
+  if (stats && (rc = sc.ensure_events())) return rc;
   uint64_t* F[2] = {sc.frontier[0].as<uint64_t>(), sc.frontier[1].as<uint64_t>()};
   Cell* acc[2] = {sc.acc[0].as<Cell>(), sc.acc[1].as<Cell>()};
   const unsigned cgrid = grid_for(n * (int64_t)(C >= kWave ? kWave : C), kThreads, 8192);
-  k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroValue<T>{x}, n, C, F[0], counts);
+  k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroValue<T>{x}, n, C, F[0], counts, nullptr);
 
   LevelArgs A;
   A.rp = g->row_ptr;
@@ -572,6 +651,9 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   A.counters = counters;
   A.err = flags;
   A.positive = positive ? 1 : 0;
+  A.dense_cut = std::max<unsigned long long>(1ull, static_cast<unsigned long long>(cells / 32));
+  A.mode = mode;
+  A.mass = mass;
   for (int32_t i = 0; i <= L; ++i) {
     A.level = i;
     A.rho = rho[i];
@@ -583,6 +665,7 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
     Cell* cur = acc[i & 1];
     Cell* nxt = acc[(i + 1) & 1];
     const bool first = i == 0, last = i == L;
+    if (stats) AGP_HIP(hipEventRecord(ev[2 * i], s));
     if (first && last)
       k_level<T, true, true><<<kLevelBlocks, kThreads, 0, s>>>(A, x, cur, nxt, out);
     else if (first)
@@ -591,13 +674,20 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
       k_level<T, false, true><<<kLevelBlocks, kThreads, 0, s>>>(A, x, cur, nxt, out);
     else
       k_level<T, false, false><<<kLevelBlocks, kThreads, 0, s>>>(A, x, cur, nxt, out);
-    if (!last && !positive)
-      k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, F[(i + 1) & 1], counts + i + 1);
+    if (stats) AGP_HIP(hipEventRecord(ev[2 * i + 1], s));
+    if (!last)
+      k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, F[(i + 1) & 1], counts + i + 1,
+                                           mode + i + 1);
   }
   AGP_HIP(hipGetLastError());
-  if (stats) AGP_HIP(hipEventRecord(ev1, s));
+  std::vector<double> hmass(static_cast<size_t>(L) + 1);
   AGP_HIP(hipMemcpyAsync(hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  AGP_HIP(hipMemcpyAsync(hmass.data(), mass, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, s));
   AGP_HIP(hipStreamSynchronize(s));
+  // no partial sum can wrap while a level's total magnitude stays below the cell range
+  const double mass_cap = sizeof(T) == 4 ? 0x1p61 : 0x1p125;
+  for (int32_t i = 0; i <= L; ++i)
+    if (!(hmass[i] < mass_cap)) hflags[0] |= 1;
   if (hflags[0]) {
     // restore the all-zero invariant of the accumulators
     AGP_HIP(hipMemsetAsync(sc.acc[0].ptr, 0, sc.acc[0].bytes, s));
@@ -619,10 +709,12 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
       stats->acc[i] = h[i * kNumCounters + 4];
     }
     float ms = 0.0f;
-    AGP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    for (int32_t i = 0; i <= L; ++i) {
+      AGP_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      stats->level_ms[i] = ms;
+    }
+    AGP_HIP(hipEventElapsedTime(&ms, ev[0], ev[2 * L + 1]));
     stats->device_ms = ms;
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
   }
   return AGP_OK;
 }

@@ -153,6 +153,69 @@ int agp_propagate_f64(const agp_graph_t* g, double a, double b, const double* w,
                       const double* x, int32_t C, double eps, uint64_t seed,
                       const uint32_t* qids, double* out, void* stream, agp_stats_t* stats);
 
+/* ----------------------------------------------------------------- serving */
+
+/* A single-source proximity query: x = e_source (||x||_1 = 1, so theta = eps).
+ * PPR, heat kernel PageRank, Katz and L-hop transition probability are the
+ * models of Table 1 with x = e_s. */
+typedef struct agp_query {
+  int64_t source;    /* node id, 0 <= source < n                                */
+  double a, b;       /* exponents in [0, 1]                                     */
+  int32_t L;         /* levels, 0 <= L <= AGP_MAX_LEVELS                        */
+  const double* w;   /* host double[L + 1], finite, >= 0; copied by agp_submit  */
+  double eps;        /* error parameter; 2^-38 <= eps (exact-accumulator range) */
+  uint64_t seed;     /* key of the query's random streams                       */
+  uint32_t query_id; /* < 2^24; with seed selects the random streams            */
+  float* out;        /* device float[n]: receives pi_hat                        */
+} agp_query_t;
+
+typedef struct agp_server_config {
+  int32_t max_slots;      /* queries advanced together per step (>= 1)          */
+  int32_t queue_capacity; /* submitted but not yet admitted queries (>= 1)      */
+  double work_budget;     /* admission cap on the summed Theorem 3.3 push
+                             estimates of running queries; 0 = no cap          */
+} agp_server_config_t;
+
+typedef struct agp_result {
+  int32_t status;     /* AGP_OK, or AGP_ERANGE if the query's residues outgrew
+                         the exact accumulators                                */
+  int32_t levels;     /* L                                                     */
+  uint64_t frontier;  /* sum over levels of the query's frontier sizes         */
+  uint64_t pushes;    /* deterministic + accepted sampled pushes               */
+  uint64_t candidates;/* sampled candidate positions                           */
+  double submit_ms;   /* times in ms on the server's clock (steady, from       */
+  double start_ms;    /*   server creation): submission, admission, and the    */
+  double end_ms;      /*   end of the step that finished the query             */
+} agp_result_t;
+
+typedef struct agp_server agp_server_t;
+
+/* Create a query server over graph g (Section 4's randomized propagation
+ * applied to a stream of single-source queries, continuously batched).  A
+ * worker thread admits queued queries into free slots, in submission order,
+ * while the summed push estimates stay within work_budget, and advances every
+ * running query by one level per step in one launch; slots may be at
+ * different levels with different a, b, L, w and eps.  A query finishes after
+ * its level L; its result is independent of what runs beside it.
+ * Device memory: about 36 bytes x n x max_slots.  The graph must outlive the
+ * server.  Errors: AGP_EINVAL, AGP_ENOMEM, AGP_EDEVICE. */
+int agp_server_create(const agp_graph_t* g, const agp_server_config_t* cfg, agp_server_t** out);
+
+/* Queue a query; *ticket identifies it for agp_poll.  The descriptor and the
+ * weights are copied; the caller keeps ownership of q->out, which the server
+ * writes (zero-filled first) only while the query runs.  Returns AGP_EINVAL
+ * for an invalid query (nothing is queued), AGP_EBUSY when the queue is full. */
+int agp_submit(agp_server_t* s, const agp_query_t* q, uint64_t* ticket);
+
+/* AGP_OK with *res filled once the query has finished (the ticket is then
+ * released), AGP_PENDING while it is queued or running, AGP_ENOENT for an
+ * unknown or already collected ticket.  Thread-safe. */
+int agp_poll(agp_server_t* s, uint64_t ticket, agp_result_t* res);
+
+/* Stop admitting, finish the running queries, drop the queued ones and free
+ * the server.  Synchronous. */
+int agp_server_destroy(agp_server_t* s);
+
 /* ------------------------------------------- weight sequences (Table 1) */
 
 /* w_i = alpha (1 - alpha)^i, i = 0..L (PageRank, PPR, APPNP). */

@@ -22,7 +22,8 @@ MAX_LEVELS = 255
 EXPORTED = [
     "agp_last_error", "agp_graph_create", "agp_graph_info", "agp_graph_export",
     "agp_graph_destroy", "agp_propagate", "agp_propagate_f64", "agp_weights_ppr",
-    "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp",
+    "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp", "agp_server_create", "agp_submit",
+    "agp_poll", "agp_server_destroy",
 ]
 
 
@@ -212,3 +213,75 @@ def weights_tp(L: int) -> np.ndarray:
     w = np.empty(L + 1, dtype=np.float64)
     _check(lib().agp_weights_tp(L, w.ctypes.data_as(ct.POINTER(ct.c_double))))
     return w
+
+
+class Query(ct.Structure):
+    _fields_ = [("source", ct.c_int64), ("a", ct.c_double), ("b", ct.c_double), ("L", ct.c_int32),
+                ("w", ct.POINTER(ct.c_double)), ("eps", ct.c_double), ("seed", ct.c_uint64),
+                ("query_id", ct.c_uint32), ("out", ct.c_void_p)]
+
+
+class ServerConfig(ct.Structure):
+    _fields_ = [("max_slots", ct.c_int32), ("queue_capacity", ct.c_int32), ("work_budget", ct.c_double)]
+
+
+class Result(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("levels", ct.c_int32), ("frontier", ct.c_uint64),
+                ("pushes", ct.c_uint64), ("candidates", ct.c_uint64), ("submit_ms", ct.c_double),
+                ("start_ms", ct.c_double), ("end_ms", ct.c_double)]
+
+    def to_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _server_lib():
+    L = lib()
+    if not getattr(L, "_server_ready", False):
+        vp = ct.c_void_p
+        L.agp_server_create.argtypes = [vp, ct.POINTER(ServerConfig), ct.POINTER(vp)]
+        L.agp_submit.argtypes = [vp, ct.POINTER(Query), ct.POINTER(ct.c_uint64)]
+        L.agp_poll.argtypes = [vp, ct.c_uint64, ct.POINTER(Result)]
+        L.agp_server_destroy.argtypes = [vp]
+        L._server_ready = True
+    return L
+
+
+class Server:
+    """Continuous-batching server of single-source queries on one graph."""
+
+    def __init__(self, graph: Graph, max_slots: int = 64, queue_capacity: int = 4096,
+                 work_budget: float = 0.0):
+        L = _server_lib()
+        self.graph = graph  # keeps the graph alive
+        cfg = ServerConfig(max_slots, queue_capacity, work_budget)
+        h = ct.c_void_p()
+        _check(L.agp_server_create(graph.handle, ct.byref(cfg), ct.byref(h)))
+        self._h = h
+
+    def submit(self, source: int, a: float, b: float, w, eps: float, seed: int, query_id: int, out) -> int:
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        q = Query(int(source), float(a), float(b), w.size - 1, w.ctypes.data_as(ct.POINTER(ct.c_double)),
+                  float(eps), ct.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(query_id), _dptr(out))
+        t = ct.c_uint64()
+        _check(_server_lib().agp_submit(self._h, ct.byref(q), ct.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """Result dict when finished, None while pending (raises on unknown tickets)."""
+        r = Result()
+        rc = _server_lib().agp_poll(self._h, ticket, ct.byref(r))
+        if rc == AGP_PENDING:
+            return None
+        _check(rc)
+        return r.to_dict()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _server_lib().agp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,457 @@
+// Continuous-batching query server: single-source proximity queries (PPR,
+// heat kernel PageRank, Katz, L-hop transition probability) arrive at any
+// time; each is admitted into a free slot (a column of the level kernel) and
+// advances one level per step together with every other running query,
+// whatever their levels, weights, exponents and thresholds.  The random
+// streams are keyed by (seed, query_id) and the level sums are exact, so a
+// query's result is the same alone, in a batch or in any mix.
+//
+// Slot c owns the n-vector cells c * n .. c * n + n - 1 of two accumulator
+// arrays; the reserve goes straight to the query's output buffer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "agp_internal.h"
+#include "level_kernels.h"
+
+namespace agp {
+namespace srv {
+struct AdmitItem {
+  long long units;  // the initial residue 1.0 in the column's units
+  uint32_t source;
+  uint32_t slot;
+};
+}  // namespace srv
+
+namespace {
+
+using namespace lvl;
+using srv::AdmitItem;
+
+// New slots: seed the residue of the source, append it to the frontier, clear
+// the slot's counters.
+__global__ void k_admit(const AdmitItem* __restrict__ items, int k, long long* __restrict__ acc, int64_t n,
+                        uint64_t* __restrict__ F, unsigned long long* __restrict__ cnt,
+                        unsigned long long* __restrict__ counters, double* __restrict__ mass,
+                        int* __restrict__ err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  const AdmitItem it = items[i];
+  acc[static_cast<size_t>(it.slot) * static_cast<size_t>(n) + it.source] = it.units;
+  const unsigned long long pos = atomicAdd(cnt, 1ull);
+  F[pos] = (static_cast<uint64_t>(it.source) << 32) | it.slot;
+  for (int j = 0; j < kNumCounters; ++j) counters[static_cast<size_t>(it.slot) * kNumCounters + j] = 0;
+  mass[it.slot] = 0.0;
+  err[it.slot] = 0;
+}
+
+__global__ void k_zero_count(unsigned long long* c) { *c = 0; }
+
+double now_ms(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+}  // namespace agp
+
+using agp::lvl::ColParams;
+
+struct QueryRec {
+  agp_query_t q;
+  std::vector<double> w;
+  std::vector<double> rho, kappa;
+  double estimate = 0.0;
+  int slot = -1;
+  int level = 0;
+  bool fresh = false;  // admitted; its source residue is seeded in the next step
+  bool done = false;
+  bool failed = false;
+  agp_result_t res{};
+};
+
+struct agp_server {
+  agp_graph* g = nullptr;
+  agp_server_config_t cfg{};
+  int64_t n = 0;
+  int S = 0;
+  hipStream_t stream = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  // device state
+  agp::DevBuf acc[2], F[2], counts, counters, mass, err, cp, admit, mode;
+  int cur = 0;
+  // host state (guarded by mu)
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<uint64_t> pending;
+  std::unordered_map<uint64_t, QueryRec> recs;
+  std::vector<uint64_t> slot_ticket;  // 0 = free
+  double running_estimate = 0.0;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+  // pinned staging
+  ColParams* h_cp = nullptr;
+  agp::srv::AdmitItem* h_admit = nullptr;
+  unsigned long long* h_counters = nullptr;
+  double* h_mass = nullptr;
+  int* h_err = nullptr;
+  int worker_error = AGP_OK;
+};
+
+namespace agp {
+namespace {
+
+// unit of a column with threshold theta (binary32): ulp of fl(theta)
+void unit_of(double theta, int* ue, double* scale, long long* dtheta) {
+  const float tw = static_cast<float>(theta);
+  int e = -149;
+  if (tw > 0.0f) {
+    int ex;
+    std::frexp(static_cast<double>(tw), &ex);
+    e = (ex - 1) - 23 < -149 ? -149 : (ex - 1) - 23;
+  }
+  *ue = e;
+  *scale = std::ldexp(1.0, -e);
+  *dtheta = static_cast<long long>(static_cast<double>(tw) * *scale);
+}
+
+int validate(const agp_server* s, const agp_query_t* q) {
+  if (!q) return fail(AGP_EINVAL, "agp_submit: NULL query");
+  if (q->source < 0 || q->source >= s->n) return fail(AGP_EINVAL, "agp_submit: source out of range");
+  if (!(q->a >= 0.0 && q->a <= 1.0) || !(q->b >= 0.0 && q->b <= 1.0))
+    return fail(AGP_EINVAL, "agp_submit: a and b must lie in [0, 1]");
+  if (q->L < 0 || q->L > AGP_MAX_LEVELS) return fail(AGP_EINVAL, "agp_submit: need 0 <= L <= 255");
+  if (!q->w || !q->out) return fail(AGP_EINVAL, "agp_submit: NULL weights or output");
+  if (!(q->eps > 0.0) || !std::isfinite(q->eps)) return fail(AGP_EINVAL, "agp_submit: need eps > 0");
+  if (q->query_id >= (1u << 24)) return fail(AGP_EINVAL, "agp_submit: query_id must be < 2^24");
+  for (int32_t i = 0; i <= q->L; ++i)
+    if (!(q->w[i] >= 0.0) || !std::isfinite(q->w[i]))
+      return fail(AGP_EINVAL, "agp_submit: weights must be finite and >= 0");
+  int ue;
+  double scale;
+  long long dth;
+  unit_of(q->eps, &ue, &scale, &dth);
+  if (-ue > 61) return fail(AGP_EINVAL, "agp_submit: eps below the exact-accumulator range (2^-38)");
+  return AGP_OK;
+}
+
+// One step: admit, advance every running query by one level, retire.
+int step(agp_server* s) {
+  hipStream_t st = s->stream;
+  std::vector<uint64_t> admitted;
+  int nadmit = 0;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (int c = 0; c < s->S && !s->pending.empty(); ++c) {
+      if (s->slot_ticket[c]) continue;
+      QueryRec& r = s->recs[s->pending.front()];
+      const bool idle = s->running_estimate == 0.0;
+      if (s->cfg.work_budget > 0.0 && !idle && s->running_estimate + r.estimate > s->cfg.work_budget) break;
+      const uint64_t t = s->pending.front();
+      s->pending.pop_front();
+      r.slot = c;
+      r.level = 0;
+      r.fresh = true;
+      r.res.start_ms = now_ms(s->t0);
+      s->slot_ticket[c] = t;
+      s->running_estimate += r.estimate;
+      admitted.push_back(t);
+    }
+    // per-slot parameters of this step
+    for (int c = 0; c < s->S; ++c) {
+      ColParams& p = s->h_cp[c];
+      const uint64_t t = s->slot_ticket[c];
+      if (!t) {
+        p.flags = kDrop;
+        continue;
+      }
+      QueryRec& r = s->recs[t];
+      const int i = r.level;
+      p.theta = r.q.eps;  // ||e_s||_1 = 1
+      unit_of(p.theta, &p.ue, &p.scale, &p.dtheta);
+      p.rho = r.rho[i];
+      p.kappa = r.kappa[i];
+      p.out = r.q.out;
+      p.out_stride = 1;
+      p.qid = r.q.query_id;
+      p.key0 = static_cast<uint32_t>(r.q.seed);
+      p.key1 = static_cast<uint32_t>(r.q.seed >> 32);
+      p.level = i;
+      p.flags = (i == r.q.L ? kLastLevel : 0) | (r.q.a == 0.0 ? kAZero : 0) | (r.failed ? kDrop : 0);
+      if (r.fresh) {
+        r.fresh = false;
+        s->h_admit[nadmit].units = static_cast<long long>(std::ldexp(1.0, -p.ue));
+        s->h_admit[nadmit].source = static_cast<uint32_t>(r.q.source);
+        s->h_admit[nadmit].slot = static_cast<uint32_t>(c);
+        ++nadmit;
+      }
+    }
+  }
+  // degree tables (created under the graph's lock) and output zero-fill
+  for (uint64_t t : admitted) {
+    QueryRec* r;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      r = &s->recs[t];
+    }
+    const double *da, *db;
+    {
+      std::lock_guard<std::mutex> lk(s->g->mu);
+      int rc;
+      if ((rc = pow_table(s->g, r->q.a, &da)) || (rc = pow_table(s->g, r->q.b, &db))) return rc;
+    }
+    s->h_cp[r->slot].da = da;
+    s->h_cp[r->slot].db = db;
+    AGP_HIP(hipMemsetAsync(r->q.out, 0, sizeof(float) * static_cast<size_t>(s->n), st));
+  }
+  const int cur = s->cur, nxt = 1 - s->cur;
+  unsigned long long* counts = s->counts.as<unsigned long long>();
+  long long* acc[2] = {s->acc[0].as<long long>(), s->acc[1].as<long long>()};
+  uint64_t* F[2] = {s->F[0].as<uint64_t>(), s->F[1].as<uint64_t>()};
+  AGP_HIP(hipMemcpyAsync(s->cp.ptr, s->h_cp, sizeof(ColParams) * s->S, hipMemcpyHostToDevice, st));
+  if (nadmit) {
+    AGP_HIP(hipMemcpyAsync(s->admit.ptr, s->h_admit, sizeof(srv::AdmitItem) * nadmit, hipMemcpyHostToDevice, st));
+    k_admit<<<grid_for(nadmit, 64), 64, 0, st>>>(s->admit.as<srv::AdmitItem>(), nadmit, acc[cur], s->n, F[cur],
+                                                  counts + cur, s->counters.as<unsigned long long>(),
+                                                  s->mass.as<double>(), s->err.as<int>());
+  }
+  k_zero_count<<<1, 1, 0, st>>>(counts + nxt);
+  LevelArgs A;
+  A.rp = s->g->row_ptr;
+  A.col = s->g->col;
+  A.nd = s->g->ndeg;
+  A.deg = s->g->degree;
+  A.cp = s->cp.as<ColParams>();
+  A.su = 1;
+  A.sc = s->n;
+  A.level = 0;
+  A.fin = F[cur];
+  A.cnt_in = counts + cur;
+  A.fout = F[nxt];
+  A.cnt_out = counts + nxt;
+  A.counters = s->counters.as<unsigned long long>();
+  A.mass = s->mass.as<double>();
+  A.err = s->err.as<int>();
+  A.positive = 1;
+  A.dense_cut = std::max<unsigned long long>(1ull, static_cast<unsigned long long>(s->n) * s->S / 32);
+  A.mode_out = s->mode.as<int>();
+  k_level<float, false, true><<<kLevelBlocks, kThreads, 0, st>>>(A, nullptr, acc[cur], acc[nxt]);
+  k_compact<<<grid_for(s->n * (int64_t)s->S, kThreads, 8192), kThreads, 0, st>>>(
+      NonZeroCell<float>{acc[nxt]}, s->n, s->S, 1ll, (long long)s->n, F[nxt], counts + nxt, s->mode.as<int>());
+  AGP_HIP(hipGetLastError());
+  AGP_HIP(hipMemcpyAsync(s->h_counters, s->counters.ptr, sizeof(unsigned long long) * kNumCounters * s->S,
+                         hipMemcpyDeviceToHost, st));
+  AGP_HIP(hipMemcpyAsync(s->h_mass, s->mass.ptr, sizeof(double) * s->S, hipMemcpyDeviceToHost, st));
+  AGP_HIP(hipMemcpyAsync(s->h_err, s->err.ptr, sizeof(int) * s->S, hipMemcpyDeviceToHost, st));
+  AGP_HIP(hipStreamSynchronize(st));
+  s->cur = nxt;
+  // retire
+  std::lock_guard<std::mutex> lk(s->mu);
+  const double t_end = now_ms(s->t0);
+  for (int c = 0; c < s->S; ++c) {
+    const uint64_t t = s->slot_ticket[c];
+    if (!t) continue;
+    QueryRec& r = s->recs[t];
+    const bool overflow = s->h_err[c] != 0 || !(s->h_mass[c] < 0x1p61);
+    bool finish = false;
+    if (r.failed) {
+      finish = true;  // its residues were dropped in this step
+    } else if (overflow) {
+      r.failed = true;  // drop its remaining residues in the next step
+    } else if (r.level == r.q.L) {
+      finish = true;
+    } else {
+      ++r.level;
+    }
+    if (finish) {
+      const unsigned long long* k = s->h_counters + static_cast<size_t>(c) * kNumCounters;
+      r.res.status = r.failed ? AGP_ERANGE : AGP_OK;
+      r.res.levels = r.q.L;
+      r.res.frontier = k[0];
+      r.res.pushes = k[2] + k[4];
+      r.res.candidates = k[3];
+      r.res.end_ms = t_end;
+      r.done = true;
+      s->slot_ticket[c] = 0;
+      s->running_estimate -= r.estimate;
+      if (s->running_estimate < 1e-9) s->running_estimate = 0.0;
+    }
+  }
+  s->cv.notify_all();
+  return AGP_OK;
+}
+
+void worker_main(agp_server* s) {
+  (void)hipSetDevice(s->g->device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [s] {
+        bool active = false;
+        for (uint64_t t : s->slot_ticket) active |= (t != 0);
+        return s->stop || active || !s->pending.empty();
+      });
+      bool active = false;
+      for (uint64_t t : s->slot_ticket) active |= (t != 0);
+      if (s->stop && !active) break;
+      if (s->stop) s->pending.clear();
+    }
+    const int rc = step(s);
+    if (rc != AGP_OK) {
+      // a device failure ends every running and queued query
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->worker_error = rc;
+      for (auto& kv : s->recs) {
+        if (!kv.second.done) {
+          kv.second.done = true;
+          kv.second.res.status = rc;
+        }
+      }
+      s->pending.clear();
+      std::fill(s->slot_ticket.begin(), s->slot_ticket.end(), 0);
+      s->cv.notify_all();
+      break;
+    }
+  }
+}
+
+}  // namespace
+}  // namespace agp
+
+extern "C" {
+
+int agp_server_create(const agp_graph_t* g, const agp_server_config_t* cfg, agp_server_t** out) {
+  using namespace agp;
+  if (!out) return fail(AGP_EINVAL, "agp_server_create: out is NULL");
+  *out = nullptr;
+  if (!g || !cfg || cfg->max_slots < 1 || cfg->queue_capacity < 1 || !(cfg->work_budget >= 0.0))
+    return fail(AGP_EINVAL, "agp_server_create: need a graph, max_slots >= 1, queue_capacity >= 1");
+  agp_server* s = new (std::nothrow) agp_server();
+  if (!s) return fail(AGP_ENOMEM, "agp_server_create: host allocation failed");
+  s->g = const_cast<agp_graph*>(g);
+  s->cfg = *cfg;
+  s->n = g->n;
+  s->S = cfg->max_slots;
+  s->t0 = std::chrono::steady_clock::now();
+  s->slot_ticket.assign(s->S, 0);
+  const size_t cells = static_cast<size_t>(s->n) * static_cast<size_t>(s->S);
+  int rc = AGP_OK;
+  hipError_t e = hipStreamCreate(&s->stream);
+  if (e != hipSuccess) rc = fail(AGP_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+  if (!rc) {
+    if ((rc = s->acc[0].reserve(cells * sizeof(long long), true, s->stream)) ||
+        (rc = s->acc[1].reserve(cells * sizeof(long long), true, s->stream)) ||
+        (rc = s->F[0].reserve(cells * sizeof(uint64_t), false, s->stream)) ||
+        (rc = s->F[1].reserve(cells * sizeof(uint64_t), false, s->stream)) ||
+        (rc = s->counts.reserve(2 * sizeof(unsigned long long), true, s->stream)) ||
+        (rc = s->counters.reserve(sizeof(unsigned long long) * lvl::kNumCounters * s->S, true, s->stream)) ||
+        (rc = s->mass.reserve(sizeof(double) * s->S, true, s->stream)) ||
+        (rc = s->err.reserve(sizeof(int) * s->S, true, s->stream)) ||
+        (rc = s->cp.reserve(sizeof(ColParams) * s->S, false, s->stream)) ||
+        (rc = s->admit.reserve(sizeof(srv::AdmitItem) * s->S, false, s->stream)) ||
+        (rc = s->mode.reserve(sizeof(int), true, s->stream))) {
+    }
+  }
+  if (!rc) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&s->h_cp), sizeof(ColParams) * s->S) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&s->h_admit), sizeof(srv::AdmitItem) * s->S) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&s->h_counters),
+                      sizeof(unsigned long long) * lvl::kNumCounters * s->S) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&s->h_mass), sizeof(double) * s->S) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&s->h_err), sizeof(int) * s->S) != hipSuccess)
+      rc = fail(AGP_ENOMEM, "agp_server_create: pinned host allocation failed");
+  }
+  if (!rc && hipStreamSynchronize(s->stream) != hipSuccess) rc = fail(AGP_EDEVICE, "agp_server_create: sync");
+  if (rc) {
+    agp_server_destroy(s);
+    return rc;
+  }
+  std::memset(static_cast<void*>(s->h_cp), 0, sizeof(ColParams) * s->S);
+  s->worker = std::thread(agp::worker_main, s);
+  *out = s;
+  return AGP_OK;
+}
+
+int agp_submit(agp_server_t* s, const agp_query_t* q, uint64_t* ticket) {
+  using namespace agp;
+  if (!s || !ticket) return fail(AGP_EINVAL, "agp_submit: NULL server or ticket");
+  int rc = validate(s, q);
+  if (rc) return rc;
+  QueryRec r;
+  r.q = *q;
+  r.w.assign(q->w, q->w + q->L + 1);
+  r.q.w = r.w.data();
+  // level tables: Y_i = sum_{k=i..L} w_k from k = L down; rho, kappa as in
+  // the batched path
+  const int32_t L = q->L;
+  std::vector<double> Y(static_cast<size_t>(L) + 2, 0.0);
+  for (int32_t k = L; k >= 0; --k) Y[k] = Y[k + 1] + r.w[k];
+  const double S = Y[0];
+  r.rho.resize(L + 1);
+  r.kappa.resize(L + 1);
+  double est = 0.0;
+  for (int32_t i = 0; i <= L; ++i) {
+    r.rho[i] = (Y[i] == 0.0) ? 0.0 : Y[i + 1] / Y[i];
+    r.kappa[i] = (Y[i] == 0.0) ? 0.0 : (S * r.w[i]) / Y[i];
+    if (i >= 1 && S > 0.0) est += std::min((Y[i] / S) / q->eps, static_cast<double>(s->g->nnz));
+  }
+  r.estimate = est;  // Theorem 3.3: E[pushes] <= (1/eps) sum_{i>=1} ||Y_i P^i x||_1
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->worker_error) return fail(s->worker_error, "agp_submit: the server stopped after a device error");
+  if (s->stop) return fail(AGP_EINVAL, "agp_submit: the server is shutting down");
+  if (static_cast<int32_t>(s->pending.size()) >= s->cfg.queue_capacity)
+    return fail(AGP_EBUSY, "agp_submit: queue full");
+  const uint64_t t = s->next_ticket++;
+  r.res.submit_ms = now_ms(s->t0);
+  s->recs.emplace(t, std::move(r));
+  s->recs[t].q.w = s->recs[t].w.data();
+  s->pending.push_back(t);
+  *ticket = t;
+  s->cv.notify_all();
+  return AGP_OK;
+}
+
+int agp_poll(agp_server_t* s, uint64_t ticket, agp_result_t* res) {
+  using namespace agp;
+  if (!s) return fail(AGP_EINVAL, "agp_poll: NULL server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->recs.find(ticket);
+  if (it == s->recs.end()) return fail(AGP_ENOENT, "agp_poll: unknown ticket");
+  if (!it->second.done) return AGP_PENDING;
+  if (res) *res = it->second.res;
+  s->recs.erase(it);
+  return AGP_OK;
+}
+
+int agp_server_destroy(agp_server_t* s) {
+  if (!s) return AGP_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  for (auto* b : {&s->acc[0], &s->acc[1], &s->F[0], &s->F[1], &s->counts, &s->counters, &s->mass, &s->err,
+                  &s->cp, &s->admit, &s->mode})
+    b->release();
+  if (s->h_cp) (void)hipHostFree(s->h_cp);
+  if (s->h_admit) (void)hipHostFree(s->h_admit);
+  if (s->h_counters) (void)hipHostFree(s->h_counters);
+  if (s->h_mass) (void)hipHostFree(s->h_mass);
+  if (s->h_err) (void)hipHostFree(s->h_err);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+  return AGP_OK;
+}
+
+}  // extern "C"

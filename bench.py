@@ -1,6 +1,7 @@
 """Benchmark of the randomized level push on one MI355X.
 
-Default workload (one step = one pass of the whole hot path over one batch):
+Default workload, `--workload katz-tp` (one step = one pass of the whole hot
+path over one batch):
   R-MAT graph, scale 22 (4,194,304 nodes), 16 generated edges per node,
   (a, b, c) = (0.57, 0.19, 0.19), symmetrised, deduplicated, loops dropped;
   256 sources drawn uniformly among nodes of degree >= 1;
@@ -8,10 +9,14 @@ Default workload (one step = one pass of the whole hot path over one batch):
     FP64 power iteration), L = 30, eps = 1e-7, the 256 sources in one call;
   * 10-step transition probability: a = 0, b = 1, w_10 = 1, L = 10,
     eps = 1e-7, the same 256 sources in one call.
+Other workloads:
+  `--workload gnn-hkpr`: heat-kernel feature propagation (t = 5, L = 10,
+    a = b = 1/2, eps = 1e-7) of a 2.4M x 128 N(0,1) matrix on a Chung-Lu
+    graph (n = 2.4M, mean degree 50, exponent 2.5, one self-loop per node).
 The value is edge pushes (deterministic + accepted sampled pushes, the cost
 unit of Theorem 3.3) per second over the timed steps, inputs resident in HBM.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
@@ -19,6 +24,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -48,32 +54,198 @@ def alg_bytes(st: dict, levels, a_zero: bool) -> float:
     return tot
 
 
-def build_workload(log_fn, cache_dir):
+def cached(cache_dir, name, make):
+    """Generated inputs, kept in cache_dir between runs of one session."""
     from paper_2106_03058_amd import inputs
 
-    path = os.path.join(cache_dir, "rmat22_ef16_s2.npz") if cache_dir else None
+    path = os.path.join(cache_dir, name + ".npz") if cache_dir else None
     t = time.time()
     if path and os.path.exists(path):
         z = np.load(path)
         g = inputs.Graph(int(z["n"]), z["row_ptr"], z["col"])
-        lam = float(z["lam"])
-        log_fn(f"graph and lambda_1 loaded from {path} in {time.time() - t:.1f}s")
-    else:
+        extra = {k: z[k] for k in z.files if k not in ("n", "row_ptr", "col")}
+        log(f"{name} loaded from cache in {time.time() - t:.1f}s")
+        return g, extra
+    g, extra = make()
+    log(f"{name}: {g.describe()} in {time.time() - t:.1f}s")
+    if path:
+        os.makedirs(cache_dir, exist_ok=True)
+        np.savez(path, n=g.n, row_ptr=g.row_ptr, col=g.col, **extra)
+    return g, extra
+
+
+def workload_katz_tp(args):
+    from paper_2106_03058_amd import inputs
+
+    def make():
         g = inputs.rmat(22, 16, 0.57, 0.19, 0.19, seed=2)
-        log_fn(f"graph {g.describe()} in {time.time() - t:.1f}s")
         t = time.time()
         lam = inputs.lambda_max(g, tol=1e-10, max_iter=1000)
-        log_fn(f"lambda_1 = {lam:.6f} in {time.time() - t:.1f}s")
-        if path:
-            os.makedirs(cache_dir, exist_ok=True)
-            np.savez(path, n=g.n, row_ptr=g.row_ptr, col=g.col, lam=lam)
+        log(f"lambda_1 = {lam:.6f} in {time.time() - t:.1f}s")
+        return g, {"lam": np.array(lam)}
+
+    g, extra = cached(args.cache, "rmat22_ef16_s2", make)
+    lam = float(extra["lam"])
     beta = 0.85 / lam
-    src = inputs.sources_uniform(g, 256, seed=102)
-    katz = dict(name="katz", a=0.0, b=0.0, w=inputs.weights_katz(beta, 30, 0.85), eps=1e-7,
-                qids=np.arange(256, dtype=np.uint32))
-    tp = dict(name="tp", a=0.0, b=1.0, w=inputs.weights_tp(10), eps=1e-7,
-              qids=np.arange(256, 512, dtype=np.uint32))
-    return g, src, [katz, tp], lam
+    src = inputs.sources_uniform(g, 256, seed=102)[: args.columns]
+    C = src.size
+    models = [
+        dict(name="katz", a=0.0, b=0.0, w=inputs.weights_katz(beta, 30, 0.85), eps=1e-7,
+             qids=np.arange(C, dtype=np.uint32)),
+        dict(name="tp", a=0.0, b=1.0, w=inputs.weights_tp(10), eps=1e-7,
+             qids=np.arange(256, 256 + C, dtype=np.uint32)),
+    ]
+    keep = set(args.models.split(","))
+    models = [m for m in models if m["name"] in keep]
+
+    def signal():
+        x = np.zeros((g.n, C), dtype=np.float32)
+        x[src, np.arange(C)] = 1.0
+        return x
+
+    cfg = {"workload": "+".join(m["name"] for m in models) + f", {C} sources each, rmat scale 22",
+           "graph": g.describe(), "lambda_1": lam, "columns_per_call": C,
+           "models": {m["name"]: {"a": m["a"], "b": m["b"], "L": len(m["w"]) - 1, "eps": m["eps"]}
+                      for m in models}}
+    return g, signal, models, cfg, "queries"
+
+
+def workload_gnn_hkpr(args):
+    from paper_2106_03058_amd import inputs
+
+    def make():
+        return inputs.chung_lu(2_400_000, 50, 2.5, seed=3, self_loops=True), {}
+
+    g, _ = cached(args.cache, "chunglu_2m4_d50_s3_loops", make)
+    C = min(args.columns, 128)
+    models = [dict(name="hkpr", a=0.5, b=0.5, w=inputs.weights_hkpr(5.0, 10), eps=1e-7,
+                   qids=np.arange(C, dtype=np.uint32))]
+
+    def signal():
+        return np.ascontiguousarray(inputs.features_normal(g.n, 128, seed=303)[:, :C])
+
+    cfg = {"workload": f"gnn heat-kernel feature propagation, {C} N(0,1) columns, chung-lu n=2.4M d=50",
+           "graph": g.describe(), "columns_per_call": C,
+           "models": {"hkpr": {"a": 0.5, "b": 0.5, "L": 10, "t": 5.0, "eps": 1e-7}}}
+    return g, signal, models, cfg, "columns"
+
+
+WORKLOADS = {"katz-tp": workload_katz_tp, "gnn-hkpr": workload_gnn_hkpr}
+
+
+def run_serve(args) -> dict:
+    """Served query stream: Poisson arrivals of single-source queries (1/3
+    PPR with alpha ~ U[0.1, 0.3], 1/3 Katz, 1/3 transition probability;
+    L ~ U{10..40}; eps ~ U{1e-5, 1e-6, 1e-7}; sources drawn proportional to
+    degree) on an R-MAT scale-24 graph (32 edges per node), admitted into the
+    continuous-batching server, against the same queries one per launch."""
+    import torch
+
+    from paper_2106_03058_amd import agp, inputs
+
+    dev = torch.device("cuda:0")
+    t = time.time()
+    n, rp, col = inputs.rmat_device(24, 32, 0.57, 0.19, 0.19, seed=4, device=dev)
+    nnz = int(rp[-1].item())
+    log(f"rmat24: n={n} arcs={nnz} in {time.time() - t:.1f}s")
+    t = time.time()
+    lam = inputs.lambda_max_device(n, rp, col, tol=1e-10, max_iter=1000)
+    log(f"lambda_1 = {lam:.6f} in {time.time() - t:.1f}s")
+    G = agp.Graph(rp, col)
+    deg = (rp[1:] - rp[:-1]).cpu().numpy().astype(np.float64)
+    del rp, col
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(404)
+    N = args.queries
+    src = rng.choice(n, size=N, p=deg / deg.sum())
+    qs = []
+    for i in range(N):
+        L = int(rng.integers(10, 41))
+        eps = float(rng.choice([1e-5, 1e-6, 1e-7]))
+        kind = i % 3
+        if kind == 0:
+            qs.append(("ppr", 0.0, 1.0, inputs.weights_ppr(float(rng.uniform(0.1, 0.3)), L), eps))
+        elif kind == 1:
+            qs.append(("katz", 0.0, 0.0, inputs.weights_katz(0.85 / lam, L, 0.85), eps))
+        else:
+            qs.append(("tp", 0.0, 1.0, inputs.weights_tp(L), eps))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=N))
+    S = args.slots
+    pool = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(S + 32)]
+    keep = min(args.single, N)
+    kept = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(keep)]
+    srv = agp.Server(G, max_slots=S, queue_capacity=N + 1)
+    free = list(range(len(pool)))
+    outstanding = {}
+    lat, lat_admit, pushes = [], [], 0
+    submitted = 0
+    t0 = time.perf_counter()
+    while submitted < N or outstanding:
+        now = time.perf_counter() - t0
+        while submitted < N and arrivals[submitted] <= now and (submitted < keep or free):
+            i = submitted
+            name, a, b, w, eps = qs[i]
+            slot = -1 if i < keep else free.pop()
+            buf = kept[i] if i < keep else pool[slot]
+            tk = srv.submit(int(src[i]), a, b, w, eps, 5000 + i, i, buf)
+            outstanding[tk] = (i, slot)
+            submitted += 1
+        done = []
+        for tk, (i, slot) in outstanding.items():
+            r = srv.poll(tk)
+            if r is not None:
+                t_done = time.perf_counter() - t0
+                lat.append((t_done - arrivals[i]) * 1e3)
+                lat_admit.append(r["end_ms"] - r["submit_ms"])
+                pushes += r["pushes"]
+                done.append(tk)
+                if slot >= 0:
+                    free.append(slot)
+        for tk in done:
+            del outstanding[tk]
+        if not done:
+            time.sleep(0.0002)
+    makespan = time.perf_counter() - t0 - arrivals[0]
+    srv.close()
+    lat = np.array(lat)
+    # the same first queries, one per launch (identical results by construction)
+    lat1, pushes1, same = [], 0, True
+    for i in range(keep):
+        name, a, b, w, eps = qs[i]
+        x = torch.zeros((n, 1), dtype=torch.float32, device=dev)
+        x[int(src[i]), 0] = 1.0
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        o, st = agp.propagate(G, a, b, w, x, eps, 5000 + i, qids=[i], stats=True)
+        lat1.append((time.perf_counter() - ts) * 1e3)
+        pushes1 += st["pushes"]
+        same &= bool(torch.equal(o[:, 0], kept[i]))
+    lat1 = np.array(lat1)
+    return {
+        "metric": METRIC,
+        "value": pushes / makespan,
+        "unit": "edge-pushes/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": makespan * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"served stream of {N} queries (ppr/katz/tp, L 10-40, eps 1e-5..1e-7) "
+                               f"at {args.rate:g}/s offered, rmat scale 24",
+                   "graph": {"n": n, "arcs": nnz}, "lambda_1": lam, "slots": S},
+        "queries_per_s_served": N / makespan,
+        "latency_ms_served": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                              "note": "arrival to completion, including queueing"},
+        "queries_per_s_one_per_launch": 1e3 / lat1.mean(),
+        "latency_ms_one_per_launch": {"p50": float(np.percentile(lat1, 50)),
+                                      "p99": float(np.percentile(lat1, 99)), "queries": keep},
+        "pushes_per_s_one_per_launch": pushes1 / (lat1.sum() / 1e3),
+        "served_equals_one_per_launch": same,
+    }
 
 
 def main() -> int:
@@ -82,13 +254,18 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2021)
-    ap.add_argument("--single", type=int, default=16, help="queries timed one per launch")
+    ap.add_argument("--workload", default="katz-tp", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--queries", type=int, default=1024, help="serve: queries in the stream")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: offered arrivals per second")
+    ap.add_argument("--slots", type=int, default=64, help="serve: server slots")
+    ap.add_argument("--single", type=int, default=16, help="units timed one per launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-queries", type=int, default=4, help="oracle sample per model")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--cpu-units", type=int, default=4, help="oracle sample per model")
     ap.add_argument("--cache", default=os.environ.get("AGP_BENCH_CACHE", ""),
                     help="directory to keep the generated graph between runs")
-    ap.add_argument("--models", default="katz,tp", help="subset of the step to run (profiling)")
-    ap.add_argument("--columns", type=int, default=256, help="queries per call (profiling)")
+    ap.add_argument("--models", default="katz,tp,hkpr", help="subset of the step to run (profiling)")
+    ap.add_argument("--columns", type=int, default=256, help="columns per call (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device to device first (reference for HBM counters)")
     args = ap.parse_args()
@@ -102,26 +279,31 @@ def main() -> int:
 
     agp.lib()
     dev = torch.device("cuda:0")
-    g, src, models, lam = build_workload(log, args.cache)
-    keep = set(args.models.split(","))
-    models = [m for m in models if m["name"] in keep]
-    src = src[: args.columns]
-    for m in models:
-        m["qids"] = m["qids"][: args.columns]
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
+        return 0
+    g, signal, models, cfg, unit_name = WORKLOADS[args.workload](args)
     if args.calibrate_copy:
-        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        b_ = torch.empty_like(a)
-        b_.copy_(a)
+        a_ = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b_ = torch.empty_like(a_)
+        b_.copy_(a_)
         torch.cuda.synchronize()
-        del a, b_
+        del a_, b_
     t = time.time()
     G = agp.Graph.from_inputs(g)
     torch.cuda.synchronize()
     log(f"device graph build (degree sort) {time.time() - t:.2f}s, max degree {G.max_degree}")
-    C = src.size
-    X = torch.zeros((g.n, C), dtype=torch.float32, device=dev)
-    X[torch.from_numpy(src).to(dev), torch.arange(C, device=dev)] = 1.0
+    xh = signal()
+    X = torch.from_numpy(xh).to(dev)
+    C = X.shape[1]
     outs = [torch.empty_like(X) for _ in models]
+
+    tunings = {}
+    if not args.no_tune:
+        for m, o in zip(models, outs):
+            tunings[m["name"]] = agp.autotune(G, m["a"], m["b"], m["w"], X, m["eps"], args.seed,
+                                              qids=m["qids"], out=o)
+        log(f"autotuned: {tunings}")
 
     def step(stats: bool):
         res = []
@@ -153,8 +335,7 @@ def main() -> int:
     for r in runs:
         for (st, _), m in zip(r, models):
             L = st["levels"]
-            mids = range(1, L)
-            mid_bytes += alg_bytes(st, mids, m["a"] == 0.0)
+            mid_bytes += alg_bytes(st, range(1, L), m["a"] == 0.0)
             mid_ms += float(st["level_ms"][1:L].sum())
             launches += max(L - 1, 0)
             all_bytes += alg_bytes(st, range(L + 1), m["a"] == 0.0)
@@ -167,18 +348,18 @@ def main() -> int:
                           "pushes": [int(d + a) for d, a in zip(st["det"], st["acc"])],
                           "level_ms": [round(float(v), 4) for v in st["level_ms"]]})
 
-    # batched vs one query per launch, same eps and keys (identical results)
+    # batched vs one unit (query or column) per launch, same eps and keys
     lat_b = []
     for (st, ms), m in zip(runs[-1], models):
         lat_b += [ms] * C
     lat_b = np.array(lat_b)
     q_per_s_batched = len(models) * C / (ms_per_step / 1e3)
     lat_s = []
-    nq = args.single // len(models)
+    nq = args.single // max(len(models), 1)
     one = torch.empty((g.n, 1), dtype=torch.float32, device=dev)
     single_ok = True
     for m, o in zip(models, outs):
-        for c in range(nq):
+        for c in range(min(nq, C)):
             xc = X[:, c:c + 1].contiguous()
             torch.cuda.synchronize()
             ts = time.perf_counter()
@@ -186,7 +367,6 @@ def main() -> int:
             lat_s.append((time.perf_counter() - ts) * 1e3)
             single_ok &= bool(torch.equal(one[:, 0], o[:, c]))
     lat_s = np.array(lat_s) if lat_s else np.zeros(1)
-    q_per_s_single = 1e3 / lat_s.mean() if lat_s.any() else 0.0
 
     result = {
         "metric": METRIC,
@@ -201,20 +381,15 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": "+".join(m["name"] for m in models) + f", {C} sources each, rmat scale 22",
-            "graph": g.describe(),
-            "models": {m["name"]: {"a": m["a"], "b": m["b"], "L": len(m["w"]) - 1, "eps": m["eps"]} for m in models},
-            "lambda_1": lam,
-            "columns_per_call": C,
-        },
+        "config": cfg,
+        "tuning": tunings,
         "pushes_per_step": pushes_step,
         "hbm_gbps_algorithmic_all_levels": all_bytes / (all_ms / 1e3) / 1e9,
-        "queries_per_s_batched": q_per_s_batched,
+        f"{unit_name}_per_s_batched": q_per_s_batched,
         "latency_ms_batched": {"p50": float(np.percentile(lat_b, 50)), "p99": float(np.percentile(lat_b, 99))},
-        "queries_per_s_one_per_launch": q_per_s_single,
+        f"{unit_name}_per_s_one_per_launch": (1e3 / lat_s.mean()) if lat_s.any() else 0.0,
         "latency_ms_one_per_launch": {"p50": float(np.percentile(lat_s, 50)),
-                                      "p99": float(np.percentile(lat_s, 99)), "queries": int(lat_s.size)},
+                                      "p99": float(np.percentile(lat_s, 99)), "units": int(len(lat_s))},
         "one_per_launch_equals_batched": single_ok,
         "roofline": {
             "bound": "hbm",
@@ -233,31 +408,26 @@ def main() -> int:
     if not args.no_cpu_baseline:
         import oracle
 
-        k = args.cpu_queries
-        threads = min(2 * k, 16, os.cpu_count() or 1)
+        k = min(args.cpu_units, C)
+        threads = min(k * len(models), 16, os.cpu_count() or 1)
         t = time.time()
         sg = oracle.degree_sort(g)
         log(f"oracle degree sort {time.time() - t:.1f}s")
-        cols = np.arange(k)
-        tot_push = 0
-        parity = True
-        t = time.time()
-        xs = np.zeros((g.n, k), dtype=np.float32)
-        xs[src[cols], np.arange(k)] = 1.0
-        import threading
-
         results = {}
 
         def run(mi, m):
-            results[mi] = oracle.propagate(sg, m["a"], m["b"], m["w"], xs, m["eps"], args.seed,
-                                           qids=m["qids"][cols], threads=max(threads // len(models), 1))
+            results[mi] = oracle.propagate(sg, m["a"], m["b"], m["w"], xh[:, :k], m["eps"], args.seed,
+                                           qids=m["qids"][:k], threads=max(threads // len(models), 1))
 
+        t = time.time()
         ths = [threading.Thread(target=run, args=(mi, m)) for mi, m in enumerate(models)]
         for th in ths:
             th.start()
         for th in ths:
             th.join()
         wall = time.time() - t
+        tot_push = 0
+        parity = True
         for mi, m in enumerate(models):
             ref, cnt = results[mi]
             tot_push += int(cnt["det"].sum() + cnt["acc"].sum())
@@ -269,9 +439,10 @@ def main() -> int:
             "unit": "edge-pushes/s",
             "cores": threads,
             "kind": "oracle",
-            "sample": f"{k} Katz + {k} TP queries (first {k} sources, same seeds), {wall:.1f}s wall",
+            "sample": f"{k} {unit_name} of each model ({', '.join(m['name'] for m in models)}), same inputs "
+                      f"and seeds, {wall:.1f}s wall",
         }
-        result["parity_full_size"] = {"columns_checked": 2 * k, "bit_exact": parity}
+        result["parity_full_size"] = {"units_checked": k * len(models), "bit_exact": parity}
     print(json.dumps(result), flush=True)
     return 0
 

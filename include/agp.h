@@ -153,6 +153,29 @@ int agp_propagate_f64(const agp_graph_t* g, double a, double b, const double* w,
                       const double* x, int32_t C, double eps, uint64_t seed,
                       const uint32_t* qids, double* out, void* stream, agp_stats_t* stats);
 
+/* ------------------------------------------------------------------ tuning */
+
+/* Execution choices of agp_propagate that never change its results. */
+typedef struct agp_tuning {
+  int32_t aggregation;  /* 0: integer atomics into the accumulators;
+                           1: push records binned by destination, summed in LDS */
+  int32_t level_blocks; /* workgroups of the level kernel (>= 256)               */
+} agp_tuning_t;
+
+/* Autotuner: runs the propagation of the arguments (as agp_propagate) once
+ * per candidate choice, timing each with HIP events on `stream`, and keeps
+ * the fastest for later agp_propagate calls on g with the same column count
+ * and exponents (a, b).  `out` holds the result on return (identical for
+ * every candidate).  *best (nullable) receives the choice.  Errors as
+ * agp_propagate. */
+int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int32_t L,
+                 const float* x, int32_t C, double eps, uint64_t seed, const uint32_t* qids,
+                 float* out, void* stream, agp_tuning_t* best);
+
+/* The choice agp_propagate uses for (g, C, a, b): the tuned one, else the
+ * default (atomics, 2048 workgroups). */
+int agp_get_tuning(const agp_graph_t* g, int32_t C, double a, double b, agp_tuning_t* out);
+
 /* ----------------------------------------------------------------- serving */
 
 /* A single-source proximity query: x = e_source (||x||_1 = 1, so theta = eps).

@@ -23,7 +23,7 @@ EXPORTED = [
     "agp_last_error", "agp_graph_create", "agp_graph_info", "agp_graph_export",
     "agp_graph_destroy", "agp_propagate", "agp_propagate_f64", "agp_weights_ppr",
     "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp", "agp_server_create", "agp_submit",
-    "agp_poll", "agp_server_destroy",
+    "agp_poll", "agp_server_destroy", "agp_autotune", "agp_get_tuning",
 ]
 
 
@@ -107,13 +107,26 @@ class Graph:
 
     def __init__(self, row_ptr, col, *, validate: bool = False, self_loops: bool = False,
                  stream=None):
-        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
-        cl = np.ascontiguousarray(col, dtype=np.int32)
-        n = rp.size - 1
-        flags = AGP_HOST_PTRS | (AGP_VALIDATE if validate else 0) | (AGP_ADD_SELF_LOOPS if self_loops else 0)
+        """row_ptr / col: host arrays, or CUDA tensors (int64 / int32) on the device."""
+        flags = (AGP_VALIDATE if validate else 0) | (AGP_ADD_SELF_LOOPS if self_loops else 0)
+        if hasattr(row_ptr, "is_cuda") and row_ptr.is_cuda:
+            import torch
+
+            if row_ptr.dtype != torch.int64 or col.dtype != torch.int32:
+                raise ValueError("device CSR needs int64 row_ptr and int32 col")
+            rp_t, cl_t = row_ptr.contiguous(), col.contiguous()
+            n = rp_t.numel() - 1
+            nnz = int(rp_t[-1].item())
+            rp_p, cl_p = rp_t.data_ptr(), (cl_t.data_ptr() if cl_t.numel() else None)
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            cl = np.ascontiguousarray(col, dtype=np.int32)
+            n = rp.size - 1
+            nnz = int(rp[-1])
+            flags |= AGP_HOST_PTRS
+            rp_p, cl_p = rp.ctypes.data, (cl.ctypes.data if cl.size else None)
         h = ct.c_void_p()
-        _check(lib().agp_graph_create(n, int(rp[-1]), rp.ctypes.data, cl.ctypes.data if cl.size else None,
-                                      flags, _stream_ptr(stream), ct.byref(h)))
+        _check(lib().agp_graph_create(n, nnz, rp_p, cl_p, flags, _stream_ptr(stream), ct.byref(h)))
         self._h = h
         n_, nnz, md = ct.c_int64(), ct.c_int64(), ct.c_int32()
         _check(lib().agp_graph_info(h, ct.byref(n_), ct.byref(nnz), ct.byref(md)))
@@ -189,6 +202,52 @@ def propagate(graph: Graph, a: float, b: float, w, x, eps: float, seed: int, *, 
               _stream_ptr(stream), ct.byref(st) if st is not None else None))
     res = o.reshape(-1) if vec else o
     return res, (st.to_dict() if st is not None else None)
+
+
+class Tuning(ct.Structure):
+    _fields_ = [("aggregation", ct.c_int32), ("level_blocks", ct.c_int32)]
+
+    def to_dict(self) -> dict:
+        return {"aggregation": "binned" if self.aggregation else "atomic", "level_blocks": self.level_blocks}
+
+
+def _tune_lib():
+    L = lib()
+    if not getattr(L, "_tune_ready", False):
+        vp = ct.c_void_p
+        L.agp_autotune.argtypes = [vp, ct.c_double, ct.c_double, ct.POINTER(ct.c_double), ct.c_int32, vp,
+                                   ct.c_int32, ct.c_double, ct.c_uint64, ct.POINTER(ct.c_uint32), vp, vp,
+                                   ct.POINTER(Tuning)]
+        L.agp_get_tuning.argtypes = [vp, ct.c_int32, ct.c_double, ct.c_double, ct.POINTER(Tuning)]
+        L._tune_ready = True
+    return L
+
+
+def autotune(graph: Graph, a: float, b: float, w, x, eps: float, seed: int, *, qids=None, out=None,
+             stream=None) -> dict:
+    """Time the interchangeable execution choices on this workload (binary32)
+    and keep the fastest for later calls with the same C, a, b."""
+    import torch
+
+    X = x.reshape(graph.n, -1).contiguous()
+    if X.dtype != torch.float32:
+        raise ValueError("autotune takes binary32 signals")
+    C = X.shape[1]
+    o = torch.empty_like(X) if out is None else out.reshape(graph.n, -1)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    q = None if qids is None else np.ascontiguousarray(qids, dtype=np.uint32)
+    t = Tuning()
+    _check(_tune_lib().agp_autotune(graph.handle, float(a), float(b), w.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                    w.size - 1, _dptr(X), C, float(eps), ct.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF),
+                                    None if q is None else q.ctypes.data_as(ct.POINTER(ct.c_uint32)), _dptr(o),
+                                    _stream_ptr(stream), ct.byref(t)))
+    return t.to_dict()
+
+
+def get_tuning(graph: Graph, C: int, a: float, b: float) -> dict:
+    t = Tuning()
+    _check(_tune_lib().agp_get_tuning(graph.handle, int(C), float(a), float(b), ct.byref(t)))
+    return t.to_dict()
 
 
 def _weights(fn, *args, L: int) -> np.ndarray:

@@ -29,16 +29,15 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
                                             uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
-    const uint32_t m0lo = 0xD2511F53u * c0;
-    const uint32_t m0hi = __umulhi(0xD2511F53u, c0);
-    const uint32_t m1lo = 0xCD9E8D57u * c2;
-    const uint32_t m1hi = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t y0 = m1hi ^ c1 ^ k0;
-    const uint32_t y2 = m0hi ^ c3 ^ k1;
+    // one 32 x 32 -> 64-bit product per multiplier (a single v_mad_u64_u32)
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t y0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t y2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
     c0 = y0;
-    c1 = m1lo;
+    c1 = static_cast<uint32_t>(p1);
     c2 = y2;
-    c3 = m0lo;
+    c3 = static_cast<uint32_t>(p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -47,8 +46,11 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 
 // 53 random bits (32 from `hi`, the top 21 of `lo`) as a double in [0, 1).
 __device__ __forceinline__ double unit_double(uint32_t hi, uint32_t lo) {
-  const uint64_t m = (static_cast<uint64_t>(hi) << 21) | static_cast<uint64_t>(lo >> 11);
-  return static_cast<double>(m) * 0x1p-53;
+  // hi * 2^21 + (lo >> 11) is an integer below 2^53: both terms and the sum
+  // are exact in binary64
+  const double h = static_cast<double>(hi) * 2097152.0;
+  const double l = static_cast<double>(lo >> 11);
+  return (h + l) * 0x1p-53;
 }
 
 // --------------------------------------------------------- geometric skip
@@ -276,13 +278,14 @@ __device__ __forceinline__ void stage_flush(uint64_t* stage, int& staged, uint64
   staged = 0;
 }
 
+template <int kCap = kStage>
 __device__ __forceinline__ void stage_push(uint64_t* stage, int& staged, uint64_t item, bool pred,
                                            uint64_t* __restrict__ list,
                                            unsigned long long* __restrict__ count) {
   const unsigned long long mask = __ballot(pred);
   if (pred) stage[staged + __popcll(mask & ((1ull << lane_id()) - 1ull))] = item;
   staged += __popcll(mask);
-  if (staged > kStage - kWave) stage_flush(stage, staged, list, count);
+  if (staged > kCap - kWave) stage_flush(stage, staged, list, count);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {

@@ -46,12 +46,24 @@ struct Scratch {
   DevBuf partial;    // per-block partial norms
   DevBuf flags;      // error and signal flags
   DevBuf levelinfo;  // per level: contribution mass (double), frontier mode (int)
+  DevBuf rec[2];     // binned aggregation: push records, partitioned records
+  DevBuf bins;       // bucket counts, offsets, cursors, per-level record counts
   hipEvent_t events[2 * (AGP_MAX_LEVELS + 1)] = {};  // level timing, created on demand
   int ensure_events();
   void release();
 };
 
 }  // namespace agp
+
+struct agp_tune_key {
+  int32_t C;
+  double a, b;
+  bool operator<(const agp_tune_key& o) const {
+    if (C != o.C) return C < o.C;
+    if (a != o.a) return a < o.a;
+    return b < o.b;
+  }
+};
 
 struct agp_graph {
   int64_t n = 0;
@@ -63,6 +75,7 @@ struct agp_graph {
   uint32_t* ndeg = nullptr;     // device uint32[nnz], degree of col[j]
   int32_t* degree = nullptr;    // device int32[n]
   std::map<double, double*> pow_tables;  // exponent e -> device d^-e, d = 0..max_degree
+  std::map<agp_tune_key, agp_tuning_t> tuning;  // autotuned execution choices
   std::mutex mu;
   agp::Scratch scratch;
 };

@@ -56,6 +56,9 @@ void Scratch::release() {
   partial.release();
   flags.release();
   levelinfo.release();
+  rec[0].release();
+  rec[1].release();
+  bins.release();
 }
 
 // d^-e on the host in binary64: exact IEEE forms 1, 1/sqrt(d), 1/d for the

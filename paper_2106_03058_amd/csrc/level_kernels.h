@@ -36,8 +36,25 @@ constexpr int kTile = 256;  // frontier entries per block tile
 constexpr int kLevelBlocks = 2048;
 constexpr int kNumCounters = 5;   // frontier, hash, det, cand, acc
 constexpr int kThetaRows = 4096;  // rows per partial sum of ||x||_1
+constexpr int kServeLdsSlots = 128;  // server columns whose counters a block sums in LDS
 
 enum : int { kLastLevel = 1, kAZero = 2, kDrop = 4 };
+
+// How the next frontier of a level is formed (written by k_level):
+enum : int {
+  kModeSparse = 0,    // first contributions appended directly
+  kModeCompact = 1,   // fire-and-forget atomics, then a compaction scan
+  kModeBinned = 2,    // records binned by destination and summed in LDS
+  kModeOverflow = 3,  // record buffer overflowed: atomics, then compaction
+};
+
+// Binned aggregation: a record is (cell << 32 | fp32 bits of the
+// contribution); cells are grouped into 1024 buckets of 1024 bins of 4096
+// cells (an LDS accumulator of 32 KiB), so n * C must stay below 2^32.
+constexpr int kBinLog2 = 12;
+constexpr int kBinsPerBucketLog2 = 10;
+constexpr int kBucketShift = kBinLog2 + kBinsPerBucketLog2;
+constexpr int kBuckets = 1024;
 
 struct ColParams {
   double theta;          // eps * ||x_c||_1
@@ -54,6 +71,7 @@ struct ColParams {
   uint32_t key0, key1;   // 64-bit seed
   int level;
   int flags;             // kLastLevel | kAZero | kDrop
+  float theta_w;         // fl(theta) in binary32
 };
 
 struct LevelArgs {
@@ -73,7 +91,12 @@ struct LevelArgs {
   int* err;                      // batched: one flag; server: one per column
   int positive;                  // non-negative signals: sparse levels allowed
   unsigned long long dense_cut;  // frontier size from which a level is dense
-  int* mode_out;                 // 1: the next frontier must be compacted
+  int* mode_out;                 // how the next frontier is formed (kMode*)
+  // binned aggregation (binary32 batched calls; rec == nullptr: disabled)
+  uint64_t* rec;
+  unsigned long long* rec_count;
+  unsigned long long rec_cap;
+  unsigned int* bucket_count;    // records per bucket of this level
 };
 
 // ----------------------------------------------------- working precision
@@ -162,6 +185,64 @@ struct Prec<double> {
 __device__ __forceinline__ float to_w(double v, float) { return static_cast<float>(v); }
 __device__ __forceinline__ double to_w(double v, double) { return v; }
 
+// ------------------------------------------------- record staging
+// Records go to A.rec in chunks (one atomic per chunk).  Records beyond the
+// buffer capacity are added to the accumulator directly; the level then ends
+// in kModeOverflow (the buffered records are applied with atomics too).
+template <typename Cell>
+__device__ __forceinline__ void apply_record(const LevelArgs& A, Cell* acc, uint64_t rec);
+
+template <>
+__device__ __forceinline__ void apply_record<long long>(const LevelArgs& A, long long* acc, uint64_t rec) {
+  const uint32_t cell = static_cast<uint32_t>(rec >> 32);
+  const float val = __uint_as_float(static_cast<uint32_t>(rec));
+  const uint32_t c = cell % static_cast<uint32_t>(A.su);
+  long long d;
+  if (f32_to_units(val, A.cp[c].scale, &d))
+    atomic_add_relaxed(reinterpret_cast<unsigned long long*>(acc + cell), static_cast<unsigned long long>(d));
+  else
+    atomicOr(A.err, 1);
+}
+
+template <>
+__device__ __forceinline__ void apply_record<unsigned long long>(const LevelArgs&, unsigned long long*, uint64_t) {}
+
+template <typename Cell>
+__device__ __forceinline__ void stage_flush_records(uint64_t* stage, int& staged, const LevelArgs& A, Cell* acc) {
+  if (staged == 0) return;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(A.rec_count, static_cast<unsigned long long>(staged));
+  base = __shfl(base, 0);
+  for (int i = lane_id(); i < staged; i += kWave) {
+    if (base + i < A.rec_cap)
+      A.rec[base + i] = stage[i];
+    else
+      apply_record(A, acc, stage[i]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  staged = 0;
+}
+
+template <typename Cell>
+__device__ __forceinline__ void stage_push_records(uint64_t* stage, int& staged, uint64_t rec, bool pred,
+                                                   const LevelArgs& A, Cell* acc) {
+  const unsigned long long mask = __ballot(pred);
+  if (pred) stage[staged + __popcll(mask & ((1ull << lane_id()) - 1ull))] = rec;
+  staged += __popcll(mask);
+  if (staged > kStage - kWave) stage_flush_records(stage, staged, A, acc);
+}
+
+// Server counters: LDS sums for the first kServeLdsSlots columns, global
+// atomics beyond.
+__device__ __forceinline__ void serve_count(const LevelArgs& A, unsigned long long (*lds)[kNumCounters],
+                                            uint32_t c, int k, unsigned long long v) {
+  if (c < kServeLdsSlots)
+    atomicAdd(&lds[c][k], v);
+  else
+    atomicAdd(A.counters + static_cast<size_t>(c) * kNumCounters + k, v);
+}
+
 // ------------------------------------------------------------ the level
 // kFirst: the residues are the signal x (level 0 of a batched call).
 // kServe: counters and overflow mass are kept per column instead of per level.
@@ -174,6 +255,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   __shared__ long long s_off[kTile + 1];
   __shared__ int64_t s_rp[kTile];
   __shared__ double s_cv[kTile];
+  __shared__ double s_p0[kTile];  // a = 0: the sampling probability of every run
   __shared__ uint32_t s_u[kTile];
   __shared__ uint32_t s_c[kTile];
   __shared__ uint32_t s_d[kTile];
@@ -181,13 +263,30 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   __shared__ uint32_t s_neg[kTile];
   __shared__ long long s_wave[kThreads / kWave];
   __shared__ uint64_t s_stage[kThreads / kWave][kStage];
+  __shared__ unsigned int s_hist[kBuckets];
+  // server: per-column counters summed in LDS, flushed once per block
+  __shared__ unsigned long long s_scnt[kServe ? kServeLdsSlots : 1][kNumCounters];
+  __shared__ double s_smass[kServe ? kServeLdsSlots : 1];
 
   const unsigned long long count = *A.cnt_in;
-  // Sparse levels detect the first contribution to a cell from the atomic's
-  // old value and append the cell to the next frontier; dense levels use
-  // fire-and-forget atomics and a compaction pass builds the next frontier.
-  const bool sparse = A.positive && count < A.dense_cut;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *A.mode_out = sparse ? 0 : 1;
+  // Binned levels write (cell, value) records that later kernels group by
+  // destination and sum in LDS.  Without binning, sparse levels detect the
+  // first contribution to a cell from the atomic's old value and append the
+  // cell to the next frontier; dense levels use fire-and-forget atomics and a
+  // compaction pass builds the next frontier.
+  const bool binned = A.rec != nullptr;
+  const bool sparse = !binned && A.positive && count < A.dense_cut;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    *A.mode_out = binned ? kModeBinned : (sparse ? kModeSparse : kModeCompact);
+  if (binned) {
+    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) s_hist[i] = 0;
+    __syncthreads();
+  }
+  if (kServe) {
+    for (int i = threadIdx.x; i < kServeLdsSlots * kNumCounters; i += blockDim.x) (&s_scnt[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < kServeLdsSlots; i += blockDim.x) s_smass[i] = 0.0;
+    __syncthreads();
+  }
   unsigned long long te = (count + gridDim.x - 1) / gridDim.x;
   te = te < 1 ? 1 : (te > (unsigned long long)kTile ? (unsigned long long)kTile : te);
   const unsigned long long ntiles = (count + te - 1) / te;
@@ -219,7 +318,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       double cv = 0.0;
       if (!(cp.flags & kDrop)) {
         if (kServe) {
-          atomicAdd(A.counters + static_cast<size_t>(c) * kNumCounters + 0, 1ull);
+          serve_count(A, s_scnt, c, 0, 1ull);
         } else {
           ++n_front;
           n_hash += splitmix64(u);
@@ -242,6 +341,8 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
             double inc0 = cv;
             if (azero) {
               J = (cv >= th) ? d : 0u;
+              const double num = cv * 1.0;  // every neighbour's factor d^-0 is 1
+              s_p0[tid] = num / th;
             } else {  // increments fall along the degree-sorted row: binary search
               inc0 = cv * cp.da[A.nd[rpu]];
               uint32_t lo = 0, hi = d;
@@ -263,8 +364,11 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
             const T big = to_w(inc0 > th ? inc0 : th, T());
             const double m = static_cast<double>(d) * P::mag_units(big, cp);
             if (kServe) {
-              atomicAdd(A.counters + static_cast<size_t>(c) * kNumCounters + 2, static_cast<unsigned long long>(J));
-              atomicAdd(A.mass + c, m);
+              serve_count(A, s_scnt, c, 2, static_cast<unsigned long long>(J));
+              if (c < kServeLdsSlots)
+                atomicAdd(&s_smass[c], m);
+              else
+                atomicAdd(A.mass + c, m);
             } else {
               n_det += J;
               mass += m;
@@ -306,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
     uint32_t u = 0, c = 0, s = 0, wend = 0, run_end = 0, pos = 0, t = 0, ctr3 = 0;
     uint32_t win_cand = 0, win_acc = 0;
     int64_t rpu = 0;
-    double cv = 0.0, dstart = 1.0, th = 0.0;
+    double cv = 0.0, dstart = 1.0, th = 0.0, p0 = 0.0;
     long long local = 0;
     const ColParams* cpp = nullptr;
     SkipTable tab;
@@ -331,6 +435,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         neg = s_neg[e] != 0;
         cpp = A.cp + c;
         azero = (cpp->flags & kAZero) != 0;
+        if (azero) p0 = s_p0[e];
         if (local < static_cast<long long>(J)) {
           ttype = 1;
         } else {
@@ -348,6 +453,8 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       if (!__any(ttype != 0)) break;
 
       bool emit = false;
+      bool ttype_val_det = false;
+      T det_val = T(0);
       Delta delta{};
       uint32_t v = 0;
       if (ttype == 1) {
@@ -360,15 +467,16 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         if (neg) val = -val;
         emit = P::to_units(val, *cpp, &delta);
         if (!emit) atomicOr(A.err + (kServe ? c : 0u), 1);
+        ttype_val_det = true;
+        det_val = val;
         ttype = 0;
       } else if (ttype == 2) {
         if (need_run) {
           if (s >= wend) {
             ttype = 0;
             if (kServe && win_cand) {
-              atomicAdd(A.counters + static_cast<size_t>(c) * kNumCounters + 3, static_cast<unsigned long long>(win_cand));
-              if (win_acc)
-                atomicAdd(A.counters + static_cast<size_t>(c) * kNumCounters + 4, static_cast<unsigned long long>(win_acc));
+              serve_count(A, s_scnt, c, 3, static_cast<unsigned long long>(win_cand));
+              if (win_acc) serve_count(A, s_scnt, c, 4, static_cast<unsigned long long>(win_acc));
             }
           } else {  // a run: same degree group (a > 0) inside the window
             run_end = wend;
@@ -390,8 +498,11 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
                 run_end = blo;
               }
             }
-            const double num = cv * dstart;
-            const double pstar = num / th;
+            double pstar = p0;  // a = 0: computed once per entry, (cv * 1) / theta
+            if (!azero) {
+              const double num = cv * dstart;
+              pstar = num / th;
+            }
             tab = make_skip_table(pstar);
             pos = s;
             t = 0;
@@ -401,7 +512,6 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         if (ttype == 2 && !need_run) {
           const U4 o = philox4x32_10(t, s, u, ctr3, cpp->key0, cpp->key1);
           const double V = unit_double(o.x, o.y);
-          const double V2 = unit_double(o.z, o.w);
           const uint32_t cand = pos + static_cast<uint32_t>(geometric_skip(tab, V));
           if (cand >= run_end) {
             s = run_end;
@@ -410,9 +520,12 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
             ++n_cand;
             ++win_cand;
             const int64_t arc = rpu + cand;
-            double ratio = 1.0;
-            if (!azero) ratio = cpp->da[A.nd[arc]] / dstart;
-            if (V2 < ratio) {
+            bool accept = true;  // a = 0: the ratio is 1 and every uniform is below it
+            if (!azero) {
+              const double ratio = cpp->da[A.nd[arc]] / dstart;
+              accept = unit_double(o.z, o.w) < ratio;
+            }
+            if (accept) {
               ++n_acc;
               ++win_acc;
               v = A.col[arc];
@@ -425,19 +538,49 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         }
       }
       bool first = false;
-      if (emit) {
-        const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(c) * A.sc;
-        if (sparse)
-          first = P::add_ret(acc_next, vcell, delta);
-        else
-          P::add(acc_next, vcell, delta);
+      const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(c) * A.sc;
+      if (binned) {  // wave-uniform: stage records, flush in chunks
+        uint64_t rec = 0;
+        if (emit) {
+          T val = T(0);
+          if (ttype_val_det) {
+            val = det_val;
+          } else {
+            val = neg ? -static_cast<T>(cpp->theta_w) : static_cast<T>(cpp->theta_w);
+          }
+          rec = (static_cast<uint64_t>(vcell) << 32) | static_cast<uint64_t>(__float_as_uint(static_cast<float>(val)));
+          atomicAdd(&s_hist[vcell >> kBucketShift], 1u);
+        }
+        stage_push_records(stage, staged, rec, emit, A, acc_next);
+      } else {
+        if (emit) {
+          if (sparse)
+            first = P::add_ret(acc_next, vcell, delta);
+          else
+            P::add(acc_next, vcell, delta);
+        }
+        if (sparse)  // wave-uniform: stage first-touched cells, flush in chunks
+          stage_push(stage, staged, (static_cast<uint64_t>(v) << 32) | c, first, A.fout, A.cnt_out);
       }
-      if (sparse)  // wave-uniform: stage first-touched cells, flush in chunks
-        stage_push(stage, staged, (static_cast<uint64_t>(v) << 32) | c, first, A.fout, A.cnt_out);
     }
     __syncthreads();
   }
   if (sparse) stage_flush(stage, staged, A.fout, A.cnt_out);
+  if (binned) {
+    stage_flush_records(stage, staged, A, acc_next);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
+      if (s_hist[i]) atomicAdd(A.bucket_count + i, s_hist[i]);
+  }
+  if (kServe) {  // flush the block's per-column sums
+    __syncthreads();
+    for (int i = threadIdx.x; i < kServeLdsSlots * kNumCounters; i += blockDim.x) {
+      const unsigned long long v = (&s_scnt[0][0])[i];
+      if (v) atomicAdd(A.counters + i, v);
+    }
+    for (int i = threadIdx.x; i < kServeLdsSlots; i += blockDim.x)
+      if (s_smass[i] != 0.0) atomicAdd(A.mass + i, s_smass[i]);
+  }
   if (!kServe) {  // per-level counters: one atomic per wave
     unsigned long long* cnt = A.counters + static_cast<size_t>(A.level) * kNumCounters;
     const unsigned long long v0 = wave_sum_u64(n_front);
@@ -468,7 +611,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int 
                                                       uint64_t* __restrict__ F,
                                                       unsigned long long* __restrict__ cnt,
                                                       const int* __restrict__ mode) {
-  if (mode && *mode == 0) return;  // this frontier was appended directly
+  if (mode && *mode != kModeCompact && *mode != kModeOverflow) return;  // formed elsewhere
   __shared__ uint64_t s_stage[kThreads / kWave][kStage];
   const int lane = lane_id();
   uint64_t* stage = s_stage[threadIdx.x / kWave];

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -67,6 +68,7 @@ __global__ void k_theta_final(const double* __restrict__ partial, int64_t nblock
     p.ue = ue;
     p.scale = ldexp(1.0, -ue);
     p.dtheta = static_cast<long long>(static_cast<double>(tw) * p.scale);
+    p.theta_w = tw;
   } else {
     int ue = -1074;
     if (p.theta > 0.0) {
@@ -78,6 +80,7 @@ __global__ void k_theta_final(const double* __restrict__ partial, int64_t nblock
     U128 d;
     f64_to_units(p.theta, ue, &d);
     p.dtheta = static_cast<long long>(d.lo);  // theta < 2^53 units
+    p.theta_w = static_cast<float>(p.theta);
   }
   cp[c] = p;
 }
@@ -101,11 +104,248 @@ __global__ void k_set_level(ColParams* __restrict__ cp, int C, int level, double
   p.out_stride = out_stride;
 }
 
+// ------------------------------------------------ binned aggregation
+// After a binned level: bucket offsets (one block), then the records are
+// partitioned into 1024 buckets, and one block per bucket splits its bucket
+// into 1024 bins of 4096 cells, sums every bin exactly in LDS (64-bit
+// integer units, so the order of the records is irrelevant), writes the
+// non-zero sums to the next accumulator and appends them to the frontier.
+constexpr int kPartTile = 65536;
+constexpr int kMaxBinnedC = 1024;
+constexpr int kReduceThreads = 512;
+
+__global__ __launch_bounds__(1024) void k_bins_scan(unsigned int* __restrict__ bucket_count,
+                                                    unsigned long long* __restrict__ bucket_off,
+                                                    unsigned long long* __restrict__ cursor,
+                                                    const unsigned long long* __restrict__ rec_count,
+                                                    unsigned long long cap, int* __restrict__ mode) {
+  __shared__ unsigned long long s[kBuckets];
+  const int t = threadIdx.x;
+  const int m = *mode;
+  if (m != kModeBinned) return;
+  const unsigned long long v = bucket_count[t];
+  bucket_count[t] = 0;  // ready for the next level
+  if (*rec_count > cap) {
+    if (t == 0) *mode = kModeOverflow;
+    return;
+  }
+  s[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kBuckets; off <<= 1) {
+    const unsigned long long add = t >= off ? s[t - off] : 0ull;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  const unsigned long long excl = s[t] - v;
+  bucket_off[t] = excl;
+  cursor[t] = excl;
+  if (t == kBuckets - 1) bucket_off[kBuckets] = s[t];
+}
+
+__global__ __launch_bounds__(kThreads) void k_apply_overflow(LevelArgs A, long long* __restrict__ acc,
+                                                             const int* __restrict__ mode) {
+  if (*mode != kModeOverflow) return;
+  const unsigned long long n = *A.rec_count < A.rec_cap ? *A.rec_count : A.rec_cap;
+  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x)
+    apply_record(A, acc, A.rec[i]);
+}
+
+constexpr int kBatch = 8;  // records per thread per load batch (memory-level parallelism)
+
+__global__ __launch_bounds__(kThreads) void k_partition(const uint64_t* __restrict__ rec,
+                                                        const unsigned long long* __restrict__ rec_count,
+                                                        unsigned long long* __restrict__ cursor,
+                                                        uint64_t* __restrict__ out, const int* __restrict__ mode) {
+  if (*mode != kModeBinned) return;
+  __shared__ unsigned int hist[kBuckets];
+  __shared__ unsigned long long base[kBuckets];
+  const unsigned long long total = *rec_count;
+  for (unsigned long long lo = (unsigned long long)blockIdx.x * kPartTile; lo < total;
+       lo += (unsigned long long)gridDim.x * kPartTile) {
+    const unsigned long long hi = lo + kPartTile < total ? lo + kPartTile : total;
+    for (int b = threadIdx.x; b < kBuckets; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatch; i0 < hi;
+         i0 += (unsigned long long)blockDim.x * kBatch) {
+      uint64_t r[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) r[k] = (i0 + k < hi) ? rec[i0 + k] : 0ull;
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k)
+        if (i0 + k < hi) atomicAdd(&hist[r[k] >> (32 + kBucketShift)], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBuckets; b += blockDim.x) {
+      const unsigned int h = hist[b];
+      base[b] = h ? atomicAdd(cursor + b, static_cast<unsigned long long>(h)) : 0ull;
+      hist[b] = 0;
+    }
+    __syncthreads();
+    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatch; i0 < hi;
+         i0 += (unsigned long long)blockDim.x * kBatch) {
+      uint64_t r[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) r[k] = (i0 + k < hi) ? rec[i0 + k] : 0ull;
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        if (i0 + k < hi) {
+          const unsigned int b = static_cast<unsigned int>(r[k] >> (32 + kBucketShift));
+          out[base[b] + atomicAdd(&hist[b], 1u)] = r[k];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_bin_reduce(const uint64_t* __restrict__ part,
+                                                         uint64_t* __restrict__ tmp,
+                                                         const unsigned long long* __restrict__ bucket_off,
+                                                         const ColParams* __restrict__ cp, int C,
+                                                         long long* __restrict__ acc, uint64_t* __restrict__ F,
+                                                         unsigned long long* __restrict__ cnt,
+                                                         const int* __restrict__ mode) {
+  if (*mode != kModeBinned) return;
+  constexpr int kBin = 1 << kBinLog2;
+  constexpr int kBinsPer = 1 << kBinsPerBucketLog2;
+  __shared__ long long s_acc[kBin];
+  __shared__ unsigned int s_cur[kBinsPer];
+  __shared__ unsigned int s_off[kBinsPer + 1];
+  __shared__ double s_scale[kMaxBinnedC];
+  __shared__ uint64_t s_stage[kReduceThreads / kWave][kStage / 2];
+  __shared__ unsigned int s_wsum[kReduceThreads / kWave];
+  uint64_t* stage = s_stage[threadIdx.x / kWave];
+  int staged = 0;
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) s_scale[c] = cp[c].scale;
+  for (int b = blockIdx.x; b < kBuckets; b += gridDim.x) {
+    const unsigned long long lo = bucket_off[b], hi = bucket_off[b + 1];
+    if (lo == hi) continue;  // uniform per block
+    for (int f = threadIdx.x; f < kBinsPer; f += blockDim.x) s_cur[f] = 0;
+    __syncthreads();
+    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatch; i0 < hi;
+         i0 += (unsigned long long)blockDim.x * kBatch) {
+      uint64_t r[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) r[k] = (i0 + k < hi) ? part[i0 + k] : 0ull;
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k)
+        if (i0 + k < hi) atomicAdd(&s_cur[(r[k] >> (32 + kBinLog2)) & (kBinsPer - 1)], 1u);
+    }
+    __syncthreads();
+    {  // exclusive scan of the 1024 bin sizes, 2 per thread
+      constexpr int kPer = kBinsPer / kReduceThreads;
+      unsigned int v[kPer];
+      unsigned int run = 0;
+      for (int k = 0; k < kPer; ++k) {
+        v[k] = s_cur[threadIdx.x * kPer + k];
+        run += v[k];
+      }
+      unsigned int incl = run;
+      for (int off = 1; off < kWave; off <<= 1) {
+        const unsigned int t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+      }
+      if (lane == kWave - 1) s_wsum[wave] = incl;
+      __syncthreads();
+      unsigned int acc0 = 0;
+      for (int w = 0; w < wave; ++w) acc0 += s_wsum[w];
+      acc0 += incl - run;
+      for (int k = 0; k < kPer; ++k) {
+        s_off[threadIdx.x * kPer + k] = acc0;
+        acc0 += v[k];
+      }
+      if (threadIdx.x == kReduceThreads - 1) s_off[kBinsPer] = acc0;
+      __syncthreads();
+      for (int f = threadIdx.x; f < kBinsPer; f += blockDim.x) s_cur[f] = 0;
+      __syncthreads();
+    }
+    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatch; i0 < hi;
+         i0 += (unsigned long long)blockDim.x * kBatch) {
+      uint64_t r[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) r[k] = (i0 + k < hi) ? part[i0 + k] : 0ull;
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        if (i0 + k < hi) {
+          const unsigned int f = static_cast<unsigned int>(r[k] >> (32 + kBinLog2)) & (kBinsPer - 1);
+          tmp[lo + s_off[f] + atomicAdd(&s_cur[f], 1u)] = r[k];
+        }
+      }
+    }
+    __syncthreads();
+    for (int f = 0; f < kBinsPer; ++f) {
+      const unsigned int fl = s_off[f], fh = s_off[f + 1];
+      if (fl == fh) continue;  // uniform per block
+      for (int j = threadIdx.x; j < kBin; j += blockDim.x) s_acc[j] = 0;
+      __syncthreads();
+      const unsigned long long bhi = lo + fh;
+      for (unsigned long long i0 = lo + fl + (unsigned long long)threadIdx.x * 4; i0 < bhi;
+           i0 += (unsigned long long)blockDim.x * 4) {
+        uint64_t rr[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) rr[k] = (i0 + k < bhi) ? tmp[i0 + k] : 0ull;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (i0 + k < bhi) {
+            const uint64_t r = rr[k];
+            const uint32_t cell = static_cast<uint32_t>(r >> 32);
+            const uint32_t c = cell % static_cast<uint32_t>(C);
+            const float val = __uint_as_float(static_cast<uint32_t>(r));
+            const long long d = static_cast<long long>(static_cast<double>(val) * s_scale[c]);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&s_acc[cell & (kBin - 1)]),
+                      static_cast<unsigned long long>(d));
+          }
+        }
+      }
+      __syncthreads();
+      const uint32_t cell0 = (static_cast<uint32_t>(b) << kBucketShift) | (static_cast<uint32_t>(f) << kBinLog2);
+      for (int j = threadIdx.x; j < kBin; j += blockDim.x) {  // wave-uniform trip count
+        const long long v = s_acc[j];
+        const uint32_t cell = cell0 + static_cast<uint32_t>(j);
+        if (v != 0) acc[cell] = v;
+        const uint32_t u = cell / static_cast<uint32_t>(C);
+        const uint32_t c = cell - u * static_cast<uint32_t>(C);
+        stage_push<kStage / 2>(stage, staged, (static_cast<uint64_t>(u) << 32) | c, v != 0, F, cnt);
+      }
+      __syncthreads();
+    }
+  }
+  stage_flush(stage, staged, F, cnt);
+}
+
 // ------------------------------------------------------------ driver
+agp_tuning_t default_tuning() {
+  agp_tuning_t t;
+  t.aggregation = 0;
+  t.level_blocks = kLevelBlocks;
+  return t;
+}
+
+// The tuning in force for a call: an explicit one, else the autotuned one,
+// else the default; AGP_AGGREGATION=atomic|binned overrides the aggregation.
+agp_tuning_t tuning_for(agp_graph* g, int32_t C, double a, double b, const agp_tuning_t* force) {
+  agp_tuning_t t = default_tuning();
+  if (force) {
+    t = *force;
+  } else {
+    auto it = g->tuning.find(agp_tune_key{C, a, b});
+    if (it != g->tuning.end()) t = it->second;
+  }
+  if (const char* e = std::getenv("AGP_AGGREGATION")) {
+    if (std::strcmp(e, "atomic") == 0) t.aggregation = 0;
+    if (std::strcmp(e, "binned") == 0) t.aggregation = 1;
+  }
+  if (t.level_blocks < 256) t.level_blocks = 256;
+  return t;
+}
+
 template <typename T>
 int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L, const T* x,
                    int32_t C, double eps, uint64_t seed, const uint32_t* qids, T* out,
-                   hipStream_t s, agp_stats_t* stats) {
+                   hipStream_t s, agp_stats_t* stats, const agp_tuning_t* force = nullptr) {
   using Cell = typename Prec<T>::Cell;
   const char* fn = sizeof(T) == 4 ? "agp_propagate" : "agp_propagate_f64";
   if (!g) return fail(AGP_EINVAL, std::string(fn) + ": NULL graph");
@@ -140,6 +380,7 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   }
 
   std::lock_guard<std::mutex> lk(g->mu);
+  const agp_tuning_t tune = tuning_for(g, C, a, b, force);
   int rc;
   const double *da = nullptr, *db = nullptr;
   if ((rc = pow_table(g, a, &da)) || (rc = pow_table(g, b, &db))) return rc;
@@ -185,6 +426,31 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   if (hflags[1] & 1) return fail(AGP_EINVAL, std::string(fn) + ": x holds a non-finite value");
   const bool positive = sizeof(T) == 4 && !(hflags[1] & 2);
 
+  // binned aggregation: binary32, cells addressable in 32 bits, LDS scale table
+  bool binned = tune.aggregation == 1 && sizeof(T) == 4 && cells < (1ull << 32) && C <= kMaxBinnedC && cells > 0;
+  unsigned long long rec_cap = 0;
+  if (binned) {
+    rec_cap = std::min<unsigned long long>((1ull << 32) - 1, std::max<unsigned long long>(1ull << 20, 3ull * cells));
+    if (const char* e = std::getenv("AGP_RECORD_CAP")) {  // smaller record buffer (tuning / tests)
+      const unsigned long long v = std::strtoull(e, nullptr, 10);
+      if (v > 0 && v < rec_cap) rec_cap = v;
+    }
+    if (sc.rec[0].reserve(rec_cap * sizeof(uint64_t), false, s) ||
+        sc.rec[1].reserve(rec_cap * sizeof(uint64_t), false, s) ||
+        sc.bins.reserve(sizeof(unsigned int) * kBuckets + sizeof(unsigned long long) * (2 * kBuckets + 1) +
+                            sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1), true, s)) {
+      sc.rec[0].release();  // not enough memory for the record buffers: atomics instead
+      sc.rec[1].release();
+      binned = false;
+      (void)hipGetLastError();
+    }
+  }
+  unsigned int* bucket_count = binned ? sc.bins.as<unsigned int>() : nullptr;
+  unsigned long long* bucket_off = binned ? reinterpret_cast<unsigned long long*>(bucket_count + kBuckets) : nullptr;
+  unsigned long long* cursor = binned ? bucket_off + kBuckets + 1 : nullptr;
+  unsigned long long* rec_counts = binned ? cursor + kBuckets : nullptr;
+  if (binned) AGP_HIP(hipMemsetAsync(rec_counts, 0, sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1), s));
+
   AGP_HIP(hipMemsetAsync(out, 0, cells * sizeof(T), s));
   hipEvent_t* ev = sc.events;
   if (stats && (rc = sc.ensure_events())) return rc;
@@ -193,7 +459,7 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   const unsigned cgrid = grid_for(n * (int64_t)(C >= kWave ? kWave : C), kThreads, 8192);
   k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroValue<T>{x}, n, C, (long long)C, 1ll, F[0], counts, nullptr);
 
-  LevelArgs A;
+  LevelArgs A{};
   A.rp = g->row_ptr;
   A.col = g->col;
   A.nd = g->ndeg;
@@ -206,6 +472,10 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   A.err = flags;
   A.positive = positive ? 1 : 0;
   A.dense_cut = std::max<unsigned long long>(1ull, static_cast<unsigned long long>(cells / 32));
+  A.rec = nullptr;
+  A.rec_count = nullptr;
+  A.rec_cap = rec_cap;
+  A.bucket_count = bucket_count;
   const uint32_t key0 = static_cast<uint32_t>(seed), key1 = static_cast<uint32_t>(seed >> 32);
   for (int32_t i = 0; i <= L; ++i) {
     const int lflags = (i == L ? kLastLevel : 0) | (a == 0.0 ? kAZero : 0);
@@ -217,14 +487,26 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
     A.fout = F[(i + 1) & 1];
     A.cnt_out = counts + i + 1;
     A.mode_out = mode + i + 1;
+    const bool bin_level = binned && i < L;
+    A.rec = bin_level ? sc.rec[0].as<uint64_t>() : nullptr;
+    A.rec_count = bin_level ? rec_counts + i : nullptr;
     Cell* cur = acc[i & 1];
     Cell* nxt = acc[(i + 1) & 1];
     if (stats) AGP_HIP(hipEventRecord(ev[2 * i], s));
     if (i == 0)
-      k_level<T, true, false><<<kLevelBlocks, kThreads, 0, s>>>(A, x, cur, nxt);
+      k_level<T, true, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
     else
-      k_level<T, false, false><<<kLevelBlocks, kThreads, 0, s>>>(A, x, cur, nxt);
+      k_level<T, false, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
     if (stats) AGP_HIP(hipEventRecord(ev[2 * i + 1], s));
+    if (bin_level) {
+      uint64_t* r0 = sc.rec[0].as<uint64_t>();
+      uint64_t* r1 = sc.rec[1].as<uint64_t>();
+      k_bins_scan<<<1, kBuckets, 0, s>>>(bucket_count, bucket_off, cursor, rec_counts + i, rec_cap, mode + i + 1);
+      k_apply_overflow<<<2048, kThreads, 0, s>>>(A, reinterpret_cast<long long*>(nxt), mode + i + 1);
+      k_partition<<<2048, kThreads, 0, s>>>(r0, rec_counts + i, cursor, r1, mode + i + 1);
+      k_bin_reduce<<<kBuckets, kReduceThreads, 0, s>>>(r1, r0, bucket_off, cp, C, reinterpret_cast<long long*>(nxt),
+                                                 F[(i + 1) & 1], counts + i + 1, mode + i + 1);
+    }
     if (i < L)
       k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, (long long)C, 1ll, F[(i + 1) & 1],
                                            counts + i + 1, mode + i + 1);
@@ -273,6 +555,56 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
 }  // namespace agp
 
 extern "C" {
+
+int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int32_t L, const float* x,
+                 int32_t C, double eps, uint64_t seed, const uint32_t* qids, float* out, void* stream,
+                 agp_tuning_t* best) {
+  using namespace agp;
+  agp_graph* gg = const_cast<agp_graph*>(g);
+  if (!gg) return fail(AGP_EINVAL, "agp_autotune: NULL graph");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  AGP_HIP(hipEventCreate(&e0));
+  AGP_HIP(hipEventCreate(&e1));
+  agp_tuning_t cands[6];
+  int nc = 0;
+  for (int agg = 0; agg < 2; ++agg)
+    for (int blocks : {1024, 2048, 4096}) cands[nc++] = agp_tuning_t{agg, blocks};
+  float best_ms = 0.0f;
+  agp_tuning_t pick = default_tuning();
+  int rc = AGP_OK;
+  for (int k = 0; k < nc && rc == AGP_OK; ++k) {
+    (void)hipEventRecord(e0, s);
+    rc = propagate_impl<float>(gg, a, b, w, L, x, C, eps, seed, qids, out, s, nullptr, &cands[k]);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (rc == AGP_OK && (k == 0 || ms < best_ms)) {
+      best_ms = ms;
+      pick = cands[k];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != AGP_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lk(gg->mu);
+    gg->tuning[agp_tune_key{C, a, b}] = pick;
+  }
+  // leave `out` with the result (every candidate gives the same bits)
+  if (best) *best = pick;
+  return AGP_OK;
+}
+
+int agp_get_tuning(const agp_graph_t* g, int32_t C, double a, double b, agp_tuning_t* out) {
+  using namespace agp;
+  if (!g || !out) return fail(AGP_EINVAL, "agp_get_tuning: NULL argument");
+  agp_graph* gg = const_cast<agp_graph*>(g);
+  std::lock_guard<std::mutex> lk(gg->mu);
+  *out = tuning_for(gg, C, a, b, nullptr);
+  return AGP_OK;
+}
 
 int agp_propagate(const agp_graph_t* g, double a, double b, const double* w, int32_t L, const float* x,
                   int32_t C, double eps, uint64_t seed, const uint32_t* qids, float* out, void* stream,

@@ -178,6 +178,7 @@ int step(agp_server* s) {
       const int i = r.level;
       p.theta = r.q.eps;  // ||e_s||_1 = 1
       unit_of(p.theta, &p.ue, &p.scale, &p.dtheta);
+      p.theta_w = static_cast<float>(p.theta);
       p.rho = r.rho[i];
       p.kappa = r.kappa[i];
       p.out = r.q.out;
@@ -225,7 +226,7 @@ int step(agp_server* s) {
                                                   s->mass.as<double>(), s->err.as<int>());
   }
   k_zero_count<<<1, 1, 0, st>>>(counts + nxt);
-  LevelArgs A;
+  LevelArgs A{};
   A.rp = s->g->row_ptr;
   A.col = s->g->col;
   A.nd = s->g->ndeg;
@@ -244,6 +245,10 @@ int step(agp_server* s) {
   A.positive = 1;
   A.dense_cut = std::max<unsigned long long>(1ull, static_cast<unsigned long long>(s->n) * s->S / 32);
   A.mode_out = s->mode.as<int>();
+  A.rec = nullptr;  // the server aggregates with atomics
+  A.rec_count = nullptr;
+  A.rec_cap = 0;
+  A.bucket_count = nullptr;
   k_level<float, false, true><<<kLevelBlocks, kThreads, 0, st>>>(A, nullptr, acc[cur], acc[nxt]);
   k_compact<<<grid_for(s->n * (int64_t)s->S, kThreads, 8192), kThreads, 0, st>>>(
       NonZeroCell<float>{acc[nxt]}, s->n, s->S, 1ll, (long long)s->n, F[nxt], counts + nxt, s->mode.as<int>());

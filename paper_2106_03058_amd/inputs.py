@@ -263,3 +263,70 @@ def lambda_max(g: Graph, *, tol: float = 1e-10, max_iter: int = 1000) -> float:
             return new
         lam = new
     return lam
+
+
+# ------------------------------------------------ device-side generation
+# Large stand-ins (hundreds of millions of arcs) are generated with PyTorch on
+# the GPU: the same recipes as above, seeded, returning CSR tensors on the
+# device (and nothing of the propagation method).
+
+def rmat_device(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
+                device="cuda:0", chunk: int = 1 << 26):
+    """R-MAT graph built on the GPU; returns (n, row_ptr int64, col int32) tensors.
+
+    Quadrants from uniform floats per bit level, labels shuffled by a seeded
+    permutation, symmetrised, loops dropped, duplicates removed."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    n = 1 << scale
+    m = n * edge_factor
+    keys = []
+    perm = torch.randperm(n, generator=gen, device=device)
+    for lo in range(0, m, chunk):
+        k = min(chunk, m - lo)
+        s = torch.zeros(k, dtype=torch.int64, device=device)
+        d = torch.zeros(k, dtype=torch.int64, device=device)
+        for _ in range(scale):
+            u = torch.rand(k, generator=gen, device=device, dtype=torch.float64)
+            bs = u >= (a + b)
+            bd = ((u >= a) & (u < a + b)) | (u >= a + b + c)
+            s = s * 2 + bs.to(torch.int64)
+            d = d * 2 + bd.to(torch.int64)
+        s = perm[s]
+        d = perm[d]
+        keep = s != d
+        s, d = s[keep], d[keep]
+        keys.append(s * n + d)
+        keys.append(d * n + s)
+        del s, d, keep
+    key = torch.unique(torch.cat(keys))
+    del keys
+    rows = torch.div(key, n, rounding_mode="floor")
+    col = (key - rows * n).to(torch.int32)
+    counts = torch.bincount(rows, minlength=n)
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    row_ptr[1:] = torch.cumsum(counts, 0)
+    return n, row_ptr, col
+
+
+def lambda_max_device(n: int, row_ptr, col, *, tol: float = 1e-10, max_iter: int = 1000) -> float:
+    """Largest adjacency eigenvalue by FP64 power iteration on the GPU."""
+    import torch
+
+    vals = torch.ones(col.numel(), dtype=torch.float64, device=col.device)
+    A = torch.sparse_csr_tensor(row_ptr, col.to(torch.int64), vals, size=(n, n))
+    v = torch.full((n, 1), 1.0 / float(n) ** 0.5, dtype=torch.float64, device=col.device)
+    lam = 0.0
+    for _ in range(max_iter):
+        y = A @ v
+        new = float((v * y).sum())
+        nrm = float(torch.linalg.vector_norm(y))
+        if nrm == 0.0:
+            return 0.0
+        v = y / nrm
+        if lam and abs(new - lam) <= tol * abs(new):
+            return new
+        lam = new
+    return lam

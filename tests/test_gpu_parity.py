@@ -244,3 +244,43 @@ def test_error_paths(agp, torch_dev):
     got, st = _run(agp, torch_dev, g, 0.0, 1.0, w, inputs.one_hot(g.n, [0]), 1e-4, seed=3, G=G)
     ref, cnt = _oracle(g, 0.0, 1.0, w, inputs.one_hot(g.n, [0]), 1e-4, 3)
     _assert_parity(got, st, ref, cnt, 5)
+
+
+@pytest.mark.parametrize("name", ["ppr", "tp", "gdc_signed", "general_ab"])
+def test_aggregation_modes_are_bit_identical(agp, torch_dev, name, monkeypatch):
+    """Binned LDS aggregation, its record-overflow fallback and plain atomics
+    give the same bits (exact integer sums), equal to the oracle's."""
+    a, b, w, eps, kind = CASES[name]
+    g = inputs.chung_lu(6000, 12, 2.5, seed=31, self_loops=kind != "onehot")
+    x = _signal(g, kind, 33, seed=4)
+    G = agp.Graph.from_inputs(g)
+    ref, cnt = _oracle(g, a, b, w, x, eps, 5)
+    results = []
+    for env in ({}, {"AGP_AGGREGATION": "atomic"}, {"AGP_RECORD_CAP": "5000"}):
+        monkeypatch.delenv("AGP_AGGREGATION", raising=False)
+        monkeypatch.delenv("AGP_RECORD_CAP", raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        got, st = _run(agp, torch_dev, g, a, b, w, x, eps, seed=5, G=G)
+        _assert_parity(got, st, ref, cnt, len(w) - 1)
+        results.append(got)
+    assert all(np.array_equal(results[0], r) for r in results[1:])
+
+
+def test_autotune_keeps_results(agp, torch_dev):
+    """Every autotuned choice gives the same bits; the pick is reused."""
+    torch, dev = torch_dev
+    g = inputs.chung_lu(5000, 10, 2.5, seed=41)
+    G = agp.Graph.from_inputs(g)
+    x = inputs.one_hot(g.n, inputs.sources_uniform(g, 40, seed=6))
+    w = inputs.weights_ppr(0.2, 12)
+    X = torch.from_numpy(x).to(dev)
+    before = agp.get_tuning(G, 40, 0.0, 1.0)
+    assert before == {"aggregation": "atomic", "level_blocks": 2048}
+    out = torch.empty_like(X)
+    pick = agp.autotune(G, 0.0, 1.0, w, X, 1e-5, 9, out=out)
+    assert agp.get_tuning(G, 40, 0.0, 1.0) == pick
+    ref, _ = _oracle(g, 0.0, 1.0, w, x, 1e-5, 9)
+    assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
+    again, _ = agp.propagate(G, 0.0, 1.0, w, X, 1e-5, 9)
+    assert np.array_equal(again.cpu().numpy().astype(np.float64), ref)

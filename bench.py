@@ -33,6 +33,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+
+# HBM bytes per launch of the level kernel (levels 1..L), from two rocprofv3
+# --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) with
+# --calibrate-copy; FETCH_SIZE is scaled by the factor that makes the 1 GiB
+# copy read 1 GiB.  Valid only for the kernel sources they were taken from.
+TRAFFIC = {}
+KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
+                  "paper_2106_03058_amd/csrc/propagate.hip")
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 METRIC = "edge-pushes/s + HBM GB/s; queries/s and p99 latency batched vs per-query at eps"
 
 
@@ -260,7 +278,8 @@ def main() -> int:
     ap.add_argument("--slots", type=int, default=64, help="serve: server slots")
     ap.add_argument("--single", type=int, default=16, help="units timed one per launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune aggregation and grid per model before timing (default: library defaults)")
     ap.add_argument("--cpu-units", type=int, default=4, help="oracle sample per model")
     ap.add_argument("--cache", default=os.environ.get("AGP_BENCH_CACHE", ""),
                     help="directory to keep the generated graph between runs")
@@ -299,7 +318,7 @@ def main() -> int:
     outs = [torch.empty_like(X) for _ in models]
 
     tunings = {}
-    if not args.no_tune:
+    if args.tune:
         for m, o in zip(models, outs):
             tunings[m["name"]] = agp.autotune(G, m["a"], m["b"], m["w"], X, m["eps"], args.seed,
                                               qids=m["qids"], out=o)
@@ -328,16 +347,18 @@ def main() -> int:
     value = pushes_step / (ms_per_step / 1e3)
     log(f"{ms_per_step:.1f} ms/step, {pushes_step:.3e} pushes/step")
 
-    # roofline of the dominant kernel: the level kernel of the middle levels
+    # roofline of the dominant kernel: the level kernel of levels 1..L
+    # (k_level<float, false, false>; level 0 reads the signal and is a
+    # separate instantiation)
     mid_bytes = mid_ms = 0.0
     launches = 0
     all_bytes = all_ms = 0.0
     for r in runs:
         for (st, _), m in zip(r, models):
             L = st["levels"]
-            mid_bytes += alg_bytes(st, range(1, L), m["a"] == 0.0)
-            mid_ms += float(st["level_ms"][1:L].sum())
-            launches += max(L - 1, 0)
+            mid_bytes += alg_bytes(st, range(1, L + 1), m["a"] == 0.0)
+            mid_ms += float(st["level_ms"][1:L + 1].sum())
+            launches += L
             all_bytes += alg_bytes(st, range(L + 1), m["a"] == 0.0)
             all_ms += float(st["level_ms"].sum())
     achieved = mid_bytes / (mid_ms / 1e3) / 1e9
@@ -368,6 +389,11 @@ def main() -> int:
             single_ok &= bool(torch.equal(one[:, 0], o[:, c]))
     lat_s = np.array(lat_s) if lat_s else np.zeros(1)
 
+    rec = TRAFFIC.get(args.workload)
+    traffic = None
+    if rec and rec["sources"] == kernel_sources_sha() and rec["columns"] == C and not args.tune:
+        traffic = rec["bytes_per_launch"] / (mid_ms / max(launches, 1) / 1e3) / 1e9
+
     result = {
         "metric": METRIC,
         "value": value,
@@ -393,12 +419,13 @@ def main() -> int:
         "one_per_launch_equals_batched": single_ok,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_level<float, false, false> (levels 1..L-1)",
+            "kernel": "k_level<float, false, false> (levels 1..L)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_bytes_per_launch": rec["bytes_per_launch"] if traffic is not None else None,
             "avg_launch_ms": mid_ms / max(launches, 1),
             "alg_bytes_per_launch": mid_bytes / max(launches, 1),
         },

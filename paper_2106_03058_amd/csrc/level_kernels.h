@@ -32,8 +32,7 @@ namespace agp {
 namespace lvl {
 
 constexpr int kThreads = 256;
-constexpr int kTile = 256;  // frontier entries per block tile
-constexpr int kLevelBlocks = 2048;
+constexpr int kLevelBlocks = 4096;
 constexpr int kNumCounters = 5;   // frontier, hash, det, cand, acc
 constexpr int kThetaRows = 4096;  // rows per partial sum of ||x||_1
 constexpr int kServeLdsSlots = 128;  // server columns whose counters a block sums in LDS
@@ -244,6 +243,44 @@ __device__ __forceinline__ void serve_count(const LevelArgs& A, unsigned long lo
 }
 
 // ------------------------------------------------------------ the level
+// Work is organised per wave.  A wave takes batches of up to 64 frontier
+// entries (batch b of the level goes to wave b mod #waves); for each batch a lane
+// sets up one entry (reserve update, c, the deterministic prefix J, the
+// number of sampled work items), the wave then makes the batch's
+// deterministic pushes with all lanes, one push per lane and step, and puts
+// the sampled work items in a queue that idle lanes draw from.  A sampled
+// work item is up to kWinPerItem consecutive 64-position windows of one
+// entry's suffix; a lane walks their Philox / geometric-skip chains one draw
+// per step and takes the next item from the queue in the step after its last
+// draw, so lanes stay busy across entries and batches.  All loops run in
+// lockstep per wave so that staging can use wave-wide ballots.
+constexpr int kBatch = kWave;
+constexpr int kWinPerItem = 16;
+
+struct BatchLds {
+  int64_t rp[kBatch];
+  double cv[kBatch];
+  double p0[kBatch];           // a = 0: sampling probability of every run of the entry
+  long long doff[kBatch + 1];  // deterministic pushes before each entry (exclusive scan)
+  long long ioff[kBatch + 1];  // sampled work items before each entry
+  uint32_t u[kBatch], c[kBatch], d[kBatch], J[kBatch], neg[kBatch];
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// largest e in [0, 64) with off[e] <= k (off non-decreasing, off[0] <= k)
+__device__ __forceinline__ int batch_find(const long long* off, long long k) {
+  int e = 0;
+#pragma unroll
+  for (int step = kBatch / 2; step > 0; step >>= 1)
+    if (off[e + step] <= k) e += step;
+  return e;
+}
+
 // kFirst: the residues are the signal x (level 0 of a batched call).
 // kServe: counters and overflow mass are kept per column instead of per level.
 template <typename T, bool kFirst, bool kServe>
@@ -252,17 +289,9 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
                                                     typename Prec<T>::Cell* __restrict__ acc_next) {
   using P = Prec<T>;
   using Delta = typename P::Delta;
-  __shared__ long long s_off[kTile + 1];
-  __shared__ int64_t s_rp[kTile];
-  __shared__ double s_cv[kTile];
-  __shared__ double s_p0[kTile];  // a = 0: the sampling probability of every run
-  __shared__ uint32_t s_u[kTile];
-  __shared__ uint32_t s_c[kTile];
-  __shared__ uint32_t s_d[kTile];
-  __shared__ uint32_t s_J[kTile];
-  __shared__ uint32_t s_neg[kTile];
-  __shared__ long long s_wave[kThreads / kWave];
-  __shared__ uint64_t s_stage[kThreads / kWave][kStage];
+  constexpr int kWaves = kThreads / kWave;
+  __shared__ BatchLds s_batch[kWaves];
+  __shared__ uint64_t s_stage[kWaves][kStage];
   __shared__ unsigned int s_hist[kBuckets];
   // server: per-column counters summed in LDS, flushed once per block
   __shared__ unsigned long long s_scnt[kServe ? kServeLdsSlots : 1][kNumCounters];
@@ -287,283 +316,305 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
     for (int i = threadIdx.x; i < kServeLdsSlots; i += blockDim.x) s_smass[i] = 0.0;
     __syncthreads();
   }
-  unsigned long long te = (count + gridDim.x - 1) / gridDim.x;
-  te = te < 1 ? 1 : (te > (unsigned long long)kTile ? (unsigned long long)kTile : te);
-  const unsigned long long ntiles = (count + te - 1) / te;
-  const int tid = threadIdx.x;
   const int lane = lane_id();
-  const int wave = tid / kWave;
+  const int wave = threadIdx.x / kWave;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  BatchLds& B = s_batch[wave];
   uint64_t* stage = s_stage[wave];
   int staged = 0;  // wave-uniform
 
   unsigned long long n_front = 0, n_hash = 0, n_det = 0, n_cand = 0, n_acc = 0;
   double mass = 0.0;
 
-  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const unsigned long long e0 = tile * te;
-    const int ne = static_cast<int>((count - e0) < te ? (count - e0) : te);
-    long long work = 0;
-    if (tid < ne) {
-      const uint64_t item = A.fin[e0 + tid];
-      const uint32_t u = static_cast<uint32_t>(item >> 32);
-      const uint32_t c = static_cast<uint32_t>(item);
-      const size_t cell = static_cast<size_t>(u) * A.su + static_cast<size_t>(c) * A.sc;
-      const ColParams& cp = A.cp[c];
-      T r;
-      if (kFirst)
-        r = x[cell];
-      else
-        r = P::take(acc_cur, cell, cp);
-      uint32_t d = 0, J = 0;
-      double cv = 0.0;
-      if (!(cp.flags & kDrop)) {
-        if (kServe) {
-          serve_count(A, s_scnt, c, 0, 1ull);
-        } else {
-          ++n_front;
-          n_hash += splitmix64(u);
-        }
-        // reserve: pi(u) += (S w_i / Y_i) r(u), rounded to the working precision
-        if (cp.kappa != 0.0) {
-          T* o = static_cast<T*>(cp.out) + static_cast<size_t>(u) * static_cast<size_t>(cp.out_stride);
-          const T q = to_w(cp.kappa * static_cast<double>(r), T());
-          *o = *o + q;
-        }
-        if (!(cp.flags & kLastLevel) && cp.rho != 0.0) {
-          d = static_cast<uint32_t>(A.deg[u]);
-          if (d > 0) {
-            const double absr = fabs(static_cast<double>(r));
-            const double t0 = cp.rho * absr;
-            cv = t0 * cp.db[d];
-            const double th = cp.theta;
-            const int64_t rpu = A.rp[u];
-            const bool azero = (cp.flags & kAZero) != 0;
-            double inc0 = cv;
-            if (azero) {
-              J = (cv >= th) ? d : 0u;
-              const double num = cv * 1.0;  // every neighbour's factor d^-0 is 1
-              s_p0[tid] = num / th;
-            } else {  // increments fall along the degree-sorted row: binary search
-              inc0 = cv * cp.da[A.nd[rpu]];
-              uint32_t lo = 0, hi = d;
-              while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                const double inc = cv * cp.da[A.nd[rpu + mid]];
-                if (inc >= th)
-                  lo = mid + 1;
-                else
-                  hi = mid;
+  // One contribution per lane (or none): exact units to the next residue,
+  // or a record for the binned aggregation.  Wave-uniform call.
+  auto emit_one = [&](bool emit, uint32_t v, uint32_t ec, const Delta& delta, T val) {
+    const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(ec) * A.sc;
+    if (binned) {
+      uint64_t rec = 0;
+      if (emit) {
+        rec = (static_cast<uint64_t>(vcell) << 32) | static_cast<uint64_t>(__float_as_uint(static_cast<float>(val)));
+        atomicAdd(&s_hist[vcell >> kBucketShift], 1u);
+      }
+      stage_push_records(stage, staged, rec, emit, A, acc_next);
+    } else {
+      bool first = false;
+      if (emit) {
+        if (sparse)
+          first = P::add_ret(acc_next, vcell, delta);
+        else
+          P::add(acc_next, vcell, delta);
+      }
+      if (sparse)  // stage first-touched cells, flush in chunks
+        stage_push(stage, staged, (static_cast<uint64_t>(v) << 32) | ec, first, A.fout, A.cnt_out);
+    }
+  };
+
+  // up to 64 entries per batch; fewer when the level has fewer entries than
+  // 64 per wave, so that small frontiers still spread over the whole grid
+  const unsigned long long nwaves = static_cast<unsigned long long>(gridDim.x) * kWaves;
+  const unsigned long long eb_raw = count / nwaves;
+  const unsigned long long eb = eb_raw < 1ull ? 1ull : (eb_raw > (unsigned long long)kBatch ? kBatch : eb_raw);
+  const unsigned long long nbatch = (count + eb - 1) / eb;
+  const unsigned long long bstride = static_cast<unsigned long long>(gridDim.x) * kWaves;
+  unsigned long long bnext = static_cast<unsigned long long>(blockIdx.x) * kWaves + wave;
+  long long it_next = 0, it_total = 0;  // wave-uniform: queue of the loaded batch
+
+  // lane state: the sampled work item in progress
+  bool active = false, need_run = false, neg = false, azero = true;
+  uint32_t u = 0, c = 0, s = 0, rend = 0, run_end = 0, pos = 0, t = 0, ctr3 = 0, key0 = 0, key1 = 0;
+  uint32_t it_cand = 0, it_acc = 0;
+  int64_t rpu = 0;
+  double cv = 0.0, dstart = 1.0, th = 0.0;
+  const ColParams* cpp = A.cp;
+  SkipTable tab;
+
+  for (;;) {
+    // (a) a lane whose item has no window left becomes idle
+    if (active && need_run && s >= rend) {
+      active = false;
+      if (kServe && it_cand) {
+        serve_count(A, s_scnt, c, 3, static_cast<unsigned long long>(it_cand));
+        if (it_acc) serve_count(A, s_scnt, c, 4, static_cast<unsigned long long>(it_acc));
+      }
+    }
+    // (b) the queue is empty and a lane is idle: set up the next batch
+    if (it_next >= it_total && bnext < nbatch && __any(!active)) {
+      wave_sync();  // every lane has read the previous batch
+      const unsigned long long e0 = bnext * eb;
+      bnext += bstride;
+      const int ne = static_cast<int>((count - e0) < eb ? (count - e0) : eb);
+      long long dwork = 0, iwork = 0;
+      uint32_t eu = 0, ec = 0, ed = 0, eJ = 0;
+      int64_t erp = 0;
+      double ecv = 0.0, ep0 = 0.0;
+      bool eneg = false;
+      if (lane < ne) {
+        const uint64_t item = A.fin[e0 + lane];
+        eu = static_cast<uint32_t>(item >> 32);
+        ec = static_cast<uint32_t>(item);
+        const size_t cell = static_cast<size_t>(eu) * A.su + static_cast<size_t>(ec) * A.sc;
+        const ColParams& cp = A.cp[ec];
+        T r;
+        if (kFirst)
+          r = x[cell];
+        else
+          r = P::take(acc_cur, cell, cp);
+        eneg = r < T(0);
+        if (!(cp.flags & kDrop)) {
+          if (kServe) {
+            serve_count(A, s_scnt, ec, 0, 1ull);
+          } else {
+            ++n_front;
+            n_hash += splitmix64(eu);
+          }
+          // reserve: pi(u) += (S w_i / Y_i) r(u), rounded to the working precision
+          if (cp.kappa != 0.0) {
+            T* o = static_cast<T*>(cp.out) + static_cast<size_t>(eu) * static_cast<size_t>(cp.out_stride);
+            const T q = to_w(cp.kappa * static_cast<double>(r), T());
+            *o = *o + q;
+          }
+          if (!(cp.flags & kLastLevel) && cp.rho != 0.0) {
+            ed = static_cast<uint32_t>(A.deg[eu]);
+            if (ed > 0) {
+              const double absr = fabs(static_cast<double>(r));
+              const double t0 = cp.rho * absr;
+              ecv = t0 * cp.db[ed];
+              const double eth = cp.theta;
+              erp = A.rp[eu];
+              double inc0 = ecv;
+              if (cp.flags & kAZero) {
+                eJ = (ecv >= eth) ? ed : 0u;
+                const double num = ecv * 1.0;  // every neighbour's factor d^-0 is 1
+                ep0 = num / eth;
+              } else {  // increments fall along the degree-sorted row: binary search
+                inc0 = ecv * cp.da[A.nd[erp]];
+                uint32_t lo = 0, hi = ed;
+                while (lo < hi) {
+                  const uint32_t mid = (lo + hi) >> 1;
+                  const double inc = ecv * cp.da[A.nd[erp + mid]];
+                  if (inc >= eth)
+                    lo = mid + 1;
+                  else
+                    hi = mid;
+                }
+                eJ = lo;
               }
-              J = lo;
+              const long long windows =
+                  (eJ < ed) ? static_cast<long long>(((ed - 1) >> kSegLog2) - (eJ >> kSegLog2) + 1) : 0;
+              dwork = eJ;
+              iwork = (windows + kWinPerItem - 1) / kWinPerItem;
+              // bound on the magnitude this entry can add (every contribution
+              // is at most max(inc_0, theta)), for the overflow check
+              const T big = to_w(inc0 > eth ? inc0 : eth, T());
+              const double m = static_cast<double>(ed) * P::mag_units(big, cp);
+              if (kServe) {
+                serve_count(A, s_scnt, ec, 2, static_cast<unsigned long long>(eJ));
+                if (ec < kServeLdsSlots)
+                  atomicAdd(&s_smass[ec], m);
+                else
+                  atomicAdd(A.mass + ec, m);
+              } else {
+                n_det += eJ;
+                mass += m;
+              }
             }
-            const long long windows =
-                (J < d) ? static_cast<long long>(((d - 1) >> kSegLog2) - (J >> kSegLog2) + 1) : 0;
-            work = static_cast<long long>(J) + windows;
-            // bound on the magnitude this entry can add (every contribution
-            // is at most max(inc_0, theta)), for the overflow check
-            const T big = to_w(inc0 > th ? inc0 : th, T());
-            const double m = static_cast<double>(d) * P::mag_units(big, cp);
-            if (kServe) {
-              serve_count(A, s_scnt, c, 2, static_cast<unsigned long long>(J));
-              if (c < kServeLdsSlots)
-                atomicAdd(&s_smass[c], m);
-              else
-                atomicAdd(A.mass + c, m);
-            } else {
-              n_det += J;
-              mass += m;
-            }
-            s_rp[tid] = rpu;
           }
         }
       }
-      s_u[tid] = u;
-      s_c[tid] = c;
-      s_d[tid] = d;
-      s_J[tid] = J;
-      s_cv[tid] = cv;
-      s_neg[tid] = (r < T(0)) ? 1u : 0u;
-    }
-    // block exclusive scan of the work counts
-    long long incl = work;
+      long long dinc = dwork, iinc = iwork;
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const long long t = __shfl_up(incl, off);
-      if (lane >= off) incl += t;
-    }
-    if (lane == kWave - 1) s_wave[wave] = incl;
-    __syncthreads();
-    long long wbase = 0;
-    for (int w = 0; w < wave; ++w) wbase += s_wave[w];
-    s_off[tid] = wbase + incl - work;
-    if (tid == kThreads - 1) s_off[kThreads] = wbase + incl;
-    __syncthreads();
-    const long long total = s_off[kThreads];
-
-    // Every lane pulls work items k = tid, tid + 256, ...: a single push of
-    // the deterministic prefix, or a 64-position window of the sampled suffix
-    // walked one random draw per step.  The loop runs in lockstep per wave so
-    // that frontier staging can use wave-wide ballots.
-    long long k = tid;
-    int ttype = 0;  // 0 idle, 1 single push, 2 window
-    bool need_run = false, neg = false, azero = true;
-    uint32_t u = 0, c = 0, s = 0, wend = 0, run_end = 0, pos = 0, t = 0, ctr3 = 0;
-    uint32_t win_cand = 0, win_acc = 0;
-    int64_t rpu = 0;
-    double cv = 0.0, dstart = 1.0, th = 0.0, p0 = 0.0;
-    long long local = 0;
-    const ColParams* cpp = nullptr;
-    SkipTable tab;
-    for (;;) {
-      if (ttype == 0 && k < total) {
-        int lo = 0, hi = ne - 1;  // largest e with s_off[e] <= k
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_off[mid] <= k)
-            lo = mid;
-          else
-            hi = mid - 1;
+      for (int off = 1; off < kWave; off <<= 1) {
+        const long long td = __shfl_up(dinc, off);
+        const long long ti = __shfl_up(iinc, off);
+        if (lane >= off) {
+          dinc += td;
+          iinc += ti;
         }
-        const int e = lo;
-        local = k - s_off[e];
-        k += kThreads;
-        const uint32_t J = s_J[e];
-        u = s_u[e];
-        c = s_c[e];
-        rpu = s_rp[e];
-        cv = s_cv[e];
-        neg = s_neg[e] != 0;
-        cpp = A.cp + c;
-        azero = (cpp->flags & kAZero) != 0;
-        if (azero) p0 = s_p0[e];
-        if (local < static_cast<long long>(J)) {
-          ttype = 1;
-        } else {
-          ttype = 2;
-          const uint32_t d = s_d[e];
-          const uint32_t wstart = ((J >> kSegLog2) + static_cast<uint32_t>(local - J)) << kSegLog2;
-          s = wstart > J ? wstart : J;
-          wend = (wstart + static_cast<uint32_t>(kSeg)) < d ? wstart + static_cast<uint32_t>(kSeg) : d;
-          need_run = true;
+      }
+      B.rp[lane] = erp;
+      B.cv[lane] = ecv;
+      B.p0[lane] = ep0;
+      B.doff[lane] = dinc - dwork;
+      B.ioff[lane] = iinc - iwork;
+      if (lane == kWave - 1) {
+        B.doff[kBatch] = dinc;
+        B.ioff[kBatch] = iinc;
+      }
+      B.u[lane] = eu;
+      B.c[lane] = ec;
+      B.d[lane] = ed;
+      B.J[lane] = eJ;
+      B.neg[lane] = eneg ? 1u : 0u;
+      wave_sync();
+      // deterministic pushes of the batch: the increment reaches theta
+      const long long dtot = B.doff[kBatch];
+      for (long long kb = 0; kb < dtot; kb += kWave) {
+        const long long k = kb + lane;
+        bool emit = false;
+        uint32_t v = 0, vc = 0;
+        Delta delta{};
+        T val = T(0);
+        if (k < dtot) {
+          const int e = batch_find(B.doff, k);
+          const int64_t arc = B.rp[e] + (k - B.doff[e]);
+          vc = B.c[e];
+          const ColParams* cpd = A.cp + vc;
+          v = A.col[arc];
+          double inc = B.cv[e];
+          if (!(cpd->flags & kAZero)) inc = inc * cpd->da[A.nd[arc]];
+          val = to_w(inc, T());
+          if (B.neg[e]) val = -val;
+          emit = P::to_units(val, *cpd, &delta);
+          if (!emit) atomicOr(A.err + (kServe ? vc : 0u), 1);
+        }
+        emit_one(emit, v, vc, delta, val);
+      }
+      it_next = 0;
+      it_total = B.ioff[kBatch];
+    }
+    // (c) idle lanes take sampled work items from the queue
+    {
+      const unsigned long long idle = __ballot(!active);
+      if (!active) {
+        const long long it = it_next + __popcll(idle & lt_mask);
+        if (it < it_total) {
+          const int e = batch_find(B.ioff, it);
+          const uint32_t il = static_cast<uint32_t>(it - B.ioff[e]);
+          u = B.u[e];
+          c = B.c[e];
+          rpu = B.rp[e];
+          cv = B.cv[e];
+          neg = B.neg[e] != 0;
+          const uint32_t J = B.J[e], d = B.d[e];
+          cpp = A.cp + c;
+          azero = (cpp->flags & kAZero) != 0;
           th = cpp->theta;
           ctr3 = (cpp->qid << 8) | static_cast<uint32_t>(cpp->level);
-          win_cand = win_acc = 0;
+          key0 = cpp->key0;
+          key1 = cpp->key1;
+          const uint32_t nwin = ((d - 1) >> kSegLog2) - (J >> kSegLog2) + 1;
+          const uint32_t w0 = il * kWinPerItem;
+          const uint32_t w1 = (w0 + kWinPerItem) < nwin ? w0 + kWinPerItem : nwin;
+          const uint32_t ws = ((J >> kSegLog2) + w0) << kSegLog2;
+          const uint32_t we = ((J >> kSegLog2) + w1) << kSegLog2;
+          s = ws > J ? ws : J;
+          rend = we < d ? we : d;
+          if (azero) tab = make_skip_table(B.p0[e]);
+          active = true;
+          need_run = true;
+          it_cand = it_acc = 0;
         }
       }
-      if (!__any(ttype != 0)) break;
-
-      bool emit = false;
-      bool ttype_val_det = false;
-      T det_val = T(0);
-      Delta delta{};
-      uint32_t v = 0;
-      if (ttype == 1) {
-        // deterministic push: the increment reaches theta
-        const int64_t arc = rpu + local;
-        v = A.col[arc];
-        double inc = cv;
-        if (!azero) inc = cv * cpp->da[A.nd[arc]];
-        T val = to_w(inc, T());
-        if (neg) val = -val;
-        emit = P::to_units(val, *cpp, &delta);
-        if (!emit) atomicOr(A.err + (kServe ? c : 0u), 1);
-        ttype_val_det = true;
-        det_val = val;
-        ttype = 0;
-      } else if (ttype == 2) {
-        if (need_run) {
-          if (s >= wend) {
-            ttype = 0;
-            if (kServe && win_cand) {
-              serve_count(A, s_scnt, c, 3, static_cast<unsigned long long>(win_cand));
-              if (win_acc) serve_count(A, s_scnt, c, 4, static_cast<unsigned long long>(win_acc));
-            }
-          } else {  // a run: same degree group (a > 0) inside the window
-            run_end = wend;
-            dstart = 1.0;
-            if (!azero) {
-              const uint32_t ds = A.nd[rpu + s];
-              dstart = cpp->da[ds];
-              const int g = 31 - __clz(ds);
-              if (g < 31) {
-                const uint32_t lim = 1u << (g + 1);
-                uint32_t blo = s + 1, bhi = wend;
-                while (blo < bhi) {
-                  const uint32_t mid = (blo + bhi) >> 1;
-                  if (A.nd[rpu + mid] < lim)
-                    blo = mid + 1;
-                  else
-                    bhi = mid;
-                }
-                run_end = blo;
-              }
-            }
-            double pstar = p0;  // a = 0: computed once per entry, (cv * 1) / theta
-            if (!azero) {
-              const double num = cv * dstart;
-              pstar = num / th;
-            }
-            tab = make_skip_table(pstar);
-            pos = s;
-            t = 0;
-            need_run = false;
+      it_next += __popcll(idle);
+      if (it_next > it_total) it_next = it_total;
+    }
+    if (!__any(active)) {
+      if (bnext >= nbatch) break;  // queue empty (no idle lane took an item), no batch left
+      continue;
+    }
+    // (d) a run: the rest of the current window, or (a > 0) of its degree group
+    if (active && need_run) {
+      const uint32_t wnext = ((s >> kSegLog2) + 1u) << kSegLog2;
+      const uint32_t wend = wnext < rend ? wnext : rend;
+      run_end = wend;
+      if (!azero) {
+        const uint32_t ds = A.nd[rpu + s];
+        dstart = cpp->da[ds];
+        const int g = 31 - __clz(ds);
+        if (g < 31) {
+          const uint32_t lim = 1u << (g + 1);
+          uint32_t blo = s + 1, bhi = wend;
+          while (blo < bhi) {
+            const uint32_t mid = (blo + bhi) >> 1;
+            if (A.nd[rpu + mid] < lim)
+              blo = mid + 1;
+            else
+              bhi = mid;
           }
+          run_end = blo;
         }
-        if (ttype == 2 && !need_run) {
-          const U4 o = philox4x32_10(t, s, u, ctr3, cpp->key0, cpp->key1);
-          const double V = unit_double(o.x, o.y);
-          const uint32_t cand = pos + static_cast<uint32_t>(geometric_skip(tab, V));
-          if (cand >= run_end) {
-            s = run_end;
-            need_run = true;
-          } else {
-            ++n_cand;
-            ++win_cand;
-            const int64_t arc = rpu + cand;
-            bool accept = true;  // a = 0: the ratio is 1 and every uniform is below it
-            if (!azero) {
-              const double ratio = cpp->da[A.nd[arc]] / dstart;
-              accept = unit_double(o.z, o.w) < ratio;
-            }
-            if (accept) {
-              ++n_acc;
-              ++win_acc;
-              v = A.col[arc];
-              emit = true;
-              delta = P::theta_units(*cpp, neg);
-            }
-            pos = cand + 1;
-            ++t;
-          }
-        }
+        const double num = cv * dstart;
+        tab = make_skip_table(num / th);
       }
-      bool first = false;
-      const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(c) * A.sc;
-      if (binned) {  // wave-uniform: stage records, flush in chunks
-        uint64_t rec = 0;
-        if (emit) {
-          T val = T(0);
-          if (ttype_val_det) {
-            val = det_val;
-          } else {
-            val = neg ? -static_cast<T>(cpp->theta_w) : static_cast<T>(cpp->theta_w);
-          }
-          rec = (static_cast<uint64_t>(vcell) << 32) | static_cast<uint64_t>(__float_as_uint(static_cast<float>(val)));
-          atomicAdd(&s_hist[vcell >> kBucketShift], 1u);
-        }
-        stage_push_records(stage, staged, rec, emit, A, acc_next);
+      pos = s;
+      t = 0;
+      need_run = false;
+    }
+    // (e) one draw of the run's chain
+    bool emit = false;
+    uint32_t v = 0;
+    Delta delta{};
+    T val = T(0);
+    if (active && !need_run) {
+      const U4 o = philox4x32_10(t, s, u, ctr3, key0, key1);
+      const double V = unit_double(o.x, o.y);
+      const uint32_t cand = pos + static_cast<uint32_t>(geometric_skip(tab, V));
+      if (cand >= run_end) {
+        s = run_end;
+        need_run = true;
       } else {
-        if (emit) {
-          if (sparse)
-            first = P::add_ret(acc_next, vcell, delta);
-          else
-            P::add(acc_next, vcell, delta);
+        ++n_cand;
+        ++it_cand;
+        const int64_t arc = rpu + cand;
+        bool accept = true;  // a = 0: the ratio is 1 and every uniform is below it
+        if (!azero) {
+          const double ratio = cpp->da[A.nd[arc]] / dstart;
+          accept = unit_double(o.z, o.w) < ratio;
         }
-        if (sparse)  // wave-uniform: stage first-touched cells, flush in chunks
-          stage_push(stage, staged, (static_cast<uint64_t>(v) << 32) | c, first, A.fout, A.cnt_out);
+        if (accept) {
+          ++n_acc;
+          ++it_acc;
+          v = A.col[arc];
+          emit = true;
+          delta = P::theta_units(*cpp, neg);
+          val = neg ? -static_cast<T>(cpp->theta_w) : static_cast<T>(cpp->theta_w);
+        }
+        pos = cand + 1;
+        ++t;
       }
     }
-    __syncthreads();
+    emit_one(emit, v, c, delta, val);
   }
   if (sparse) stage_flush(stage, staged, A.fout, A.cnt_out);
   if (binned) {
@@ -575,8 +626,8 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   if (kServe) {  // flush the block's per-column sums
     __syncthreads();
     for (int i = threadIdx.x; i < kServeLdsSlots * kNumCounters; i += blockDim.x) {
-      const unsigned long long v = (&s_scnt[0][0])[i];
-      if (v) atomicAdd(A.counters + i, v);
+      const unsigned long long cv2 = (&s_scnt[0][0])[i];
+      if (cv2) atomicAdd(A.counters + i, cv2);
     }
     for (int i = threadIdx.x; i < kServeLdsSlots; i += blockDim.x)
       if (s_smass[i] != 0.0) atomicAdd(A.mass + i, s_smass[i]);

@@ -158,7 +158,8 @@ int agp_propagate_f64(const agp_graph_t* g, double a, double b, const double* w,
 /* Execution choices of agp_propagate that never change its results. */
 typedef struct agp_tuning {
   int32_t aggregation;  /* 0: integer atomics into the accumulators;
-                           1: push records binned by destination, summed in LDS */
+                           1: push records binned by destination, summed in LDS;
+                           2: records on dense levels, atomics on sparse ones  */
   int32_t level_blocks; /* workgroups of the level kernel (>= 256)               */
 } agp_tuning_t;
 
@@ -173,7 +174,7 @@ int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int3
                  float* out, void* stream, agp_tuning_t* best);
 
 /* The choice agp_propagate uses for (g, C, a, b): the tuned one, else the
- * default (atomics, 2048 workgroups). */
+ * default (aggregation 2, 4096 workgroups). */
 int agp_get_tuning(const agp_graph_t* g, int32_t C, double a, double b, agp_tuning_t* out);
 
 /* ----------------------------------------------------------------- serving */

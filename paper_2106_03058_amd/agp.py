@@ -208,7 +208,8 @@ class Tuning(ct.Structure):
     _fields_ = [("aggregation", ct.c_int32), ("level_blocks", ct.c_int32)]
 
     def to_dict(self) -> dict:
-        return {"aggregation": "binned" if self.aggregation else "atomic", "level_blocks": self.level_blocks}
+        names = {0: "atomic", 1: "binned", 2: "auto"}
+        return {"aggregation": names.get(self.aggregation, str(self.aggregation)), "level_blocks": self.level_blocks}
 
 
 def _tune_lib():

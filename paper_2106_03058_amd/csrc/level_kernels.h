@@ -47,12 +47,13 @@ enum : int {
   kModeOverflow = 3,  // record buffer overflowed: atomics, then compaction
 };
 
-// Binned aggregation: a record is (cell << 32 | fp32 bits of the
-// contribution); cells are grouped into 1024 buckets of 1024 bins of 4096
-// cells (an LDS accumulator of 32 KiB), so n * C must stay below 2^32.
-constexpr int kBinLog2 = 12;
-constexpr int kBinsPerBucketLog2 = 10;
-constexpr int kBucketShift = kBinLog2 + kBinsPerBucketLog2;
+// Binned aggregation: a record is (cell | sign << 31) of a sampled push;
+// cells are grouped into at most 1024 buckets of 2^shift cells (shift
+// chosen per call from n * C, at least kBinLog2) and every bucket into bins
+// of 8192 cells (32-bit counts in 32 KiB of LDS), so n * C must stay below
+// 2^31.
+constexpr int kBinLog2 = 13;
+constexpr int kMaxBinsPerBucket = 1024;
 constexpr int kBuckets = 1024;
 
 struct ColParams {
@@ -92,10 +93,13 @@ struct LevelArgs {
   unsigned long long dense_cut;  // frontier size from which a level is dense
   int* mode_out;                 // how the next frontier is formed (kMode*)
   // binned aggregation (binary32 batched calls; rec == nullptr: disabled)
-  uint64_t* rec;
+  uint32_t* rec;
   unsigned long long* rec_count;
   unsigned long long rec_cap;
   unsigned int* bucket_count;    // records per bucket of this level
+  int bucket_shift;              // cells per bucket = 2^bucket_shift
+  const double* bin_est;         // non-null: bin only if *bin_est >= bin_pushes (estimated pushes)
+  double bin_pushes;
 };
 
 // ----------------------------------------------------- working precision
@@ -185,29 +189,31 @@ __device__ __forceinline__ float to_w(double v, float) { return static_cast<floa
 __device__ __forceinline__ double to_w(double v, double) { return v; }
 
 // ------------------------------------------------- record staging
-// Records go to A.rec in chunks (one atomic per chunk).  Records beyond the
-// buffer capacity are added to the accumulator directly; the level then ends
-// in kModeOverflow (the buffered records are applied with atomics too).
+// On binned levels a sampled push becomes a 4-byte record, cell | sign << 31
+// (its value is -/+ fl(theta_c) of the cell's column c); deterministic pushes
+// still use atomics.  Records go to A.rec in chunks (one atomic per chunk).
+// Records beyond the buffer capacity are added to the accumulator directly;
+// the level then ends in kModeOverflow (the buffered records are applied
+// with atomics too).
+constexpr int kRecStage = 2 * kStage;  // 4-byte records per wave stage
+constexpr uint32_t kRecCellMask = 0x7FFFFFFFu;
+
 template <typename Cell>
-__device__ __forceinline__ void apply_record(const LevelArgs& A, Cell* acc, uint64_t rec);
+__device__ __forceinline__ void apply_record(const LevelArgs& A, Cell* acc, uint32_t rec);
 
 template <>
-__device__ __forceinline__ void apply_record<long long>(const LevelArgs& A, long long* acc, uint64_t rec) {
-  const uint32_t cell = static_cast<uint32_t>(rec >> 32);
-  const float val = __uint_as_float(static_cast<uint32_t>(rec));
+__device__ __forceinline__ void apply_record<long long>(const LevelArgs& A, long long* acc, uint32_t rec) {
+  const uint32_t cell = rec & kRecCellMask;
   const uint32_t c = cell % static_cast<uint32_t>(A.su);
-  long long d;
-  if (f32_to_units(val, A.cp[c].scale, &d))
-    atomic_add_relaxed(reinterpret_cast<unsigned long long*>(acc + cell), static_cast<unsigned long long>(d));
-  else
-    atomicOr(A.err, 1);
+  const long long d = (rec >> 31) ? -A.cp[c].dtheta : A.cp[c].dtheta;
+  atomic_add_relaxed(reinterpret_cast<unsigned long long*>(acc + cell), static_cast<unsigned long long>(d));
 }
 
 template <>
-__device__ __forceinline__ void apply_record<unsigned long long>(const LevelArgs&, unsigned long long*, uint64_t) {}
+__device__ __forceinline__ void apply_record<unsigned long long>(const LevelArgs&, unsigned long long*, uint32_t) {}
 
 template <typename Cell>
-__device__ __forceinline__ void stage_flush_records(uint64_t* stage, int& staged, const LevelArgs& A, Cell* acc) {
+__device__ __forceinline__ void stage_flush_records(uint32_t* stage, int& staged, const LevelArgs& A, Cell* acc) {
   if (staged == 0) return;
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   unsigned long long base = 0;
@@ -224,12 +230,12 @@ __device__ __forceinline__ void stage_flush_records(uint64_t* stage, int& staged
 }
 
 template <typename Cell>
-__device__ __forceinline__ void stage_push_records(uint64_t* stage, int& staged, uint64_t rec, bool pred,
+__device__ __forceinline__ void stage_push_records(uint32_t* stage, int& staged, uint32_t rec, bool pred,
                                                    const LevelArgs& A, Cell* acc) {
   const unsigned long long mask = __ballot(pred);
   if (pred) stage[staged + __popcll(mask & ((1ull << lane_id()) - 1ull))] = rec;
   staged += __popcll(mask);
-  if (staged > kStage - kWave) stage_flush_records(stage, staged, A, acc);
+  if (staged > kRecStage - kWave) stage_flush_records(stage, staged, A, acc);
 }
 
 // Server counters: LDS sums for the first kServeLdsSlots columns, global
@@ -303,7 +309,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   // first contribution to a cell from the atomic's old value and append the
   // cell to the next frontier; dense levels use fire-and-forget atomics and a
   // compaction pass builds the next frontier.
-  const bool binned = A.rec != nullptr;
+  const bool binned = A.rec != nullptr && (A.bin_est == nullptr || *A.bin_est >= A.bin_pushes);
   const bool sparse = !binned && A.positive && count < A.dense_cut;
   if (blockIdx.x == 0 && threadIdx.x == 0)
     *A.mode_out = binned ? kModeBinned : (sparse ? kModeSparse : kModeCompact);
@@ -326,27 +332,33 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   unsigned long long n_front = 0, n_hash = 0, n_det = 0, n_cand = 0, n_acc = 0;
   double mass = 0.0;
 
-  // One contribution per lane (or none): exact units to the next residue,
-  // or a record for the binned aggregation.  Wave-uniform call.
-  auto emit_one = [&](bool emit, uint32_t v, uint32_t ec, const Delta& delta, T val) {
+  // One contribution per lane (or none), in exact units of the next
+  // residue.  Wave-uniform calls.  emit_det: a deterministic push (atomics
+  // on every level); emit_sampled: a sampled push of -/+ fl(theta) (a
+  // 4-byte record on binned levels).
+  auto emit_atomic = [&](bool emit, uint32_t v, uint32_t ec, const Delta& delta) {
     const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(ec) * A.sc;
+    bool first = false;
+    if (emit) {
+      if (sparse)
+        first = P::add_ret(acc_next, vcell, delta);
+      else
+        P::add(acc_next, vcell, delta);
+    }
+    if (sparse)  // stage first-touched cells, flush in chunks
+      stage_push(stage, staged, (static_cast<uint64_t>(v) << 32) | ec, first, A.fout, A.cnt_out);
+  };
+  auto emit_sampled = [&](bool emit, uint32_t v, uint32_t ec, const Delta& delta, bool eneg) {
     if (binned) {
-      uint64_t rec = 0;
+      uint32_t rec = 0;
       if (emit) {
-        rec = (static_cast<uint64_t>(vcell) << 32) | static_cast<uint64_t>(__float_as_uint(static_cast<float>(val)));
-        atomicAdd(&s_hist[vcell >> kBucketShift], 1u);
+        const uint32_t vcell = v * static_cast<uint32_t>(A.su) + ec * static_cast<uint32_t>(A.sc);
+        rec = vcell | (eneg ? 0x80000000u : 0u);
+        atomicAdd(&s_hist[vcell >> A.bucket_shift], 1u);
       }
-      stage_push_records(stage, staged, rec, emit, A, acc_next);
+      stage_push_records(reinterpret_cast<uint32_t*>(stage), staged, rec, emit, A, acc_next);
     } else {
-      bool first = false;
-      if (emit) {
-        if (sparse)
-          first = P::add_ret(acc_next, vcell, delta);
-        else
-          P::add(acc_next, vcell, delta);
-      }
-      if (sparse)  // stage first-touched cells, flush in chunks
-        stage_push(stage, staged, (static_cast<uint64_t>(v) << 32) | ec, first, A.fout, A.cnt_out);
+      emit_atomic(emit, v, ec, delta);
     }
   };
 
@@ -494,7 +506,6 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         bool emit = false;
         uint32_t v = 0, vc = 0;
         Delta delta{};
-        T val = T(0);
         if (k < dtot) {
           const int e = batch_find(B.doff, k);
           const int64_t arc = B.rp[e] + (k - B.doff[e]);
@@ -503,12 +514,12 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
           v = A.col[arc];
           double inc = B.cv[e];
           if (!(cpd->flags & kAZero)) inc = inc * cpd->da[A.nd[arc]];
-          val = to_w(inc, T());
+          T val = to_w(inc, T());
           if (B.neg[e]) val = -val;
           emit = P::to_units(val, *cpd, &delta);
           if (!emit) atomicOr(A.err + (kServe ? vc : 0u), 1);
         }
-        emit_one(emit, v, vc, delta, val);
+        emit_atomic(emit, v, vc, delta);
       }
       it_next = 0;
       it_total = B.ioff[kBatch];
@@ -585,7 +596,6 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
     bool emit = false;
     uint32_t v = 0;
     Delta delta{};
-    T val = T(0);
     if (active && !need_run) {
       const U4 o = philox4x32_10(t, s, u, ctr3, key0, key1);
       const double V = unit_double(o.x, o.y);
@@ -608,17 +618,16 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
           v = A.col[arc];
           emit = true;
           delta = P::theta_units(*cpp, neg);
-          val = neg ? -static_cast<T>(cpp->theta_w) : static_cast<T>(cpp->theta_w);
         }
         pos = cand + 1;
         ++t;
       }
     }
-    emit_one(emit, v, c, delta, val);
+    emit_sampled(emit, v, c, delta, neg);
   }
   if (sparse) stage_flush(stage, staged, A.fout, A.cnt_out);
   if (binned) {
-    stage_flush_records(stage, staged, A, acc_next);
+    stage_flush_records(reinterpret_cast<uint32_t*>(stage), staged, A, acc_next);
     __syncthreads();
     for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
       if (s_hist[i]) atomicAdd(A.bucket_count + i, s_hist[i]);
@@ -651,6 +660,43 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       if (m != 0.0) atomicAdd(A.mass + A.level, m);
     }
   }
+}
+
+// ------------------------------------------------- push estimate
+// An upper bound on the pushes of a level (deterministic rows count d_u,
+// sampled rows their expected d_u c / theta with c = rho |r| d_u^-b), summed
+// over the frontier: decides whether the level is worth binning.
+template <typename T, bool kFirst>
+__global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __restrict__ x,
+                                                       const typename Prec<T>::Cell* __restrict__ acc_cur,
+                                                       double* __restrict__ est) {
+  const unsigned long long count = *A.cnt_in;
+  double sum = 0.0;
+  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < count;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const uint64_t item = A.fin[i];
+    const uint32_t u = static_cast<uint32_t>(item >> 32);
+    const uint32_t c = static_cast<uint32_t>(item);
+    const ColParams& cp = A.cp[c];
+    if ((cp.flags & (kDrop | kLastLevel)) || cp.rho == 0.0) continue;
+    const uint32_t d = static_cast<uint32_t>(A.deg[u]);
+    if (d == 0) continue;
+    const size_t cell = static_cast<size_t>(u) * A.su + static_cast<size_t>(c) * A.sc;
+    double absr;
+    if (kFirst) {
+      absr = fabs(static_cast<double>(x[cell]));
+    } else if (sizeof(T) == 4) {
+      const long long K = reinterpret_cast<const long long*>(acc_cur)[cell];
+      absr = fabs(static_cast<double>(K)) / cp.scale;
+    } else {
+      absr = 0.0;  // binary64 calls are never binned
+    }
+    const double cv = cp.rho * absr * cp.db[d];
+    sum += cv >= cp.theta ? static_cast<double>(d) : static_cast<double>(d) * (cv / cp.theta);
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off);
+  if (lane_id() == 0 && sum != 0.0) atomicAdd(est, sum);
 }
 
 // ------------------------------------------------- frontier compaction

@@ -106,13 +106,14 @@ __global__ void k_set_level(ColParams* __restrict__ cp, int C, int level, double
 
 // ------------------------------------------------ binned aggregation
 // After a binned level: bucket offsets (one block), then the records are
-// partitioned into 1024 buckets, and one block per bucket splits its bucket
-// into 1024 bins of 4096 cells, sums every bin exactly in LDS (64-bit
-// integer units, so the order of the records is irrelevant), writes the
-// non-zero sums to the next accumulator and appends them to the frontier.
-constexpr int kPartTile = 65536;
+// partitioned into buckets, and one block per bucket splits its bucket into
+// bins of 8192 cells, counts the signed records of every bin in LDS, adds
+// count * fl(theta_c) in units to each cell (the deterministic pushes are
+// already there: integer sums, so the order is irrelevant) and appends every
+// non-zero cell to the next frontier.
 constexpr int kMaxBinnedC = 1024;
 constexpr int kReduceThreads = 512;
+constexpr int kPartTile = 65536;
 
 __global__ __launch_bounds__(1024) void k_bins_scan(unsigned int* __restrict__ bucket_count,
                                                     unsigned long long* __restrict__ bucket_off,
@@ -152,12 +153,13 @@ __global__ __launch_bounds__(kThreads) void k_apply_overflow(LevelArgs A, long l
     apply_record(A, acc, A.rec[i]);
 }
 
-constexpr int kBatch = 8;  // records per thread per load batch (memory-level parallelism)
+constexpr int kBatchLoads = 8;  // records per thread per load batch (memory-level parallelism)
 
-__global__ __launch_bounds__(kThreads) void k_partition(const uint64_t* __restrict__ rec,
+__global__ __launch_bounds__(kThreads) void k_partition(const uint32_t* __restrict__ rec,
                                                         const unsigned long long* __restrict__ rec_count,
                                                         unsigned long long* __restrict__ cursor,
-                                                        uint64_t* __restrict__ out, const int* __restrict__ mode) {
+                                                        uint32_t* __restrict__ out, const int* __restrict__ mode,
+                                                        int shift) {
   if (*mode != kModeBinned) return;
   __shared__ unsigned int hist[kBuckets];
   __shared__ unsigned long long base[kBuckets];
@@ -167,14 +169,14 @@ __global__ __launch_bounds__(kThreads) void k_partition(const uint64_t* __restri
     const unsigned long long hi = lo + kPartTile < total ? lo + kPartTile : total;
     for (int b = threadIdx.x; b < kBuckets; b += blockDim.x) hist[b] = 0;
     __syncthreads();
-    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatch; i0 < hi;
-         i0 += (unsigned long long)blockDim.x * kBatch) {
-      uint64_t r[kBatch];
+    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatchLoads; i0 < hi;
+         i0 += (unsigned long long)blockDim.x * kBatchLoads) {
+      uint32_t r[kBatchLoads];
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k) r[k] = (i0 + k < hi) ? rec[i0 + k] : 0ull;
+      for (int k = 0; k < kBatchLoads; ++k) r[k] = (i0 + k < hi) ? rec[i0 + k] : 0u;
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k)
-        if (i0 + k < hi) atomicAdd(&hist[r[k] >> (32 + kBucketShift)], 1u);
+      for (int k = 0; k < kBatchLoads; ++k)
+        if (i0 + k < hi) atomicAdd(&hist[(r[k] & kRecCellMask) >> shift], 1u);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kBuckets; b += blockDim.x) {
@@ -183,15 +185,15 @@ __global__ __launch_bounds__(kThreads) void k_partition(const uint64_t* __restri
       hist[b] = 0;
     }
     __syncthreads();
-    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatch; i0 < hi;
-         i0 += (unsigned long long)blockDim.x * kBatch) {
-      uint64_t r[kBatch];
+    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatchLoads; i0 < hi;
+         i0 += (unsigned long long)blockDim.x * kBatchLoads) {
+      uint32_t r[kBatchLoads];
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k) r[k] = (i0 + k < hi) ? rec[i0 + k] : 0ull;
+      for (int k = 0; k < kBatchLoads; ++k) r[k] = (i0 + k < hi) ? rec[i0 + k] : 0u;
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k) {
+      for (int k = 0; k < kBatchLoads; ++k) {
         if (i0 + k < hi) {
-          const unsigned int b = static_cast<unsigned int>(r[k] >> (32 + kBucketShift));
+          const unsigned int b = (r[k] & kRecCellMask) >> shift;
           out[base[b] + atomicAdd(&hist[b], 1u)] = r[k];
         }
       }
@@ -200,47 +202,49 @@ __global__ __launch_bounds__(kThreads) void k_partition(const uint64_t* __restri
   }
 }
 
-__global__ __launch_bounds__(kReduceThreads) void k_bin_reduce(const uint64_t* __restrict__ part,
-                                                         uint64_t* __restrict__ tmp,
-                                                         const unsigned long long* __restrict__ bucket_off,
-                                                         const ColParams* __restrict__ cp, int C,
-                                                         long long* __restrict__ acc, uint64_t* __restrict__ F,
-                                                         unsigned long long* __restrict__ cnt,
-                                                         const int* __restrict__ mode) {
+__global__ __launch_bounds__(kReduceThreads) void k_bin_reduce(const uint32_t* __restrict__ part,
+                                                               uint32_t* __restrict__ tmp,
+                                                               const unsigned long long* __restrict__ bucket_off,
+                                                               const ColParams* __restrict__ cp, int C,
+                                                               unsigned long long cells,
+                                                               long long* __restrict__ acc, uint64_t* __restrict__ F,
+                                                               unsigned long long* __restrict__ cnt,
+                                                               const int* __restrict__ mode, int shift) {
   if (*mode != kModeBinned) return;
   constexpr int kBin = 1 << kBinLog2;
-  constexpr int kBinsPer = 1 << kBinsPerBucketLog2;
-  __shared__ long long s_acc[kBin];
-  __shared__ unsigned int s_cur[kBinsPer];
-  __shared__ unsigned int s_off[kBinsPer + 1];
-  __shared__ double s_scale[kMaxBinnedC];
+  const int kBinsPer = 1 << (shift - kBinLog2);  // <= kMaxBinsPerBucket
+  __shared__ int s_cnt[kBin];
+  __shared__ unsigned int s_cur[kMaxBinsPerBucket];
+  __shared__ unsigned int s_off[kMaxBinsPerBucket + 1];
+  __shared__ long long s_dth[kMaxBinnedC];
   __shared__ uint64_t s_stage[kReduceThreads / kWave][kStage / 2];
   __shared__ unsigned int s_wsum[kReduceThreads / kWave];
   uint64_t* stage = s_stage[threadIdx.x / kWave];
   int staged = 0;
   const int lane = lane_id(), wave = threadIdx.x / kWave;
-  for (int c = threadIdx.x; c < C; c += blockDim.x) s_scale[c] = cp[c].scale;
-  for (int b = blockIdx.x; b < kBuckets; b += gridDim.x) {
+  for (int c = threadIdx.x; c < C; c += blockDim.x) s_dth[c] = cp[c].dtheta;
+  const unsigned long long nbuckets = ((cells - 1) >> shift) + 1;
+  for (unsigned long long b = blockIdx.x; b < nbuckets; b += gridDim.x) {
     const unsigned long long lo = bucket_off[b], hi = bucket_off[b + 1];
-    if (lo == hi) continue;  // uniform per block
     for (int f = threadIdx.x; f < kBinsPer; f += blockDim.x) s_cur[f] = 0;
     __syncthreads();
-    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatch; i0 < hi;
-         i0 += (unsigned long long)blockDim.x * kBatch) {
-      uint64_t r[kBatch];
+    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatchLoads; i0 < hi;
+         i0 += (unsigned long long)blockDim.x * kBatchLoads) {
+      uint32_t r[kBatchLoads];
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k) r[k] = (i0 + k < hi) ? part[i0 + k] : 0ull;
+      for (int k = 0; k < kBatchLoads; ++k) r[k] = (i0 + k < hi) ? part[i0 + k] : 0u;
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k)
-        if (i0 + k < hi) atomicAdd(&s_cur[(r[k] >> (32 + kBinLog2)) & (kBinsPer - 1)], 1u);
+      for (int k = 0; k < kBatchLoads; ++k)
+        if (i0 + k < hi) atomicAdd(&s_cur[((r[k] & kRecCellMask) >> kBinLog2) & (kBinsPer - 1)], 1u);
     }
     __syncthreads();
-    {  // exclusive scan of the 1024 bin sizes, 2 per thread
-      constexpr int kPer = kBinsPer / kReduceThreads;
+    {  // exclusive scan of the bin sizes, 2 slots per thread
+      constexpr int kPer = kMaxBinsPerBucket / kReduceThreads;
       unsigned int v[kPer];
       unsigned int run = 0;
       for (int k = 0; k < kPer; ++k) {
-        v[k] = s_cur[threadIdx.x * kPer + k];
+        const int f = threadIdx.x * kPer + k;
+        v[k] = f < kBinsPer ? s_cur[f] : 0u;
         run += v[k];
       }
       unsigned int incl = run;
@@ -254,7 +258,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_bin_reduce(const uint64_t* _
       for (int w = 0; w < wave; ++w) acc0 += s_wsum[w];
       acc0 += incl - run;
       for (int k = 0; k < kPer; ++k) {
-        s_off[threadIdx.x * kPer + k] = acc0;
+        const int f = threadIdx.x * kPer + k;
+        if (f < kBinsPer) s_off[f] = acc0;
         acc0 += v[k];
       }
       if (threadIdx.x == kReduceThreads - 1) s_off[kBinsPer] = acc0;
@@ -262,53 +267,52 @@ __global__ __launch_bounds__(kReduceThreads) void k_bin_reduce(const uint64_t* _
       for (int f = threadIdx.x; f < kBinsPer; f += blockDim.x) s_cur[f] = 0;
       __syncthreads();
     }
-    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatch; i0 < hi;
-         i0 += (unsigned long long)blockDim.x * kBatch) {
-      uint64_t r[kBatch];
+    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatchLoads; i0 < hi;
+         i0 += (unsigned long long)blockDim.x * kBatchLoads) {
+      uint32_t r[kBatchLoads];
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k) r[k] = (i0 + k < hi) ? part[i0 + k] : 0ull;
+      for (int k = 0; k < kBatchLoads; ++k) r[k] = (i0 + k < hi) ? part[i0 + k] : 0u;
 #pragma unroll
-      for (int k = 0; k < kBatch; ++k) {
+      for (int k = 0; k < kBatchLoads; ++k) {
         if (i0 + k < hi) {
-          const unsigned int f = static_cast<unsigned int>(r[k] >> (32 + kBinLog2)) & (kBinsPer - 1);
+          const unsigned int f = ((r[k] & kRecCellMask) >> kBinLog2) & (kBinsPer - 1);
           tmp[lo + s_off[f] + atomicAdd(&s_cur[f], 1u)] = r[k];
         }
       }
     }
     __syncthreads();
     for (int f = 0; f < kBinsPer; ++f) {
-      const unsigned int fl = s_off[f], fh = s_off[f + 1];
-      if (fl == fh) continue;  // uniform per block
-      for (int j = threadIdx.x; j < kBin; j += blockDim.x) s_acc[j] = 0;
+      const unsigned long long cell0 = (b << shift) | (static_cast<unsigned long long>(f) << kBinLog2);
+      if (cell0 >= cells) break;  // uniform per block
+      for (int j = threadIdx.x; j < kBin; j += blockDim.x) s_cnt[j] = 0;
       __syncthreads();
-      const unsigned long long bhi = lo + fh;
-      for (unsigned long long i0 = lo + fl + (unsigned long long)threadIdx.x * 4; i0 < bhi;
+      const unsigned long long blo = lo + s_off[f], bhi = lo + s_off[f + 1];
+      for (unsigned long long i0 = blo + (unsigned long long)threadIdx.x * 4; i0 < bhi;
            i0 += (unsigned long long)blockDim.x * 4) {
-        uint64_t rr[4];
+        uint32_t rr[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) rr[k] = (i0 + k < bhi) ? tmp[i0 + k] : 0ull;
+        for (int k = 0; k < 4; ++k) rr[k] = (i0 + k < bhi) ? tmp[i0 + k] : 0u;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (i0 + k < bhi) {
-            const uint64_t r = rr[k];
-            const uint32_t cell = static_cast<uint32_t>(r >> 32);
-            const uint32_t c = cell % static_cast<uint32_t>(C);
-            const float val = __uint_as_float(static_cast<uint32_t>(r));
-            const long long d = static_cast<long long>(static_cast<double>(val) * s_scale[c]);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&s_acc[cell & (kBin - 1)]),
-                      static_cast<unsigned long long>(d));
-          }
-        }
+        for (int k = 0; k < 4; ++k)
+          if (i0 + k < bhi) atomicAdd(&s_cnt[rr[k] & (kBin - 1)], (rr[k] >> 31) ? -1 : 1);
       }
       __syncthreads();
-      const uint32_t cell0 = (static_cast<uint32_t>(b) << kBucketShift) | (static_cast<uint32_t>(f) << kBinLog2);
       for (int j = threadIdx.x; j < kBin; j += blockDim.x) {  // wave-uniform trip count
-        const long long v = s_acc[j];
-        const uint32_t cell = cell0 + static_cast<uint32_t>(j);
-        if (v != 0) acc[cell] = v;
-        const uint32_t u = cell / static_cast<uint32_t>(C);
-        const uint32_t c = cell - u * static_cast<uint32_t>(C);
-        stage_push<kStage / 2>(stage, staged, (static_cast<uint64_t>(u) << 32) | c, v != 0, F, cnt);
+        const unsigned long long cell = cell0 + static_cast<unsigned long long>(j);
+        const bool valid = cell < cells;
+        long long v = 0;
+        uint32_t u = 0, c = 0;
+        if (valid) {
+          u = static_cast<uint32_t>(cell / static_cast<unsigned long long>(C));
+          c = static_cast<uint32_t>(cell - static_cast<unsigned long long>(u) * C);
+          v = acc[cell];
+          const int k = s_cnt[j];
+          if (k != 0) {
+            v += static_cast<long long>(k) * s_dth[c];
+            acc[cell] = v;
+          }
+        }
+        stage_push<kStage / 2>(stage, staged, (static_cast<uint64_t>(u) << 32) | c, valid && v != 0, F, cnt);
       }
       __syncthreads();
     }
@@ -319,13 +323,13 @@ __global__ __launch_bounds__(kReduceThreads) void k_bin_reduce(const uint64_t* _
 // ------------------------------------------------------------ driver
 agp_tuning_t default_tuning() {
   agp_tuning_t t;
-  t.aggregation = 0;
+  t.aggregation = 2;  // records on levels with many pushes, atomics elsewhere
   t.level_blocks = kLevelBlocks;
   return t;
 }
 
 // The tuning in force for a call: an explicit one, else the autotuned one,
-// else the default; AGP_AGGREGATION=atomic|binned overrides the aggregation.
+// else the default; AGP_AGGREGATION=atomic|binned|auto overrides the aggregation.
 agp_tuning_t tuning_for(agp_graph* g, int32_t C, double a, double b, const agp_tuning_t* force) {
   agp_tuning_t t = default_tuning();
   if (force) {
@@ -337,6 +341,7 @@ agp_tuning_t tuning_for(agp_graph* g, int32_t C, double a, double b, const agp_t
   if (const char* e = std::getenv("AGP_AGGREGATION")) {
     if (std::strcmp(e, "atomic") == 0) t.aggregation = 0;
     if (std::strcmp(e, "binned") == 0) t.aggregation = 1;
+    if (std::strcmp(e, "auto") == 0) t.aggregation = 2;
   }
   if (t.level_blocks < 256) t.level_blocks = 256;
   return t;
@@ -396,7 +401,7 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
       (rc = sc.colparams.reserve(sizeof(ColParams) * C + sizeof(uint32_t) * C, false, s)) ||
       (rc = sc.partial.reserve(sizeof(double) * (size_t)std::max<int64_t>(tblocks, 1) * C, false, s)) ||
       (rc = sc.flags.reserve(sizeof(int) * 4, false, s)) ||
-      (rc = sc.levelinfo.reserve((sizeof(double) + sizeof(int)) * (AGP_MAX_LEVELS + 2), false, s)))
+      (rc = sc.levelinfo.reserve((2 * sizeof(double) + sizeof(int)) * (AGP_MAX_LEVELS + 2), false, s)))
     return rc;
 
   ColParams* cp = sc.colparams.as<ColParams>();
@@ -405,7 +410,8 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   unsigned long long* counters = sc.counters.as<unsigned long long>();
   int* flags = sc.flags.as<int>();
   double* mass = sc.levelinfo.as<double>();
-  int* mode = reinterpret_cast<int*>(mass + AGP_MAX_LEVELS + 2);
+  double* est = mass + AGP_MAX_LEVELS + 2;  // estimated pushes per level (auto aggregation)
+  int* mode = reinterpret_cast<int*>(est + AGP_MAX_LEVELS + 2);
   AGP_HIP(hipMemsetAsync(sc.levelinfo.ptr, 0, sc.levelinfo.bytes, s));
   AGP_HIP(hipMemsetAsync(counts, 0, sc.counts.bytes, s));
   AGP_HIP(hipMemsetAsync(counters, 0, sc.counters.bytes, s));
@@ -427,16 +433,21 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   const bool positive = sizeof(T) == 4 && !(hflags[1] & 2);
 
   // binned aggregation: binary32, cells addressable in 32 bits, LDS scale table
-  bool binned = tune.aggregation == 1 && sizeof(T) == 4 && cells < (1ull << 32) && C <= kMaxBinnedC && cells > 0;
+  bool binned = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4 && cells < (1ull << 31) &&
+                C <= kMaxBinnedC && cells > 0;
+  // buckets of 2^shift cells: at most 1024 buckets, bins of 4096 cells
+  int shift = kBinLog2;
+  while (shift < 32 && (static_cast<unsigned long long>(cells) - 1ull) >> shift >= (unsigned long long)kBuckets) ++shift;
+  const unsigned nbuckets = static_cast<unsigned>(((cells > 0 ? cells : 1) - 1) >> shift) + 1u;
   unsigned long long rec_cap = 0;
   if (binned) {
-    rec_cap = std::min<unsigned long long>((1ull << 32) - 1, std::max<unsigned long long>(1ull << 20, 3ull * cells));
+    rec_cap = std::max<unsigned long long>(1ull << 20, 3ull * cells);
     if (const char* e = std::getenv("AGP_RECORD_CAP")) {  // smaller record buffer (tuning / tests)
       const unsigned long long v = std::strtoull(e, nullptr, 10);
       if (v > 0 && v < rec_cap) rec_cap = v;
     }
-    if (sc.rec[0].reserve(rec_cap * sizeof(uint64_t), false, s) ||
-        sc.rec[1].reserve(rec_cap * sizeof(uint64_t), false, s) ||
+    if (sc.rec[0].reserve(rec_cap * sizeof(uint32_t), false, s) ||
+        sc.rec[1].reserve(rec_cap * sizeof(uint32_t), false, s) ||
         sc.bins.reserve(sizeof(unsigned int) * kBuckets + sizeof(unsigned long long) * (2 * kBuckets + 1) +
                             sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1), true, s)) {
       sc.rec[0].release();  // not enough memory for the record buffers: atomics instead
@@ -476,6 +487,9 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   A.rec_count = nullptr;
   A.rec_cap = rec_cap;
   A.bucket_count = bucket_count;
+  A.bucket_shift = shift;
+  A.bin_est = nullptr;
+  A.bin_pushes = static_cast<double>(cells) / 8.0;  // auto: bin levels with at least n C / 8 pushes
   const uint32_t key0 = static_cast<uint32_t>(seed), key1 = static_cast<uint32_t>(seed >> 32);
   for (int32_t i = 0; i <= L; ++i) {
     const int lflags = (i == L ? kLastLevel : 0) | (a == 0.0 ? kAZero : 0);
@@ -488,10 +502,18 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
     A.cnt_out = counts + i + 1;
     A.mode_out = mode + i + 1;
     const bool bin_level = binned && i < L;
-    A.rec = bin_level ? sc.rec[0].as<uint64_t>() : nullptr;
+    A.rec = bin_level ? sc.rec[0].as<uint32_t>() : nullptr;
     A.rec_count = bin_level ? rec_counts + i : nullptr;
     Cell* cur = acc[i & 1];
     Cell* nxt = acc[(i + 1) & 1];
+    A.bin_est = nullptr;
+    if (bin_level && tune.aggregation == 2) {
+      A.bin_est = est + i;
+      if (i == 0)
+        k_estimate<T, true><<<1024, kThreads, 0, s>>>(A, x, cur, est + i);
+      else
+        k_estimate<T, false><<<1024, kThreads, 0, s>>>(A, x, cur, est + i);
+    }
     if (stats) AGP_HIP(hipEventRecord(ev[2 * i], s));
     if (i == 0)
       k_level<T, true, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
@@ -499,13 +521,14 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
       k_level<T, false, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
     if (stats) AGP_HIP(hipEventRecord(ev[2 * i + 1], s));
     if (bin_level) {
-      uint64_t* r0 = sc.rec[0].as<uint64_t>();
-      uint64_t* r1 = sc.rec[1].as<uint64_t>();
+      uint32_t* r0 = sc.rec[0].as<uint32_t>();
+      uint32_t* r1 = sc.rec[1].as<uint32_t>();
       k_bins_scan<<<1, kBuckets, 0, s>>>(bucket_count, bucket_off, cursor, rec_counts + i, rec_cap, mode + i + 1);
       k_apply_overflow<<<2048, kThreads, 0, s>>>(A, reinterpret_cast<long long*>(nxt), mode + i + 1);
-      k_partition<<<2048, kThreads, 0, s>>>(r0, rec_counts + i, cursor, r1, mode + i + 1);
-      k_bin_reduce<<<kBuckets, kReduceThreads, 0, s>>>(r1, r0, bucket_off, cp, C, reinterpret_cast<long long*>(nxt),
-                                                 F[(i + 1) & 1], counts + i + 1, mode + i + 1);
+      k_partition<<<2048, kThreads, 0, s>>>(r0, rec_counts + i, cursor, r1, mode + i + 1, shift);
+      k_bin_reduce<<<nbuckets, kReduceThreads, 0, s>>>(r1, r0, bucket_off, cp, C, static_cast<unsigned long long>(cells),
+                                                       reinterpret_cast<long long*>(nxt), F[(i + 1) & 1],
+                                                       counts + i + 1, mode + i + 1, shift);
     }
     if (i < L)
       k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, (long long)C, 1ll, F[(i + 1) & 1],
@@ -568,8 +591,8 @@ int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int3
   AGP_HIP(hipEventCreate(&e1));
   agp_tuning_t cands[6];
   int nc = 0;
-  for (int agg = 0; agg < 2; ++agg)
-    for (int blocks : {1024, 2048, 4096}) cands[nc++] = agp_tuning_t{agg, blocks};
+  for (int agg = 0; agg < 3; ++agg)
+    for (int blocks : {2048, 4096}) cands[nc++] = agp_tuning_t{agg, blocks};
   float best_ms = 0.0f;
   agp_tuning_t pick = default_tuning();
   int rc = AGP_OK;

@@ -256,7 +256,8 @@ def test_aggregation_modes_are_bit_identical(agp, torch_dev, name, monkeypatch):
     G = agp.Graph.from_inputs(g)
     ref, cnt = _oracle(g, a, b, w, x, eps, 5)
     results = []
-    for env in ({}, {"AGP_AGGREGATION": "atomic"}, {"AGP_RECORD_CAP": "5000"}):
+    for env in ({}, {"AGP_AGGREGATION": "atomic"}, {"AGP_AGGREGATION": "binned"}, {"AGP_AGGREGATION": "auto"},
+                {"AGP_AGGREGATION": "binned", "AGP_RECORD_CAP": "5000"}):
         monkeypatch.delenv("AGP_AGGREGATION", raising=False)
         monkeypatch.delenv("AGP_RECORD_CAP", raising=False)
         for k, v in env.items():
@@ -276,7 +277,7 @@ def test_autotune_keeps_results(agp, torch_dev):
     w = inputs.weights_ppr(0.2, 12)
     X = torch.from_numpy(x).to(dev)
     before = agp.get_tuning(G, 40, 0.0, 1.0)
-    assert before == {"aggregation": "atomic", "level_blocks": 4096}
+    assert before == {"aggregation": "auto", "level_blocks": 4096}
     out = torch.empty_like(X)
     pick = agp.autotune(G, 0.0, 1.0, w, X, 1e-5, 9, out=out)
     assert agp.get_tuning(G, 40, 0.0, 1.0) == pick

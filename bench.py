@@ -13,6 +13,12 @@ Other workloads:
   `--workload gnn-hkpr`: heat-kernel feature propagation (t = 5, L = 10,
     a = b = 1/2, eps = 1e-7) of a 2.4M x 128 N(0,1) matrix on a Chung-Lu
     graph (n = 2.4M, mean degree 50, exponent 2.5, one self-loop per node).
+  `--workload gnn-ppr-large`: PPR feature propagation (alpha = 0.1, L = 10,
+    a = b = 1/2, eps = 1e-8) of a 111M x 128 U[-1, 1] matrix on a Chung-Lu
+    graph (n = 111,059,956, exponent 2.2, ~1.6e9 arcs plus one loop per
+    node) generated on the GPU; the columns are processed in tiles that fit
+    the free memory.  Use --steps 1 --warmup 0.
+  `--workload serve`: a served query stream on R-MAT scale 24.
 The value is edge pushes (deterministic + accepted sampled pushes, the cost
 unit of Theorem 3.3) per second over the timed steps, inputs resident in HBM.
 
@@ -92,6 +98,28 @@ def cached(cache_dir, name, make):
     return g, extra
 
 
+def host_workload(g, signal, models, cfg, unit):
+    """A workload whose graph and signal are generated on the host."""
+    import torch
+
+    from paper_2106_03058_amd import agp
+
+    state = {}
+
+    def make_graph():
+        return agp.Graph.from_inputs(g)
+
+    def signal_device():
+        state["x"] = signal()
+        return torch.from_numpy(state["x"]).to("cuda:0")
+
+    def oracle_inputs(cols):
+        return g, np.ascontiguousarray(state["x"][:, cols])
+
+    return dict(n=g.n, make_graph=make_graph, signal_device=signal_device, models=models, cfg=cfg, unit=unit,
+                oracle_inputs=oracle_inputs)
+
+
 def workload_katz_tp(args):
     from paper_2106_03058_amd import inputs
 
@@ -125,7 +153,7 @@ def workload_katz_tp(args):
            "graph": g.describe(), "lambda_1": lam, "columns_per_call": C,
            "models": {m["name"]: {"a": m["a"], "b": m["b"], "L": len(m["w"]) - 1, "eps": m["eps"]}
                       for m in models}}
-    return g, signal, models, cfg, "queries"
+    return host_workload(g, signal, models, cfg, "queries")
 
 
 def workload_gnn_hkpr(args):
@@ -145,10 +173,54 @@ def workload_gnn_hkpr(args):
     cfg = {"workload": f"gnn heat-kernel feature propagation, {C} N(0,1) columns, chung-lu n=2.4M d=50",
            "graph": g.describe(), "columns_per_call": C,
            "models": {"hkpr": {"a": 0.5, "b": 0.5, "L": 10, "t": 5.0, "eps": 1e-7}}}
-    return g, signal, models, cfg, "columns"
+    return host_workload(g, signal, models, cfg, "columns")
 
 
-WORKLOADS = {"katz-tp": workload_katz_tp, "gnn-hkpr": workload_gnn_hkpr}
+def workload_gnn_ppr_large(args):
+    """PPR (APPNP) feature propagation at the scale of a 111M-node citation
+    graph: Chung-Lu, exponent 2.2, ~1.6e9 arcs plus a loop per node, generated
+    on the GPU; an n x 128 U[-1, 1] feature matrix resident in HBM."""
+    import torch
+
+    from paper_2106_03058_amd import agp, inputs
+
+    n = args.large_n
+    arcs = int(round(1_615_685_872 * n / 111_059_956))
+    state = {}
+
+    def make_graph():
+        t = time.time()
+        _, rp, col = inputs.chung_lu_device(n, arcs / n, 2.2, seed=5, target_edges=arcs // 2)
+        state["desc"] = {"n": n, "arcs_without_loops": int(rp[-1].item()),
+                         "max_degree_without_loops": int((rp[1:] - rp[:-1]).max().item())}
+        log(f"chung-lu n={n}: {state['desc']} in {time.time() - t:.1f}s")
+        if not args.no_cpu_baseline:
+            state["rp"], state["col"] = rp.cpu().numpy(), col.cpu().numpy()
+        G = agp.Graph(rp, col, self_loops=True)
+        del rp, col
+        torch.cuda.empty_cache()
+        return G
+
+    def signal_device():
+        return inputs.features_uniform_device(n, 128, -1.0, 1.0, seed=505)
+
+    def oracle_inputs(cols):
+        t = time.time()
+        g = inputs.add_self_loops(n, state.pop("rp"), state.pop("col"))
+        log(f"host graph with loops {time.time() - t:.1f}s")
+        return g, np.ascontiguousarray(state["X"][:, cols].cpu().numpy())
+
+    models = [dict(name="ppr", a=0.5, b=0.5, w=inputs.weights_ppr(0.1, 10), eps=1e-8,
+                   qids=np.arange(128, dtype=np.uint32))]
+    cfg = {"workload": f"gnn ppr feature propagation, 128 U[-1,1] columns, chung-lu n={n} gamma=2.2 "
+                       f"(~{arcs:.3g} arcs + loops), resident in HBM",
+           "graph": state, "columns_per_call": 128,
+           "models": {"ppr": {"a": 0.5, "b": 0.5, "L": 10, "alpha": 0.1, "eps": 1e-8}}}
+    return dict(n=n, make_graph=make_graph, signal_device=signal_device, models=models, cfg=cfg, unit="columns",
+                oracle_inputs=oracle_inputs, state=state)
+
+
+WORKLOADS = {"katz-tp": workload_katz_tp, "gnn-hkpr": workload_gnn_hkpr, "gnn-ppr-large": workload_gnn_ppr_large}
 
 
 def run_serve(args) -> dict:
@@ -285,6 +357,7 @@ def main() -> int:
                     help="directory to keep the generated graph between runs")
     ap.add_argument("--models", default="katz,tp,hkpr", help="subset of the step to run (profiling)")
     ap.add_argument("--columns", type=int, default=256, help="columns per call (profiling)")
+    ap.add_argument("--large-n", type=int, default=111_059_956, help="gnn-ppr-large: nodes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device to device first (reference for HBM counters)")
     args = ap.parse_args()
@@ -301,7 +374,8 @@ def main() -> int:
     if args.workload == "serve":
         print(json.dumps(run_serve(args)), flush=True)
         return 0
-    g, signal, models, cfg, unit_name = WORKLOADS[args.workload](args)
+    W = WORKLOADS[args.workload](args)
+    models, cfg, unit_name, n = W["models"], W["cfg"], W["unit"], W["n"]
     if args.calibrate_copy:
         a_ = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b_ = torch.empty_like(a_)
@@ -309,11 +383,13 @@ def main() -> int:
         torch.cuda.synchronize()
         del a_, b_
     t = time.time()
-    G = agp.Graph.from_inputs(g)
+    G = W["make_graph"]()
     torch.cuda.synchronize()
     log(f"device graph build (degree sort) {time.time() - t:.2f}s, max degree {G.max_degree}")
-    xh = signal()
-    X = torch.from_numpy(xh).to(dev)
+    X = W["signal_device"]()
+    if "state" in W:
+        W["state"]["X"] = X
+        cfg["graph"] = W["state"].get("desc", {})
     C = X.shape[1]
     outs = [torch.empty_like(X) for _ in models]
 
@@ -377,7 +453,7 @@ def main() -> int:
     q_per_s_batched = len(models) * C / (ms_per_step / 1e3)
     lat_s = []
     nq = args.single // max(len(models), 1)
-    one = torch.empty((g.n, 1), dtype=torch.float32, device=dev)
+    one = torch.empty((n, 1), dtype=torch.float32, device=dev)
     single_ok = True
     for m, o in zip(models, outs):
         for c in range(min(nq, C)):
@@ -436,15 +512,18 @@ def main() -> int:
         import oracle
 
         k = min(args.cpu_units, C)
+        cols = np.sort(np.random.default_rng(55).choice(C, size=k, replace=False))
         threads = min(k * len(models), 16, os.cpu_count() or 1)
+        gh, xh = W["oracle_inputs"](cols)
         t = time.time()
-        sg = oracle.degree_sort(g)
+        sg = oracle.degree_sort(gh)
+        del gh
         log(f"oracle degree sort {time.time() - t:.1f}s")
         results = {}
 
         def run(mi, m):
-            results[mi] = oracle.propagate(sg, m["a"], m["b"], m["w"], xh[:, :k], m["eps"], args.seed,
-                                           qids=m["qids"][:k], threads=max(threads // len(models), 1))
+            results[mi] = oracle.propagate(sg, m["a"], m["b"], m["w"], xh, m["eps"], args.seed,
+                                           qids=m["qids"][cols], threads=max(threads // len(models), 1))
 
         t = time.time()
         ths = [threading.Thread(target=run, args=(mi, m)) for mi, m in enumerate(models)]
@@ -458,18 +537,22 @@ def main() -> int:
         for mi, m in enumerate(models):
             ref, cnt = results[mi]
             tot_push += int(cnt["det"].sum() + cnt["acc"].sum())
-            got = outs[mi][:, :k].cpu().numpy().astype(np.float64)
+            got = outs[mi][:, torch.from_numpy(cols).to(dev)].cpu().numpy().astype(np.float64)
             parity &= bool(np.array_equal(got, ref))
         log(f"oracle sample {wall:.1f}s, parity {parity}")
+        per_unit_s = wall * threads / (k * len(models))
         result["cpu_baseline"] = {
             "value": tot_push / wall,
             "unit": "edge-pushes/s",
             "cores": threads,
             "kind": "oracle",
-            "sample": f"{k} {unit_name} of each model ({', '.join(m['name'] for m in models)}), same inputs "
-                      f"and seeds, {wall:.1f}s wall",
+            "sample": f"{unit_name} {cols.tolist()} of each model ({', '.join(m['name'] for m in models)}), "
+                      f"same inputs and seeds, {wall:.1f}s wall on {threads} threads",
+            "seconds_per_unit_one_core": per_unit_s,
+            "step_seconds_extrapolated": per_unit_s * C * len(models) / threads,
         }
-        result["parity_full_size"] = {"units_checked": k * len(models), "bit_exact": parity}
+        result["parity_full_size"] = {"units_checked": k * len(models), "columns": cols.tolist(),
+                                      "bit_exact": parity}
     print(json.dumps(result), flush=True)
     return 0
 

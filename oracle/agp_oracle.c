@@ -44,6 +44,7 @@
 
 #include <math.h>
 #include <pthread.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -430,6 +431,11 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
         cnt->cand[i] = ncand;
         cnt->acc[i] = nacc;
       }
+    }
+    if (getenv("ORC_PROGRESS")) { /* long runs: one line per level on stderr */
+      fprintf(stderr, "[oracle] qid %u level %d: frontier %lld, pushes %llu\n", (unsigned)qid, (int)i,
+              (long long)nf, (unsigned long long)(ndet + nacc));
+      fflush(stderr);
     }
     if (i == L) break;
     /* empty level i; r^(i+1) is the rounded exact sum of what arrived */

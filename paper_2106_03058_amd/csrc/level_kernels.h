@@ -81,6 +81,7 @@ struct LevelArgs {
   const int32_t* deg;
   const ColParams* cp;
   long long su, sc;  // cell = u * su + c * sc
+  long long xld;     // level 0 of a batched call: x[u * xld + c]
   int level;         // batched calls: counter row
   const uint64_t* fin;
   const unsigned long long* cnt_in;
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         const ColParams& cp = A.cp[ec];
         T r;
         if (kFirst)
-          r = x[cell];
+          r = x[static_cast<size_t>(eu) * static_cast<size_t>(A.xld) + ec];
         else
           r = P::take(acc_cur, cell, cp);
         eneg = r < T(0);
@@ -442,6 +443,10 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
               } else {  // increments fall along the degree-sorted row: binary search
                 inc0 = ecv * cp.da[A.nd[erp]];
                 uint32_t lo = 0, hi = ed;
+                if (!(inc0 >= eth))
+                  hi = 0;  // no deterministic push
+                else if (ecv * cp.da[A.nd[erp + ed - 1]] >= eth)
+                  lo = ed;  // every push is deterministic
                 while (lo < hi) {
                   const uint32_t mid = (lo + hi) >> 1;
                   const double inc = ecv * cp.da[A.nd[erp + mid]];
@@ -684,7 +689,7 @@ __global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __r
     const size_t cell = static_cast<size_t>(u) * A.su + static_cast<size_t>(c) * A.sc;
     double absr;
     if (kFirst) {
-      absr = fabs(static_cast<double>(x[cell]));
+      absr = fabs(static_cast<double>(x[static_cast<size_t>(u) * static_cast<size_t>(A.xld) + c]));
     } else if (sizeof(T) == 4) {
       const long long K = reinterpret_cast<const long long*>(acc_cur)[cell];
       absr = fabs(static_cast<double>(K)) / cp.scale;
@@ -719,7 +724,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int 
     for (int64_t u = wave; u < n; u += nwaves) {
       for (int c0 = 0; c0 < C; c0 += kWave) {
         const int c = c0 + lane;
-        const bool p = (c < C) && pred(static_cast<size_t>(u) * C + c);
+        const bool p = (c < C) && pred(u, c, static_cast<size_t>(u) * C + c);
         stage_push(stage, staged, (static_cast<uint64_t>(u) << 32) | static_cast<uint32_t>(c), p, F, cnt);
       }
     }
@@ -743,7 +748,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int 
           c = i / n;
           u = i - c * n;
         }
-        p = pred(static_cast<size_t>(i));
+        p = pred(u, c, static_cast<size_t>(i));
         item = (static_cast<uint64_t>(u) << 32) | static_cast<uint32_t>(c);
       }
       stage_push(stage, staged, item, p, F, cnt);
@@ -752,16 +757,20 @@ __global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int 
   stage_flush(stage, staged, F, cnt);
 }
 
+// x[u * ld + c] != 0 (the signal, row stride ld)
 template <typename T>
 struct NonZeroValue {
   const T* x;
-  __device__ bool operator()(size_t i) const { return x[i] != T(0); }
+  long long ld;
+  __device__ bool operator()(int64_t u, int64_t c, size_t) const {
+    return x[static_cast<size_t>(u) * static_cast<size_t>(ld) + static_cast<size_t>(c)] != T(0);
+  }
 };
 
 template <typename T>
 struct NonZeroCell {
   const typename Prec<T>::Cell* acc;
-  __device__ bool operator()(size_t i) const { return Prec<T>::nonzero(acc, i); }
+  __device__ bool operator()(int64_t, int64_t, size_t cell) const { return Prec<T>::nonzero(acc, cell); }
 };
 
 inline unsigned grid_for(int64_t items, int threads, int64_t cap = 65536) {

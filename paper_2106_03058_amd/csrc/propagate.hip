@@ -30,8 +30,8 @@ using namespace lvl;
 // ||x_c||_1 in binary64: sequential over blocks of 4096 rows, then over the
 // block sums.  flags: 1 = non-finite entry, 2 = negative entry.
 template <typename T>
-__global__ void k_theta_partial(const T* __restrict__ x, int64_t n, int C, double* __restrict__ partial,
-                                int* __restrict__ flags) {
+__global__ void k_theta_partial(const T* __restrict__ x, long long ldx, int64_t n, int C,
+                                double* __restrict__ partial, int* __restrict__ flags) {
   const int c = blockIdx.y * blockDim.x + threadIdx.x;
   if (c >= C) return;
   const int64_t lo = (int64_t)blockIdx.x * kThetaRows;
@@ -39,7 +39,7 @@ __global__ void k_theta_partial(const T* __restrict__ x, int64_t n, int C, doubl
   double sum = 0.0;
   int f = 0;
   for (int64_t i = lo; i < hi; ++i) {
-    const T v = x[static_cast<size_t>(i) * C + c];
+    const T v = x[static_cast<size_t>(i) * static_cast<size_t>(ldx) + c];
     if (!isfinite(static_cast<double>(v))) f |= 1;
     if (v < T(0)) f |= 2;
     sum = sum + fabs(static_cast<double>(v));
@@ -50,14 +50,14 @@ __global__ void k_theta_partial(const T* __restrict__ x, int64_t n, int C, doubl
 
 template <typename T>
 __global__ void k_theta_final(const double* __restrict__ partial, int64_t nblocks, int C, double eps,
-                              const uint32_t* __restrict__ qids, ColParams* __restrict__ cp) {
+                              const uint32_t* __restrict__ qids, uint32_t qid_base, ColParams* __restrict__ cp) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
   double total = 0.0;
   for (int64_t b = 0; b < nblocks; ++b) total = total + partial[(size_t)b * C + c];
   ColParams p = cp[c];
   p.theta = eps * total;
-  p.qid = qids ? qids[c] : static_cast<uint32_t>(c);
+  p.qid = qids ? qids[c] : qid_base + static_cast<uint32_t>(c);
   if (sizeof(T) == 4) {
     const float tw = static_cast<float>(p.theta);
     int ue = -149;
@@ -407,45 +407,19 @@ agp_tuning_t tuning_for(agp_graph* g, int32_t C, double a, double b, const agp_t
   return t;
 }
 
+// One tile of C columns: x and out point at the tile's first column, rows
+// ldc apart; column c of the tile is column qid_base + c of the call (its
+// qid when qids is null).  Levels are timed when stats is non-null (the
+// tile's counters and times are added to it).  The caller holds g->mu and
+// has zeroed out.
 template <typename T>
-int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L, const T* x,
-                   int32_t C, double eps, uint64_t seed, const uint32_t* qids, T* out,
-                   hipStream_t s, agp_stats_t* stats, const agp_tuning_t* force = nullptr) {
+int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, double a, double b,
+                   const std::vector<double>& rho, const std::vector<double>& kappa, int32_t L, const T* x,
+                   long long ldc, int32_t C, double eps, uint64_t seed, const uint32_t* qids, uint32_t qid_base,
+                   T* out, hipStream_t s, agp_stats_t* stats) {
   using Cell = typename Prec<T>::Cell;
-  const char* fn = sizeof(T) == 4 ? "agp_propagate" : "agp_propagate_f64";
-  if (!g) return fail(AGP_EINVAL, std::string(fn) + ": NULL graph");
-  if (!(a >= 0.0 && a <= 1.0) || !(b >= 0.0 && b <= 1.0))
-    return fail(AGP_EINVAL, std::string(fn) + ": a and b must lie in [0, 1]");
-  if (L < 0 || L > AGP_MAX_LEVELS) return fail(AGP_EINVAL, std::string(fn) + ": need 0 <= L <= 255");
-  if (C < 1) return fail(AGP_EINVAL, std::string(fn) + ": need C >= 1");
-  if (!w || !x || !out) return fail(AGP_EINVAL, std::string(fn) + ": NULL array");
-  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(AGP_EINVAL, std::string(fn) + ": need eps >= 0");
-  if (eps == 0.0)
-    return fail(AGP_ENOTSUP, std::string(fn) + ": eps = 0 (Algorithm 1) is not supported on the GPU path");
-  for (int32_t i = 0; i <= L; ++i)
-    if (!(w[i] >= 0.0) || !std::isfinite(w[i]))
-      return fail(AGP_EINVAL, std::string(fn) + ": weights must be finite and >= 0");
-  if (qids)
-    for (int32_t c = 0; c < C; ++c)
-      if (qids[c] >= (1u << 24)) return fail(AGP_EINVAL, std::string(fn) + ": qid must be < 2^24");
   const int64_t n = g->n;
   const size_t cells = static_cast<size_t>(n) * static_cast<size_t>(C);
-  if (n > 0 && cells / static_cast<size_t>(n) != static_cast<size_t>(C))
-    return fail(AGP_EINVAL, std::string(fn) + ": n * C overflows");
-
-  // level tables in binary64: Y_i = sum_{k=i..L} w_k added from k = L down,
-  // S = Y_0, rho_i = Y_{i+1} / Y_i, kappa_i = (S w_i) / Y_i
-  std::vector<double> Y(static_cast<size_t>(L) + 2, 0.0), rho(static_cast<size_t>(L) + 1),
-      kappa(static_cast<size_t>(L) + 1);
-  for (int32_t k = L; k >= 0; --k) Y[k] = Y[k + 1] + w[k];
-  const double S = Y[0];
-  for (int32_t i = 0; i <= L; ++i) {
-    rho[i] = (Y[i] == 0.0) ? 0.0 : Y[i + 1] / Y[i];
-    kappa[i] = (Y[i] == 0.0) ? 0.0 : (S * w[i]) / Y[i];
-  }
-
-  std::lock_guard<std::mutex> lk(g->mu);
-  const agp_tuning_t tune = tuning_for(g, C, a, b, force);
   int rc;
   const double *da = nullptr, *db = nullptr;
   if ((rc = pow_table(g, a, &da)) || (rc = pow_table(g, b, &db))) return rc;
@@ -481,10 +455,10 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   // thresholds theta_c = eps ||x_c||_1 and signal checks
   if (tblocks > 0) {
     dim3 grid((unsigned)tblocks, (unsigned)((C + 63) / 64));
-    k_theta_partial<T><<<grid, 64, 0, s>>>(x, n, C, sc.partial.as<double>(), flags + 1);
+    k_theta_partial<T><<<grid, 64, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1);
   }
   k_theta_final<T><<<grid_for(C, 64), 64, 0, s>>>(sc.partial.as<double>(), tblocks, C, eps,
-                                                  qids ? dq : nullptr, cp);
+                                                  qids ? dq : nullptr, qid_base, cp);
   AGP_HIP(hipGetLastError());
   int hflags[4] = {0, 0, 0, 0};
   AGP_HIP(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
@@ -495,13 +469,17 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   // binned aggregation: binary32, cells addressable in 32 bits, LDS scale table
   bool binned = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4 && cells < (1ull << 31) &&
                 C <= kMaxBinnedC && cells > 0;
-  // buckets of 2^shift cells: at most 1024 buckets, bins of 4096 cells
+  // buckets of 2^shift cells: at most 1024 buckets, bins of 8192 cells
   int shift = kBinLog2;
   while (shift < 32 && (static_cast<unsigned long long>(cells) - 1ull) >> shift >= (unsigned long long)kBuckets) ++shift;
   const unsigned nbuckets = static_cast<unsigned>(((cells > 0 ? cells : 1) - 1) >> shift) + 1u;
   unsigned long long rec_cap = 0;
   if (binned) {
-    rec_cap = std::max<unsigned long long>(1ull << 20, 3ull * cells);
+    // room for 4 records per cell, within an eighth of the free memory (two buffers)
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    rec_cap = std::max<unsigned long long>(1ull << 20, 4ull * cells);
+    rec_cap = std::min<unsigned long long>(rec_cap, std::max<unsigned long long>(1ull << 20, free_b / 64));
     if (const char* e = std::getenv("AGP_RECORD_CAP")) {  // smaller record buffer (tuning / tests)
       const unsigned long long v = std::strtoull(e, nullptr, 10);
       if (v > 0 && v < rec_cap) rec_cap = v;
@@ -522,13 +500,12 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   unsigned long long* rec_counts = binned ? cursor + kBuckets : nullptr;
   if (binned) AGP_HIP(hipMemsetAsync(rec_counts, 0, sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1), s));
 
-  AGP_HIP(hipMemsetAsync(out, 0, cells * sizeof(T), s));
   hipEvent_t* ev = sc.events;
   if (stats && (rc = sc.ensure_events())) return rc;
   uint64_t* F[2] = {sc.frontier[0].as<uint64_t>(), sc.frontier[1].as<uint64_t>()};
   Cell* acc[2] = {sc.acc[0].as<Cell>(), sc.acc[1].as<Cell>()};
   const unsigned cgrid = grid_for(n * (int64_t)(C >= kWave ? kWave : C), kThreads, 8192);
-  k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroValue<T>{x}, n, C, (long long)C, 1ll, F[0], counts, nullptr);
+  k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroValue<T>{x, ldc}, n, C, (long long)C, 1ll, F[0], counts, nullptr);
 
   LevelArgs A{};
   A.rp = g->row_ptr;
@@ -538,6 +515,7 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   A.cp = cp;
   A.su = C;
   A.sc = 1;
+  A.xld = ldc;
   A.counters = counters;
   A.mass = mass;
   A.err = flags;
@@ -554,7 +532,7 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   for (int32_t i = 0; i <= L; ++i) {
     const int lflags = (i == L ? kLastLevel : 0) | (a == 0.0 ? kAZero : 0);
     k_set_level<<<grid_for(C, 64), 64, 0, s>>>(cp, C, i, rho[i], kappa[i], lflags, da, db, key0, key1, out,
-                                              (long long)C, sizeof(T));
+                                              ldc, sizeof(T));
     A.level = i;
     A.fin = F[i & 1];
     A.cnt_in = counts + i;
@@ -613,23 +591,104 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   if (stats) {
     std::vector<unsigned long long> h(static_cast<size_t>(kNumCounters) * (L + 1));
     AGP_HIP(hipMemcpy(h.data(), counters, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-    std::memset(stats, 0, sizeof(*stats));
     stats->levels = L;
-    stats->columns = C;
     for (int32_t i = 0; i <= L; ++i) {
-      stats->frontier[i] = h[i * kNumCounters + 0];
-      stats->hash[i] = h[i * kNumCounters + 1];
-      stats->det[i] = h[i * kNumCounters + 2];
-      stats->cand[i] = h[i * kNumCounters + 3];
-      stats->acc[i] = h[i * kNumCounters + 4];
+      stats->frontier[i] += h[i * kNumCounters + 0];
+      stats->hash[i] += h[i * kNumCounters + 1];
+      stats->det[i] += h[i * kNumCounters + 2];
+      stats->cand[i] += h[i * kNumCounters + 3];
+      stats->acc[i] += h[i * kNumCounters + 4];
     }
     float ms = 0.0f;
     for (int32_t i = 0; i <= L; ++i) {
       AGP_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
-      stats->level_ms[i] = ms;
+      stats->level_ms[i] += ms;
     }
     AGP_HIP(hipEventElapsedTime(&ms, ev[0], ev[2 * L + 1]));
-    stats->device_ms = ms;
+    stats->device_ms += ms;
+  }
+  return AGP_OK;
+}
+
+
+// Tile width: every column at once when the scratch fits in 85% of the free
+// memory (plus what the scratch already holds), else the widest tile that
+// does; AGP_COLUMN_TILE forces a width (tests).
+template <typename T>
+int32_t column_tile(agp_graph* g, int32_t C, bool binned) {
+  if (const char* e = std::getenv("AGP_COLUMN_TILE")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v > 0 && v < C) return static_cast<int32_t>(v);
+  }
+  const size_t cell_bytes = sizeof(typename Prec<T>::Cell) * (sizeof(T) == 4 ? 1 : 2);
+  // two accumulators and two frontier lists per cell (+ two record buffers of 4 records)
+  const size_t per_cell = 2 * cell_bytes + 2 * sizeof(uint64_t) + (binned ? 2 * 4 * sizeof(uint32_t) : 0);
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return C;
+  Scratch& sc = g->scratch;
+  const size_t held = sc.acc[0].bytes + sc.acc[1].bytes + sc.frontier[0].bytes + sc.frontier[1].bytes +
+                      sc.rec[0].bytes + sc.rec[1].bytes;
+  const double budget = 0.85 * static_cast<double>(free_b + held);
+  const double per_col = static_cast<double>(g->n > 0 ? g->n : 1) * static_cast<double>(per_cell);
+  const double fit = budget / per_col;
+  if (fit >= static_cast<double>(C)) return C;
+  return fit < 1.0 ? 1 : static_cast<int32_t>(fit);
+}
+
+template <typename T>
+int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L, const T* x,
+                   int32_t C, double eps, uint64_t seed, const uint32_t* qids, T* out,
+                   hipStream_t s, agp_stats_t* stats, const agp_tuning_t* force = nullptr) {
+  const char* fn = sizeof(T) == 4 ? "agp_propagate" : "agp_propagate_f64";
+  if (!g) return fail(AGP_EINVAL, std::string(fn) + ": NULL graph");
+  if (!(a >= 0.0 && a <= 1.0) || !(b >= 0.0 && b <= 1.0))
+    return fail(AGP_EINVAL, std::string(fn) + ": a and b must lie in [0, 1]");
+  if (L < 0 || L > AGP_MAX_LEVELS) return fail(AGP_EINVAL, std::string(fn) + ": need 0 <= L <= 255");
+  if (C < 1) return fail(AGP_EINVAL, std::string(fn) + ": need C >= 1");
+  if (!w || !x || !out) return fail(AGP_EINVAL, std::string(fn) + ": NULL array");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(AGP_EINVAL, std::string(fn) + ": need eps >= 0");
+  if (eps == 0.0)
+    return fail(AGP_ENOTSUP, std::string(fn) + ": eps = 0 (Algorithm 1) is not supported on the GPU path");
+  for (int32_t i = 0; i <= L; ++i)
+    if (!(w[i] >= 0.0) || !std::isfinite(w[i]))
+      return fail(AGP_EINVAL, std::string(fn) + ": weights must be finite and >= 0");
+  if (qids) {
+    for (int32_t c = 0; c < C; ++c)
+      if (qids[c] >= (1u << 24)) return fail(AGP_EINVAL, std::string(fn) + ": qid must be < 2^24");
+  } else if (C > (1 << 24)) {
+    return fail(AGP_EINVAL, std::string(fn) + ": more than 2^24 columns need explicit qids");
+  }
+  const int64_t n = g->n;
+  const size_t cells = static_cast<size_t>(n) * static_cast<size_t>(C);
+  if (n > 0 && cells / static_cast<size_t>(n) != static_cast<size_t>(C))
+    return fail(AGP_EINVAL, std::string(fn) + ": n * C overflows");
+
+  // level tables in binary64: Y_i = sum_{k=i..L} w_k added from k = L down,
+  // S = Y_0, rho_i = Y_{i+1} / Y_i, kappa_i = (S w_i) / Y_i
+  std::vector<double> Y(static_cast<size_t>(L) + 2, 0.0), rho(static_cast<size_t>(L) + 1),
+      kappa(static_cast<size_t>(L) + 1);
+  for (int32_t k = L; k >= 0; --k) Y[k] = Y[k + 1] + w[k];
+  const double S = Y[0];
+  for (int32_t i = 0; i <= L; ++i) {
+    rho[i] = (Y[i] == 0.0) ? 0.0 : Y[i + 1] / Y[i];
+    kappa[i] = (Y[i] == 0.0) ? 0.0 : (S * w[i]) / Y[i];
+  }
+
+  std::lock_guard<std::mutex> lk(g->mu);
+  const agp_tuning_t tune = tuning_for(g, C, a, b, force);
+  const bool may_bin = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4;
+  const int32_t tile = column_tile<T>(g, C, may_bin);
+  AGP_HIP(hipMemsetAsync(out, 0, cells * sizeof(T), s));
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  for (int32_t c0 = 0; c0 < C; c0 += tile) {
+    const int32_t ct = std::min(tile, C - c0);
+    const int rc = propagate_tile<T>(g, fn, tune, a, b, rho, kappa, L, x + c0, static_cast<long long>(C), ct, eps,
+                                     seed, qids ? qids + c0 : nullptr, static_cast<uint32_t>(c0), out + c0, s, stats);
+    if (rc != AGP_OK) return rc;
+  }
+  if (stats) {
+    stats->levels = L;
+    stats->columns = C;
   }
   return AGP_OK;
 }

@@ -311,6 +311,92 @@ def rmat_device(scale: int, edge_factor: int, a: float, b: float, c: float, seed
     return n, row_ptr, col
 
 
+def chung_lu_device(n: int, mean_degree: float, gamma: float, seed: int, *, target_edges: int | None = None,
+                    pair_factor: float = 1.0, device="cuda:0", chunk: int = 1 << 26, max_rounds: int = 4):
+    """Chung-Lu power-law graph built on the GPU with the recipe of chung_lu
+    (weights (i+1)^(-1/(gamma-1)) scaled to the mean degree and capped at
+    sqrt(n mean_degree), endpoints drawn proportionally to weight by inverse
+    CDF); loops dropped, duplicates removed, symmetrised.  With target_edges,
+    more pairs are drawn (same generator) until that many distinct undirected
+    edges exist, making up for the pairs lost to loops and duplicates.
+    Returns (n, row_ptr int64, col int32) tensors."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    w = (torch.arange(n, dtype=torch.float64, device=device) + 1.0) ** (-1.0 / (gamma - 1.0))
+    w *= mean_degree * n / float(w.sum())
+    w.clamp_(max=math.sqrt(n * mean_degree))
+    cdf = torch.cumsum(w, 0)
+    cdf /= cdf[-1].clone()
+    del w
+
+    def draw(m):
+        keys = []
+        for lo in range(0, m, chunk):
+            k = min(chunk, m - lo)
+            s = torch.searchsorted(cdf, torch.rand(k, generator=gen, device=device, dtype=torch.float64),
+                                   right=True).clamp_(max=n - 1)
+            d = torch.searchsorted(cdf, torch.rand(k, generator=gen, device=device, dtype=torch.float64),
+                                   right=True).clamp_(max=n - 1)
+            keep = s != d
+            s, d = s[keep], d[keep]
+            keys.append(torch.minimum(s, d) * n + torch.maximum(s, d))
+            del s, d, keep
+        return torch.unique(torch.cat(keys))
+
+    m = int(round(n * mean_degree / 2.0 * pair_factor))
+    key = draw(m)
+    for _ in range(max_rounds):
+        if target_edges is None or key.numel() >= target_edges:
+            break
+        short = target_edges - key.numel()
+        lost = 1.0 - key.numel() / float(m)  # fraction of drawn pairs lost so far
+        extra = int(short / max(1.0 - 2.0 * lost, 0.25) * 1.02) + 1
+        m += extra
+        key = torch.unique(torch.cat([key, draw(extra)]))
+    del cdf
+    u = torch.div(key, n, rounding_mode="floor")
+    v = key - u * n
+    del key
+    both = torch.cat([u * n + v, v * n + u])
+    del u, v
+    both, _ = torch.sort(both)
+    rows = torch.div(both, n, rounding_mode="floor")
+    col = (both - rows * n).to(torch.int32)
+    del both
+    counts = torch.bincount(rows, minlength=n)
+    del rows
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    row_ptr[1:] = torch.cumsum(counts, 0)
+    return n, row_ptr, col
+
+
+def add_self_loops(n: int, row_ptr: np.ndarray, col: np.ndarray) -> Graph:
+    """The CSR graph with one loop (u, u) appended to every row (GNN
+    propagation on A + I)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    deg = np.diff(row_ptr)
+    new_rp = row_ptr + np.arange(n + 1, dtype=np.int64)
+    new_col = np.empty(int(new_rp[-1]), dtype=np.int32)
+    shift = np.repeat(np.arange(n, dtype=np.int64), deg)  # entries of row u move by u
+    new_col[np.arange(col.size, dtype=np.int64) + shift] = col
+    del shift
+    new_col[new_rp[1:] - 1] = np.arange(n, dtype=np.int32)
+    return Graph(n, new_rp, new_col)
+
+
+def features_uniform_device(n: int, C: int, lo: float, hi: float, seed: int, device="cuda:0"):
+    """n x C binary32 features, i.i.d. uniform on [lo, hi), generated on the GPU."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    x = torch.rand((n, C), generator=gen, device=device, dtype=torch.float32)
+    x.mul_(hi - lo).add_(lo)
+    return x
+
+
 def lambda_max_device(n: int, row_ptr, col, *, tol: float = 1e-10, max_iter: int = 1000) -> float:
     """Largest adjacency eigenvalue by FP64 power iteration on the GPU."""
     import torch

@@ -285,3 +285,25 @@ def test_autotune_keeps_results(agp, torch_dev):
     assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
     again, _ = agp.propagate(G, 0.0, 1.0, w, X, 1e-5, 9)
     assert np.array_equal(again.cpu().numpy().astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("name,wp,tile", [("appnp_uniform", 32, "7"), ("ppr", 32, "5"), ("gdc_signed", 64, "3")])
+def test_column_tiles_are_bit_identical(agp, torch_dev, name, wp, tile, monkeypatch):
+    """A call split into column tiles (the last one ragged) gives the bits of
+    the untiled call and of the oracle: column c keeps its own random streams."""
+    a, b, w, eps, kind = CASES[name]
+    g = inputs.chung_lu(4000, 12, 2.5, seed=37, self_loops=kind != "onehot")
+    x = _signal(g, kind, 33, seed=8)
+    G = agp.Graph.from_inputs(g)
+    ref, cnt = _oracle(g, a, b, w, x, eps, 6, wp=wp)
+    monkeypatch.delenv("AGP_COLUMN_TILE", raising=False)
+    whole, st_whole = _run(agp, torch_dev, g, a, b, w, x, eps, seed=6, wp=wp, G=G)
+    monkeypatch.setenv("AGP_COLUMN_TILE", tile)
+    tiled, st_tiled = _run(agp, torch_dev, g, a, b, w, x, eps, seed=6, wp=wp, G=G)
+    _assert_parity(tiled, st_tiled, ref, cnt, len(w) - 1)
+    assert np.array_equal(whole, tiled)
+    # explicit qids follow their columns into the tiles
+    q = np.arange(500, 533, dtype=np.uint32)[::-1].copy()
+    ref_q, _ = _oracle(g, a, b, w, x, eps, 6, wp=wp, qids=q)
+    tiled_q, _ = _run(agp, torch_dev, g, a, b, w, x, eps, seed=6, wp=wp, G=G, qids=q)
+    assert np.array_equal(tiled_q, ref_q)

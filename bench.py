@@ -358,6 +358,8 @@ def main() -> int:
     ap.add_argument("--models", default="katz,tp,hkpr", help="subset of the step to run (profiling)")
     ap.add_argument("--columns", type=int, default=256, help="columns per call (profiling)")
     ap.add_argument("--large-n", type=int, default=111_059_956, help="gnn-ppr-large: nodes")
+    ap.add_argument("--exact-units", type=int, default=1,
+                    help="sampled units whose error against the exact FP64 sum is reported")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device to device first (reference for HBM counters)")
     args = ap.parse_args()
@@ -517,7 +519,6 @@ def main() -> int:
         gh, xh = W["oracle_inputs"](cols)
         t = time.time()
         sg = oracle.degree_sort(gh)
-        del gh
         log(f"oracle degree sort {time.time() - t:.1f}s")
         results = {}
 
@@ -553,6 +554,23 @@ def main() -> int:
         }
         result["parity_full_size"] = {"units_checked": k * len(models), "columns": cols.tolist(),
                                       "bit_exact": parity}
+        # error of the estimate against the exact FP64 sum of Eq. 1 (sparse Horner)
+        if args.exact_units > 0:
+            from oracle import dense
+
+            t = time.time()
+            errs = {}
+            ke = min(args.exact_units, k)
+            for mi, m in enumerate(models):
+                exact = dense.horner_sparse(gh, m["a"], m["b"], m["w"], xh[:, :ke])
+                got = outs[mi][:, torch.from_numpy(cols[:ke]).to(dev)].cpu().numpy().astype(np.float64)
+                diff = np.abs(got - exact)
+                errs[m["name"]] = {"columns": cols[:ke].tolist(), "eps": m["eps"], "max_abs": float(diff.max()),
+                                   "rel_l1": float(diff.sum() / max(np.abs(exact).sum(), 1e-300)),
+                                   "max_abs_over_max_exact": float(diff.max() / max(np.abs(exact).max(), 1e-300))}
+            result["error_vs_exact"] = errs
+            log(f"exact sums {time.time() - t:.1f}s: {errs}")
+        del gh
     print(json.dumps(result), flush=True)
     return 0
 

@@ -4,7 +4,8 @@ These are the plain definitions the randomized method must reproduce in
 expectation (and exactly at eps = 0), used to pin the C oracle on small graphs:
 
 * Eq. (1) of the paper truncated at level L: pi_L = sum_{i<=L} w_i P^i x with
-  P = D^-a A D^-b, evaluated by Horner's rule;
+  P = D^-a A D^-b, evaluated by Horner's rule (dense, and with a sparse P for
+  the error of full-size runs against the exact sum);
 * PPR: pi = alpha (I - (1 - alpha) A D^-1)^-1 x (Section 2);
 * single-target PPR: pi = alpha (I - (1 - alpha) D^-1 A)^-1 e_t (Section 2);
 * Katz: pi = sum_i beta^i A^i x = (I - beta A)^-1 x for beta < 1/lambda_1;
@@ -36,6 +37,26 @@ def transition(g, a: float, b: float) -> np.ndarray:
 def horner(g, a: float, b: float, w, x) -> np.ndarray:
     """sum_{i=0}^{L} w_i P^i x for x of shape (n,) or (n, C)."""
     P = transition(g, a, b)
+    w = np.asarray(w, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    acc = w[-1] * x
+    for i in range(w.size - 2, -1, -1):
+        acc = w[i] * x + P @ acc
+    return acc
+
+
+def horner_sparse(g, a: float, b: float, w, x) -> np.ndarray:
+    """sum_{i=0}^{L} w_i P^i x as horner(), with P = D^-a A D^-b held as a
+    scipy CSR matrix (for graphs too large for a dense n x n matrix)."""
+    import scipy.sparse as sp
+
+    n = g.n
+    d = np.diff(np.asarray(g.row_ptr, dtype=np.int64)).astype(np.float64)
+    with np.errstate(divide="ignore"):
+        da = np.where(d > 0, d ** (-a), 0.0)
+        db = np.where(d > 0, d ** (-b), 0.0)
+    A = sp.csr_matrix((np.ones(len(g.col)), np.asarray(g.col), np.asarray(g.row_ptr)), shape=(n, n))
+    P = sp.diags(da) @ A @ sp.diags(db)
     w = np.asarray(w, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64)
     acc = w[-1] * x

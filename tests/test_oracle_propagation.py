@@ -345,3 +345,14 @@ def test_rejects_invalid_arguments(orc):
         orc.propagate(sg, 0.0, 1.0, -w, x, 0.1, 1)
     with pytest.raises(ValueError):
         orc.propagate(sg, 0.0, 1.0, np.ones(300), x, 0.1, 1)
+
+
+def test_sparse_horner_matches_dense():
+    """The sparse Horner sum (used for full-size error reports) equals the
+    dense one, which the closed forms pin, on every model of Table 1."""
+    for seed, loops in ((3, False), (4, True)):
+        g = inputs.chung_lu(300, 6, 2.5, seed=seed, self_loops=loops)
+        x = inputs.features_normal(g.n, 3, seed=seed)
+        for a, b, w in ((0.0, 1.0, inputs.weights_ppr(0.2, 12)), (0.5, 0.5, inputs.weights_hkpr(4.0, 9)),
+                        (1.0, 0.0, inputs.weights_tp(5)), (0.3, 0.7, inputs.weights_ppr(0.1, 7))):
+            assert np.allclose(dense.horner_sparse(g, a, b, w, x), dense.horner(g, a, b, w, x), rtol=1e-12, atol=1e-14)

@@ -303,9 +303,6 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   // server: per-column counters summed in LDS, flushed once per block
   __shared__ unsigned long long s_scnt[kServe ? kServeLdsSlots : 1][kNumCounters];
   __shared__ double s_smass[kServe ? kServeLdsSlots : 1];
-  // batched calls: per-wave level counters (frontier, hash, det, cand, acc) and mass
-  __shared__ unsigned long long s_wcnt[kWaves][kNumCounters];
-  __shared__ double s_wmass[kWaves];
 
   const unsigned long long count = *A.cnt_in;
   // Binned levels write (cell, value) records that later kernels group by
@@ -333,9 +330,8 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   uint64_t* stage = s_stage[wave];
   int staged = 0;  // wave-uniform
 
-  if (lane < kNumCounters) s_wcnt[wave][lane] = 0;
-  if (lane == 0) s_wmass[wave] = 0.0;
-  wave_sync();
+  unsigned long long n_front = 0, n_hash = 0, n_det = 0, n_cand = 0, n_acc = 0;
+  double mass = 0.0;
 
   // One contribution per lane (or none), in exact units of the next
   // residue.  Wave-uniform calls.  emit_det: a deterministic push (atomics
@@ -385,29 +381,14 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   double cv = 0.0, dstart = 1.0, th = 0.0;
   const ColParams* cpp = A.cp;
   SkipTable tab;
-  // an accepted candidate's neighbour id is loaded in the step it is drawn
-  // and emitted in the next one, so the load overlaps the next draw
-  bool p_emit = false, p_neg = false;
-  uint32_t p_v = 0, p_c = 0;
-  // the contribution of a pending push: -/+ fl(theta) of its column, in units
-  auto emit_pending = [&]() {
-    Delta d{};
-    if (p_emit) d = P::theta_units(A.cp[p_c], p_neg);
-    emit_sampled(p_emit, p_v, p_c, d, p_neg);
-  };
 
   for (;;) {
     // (a) a lane whose item has no window left becomes idle
     if (active && need_run && s >= rend) {
       active = false;
-      if (it_cand) {
-        if (kServe) {
-          serve_count(A, s_scnt, c, 3, static_cast<unsigned long long>(it_cand));
-          if (it_acc) serve_count(A, s_scnt, c, 4, static_cast<unsigned long long>(it_acc));
-        } else {
-          atomicAdd(&s_wcnt[wave][3], static_cast<unsigned long long>(it_cand));
-          if (it_acc) atomicAdd(&s_wcnt[wave][4], static_cast<unsigned long long>(it_acc));
-        }
+      if (kServe && it_cand) {
+        serve_count(A, s_scnt, c, 3, static_cast<unsigned long long>(it_cand));
+        if (it_acc) serve_count(A, s_scnt, c, 4, static_cast<unsigned long long>(it_acc));
       }
     }
     // (b) the queue is empty and a lane is idle: set up the next batch
@@ -419,8 +400,8 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       long long dwork = 0, iwork = 0;
       uint32_t eu = 0, ec = 0, ed = 0, eJ = 0;
       int64_t erp = 0;
-      double ecv = 0.0, ep0 = 0.0, em = 0.0;
-      bool eneg = false, efront = false;
+      double ecv = 0.0, ep0 = 0.0;
+      bool eneg = false;
       if (lane < ne) {
         const uint64_t item = A.fin[e0 + lane];
         eu = static_cast<uint32_t>(item >> 32);
@@ -437,7 +418,8 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
           if (kServe) {
             serve_count(A, s_scnt, ec, 0, 1ull);
           } else {
-            efront = true;
+            ++n_front;
+            n_hash += splitmix64(eu);
           }
           // reserve: pi(u) += (S w_i / Y_i) r(u), rounded to the working precision
           if (cp.kappa != 0.0) {
@@ -490,24 +472,11 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
                 else
                   atomicAdd(A.mass + ec, m);
               } else {
-                em = m;
+                n_det += eJ;
+                mass += m;
               }
             }
           }
-        }
-      }
-      if (!kServe) {  // the batch's counters, summed over the wave into LDS
-        const unsigned long long f1 = wave_sum_u64(efront ? 1ull : 0ull);
-        const unsigned long long h1 = wave_sum_u64(efront ? splitmix64(eu) : 0ull);
-        const unsigned long long d1 = wave_sum_u64(static_cast<unsigned long long>(dwork));
-        double m1 = em;
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) m1 += __shfl_down(m1, off);
-        if (lane == 0) {
-          s_wcnt[wave][0] += f1;
-          s_wcnt[wave][1] += h1;
-          s_wcnt[wave][2] += d1;
-          s_wmass[wave] += m1;
         }
       }
       long long dinc = dwork, iinc = iwork;
@@ -630,7 +599,8 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
     }
     // (e) one draw of the run's chain
     bool emit = false;
-    int64_t arc_acc = 0;
+    uint32_t v = 0;
+    Delta delta{};
     if (active && !need_run) {
       const U4 o = philox4x32_10(t, s, u, ctr3, key0, key1);
       const double V = unit_double(o.x, o.y);
@@ -639,6 +609,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         s = run_end;
         need_run = true;
       } else {
+        ++n_cand;
         ++it_cand;
         const int64_t arc = rpu + cand;
         bool accept = true;  // a = 0: the ratio is 1 and every uniform is below it
@@ -647,23 +618,18 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
           accept = unit_double(o.z, o.w) < ratio;
         }
         if (accept) {
+          ++n_acc;
           ++it_acc;
-          arc_acc = arc;
+          v = A.col[arc];
           emit = true;
+          delta = P::theta_units(*cpp, neg);
         }
         pos = cand + 1;
         ++t;
       }
     }
-    emit_pending();  // the previous step's push
-    p_emit = emit;
-    if (emit) {
-      p_v = A.col[arc_acc];
-      p_c = c;
-      p_neg = neg;
-    }
+    emit_sampled(emit, v, c, delta, neg);
   }
-  emit_pending();
   if (sparse) stage_flush(stage, staged, A.fout, A.cnt_out);
   if (binned) {
     stage_flush_records(reinterpret_cast<uint32_t*>(stage), staged, A, acc_next);
@@ -681,12 +647,22 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       if (s_smass[i] != 0.0) atomicAdd(A.mass + i, s_smass[i]);
   }
   if (!kServe) {  // per-level counters: one atomic per wave
-    wave_sync();
+    unsigned long long* cnt = A.counters + static_cast<size_t>(A.level) * kNumCounters;
+    const unsigned long long v0 = wave_sum_u64(n_front);
+    const unsigned long long v1 = wave_sum_u64(n_hash);
+    const unsigned long long v2 = wave_sum_u64(n_det);
+    const unsigned long long v3 = wave_sum_u64(n_cand);
+    const unsigned long long v4 = wave_sum_u64(n_acc);
+    double m = mass;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m += __shfl_down(m, off);
     if (lane == 0) {
-      unsigned long long* cnt = A.counters + static_cast<size_t>(A.level) * kNumCounters;
-      for (int k = 0; k < kNumCounters; ++k)
-        if (s_wcnt[wave][k]) atomicAdd(cnt + k, s_wcnt[wave][k]);
-      if (s_wmass[wave] != 0.0) atomicAdd(A.mass + A.level, s_wmass[wave]);
+      if (v0) atomicAdd(cnt + 0, v0);
+      if (v1) atomicAdd(cnt + 1, v1);
+      if (v2) atomicAdd(cnt + 2, v2);
+      if (v3) atomicAdd(cnt + 3, v3);
+      if (v4) atomicAdd(cnt + 4, v4);
+      if (m != 0.0) atomicAdd(A.mass + A.level, m);
     }
   }
 }

@@ -44,7 +44,10 @@ HBM_PEAK_GBPS = 8000.0
 # --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) with
 # --calibrate-copy; FETCH_SIZE is scaled by the factor that makes the 1 GiB
 # copy read 1 GiB.  Valid only for the kernel sources they were taken from.
-TRAFFIC = {}
+TRAFFIC = {
+    "katz-tp": {"sources": "e5dea297369085ab", "columns": 256, "bytes_per_launch": 11759223998.0,
+                "fetch_bytes": 8113529992.0, "write_bytes": 3645694006.0},
+}
 KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
                   "paper_2106_03058_amd/csrc/propagate.hip")
 

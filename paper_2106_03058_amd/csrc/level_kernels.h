@@ -205,7 +205,7 @@ __device__ __forceinline__ void apply_record(const LevelArgs& A, Cell* acc, uint
 template <>
 __device__ __forceinline__ void apply_record<long long>(const LevelArgs& A, long long* acc, uint32_t rec) {
   const uint32_t cell = rec & kRecCellMask;
-  const uint32_t c = cell % static_cast<uint32_t>(A.su);
+  const uint32_t c = A.sc == 1 ? cell % static_cast<uint32_t>(A.su) : cell / static_cast<uint32_t>(A.sc);
   const long long d = (rec >> 31) ? -A.cp[c].dtheta : A.cp[c].dtheta;
   atomic_add_relaxed(reinterpret_cast<unsigned long long*>(acc + cell), static_cast<unsigned long long>(d));
 }

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <thread>
@@ -21,6 +22,7 @@
 #include <vector>
 
 #include "agp_internal.h"
+#include "bin_kernels.h"
 #include "level_kernels.h"
 
 namespace agp {
@@ -56,6 +58,12 @@ __global__ void k_admit(const AdmitItem* __restrict__ items, int k, long long* _
 
 __global__ void k_zero_count(unsigned long long* c) { *c = 0; }
 
+// binned steps: clear the record count and the push estimate of the step
+__global__ void k_bin_reset(unsigned long long* rec_count, double* est) {
+  *rec_count = 0;
+  *est = 0.0;
+}
+
 double now_ms(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -88,6 +96,13 @@ struct agp_server {
   // device state
   agp::DevBuf acc[2], F[2], counts, counters, mass, err, cp, admit, mode;
   int cur = 0;
+  // binned aggregation of steps with many pushes (records, bucket state)
+  bool binned = false;
+  double bin_pushes = 0.0;  // estimated pushes from which a step is binned
+  int bucket_shift = 0;
+  unsigned nbuckets = 0;
+  unsigned long long rec_cap = 0;
+  agp::DevBuf rec[2], bins;
   // host state (guarded by mu)
   std::mutex mu;
   std::condition_variable cv;
@@ -245,11 +260,41 @@ int step(agp_server* s) {
   A.positive = 1;
   A.dense_cut = std::max<unsigned long long>(1ull, static_cast<unsigned long long>(s->n) * s->S / 32);
   A.mode_out = s->mode.as<int>();
-  A.rec = nullptr;  // the server aggregates with atomics
+  A.rec = nullptr;
   A.rec_count = nullptr;
   A.rec_cap = 0;
   A.bucket_count = nullptr;
+  A.bin_est = nullptr;
+  unsigned int* bucket_count = nullptr;
+  unsigned long long *bucket_off = nullptr, *cursor = nullptr, *rec_count = nullptr;
+  if (s->binned) {  // records when the step's estimated pushes reach bin_pushes
+    bucket_count = s->bins.as<unsigned int>();
+    bucket_off = reinterpret_cast<unsigned long long*>(bucket_count + kBuckets);
+    cursor = bucket_off + kBuckets + 1;
+    rec_count = cursor + kBuckets;
+    double* est = reinterpret_cast<double*>(rec_count + 1);
+    A.rec = s->rec[0].as<uint32_t>();
+    A.rec_count = rec_count;
+    A.rec_cap = s->rec_cap;
+    A.bucket_count = bucket_count;
+    A.bucket_shift = s->bucket_shift;
+    A.bin_est = est;
+    A.bin_pushes = s->bin_pushes;
+    k_bin_reset<<<1, 1, 0, st>>>(rec_count, est);
+    k_estimate<float, false><<<1024, kThreads, 0, st>>>(A, nullptr, acc[cur], est);
+  }
   k_level<float, false, true><<<kLevelBlocks, kThreads, 0, st>>>(A, nullptr, acc[cur], acc[nxt]);
+  if (s->binned) {
+    uint32_t* r0 = s->rec[0].as<uint32_t>();
+    uint32_t* r1 = s->rec[1].as<uint32_t>();
+    int* mode = s->mode.as<int>();
+    k_bins_scan<<<1, kBuckets, 0, st>>>(bucket_count, bucket_off, cursor, rec_count, s->rec_cap, mode);
+    k_apply_overflow<<<2048, kThreads, 0, st>>>(A, acc[nxt], mode);
+    k_partition<<<1024, kReduceThreads, 0, st>>>(r0, rec_count, cursor, r1, mode, s->bucket_shift);
+    k_bin_reduce<<<s->nbuckets, kReduceThreads, 0, st>>>(r1, r0, bucket_off, A.cp, s->S, 1ll, (long long)s->n,
+                                                         static_cast<unsigned long long>(s->n) * s->S, acc[nxt],
+                                                         F[nxt], counts + nxt, mode, s->bucket_shift);
+  }
   k_compact<<<grid_for(s->n * (int64_t)s->S, kThreads, 8192), kThreads, 0, st>>>(
       NonZeroCell<float>{acc[nxt]}, s->n, s->S, 1ll, (long long)s->n, F[nxt], counts + nxt, s->mode.as<int>());
   AGP_HIP(hipGetLastError());
@@ -366,6 +411,35 @@ int agp_server_create(const agp_graph_t* g, const agp_server_config_t* cfg, agp_
         (rc = s->mode.reserve(sizeof(int), true, s->stream))) {
     }
   }
+  // Binned aggregation for steps with many pushes (cells addressable in 31
+  // bits); AGP_AGGREGATION=atomic turns it off, =binned bins every step.
+  if (!rc && cells > 0 && cells < (1ull << 31) && s->S <= lvl::kMaxBinnedC) {
+    const char* agg = std::getenv("AGP_AGGREGATION");
+    if (!(agg && std::strcmp(agg, "atomic") == 0)) {
+      // a binned step costs about one pass over the cells; the server's
+      // sparse steps run returning atomics, so records pay off from n S / 64
+      s->bin_pushes = (agg && std::strcmp(agg, "binned") == 0) ? 0.0 : static_cast<double>(cells) / 64.0;
+      int shift = lvl::kBinLog2;
+      while ((static_cast<unsigned long long>(cells) - 1ull) >> shift >= (unsigned long long)lvl::kBuckets) ++shift;
+      s->bucket_shift = shift;
+      s->nbuckets = static_cast<unsigned>((static_cast<unsigned long long>(cells) - 1ull) >> shift) + 1u;
+      size_t free_b = 0, total_b = 0;
+      (void)hipMemGetInfo(&free_b, &total_b);
+      s->rec_cap = std::max<unsigned long long>(1ull << 20, 4ull * cells);
+      s->rec_cap = std::min<unsigned long long>(s->rec_cap, std::max<unsigned long long>(1ull << 20, free_b / 64));
+      if (s->rec[0].reserve(s->rec_cap * sizeof(uint32_t), false, s->stream) ||
+          s->rec[1].reserve(s->rec_cap * sizeof(uint32_t), false, s->stream) ||
+          s->bins.reserve(sizeof(unsigned int) * lvl::kBuckets + sizeof(unsigned long long) * (2 * lvl::kBuckets + 2) +
+                              sizeof(double), true, s->stream)) {
+        s->rec[0].release();  // not enough memory for the records: atomics only
+        s->rec[1].release();
+        s->bins.release();
+        (void)hipGetLastError();
+      } else {
+        s->binned = true;
+      }
+    }
+  }
   if (!rc) {
     if (hipHostMalloc(reinterpret_cast<void**>(&s->h_cp), sizeof(ColParams) * s->S) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&s->h_admit), sizeof(srv::AdmitItem) * s->S) != hipSuccess ||
@@ -447,7 +521,7 @@ int agp_server_destroy(agp_server_t* s) {
   if (s->worker.joinable()) s->worker.join();
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   for (auto* b : {&s->acc[0], &s->acc[1], &s->F[0], &s->F[1], &s->counts, &s->counters, &s->mass, &s->err,
-                  &s->cp, &s->admit, &s->mode})
+                  &s->cp, &s->admit, &s->mode, &s->rec[0], &s->rec[1], &s->bins})
     b->release();
   if (s->h_cp) (void)hipHostFree(s->h_cp);
   if (s->h_admit) (void)hipHostFree(s->h_admit);

@@ -150,3 +150,20 @@ def test_queue_full_is_ebusy(env):
             busy += 1
     assert busy > 0
     srv.close()  # finishes the running query, drops the queued ones
+
+
+def test_aggregation_modes_serve_the_same_bits(env, monkeypatch):
+    """Served queries give the oracle's bits whether the server's steps use
+    atomics only, records on every step, or records on heavy steps only."""
+    torch, agp, g, G, sg, lam = env
+    qs = _mix(g, lam, 9, seed=4)
+    for mode in ("atomic", "binned", None):
+        monkeypatch.delenv("AGP_AGGREGATION", raising=False)
+        if mode:
+            monkeypatch.setenv("AGP_AGGREGATION", mode)
+        outs, res = _serve(torch, agp, G, qs, slots=4)
+        for q, o, r in zip(qs, outs, res):
+            ref, cnt = _oracle_one(g, sg, q)
+            assert r["status"] == agp.AGP_OK
+            assert np.array_equal(o, ref), f"{mode}: query {q['qid']}"
+            assert r["pushes"] == int(cnt["det"].sum() + cnt["acc"].sum())

@@ -15,10 +15,10 @@ namespace {
 
 // ------------------------------------------------ binned aggregation
 // After a binned level: bucket offsets (one block), then the records are
-// partitioned into buckets, and one block per bucket splits its bucket into
-// bins of 8192 cells, counts the signed records of every bin in LDS, adds
-// count * fl(theta_c) in units to each cell (the deterministic pushes are
-// already there: integer sums, so the order is irrelevant) and appends every
+// partitioned into buckets, then into bins of 8192 cells, and one block per
+// bin counts the signed records of every cell in LDS, adds count *
+// fl(theta_c) in units to each cell (the deterministic pushes are already
+// there: integer sums, so the order is irrelevant) and appends every
 // non-zero cell to the next frontier.
 constexpr int kMaxBinnedC = 1024;
 constexpr int kReduceThreads = 512;
@@ -152,146 +152,252 @@ __global__ __launch_bounds__(kReduceThreads) void k_partition(const uint32_t* __
   }
 }
 
-// Reduce tiles: 8192 records (the LDS buffer doubles as one bin's counts).
-constexpr int kRedPerThread = 16;
-constexpr int kRedTile = kReduceThreads * kRedPerThread;
+// ---------------------------------------------------------- bins
+// Second level: the bucket-ordered records are counted per bin (8192 cells),
+// scattered into bin order with LDS-sorted tiles, and every bin is summed by
+// its own block.  A tile's bins lie in the one or two buckets it overlaps
+// (records are bucket-sorted); bins outside that window take a global atomic
+// per record, so any record order stays correct.
+constexpr int kBinTile = 8192;                    // records per tile
+constexpr int kBinPerThread = kBinTile / kReduceThreads;
+constexpr int kBinWindow = 2 * kMaxBinsPerBucket;  // bins a tile counts in LDS
 
-__global__ __launch_bounds__(kReduceThreads) void k_bin_reduce(const uint32_t* __restrict__ part,
-                                                               uint32_t* __restrict__ tmp,
-                                                               const unsigned long long* __restrict__ bucket_off,
-                                                               const ColParams* __restrict__ cp, int C,
-                                                               long long su, long long sc, unsigned long long cells,
-                                                               long long* __restrict__ acc, uint64_t* __restrict__ F,
-                                                               unsigned long long* __restrict__ cnt,
-                                                               const int* __restrict__ mode, int shift) {
+__device__ __forceinline__ unsigned long long bin_of(uint32_t rec) {
+  return static_cast<unsigned long long>(rec & kRecCellMask) >> kBinLog2;
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_bin_count(const uint32_t* __restrict__ part,
+                                                              const unsigned long long* __restrict__ rec_count,
+                                                              unsigned long long* __restrict__ bin_count,
+                                                              const int* __restrict__ mode, int shift) {
+  if (*mode != kModeBinned) return;
+  __shared__ unsigned int s_h[kBinWindow];
+  const unsigned long long total = *rec_count;
+  const unsigned long long bpb = 1ull << (shift - kBinLog2);  // bins per bucket
+  for (unsigned long long lo = (unsigned long long)blockIdx.x * kBinTile; lo < total;
+       lo += (unsigned long long)gridDim.x * kBinTile) {
+    const unsigned long long w0 = (bin_of(part[lo]) / bpb) * bpb;  // first bin of the tile's first bucket
+    for (int i = threadIdx.x; i < kBinWindow; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    uint32_t r[kBinPerThread];
+#pragma unroll
+    for (int k = 0; k < kBinPerThread; ++k) {
+      const unsigned long long i = lo + (unsigned long long)(k * kReduceThreads + threadIdx.x);
+      r[k] = i < total ? part[i] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kBinPerThread; ++k) {
+      const unsigned long long i = lo + (unsigned long long)(k * kReduceThreads + threadIdx.x);
+      if (i < total) {
+        const unsigned long long gb = bin_of(r[k]);
+        if (gb >= w0 && gb - w0 < (unsigned long long)kBinWindow)
+          atomicAdd(&s_h[gb - w0], 1u);
+        else
+          atomicAdd(bin_count + gb, 1ull);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBinWindow; i += blockDim.x)
+      if (s_h[i]) atomicAdd(bin_count + w0 + i, static_cast<unsigned long long>(s_h[i]));
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of the bin counts (one block); clears the counts for the
+// next level and sets the scatter cursors.
+__global__ __launch_bounds__(1024) void k_bin_scan(unsigned long long* __restrict__ bin_count, long long nbins,
+                                                   unsigned long long* __restrict__ bin_off,
+                                                   unsigned long long* __restrict__ bin_cur,
+                                                   const int* __restrict__ mode) {
+  if (*mode != kModeBinned) return;
+  __shared__ unsigned long long s[1024];
+  const long long per = (nbins + 1023) / 1024;
+  const long long b0 = threadIdx.x * per;
+  const long long b1 = b0 + per < nbins ? b0 + per : nbins;
+  unsigned long long run = 0;
+  for (long long b = b0; b < b1; ++b) run += bin_count[b];
+  s[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const unsigned long long add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0ull;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  unsigned long long acc = s[threadIdx.x] - run;
+  for (long long b = b0; b < b1; ++b) {
+    const unsigned long long v = bin_count[b];
+    bin_off[b] = acc;
+    bin_cur[b] = acc;
+    bin_count[b] = 0;
+    acc += v;
+  }
+  if (threadIdx.x == 1023) bin_off[nbins] = s[1023];
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_bin_scatter(const uint32_t* __restrict__ part,
+                                                                const unsigned long long* __restrict__ rec_count,
+                                                                unsigned long long* __restrict__ bin_cur,
+                                                                uint32_t* __restrict__ out,
+                                                                const int* __restrict__ mode, int shift) {
+  if (*mode != kModeBinned) return;
+  __shared__ uint32_t s_rec[kBinTile];
+  __shared__ unsigned int s_h[kBinWindow];
+  __shared__ unsigned int s_loc[kBinWindow];
+  __shared__ unsigned long long s_base[kBinWindow];
+  __shared__ unsigned int s_wsum[kReduceThreads / kWave];
+  const unsigned long long total = *rec_count;
+  const unsigned long long bpb = 1ull << (shift - kBinLog2);
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  for (unsigned long long lo = (unsigned long long)blockIdx.x * kBinTile; lo < total;
+       lo += (unsigned long long)gridDim.x * kBinTile) {
+    const unsigned long long w0 = (bin_of(part[lo]) / bpb) * bpb;
+    for (int i = threadIdx.x; i < kBinWindow; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    uint32_t r[kBinPerThread];
+    unsigned int rank[kBinPerThread];
+#pragma unroll
+    for (int k = 0; k < kBinPerThread; ++k) {
+      const unsigned long long i = lo + (unsigned long long)(k * kReduceThreads + threadIdx.x);
+      r[k] = i < total ? part[i] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kBinPerThread; ++k) {
+      const unsigned long long i = lo + (unsigned long long)(k * kReduceThreads + threadIdx.x);
+      rank[k] = 0xFFFFFFFFu;
+      if (i < total) {
+        const unsigned long long gb = bin_of(r[k]);
+        if (gb >= w0 && gb - w0 < (unsigned long long)kBinWindow)
+          rank[k] = atomicAdd(&s_h[gb - w0], 1u);
+        else  // outside the window: a slot of its own
+          out[atomicAdd(bin_cur + gb, 1ull)] = r[k];
+      }
+    }
+    __syncthreads();
+    {  // exclusive scan of the window's counts, 4 per thread
+      constexpr int kPer = kBinWindow / kReduceThreads;
+      unsigned int x[kPer];
+      unsigned int run = 0;
+      for (int k = 0; k < kPer; ++k) {
+        x[k] = s_h[threadIdx.x * kPer + k];
+        run += x[k];
+      }
+      unsigned int incl = run;
+      for (int off = 1; off < kWave; off <<= 1) {
+        const unsigned int t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+      }
+      if (lane == kWave - 1) s_wsum[wave] = incl;
+      __syncthreads();
+      unsigned int acc0 = 0;
+      for (int w = 0; w < wave; ++w) acc0 += s_wsum[w];
+      acc0 += incl - run;
+      for (int k = 0; k < kPer; ++k) {
+        s_loc[threadIdx.x * kPer + k] = acc0;
+        acc0 += x[k];
+      }
+    }
+    for (int i = threadIdx.x; i < kBinWindow; i += blockDim.x) {
+      const unsigned int h = s_h[i];
+      s_base[i] = h ? atomicAdd(bin_cur + w0 + i, static_cast<unsigned long long>(h)) : 0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kBinPerThread; ++k)
+      if (rank[k] != 0xFFFFFFFFu) s_rec[s_loc[bin_of(r[k]) - w0] + rank[k]] = r[k];
+    __syncthreads();
+    const int nin = static_cast<int>(s_loc[kBinWindow - 1] + s_h[kBinWindow - 1]);  // records in the window
+    for (int i = threadIdx.x; i < nin; i += blockDim.x) {  // runs of one bin are contiguous
+      const uint32_t x = s_rec[i];
+      const unsigned long long j = bin_of(x) - w0;
+      out[s_base[j] + static_cast<unsigned long long>(i - static_cast<int>(s_loc[j]))] = x;
+    }
+    __syncthreads();
+  }
+}
+
+// One block per bin: signed record counts in LDS, then each cell's new value
+// acc += count * fl(theta_c) (its deterministic pushes are already in acc);
+// the bin's non-zero cells are gathered in LDS and appended to the next
+// frontier with one atomic per bin.
+constexpr int kSumThreads = 256;
+
+__global__ __launch_bounds__(kSumThreads) void k_bin_sum(const uint32_t* __restrict__ tmp,
+                                                         const unsigned long long* __restrict__ bin_off,
+                                                         const ColParams* __restrict__ cp, long long su, long long sc,
+                                                         unsigned long long cells, long long* __restrict__ acc,
+                                                         uint64_t* __restrict__ F, unsigned long long* __restrict__ cnt,
+                                                         const int* __restrict__ mode) {
   if (*mode != kModeBinned) return;
   constexpr int kBin = 1 << kBinLog2;
-  static_assert(kBin <= kRedTile, "bin counts share the tile buffer");
-  const int kBinsPer = 1 << (shift - kBinLog2);  // <= kBuckets
-  __shared__ uint32_t s_buf[kRedTile];           // a tile of records, or the counts of one bin
-  __shared__ unsigned int s_cur[kBuckets];       // per bin: count, then next free slot in tmp
-  __shared__ unsigned int s_off[kBuckets + 1];   // per bin: first slot in tmp
-  __shared__ unsigned int s_lh[kBuckets];        // per bin: records in the tile
-  __shared__ unsigned int s_lo[kBuckets];        // per bin: first slot in the sorted tile
-  __shared__ unsigned int s_gb[kBuckets];        // per bin: tile's first slot in tmp
-  __shared__ long long s_dth[kMaxBinnedC];
-  __shared__ uint64_t s_stage[kReduceThreads / kWave][kStage / 2];
-  __shared__ unsigned int s_wsum[kReduceThreads / kWave];
-  int* s_cnt = reinterpret_cast<int*>(s_buf);
-  uint64_t* stage = s_stage[threadIdx.x / kWave];
-  int staged = 0;
-  for (int c = threadIdx.x; c < C; c += blockDim.x) s_dth[c] = cp[c].dtheta;
-  const unsigned long long nbuckets = ((cells - 1) >> shift) + 1;
-  for (unsigned long long b = blockIdx.x; b < nbuckets; b += gridDim.x) {
-    const unsigned long long lo = bucket_off[b], hi = bucket_off[b + 1];
-    for (int f = threadIdx.x; f < kBuckets; f += blockDim.x) s_cur[f] = 0;
-    __syncthreads();
-    // bin sizes of the bucket
-    for (unsigned long long i0 = lo + (unsigned long long)threadIdx.x * kBatchLoads; i0 < hi;
-         i0 += (unsigned long long)blockDim.x * kBatchLoads) {
-      uint32_t r[kBatchLoads];
+  __shared__ int s_cnt[kBin];
+  __shared__ uint16_t s_nz[kBin];  // non-zero cells of the bin, as offsets
+  __shared__ unsigned int s_n;
+  __shared__ unsigned long long s_base;
+  const int lane = lane_id();
+  const unsigned long long gb = blockIdx.x;
+  const unsigned long long cell0 = gb << kBinLog2;
+  for (int j = threadIdx.x; j < kBin; j += blockDim.x) s_cnt[j] = 0;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  const unsigned long long lo = bin_off[gb], hi = bin_off[gb + 1];
+  for (unsigned long long i0 = lo + threadIdx.x; i0 < hi; i0 += (unsigned long long)blockDim.x * 8) {
+    uint32_t rr[8];
 #pragma unroll
-      for (int k = 0; k < kBatchLoads; ++k) r[k] = (i0 + k < hi) ? part[i0 + k] : 0u;
-#pragma unroll
-      for (int k = 0; k < kBatchLoads; ++k)
-        if (i0 + k < hi) atomicAdd(&s_cur[((r[k] & kRecCellMask) >> kBinLog2) & (kBinsPer - 1)], 1u);
+    for (int k = 0; k < 8; ++k) {
+      const unsigned long long i = i0 + (unsigned long long)k * blockDim.x;
+      rr[k] = i < hi ? tmp[i] : 0u;
     }
-    __syncthreads();
-    const unsigned int nrec = block_scan_1024(s_cur, s_off, s_wsum);
-    if (threadIdx.x == 0) s_off[kBuckets] = nrec;
-    for (int f = threadIdx.x; f < kBuckets; f += blockDim.x) s_cur[f] = s_off[f];
-    __syncthreads();
-    // records into bin order in tmp, one LDS-sorted tile at a time
-    for (unsigned long long t0 = lo; t0 < hi; t0 += kRedTile) {
-      const int nt = static_cast<int>(hi - t0 < (unsigned long long)kRedTile ? hi - t0 : kRedTile);
-      for (int f = threadIdx.x; f < kBuckets; f += blockDim.x) s_lh[f] = 0;
-      __syncthreads();
-      uint32_t r[kRedPerThread];
-      unsigned int rank[kRedPerThread];
 #pragma unroll
-      for (int k = 0; k < kRedPerThread; ++k) {
-        const int i = k * kReduceThreads + threadIdx.x;
-        r[k] = i < nt ? part[t0 + i] : 0u;
-      }
+    for (int k = 0; k < 8; ++k)
+      if (i0 + (unsigned long long)k * blockDim.x < hi) atomicAdd(&s_cnt[rr[k] & (kBin - 1)], (rr[k] >> 31) ? -1 : 1);
+  }
+  __syncthreads();
+  constexpr int kCellsPer = kBin / kSumThreads;
+  for (int k0 = 0; k0 < kCellsPer; k0 += 8) {
+    long long vv[8];
 #pragma unroll
-      for (int k = 0; k < kRedPerThread; ++k) {
-        const int i = k * kReduceThreads + threadIdx.x;
-        rank[k] = i < nt ? atomicAdd(&s_lh[((r[k] & kRecCellMask) >> kBinLog2) & (kBinsPer - 1)], 1u) : 0u;
-      }
-      __syncthreads();
-      block_scan_1024(s_lh, s_lo, s_wsum);
-      for (int f = threadIdx.x; f < kBuckets; f += blockDim.x) {
-        const unsigned int h = s_lh[f];
-        s_gb[f] = h ? atomicAdd(&s_cur[f], h) : 0u;
-      }
-#pragma unroll
-      for (int k = 0; k < kRedPerThread; ++k) {
-        const int i = k * kReduceThreads + threadIdx.x;
-        if (i < nt) s_buf[s_lo[((r[k] & kRecCellMask) >> kBinLog2) & (kBinsPer - 1)] + rank[k]] = r[k];
-      }
-      __syncthreads();
-      for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-        const uint32_t x = s_buf[i];
-        const unsigned int f = ((x & kRecCellMask) >> kBinLog2) & (kBinsPer - 1);
-        tmp[lo + s_gb[f] + static_cast<unsigned int>(i - static_cast<int>(s_lo[f]))] = x;
-      }
-      __syncthreads();
+    for (int k = 0; k < 8; ++k) {
+      const unsigned long long cell = cell0 + static_cast<unsigned long long>((k0 + k) * kSumThreads + threadIdx.x);
+      vv[k] = cell < cells ? acc[cell] : 0ll;
     }
-    // every bin: signed record counts in LDS, then each cell's new value
-    for (int f = 0; f < kBinsPer; ++f) {
-      const unsigned long long cell0 = (b << shift) | (static_cast<unsigned long long>(f) << kBinLog2);
-      if (cell0 >= cells) break;  // uniform per block
-      for (int j = threadIdx.x; j < kBin; j += blockDim.x) s_cnt[j] = 0;
-      __syncthreads();
-      const unsigned long long blo = lo + s_off[f], bhi = lo + s_off[f + 1];
-      // loads in flight per thread: 16 records, then 16 cells
-      for (unsigned long long i0 = blo + threadIdx.x; i0 < bhi; i0 += (unsigned long long)blockDim.x * 16) {
-        uint32_t rr[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const unsigned long long i = i0 + (unsigned long long)k * blockDim.x;
-          rr[k] = i < bhi ? tmp[i] : 0u;
+    for (int k = 0; k < 8; ++k) {
+      const int j = (k0 + k) * kSumThreads + threadIdx.x;
+      const unsigned long long cell = cell0 + static_cast<unsigned long long>(j);
+      long long v = vv[k];
+      if (cell < cells) {
+        const int kc = s_cnt[j];
+        if (kc != 0) {
+          const uint32_t c = sc == 1 ? static_cast<uint32_t>(cell % static_cast<unsigned long long>(su))
+                                     : static_cast<uint32_t>(cell / static_cast<unsigned long long>(sc));
+          v += static_cast<long long>(kc) * cp[c].dtheta;
+          acc[cell] = v;
         }
-#pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (i0 + (unsigned long long)k * blockDim.x < bhi)
-            atomicAdd(&s_cnt[rr[k] & (kBin - 1)], (rr[k] >> 31) ? -1 : 1);
       }
-      __syncthreads();
-      constexpr int kCellsPer = kBin / kReduceThreads;
-      long long vv[kCellsPer];
-#pragma unroll
-      for (int k = 0; k < kCellsPer; ++k) {
-        const unsigned long long cell = cell0 + static_cast<unsigned long long>(k * kReduceThreads + threadIdx.x);
-        vv[k] = cell < cells ? acc[cell] : 0ll;
-      }
-#pragma unroll
-      for (int k = 0; k < kCellsPer; ++k) {  // wave-uniform
-        const int j = k * kReduceThreads + threadIdx.x;
-        const unsigned long long cell = cell0 + static_cast<unsigned long long>(j);
-        const bool valid = cell < cells;
-        long long v = vv[k];
-        uint32_t u = 0, c = 0;
-        if (valid) {
-          if (sc == 1) {  // row-major: cell = u * C + c
-            u = static_cast<uint32_t>(cell / static_cast<unsigned long long>(su));
-            c = static_cast<uint32_t>(cell - static_cast<unsigned long long>(u) * su);
-          } else {  // one n-vector per column: cell = c * n + u
-            c = static_cast<uint32_t>(cell / static_cast<unsigned long long>(sc));
-            u = static_cast<uint32_t>(cell - static_cast<unsigned long long>(c) * sc);
-          }
-          const int kc = s_cnt[j];
-          if (kc != 0) {
-            v += static_cast<long long>(kc) * s_dth[c];
-            acc[cell] = v;
-          }
-        }
-        stage_push<kStage / 2>(stage, staged, (static_cast<uint64_t>(u) << 32) | c, valid && v != 0, F, cnt);
-      }
-      __syncthreads();
+      const unsigned long long m = __ballot(v != 0);
+      unsigned int base = 0;
+      if (lane == 0 && m) base = atomicAdd(&s_n, static_cast<unsigned int>(__popcll(m)));
+      base = __shfl(base, 0);
+      if (v != 0) s_nz[base + __popcll(m & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(j);
     }
   }
-  stage_flush(stage, staged, F, cnt);
+  __syncthreads();
+  const unsigned int total = s_n;
+  if (threadIdx.x == 0 && total) s_base = atomicAdd(cnt, static_cast<unsigned long long>(total));
+  __syncthreads();
+  for (unsigned int i = threadIdx.x; i < total; i += blockDim.x) {
+    const unsigned long long cell = cell0 + s_nz[i];
+    uint32_t u, c;
+    if (sc == 1) {  // row-major: cell = u * C + c
+      u = static_cast<uint32_t>(cell / static_cast<unsigned long long>(su));
+      c = static_cast<uint32_t>(cell - static_cast<unsigned long long>(u) * su);
+    } else {  // one n-vector per column: cell = c * n + u
+      c = static_cast<uint32_t>(cell / static_cast<unsigned long long>(sc));
+      u = static_cast<uint32_t>(cell - static_cast<unsigned long long>(c) * sc);
+    }
+    F[s_base + i] = (static_cast<uint64_t>(u) << 32) | c;
+  }
 }
 
 }  // namespace

@@ -197,7 +197,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   // buckets of 2^shift cells: at most 1024 buckets, bins of 8192 cells
   int shift = kBinLog2;
   while (shift < 32 && (static_cast<unsigned long long>(cells) - 1ull) >> shift >= (unsigned long long)kBuckets) ++shift;
-  const unsigned nbuckets = static_cast<unsigned>(((cells > 0 ? cells : 1) - 1) >> shift) + 1u;
+  const long long nbins = static_cast<long long>(((cells > 0 ? cells : 1) - 1) >> kBinLog2) + 1;
   unsigned long long rec_cap = 0;
   if (binned) {
     // room for 4 records per cell, within an eighth of the free memory (two buffers)
@@ -212,7 +212,8 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     if (sc.rec[0].reserve(rec_cap * sizeof(uint32_t), false, s) ||
         sc.rec[1].reserve(rec_cap * sizeof(uint32_t), false, s) ||
         sc.bins.reserve(sizeof(unsigned int) * kBuckets + sizeof(unsigned long long) * (2 * kBuckets + 1) +
-                            sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1), true, s)) {
+                            sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1) +
+                            sizeof(unsigned long long) * (3 * nbins + 1), true, s)) {
       sc.rec[0].release();  // not enough memory for the record buffers: atomics instead
       sc.rec[1].release();
       binned = false;
@@ -223,7 +224,13 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   unsigned long long* bucket_off = binned ? reinterpret_cast<unsigned long long*>(bucket_count + kBuckets) : nullptr;
   unsigned long long* cursor = binned ? bucket_off + kBuckets + 1 : nullptr;
   unsigned long long* rec_counts = binned ? cursor + kBuckets : nullptr;
-  if (binned) AGP_HIP(hipMemsetAsync(rec_counts, 0, sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1), s));
+  unsigned long long* bin_count = binned ? rec_counts + AGP_MAX_LEVELS + 1 : nullptr;
+  unsigned long long* bin_off = binned ? bin_count + nbins : nullptr;
+  unsigned long long* bin_cur = binned ? bin_off + nbins + 1 : nullptr;
+  if (binned) {
+    AGP_HIP(hipMemsetAsync(rec_counts, 0, sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1), s));
+    AGP_HIP(hipMemsetAsync(bin_count, 0, sizeof(unsigned long long) * nbins, s));
+  }
 
   hipEvent_t* ev = sc.events;
   if (stats && (rc = sc.ensure_events())) return rc;
@@ -289,10 +296,12 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
       k_bins_scan<<<1, kBuckets, 0, s>>>(bucket_count, bucket_off, cursor, rec_counts + i, rec_cap, mode + i + 1);
       k_apply_overflow<<<2048, kThreads, 0, s>>>(A, reinterpret_cast<long long*>(nxt), mode + i + 1);
       k_partition<<<1024, kReduceThreads, 0, s>>>(r0, rec_counts + i, cursor, r1, mode + i + 1, shift);
-      k_bin_reduce<<<nbuckets, kReduceThreads, 0, s>>>(r1, r0, bucket_off, cp, C, (long long)C, 1ll,
-                                                       static_cast<unsigned long long>(cells),
-                                                       reinterpret_cast<long long*>(nxt), F[(i + 1) & 1],
-                                                       counts + i + 1, mode + i + 1, shift);
+      k_bin_count<<<2048, kReduceThreads, 0, s>>>(r1, rec_counts + i, bin_count, mode + i + 1, shift);
+      k_bin_scan<<<1, 1024, 0, s>>>(bin_count, nbins, bin_off, bin_cur, mode + i + 1);
+      k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(r1, rec_counts + i, bin_cur, r0, mode + i + 1, shift);
+      k_bin_sum<<<static_cast<unsigned>(nbins), kSumThreads, 0, s>>>(
+          r0, bin_off, cp, (long long)C, 1ll, static_cast<unsigned long long>(cells),
+          reinterpret_cast<long long*>(nxt), F[(i + 1) & 1], counts + i + 1, mode + i + 1);
     }
     if (i < L)
       k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, (long long)C, 1ll, F[(i + 1) & 1],

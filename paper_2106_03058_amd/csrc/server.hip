@@ -100,7 +100,7 @@ struct agp_server {
   bool binned = false;
   double bin_pushes = 0.0;  // estimated pushes from which a step is binned
   int bucket_shift = 0;
-  unsigned nbuckets = 0;
+  long long nbins = 0;
   unsigned long long rec_cap = 0;
   agp::DevBuf rec[2], bins;
   // host state (guarded by mu)
@@ -267,12 +267,16 @@ int step(agp_server* s) {
   A.bin_est = nullptr;
   unsigned int* bucket_count = nullptr;
   unsigned long long *bucket_off = nullptr, *cursor = nullptr, *rec_count = nullptr;
+  unsigned long long *bin_count = nullptr, *bin_off = nullptr, *bin_cur = nullptr;
   if (s->binned) {  // records when the step's estimated pushes reach bin_pushes
     bucket_count = s->bins.as<unsigned int>();
     bucket_off = reinterpret_cast<unsigned long long*>(bucket_count + kBuckets);
     cursor = bucket_off + kBuckets + 1;
     rec_count = cursor + kBuckets;
     double* est = reinterpret_cast<double*>(rec_count + 1);
+    bin_count = reinterpret_cast<unsigned long long*>(est + 1);
+    bin_off = bin_count + s->nbins;
+    bin_cur = bin_off + s->nbins + 1;
     A.rec = s->rec[0].as<uint32_t>();
     A.rec_count = rec_count;
     A.rec_cap = s->rec_cap;
@@ -291,9 +295,12 @@ int step(agp_server* s) {
     k_bins_scan<<<1, kBuckets, 0, st>>>(bucket_count, bucket_off, cursor, rec_count, s->rec_cap, mode);
     k_apply_overflow<<<2048, kThreads, 0, st>>>(A, acc[nxt], mode);
     k_partition<<<1024, kReduceThreads, 0, st>>>(r0, rec_count, cursor, r1, mode, s->bucket_shift);
-    k_bin_reduce<<<s->nbuckets, kReduceThreads, 0, st>>>(r1, r0, bucket_off, A.cp, s->S, 1ll, (long long)s->n,
-                                                         static_cast<unsigned long long>(s->n) * s->S, acc[nxt],
-                                                         F[nxt], counts + nxt, mode, s->bucket_shift);
+    k_bin_count<<<2048, kReduceThreads, 0, st>>>(r1, rec_count, bin_count, mode, s->bucket_shift);
+    k_bin_scan<<<1, 1024, 0, st>>>(bin_count, s->nbins, bin_off, bin_cur, mode);
+    k_bin_scatter<<<2048, kReduceThreads, 0, st>>>(r1, rec_count, bin_cur, r0, mode, s->bucket_shift);
+    k_bin_sum<<<static_cast<unsigned>(s->nbins), kSumThreads, 0, st>>>(
+        r0, bin_off, A.cp, 1ll, (long long)s->n, static_cast<unsigned long long>(s->n) * s->S, acc[nxt], F[nxt],
+        counts + nxt, mode);
   }
   k_compact<<<grid_for(s->n * (int64_t)s->S, kThreads, 8192), kThreads, 0, st>>>(
       NonZeroCell<float>{acc[nxt]}, s->n, s->S, 1ll, (long long)s->n, F[nxt], counts + nxt, s->mode.as<int>());
@@ -422,7 +429,7 @@ int agp_server_create(const agp_graph_t* g, const agp_server_config_t* cfg, agp_
       int shift = lvl::kBinLog2;
       while ((static_cast<unsigned long long>(cells) - 1ull) >> shift >= (unsigned long long)lvl::kBuckets) ++shift;
       s->bucket_shift = shift;
-      s->nbuckets = static_cast<unsigned>((static_cast<unsigned long long>(cells) - 1ull) >> shift) + 1u;
+      s->nbins = static_cast<long long>((static_cast<unsigned long long>(cells) - 1ull) >> lvl::kBinLog2) + 1;
       size_t free_b = 0, total_b = 0;
       (void)hipMemGetInfo(&free_b, &total_b);
       s->rec_cap = std::max<unsigned long long>(1ull << 20, 4ull * cells);
@@ -430,7 +437,7 @@ int agp_server_create(const agp_graph_t* g, const agp_server_config_t* cfg, agp_
       if (s->rec[0].reserve(s->rec_cap * sizeof(uint32_t), false, s->stream) ||
           s->rec[1].reserve(s->rec_cap * sizeof(uint32_t), false, s->stream) ||
           s->bins.reserve(sizeof(unsigned int) * lvl::kBuckets + sizeof(unsigned long long) * (2 * lvl::kBuckets + 2) +
-                              sizeof(double), true, s->stream)) {
+                              sizeof(double) + sizeof(unsigned long long) * (3 * s->nbins + 1), true, s->stream)) {
         s->rec[0].release();  // not enough memory for the records: atomics only
         s->rec[1].release();
         s->bins.release();

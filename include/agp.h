@@ -52,6 +52,9 @@ extern "C" {
 #define AGP_HOST_PTRS 1u      /* row_ptr / col_idx are host pointers (else device)   */
 #define AGP_VALIDATE 2u       /* also check: no duplicate arcs, symmetric matrix          */
 #define AGP_ADD_SELF_LOOPS 4u /* give every node exactly one self-loop (GNN convention) */
+#define AGP_DIRECTED 8u       /* row u lists the out-neighbours of u in a directed graph;
+                                 pushes follow out-edges (A~ = A^T) */
+#define AGP_REVERSE 16u       /* with AGP_DIRECTED: pushes follow in-edges (A~ = A) */
 
 /* Largest supported number of levels L (the level index is 8 bits of the
  * random stream counter). */
@@ -86,30 +89,44 @@ const char* agp_last_error(void);
 /* ------------------------------------------------------------------ graphs */
 
 /* Build the library's graph from a CSR matrix (Section 2: G = (V, E)
- * undirected; Section 4: adjacency lists pre-sorted by degree).
+ * undirected; Section 4: adjacency lists pre-sorted by degree; Section 4,
+ * propagation on directed graphs).
  *  n        number of nodes, 0 <= n < 2^31
  *  nnz      number of stored arcs, row_ptr[n]; an undirected edge is stored
  *           in both rows
  *  row_ptr  int64[n + 1], non-decreasing, row_ptr[0] = 0
  *  col_idx  int32[nnz], neighbour ids in [0, n)
- *  flags    AGP_HOST_PTRS | AGP_VALIDATE | AGP_ADD_SELF_LOOPS
+ *  flags    AGP_HOST_PTRS | AGP_VALIDATE | AGP_ADD_SELF_LOOPS |
+ *           AGP_DIRECTED | AGP_REVERSE
  *  stream   stream for the build; the call is synchronous on it
  *  out      receives the graph handle
+ * Undirected (default): the matrix must be symmetric; d = row length.
+ * AGP_DIRECTED: row u holds the out-neighbours of u; propagation computes
+ * sum_i w_i (D^-a A^T D^-b)^i x (PPR, HKPR, Katz on directed graphs), i.e.
+ * pushes follow out-edges; D holds the out-degrees.  With AGP_REVERSE the
+ * pushes follow in-edges, sum_i w_i (D^-a A D^-b)^i x (single-target
+ * proximity); the library transposes the matrix itself.  A node without
+ * out-arcs counts as out-degree 1 in D.
  * The library copies the arrays; the caller may free them on return.  Inside
- * the handle every row is sorted ascending by (degree of neighbour, id).
- * Errors: AGP_EINVAL for bad sizes, ids out of range, or (with AGP_VALIDATE)
- * duplicate arcs or an asymmetric matrix; AGP_ENOMEM; AGP_EDEVICE.  Self-loops
- * already in the input are kept (a loop is an ordinary neighbour). */
+ * the handle every row (in the push direction) is sorted ascending by
+ * (degree of neighbour in D, id).
+ * Errors: AGP_EINVAL for bad sizes, ids out of range, unknown flags,
+ * AGP_REVERSE without AGP_DIRECTED, or (with AGP_VALIDATE) duplicate arcs or
+ * (undirected only) an asymmetric matrix; AGP_ENOMEM; AGP_EDEVICE.
+ * Self-loops already in the input are kept (a loop is an ordinary
+ * neighbour). */
 int agp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr,
                      const int32_t* col_idx, uint32_t flags, void* stream,
                      agp_graph_t** out);
 
-/* Sizes of a graph (any pointer may be NULL). */
+/* Sizes of a graph (any pointer may be NULL); max_degree is the longest row
+ * in the push direction. */
 int agp_graph_info(const agp_graph_t* g, int64_t* n, int64_t* nnz, int32_t* max_degree);
 
 /* Copy the library's CSR to host buffers (any may be NULL):
- * row_ptr int64[n+1], col_sorted int32[nnz] (rows sorted by (degree, id)),
- * degree int32[n]. Synchronous. */
+ * row_ptr int64[n+1], col_sorted int32[nnz] (rows in the push direction,
+ * sorted by (degree of neighbour in D, id)), degree int32[n] (row lengths).
+ * Synchronous. */
 int agp_graph_export(const agp_graph_t* g, int64_t* row_ptr, int32_t* col_sorted,
                      int32_t* degree);
 

@@ -44,7 +44,7 @@ def lib():
         u32p = ct.POINTER(ct.c_uint32)
         u64p = ct.POINTER(ct.c_uint64)
         dp = ct.POINTER(ct.c_double)
-        L.orc_degree_sort.argtypes = [ct.c_int64, i64p, i32p, i32p, i32p]
+        L.orc_degree_sort.argtypes = [ct.c_int64, i64p, i32p, i32p, i32p, i32p, i32p]
         L.orc_level_tables.argtypes = [dp, ct.c_int32, dp, dp, dp, dp]
         L.orc_theta.argtypes = [dp, ct.c_int64, ct.c_double]
         L.orc_theta.restype = ct.c_double
@@ -68,23 +68,47 @@ def _p(a, t):
 
 @dataclass
 class SortedGraph:
-    """Graph whose adjacency lists are sorted by (neighbour degree, id)."""
+    """Graph whose adjacency lists are sorted by (neighbour factor degree, id).
+
+    deg: row lengths; fdeg: the degrees in the factors d^-a, d^-b (row
+    lengths of an undirected graph, out-degrees of a directed one; >= 1)."""
 
     n: int
     row_ptr: np.ndarray
     col: np.ndarray
     deg: np.ndarray
+    fdeg: np.ndarray
 
 
-def degree_sort(g) -> SortedGraph:
+def degree_sort(g, fdeg=None) -> SortedGraph:
     rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
     col = np.ascontiguousarray(g.col, dtype=np.int32)
     out = np.empty_like(col)
     deg = np.empty(g.n, dtype=np.int32)
+    fd = np.empty(g.n, dtype=np.int32)
+    fin = None if fdeg is None else np.ascontiguousarray(fdeg, dtype=np.int32)
     rc = lib().orc_degree_sort(g.n, _p(rp, ct.c_int64), _p(col, ct.c_int32),
-                               _p(out, ct.c_int32), _p(deg, ct.c_int32))
+                               None if fin is None else _p(fin, ct.c_int32),
+                               _p(out, ct.c_int32), _p(deg, ct.c_int32), _p(fd, ct.c_int32))
     assert rc == 0
-    return SortedGraph(g.n, rp, out, deg)
+    return SortedGraph(g.n, rp, out, deg, fd)
+
+
+def directed(g, reverse: bool = False) -> SortedGraph:
+    """A directed graph given by its out-adjacency CSR (Section 4, propagation
+    on directed graphs): pushes follow out-edges (A~ = A^T), or in-edges when
+    reverse (A~ = A, single-target proximity); the factors use out-degrees."""
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    outdeg = np.diff(rp).astype(np.int32)
+    if not reverse:
+        return degree_sort(g, outdeg)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(rp))
+    dst = np.asarray(g.col, dtype=np.int64)
+    order = np.lexsort((src, dst))  # rows of the transpose: in-neighbours of each node
+    trp = np.zeros(g.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(dst, minlength=g.n), out=trp[1:])
+    gt = type(g)(g.n, trp, src[order].astype(np.int32))
+    return degree_sort(gt, outdeg)
 
 
 def level_tables(w):
@@ -149,7 +173,7 @@ def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, 
     if threads is None:
         threads = min(C, os.cpu_count() or 1)
     rc = lib().orc_propagate_many(
-        sg.n, _p(sg.row_ptr, ct.c_int64), _p(sg.col, ct.c_int32), _p(sg.deg, ct.c_int32),
+        sg.n, _p(sg.row_ptr, ct.c_int64), _p(sg.col, ct.c_int32), _p(sg.fdeg, ct.c_int32),
         float(a), float(b), _p(w, ct.c_double), L, _p(xc, ct.c_double), C, float(eps),
         ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), None if q is None else _p(q, ct.c_uint32), wp,
         _p(out, ct.c_double), _p(cnt, ct.c_uint64), max(1, int(threads)))

@@ -62,14 +62,21 @@ static int cmp_deg_id(const void* pa, const void* pb) {
 
 static pthread_mutex_t g_sort_lock = PTHREAD_MUTEX_INITIALIZER;
 
-/* Pre-sorting adjacency lists by degree (Section 4): N_u ascending in d_v. */
-int orc_degree_sort(int64_t n, const int64_t* rp, const int32_t* col,
-                    int32_t* out_col, int32_t* deg) {
+/* Pre-sorting adjacency lists by degree (Section 4): N_u ascending in the
+ * degree of the neighbour that enters the factors d^-a, d^-b.  Undirected
+ * graphs: that degree is the row length (at least 1).  Directed graphs pass
+ * the out-degrees (Section 4, propagation on directed graphs). */
+int orc_degree_sort(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* fdeg_in,
+                    int32_t* out_col, int32_t* deg, int32_t* fdeg) {
   if (n < 0) return -1;
-  for (int64_t u = 0; u < n; ++u) deg[u] = (int32_t)(rp[u + 1] - rp[u]);
+  for (int64_t u = 0; u < n; ++u) {
+    deg[u] = (int32_t)(rp[u + 1] - rp[u]);
+    const int32_t f = fdeg_in ? fdeg_in[u] : deg[u];
+    fdeg[u] = f < 1 ? 1 : f;
+  }
   memcpy(out_col, col, (size_t)rp[n] * sizeof(int32_t));
   pthread_mutex_lock(&g_sort_lock);
-  g_sort_deg = deg;
+  g_sort_deg = fdeg;
   for (int64_t u = 0; u < n; ++u)
     qsort(out_col + rp[u], (size_t)(rp[u + 1] - rp[u]), sizeof(int32_t), cmp_deg_id);
   pthread_mutex_unlock(&g_sort_lock);
@@ -368,11 +375,11 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
       hs += orc_splitmix64((uint64_t)u);
       /* reserve: pi(u) += (w_i / Y_i) r(u), rescaled by S */
       out[u] = fl_w(out[u] + fl_w(kappa[i] * ru, wp), wp);
-      if (i == L || rho[i] == 0.0 || deg[u] == 0) continue;
+      const int64_t du = rp[u + 1] - rp[u]; /* neighbours to push to */
+      if (i == L || rho[i] == 0.0 || du == 0) continue;
       const double sgn = ru < 0.0 ? -1.0 : 1.0;
       const double c = (rho[i] * fabs(ru)) * db[deg[u]];
       const int32_t* nb = col_sorted + rp[u];
-      const int64_t du = deg[u];
       /* deterministic pushes to the prefix whose increment reaches theta */
       int64_t j = 0;
       while (j < du) {

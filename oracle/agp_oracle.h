@@ -35,10 +35,12 @@ typedef struct orc_counters {
   uint64_t* acc;      /* accepted sampled pushes                      */
 } orc_counters;
 
-/* Sort every adjacency list ascending by (degree of neighbour, neighbour id).
- * rp/col: symmetric CSR; out_col gets the sorted lists, deg the degrees. */
-int orc_degree_sort(int64_t n, const int64_t* rp, const int32_t* col,
-                    int32_t* out_col, int32_t* deg);
+/* Sort every adjacency list ascending by (factor degree of neighbour, id).
+ * rp/col: CSR of the push direction; fdeg_in: factor degrees (out-degrees
+ * of a directed graph) or NULL for the row lengths.  out_col gets the sorted
+ * lists, deg the row lengths, fdeg the factor degrees clamped to >= 1. */
+int orc_degree_sort(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* fdeg_in,
+                    int32_t* out_col, int32_t* deg, int32_t* fdeg);
 
 /* S, Y_0..Y_{L+1}, rho_0..rho_L, kappa_0..kappa_L from w_0..w_L. */
 int orc_level_tables(const double* w, int32_t L, double* S, double* Y,
@@ -60,7 +62,9 @@ uint64_t orc_splitmix64(uint64_t x);
 double orc_exact_sum(const double* vals, int64_t k, int32_t wp);
 
 /* One column of Algorithm 2. x and out hold n values; with wp = 32 every x
- * must be a binary32 value. Returns 0, or -1 on invalid arguments. */
+ * must be a binary32 value; deg holds the factor degrees (fdeg of
+ * orc_degree_sort), the rows come from rp.  Returns 0, or -1 on invalid
+ * arguments. */
 int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                   const int32_t* deg, double a, double b, const double* w,
                   int32_t L, const double* x, double eps, uint64_t seed,

@@ -45,6 +45,28 @@ def horner(g, a: float, b: float, w, x) -> np.ndarray:
     return acc
 
 
+def transition_directed(g, a: float, b: float, reverse: bool = False) -> np.ndarray:
+    """P = D^-a A~ D^-b of a directed graph given by its out-adjacency
+    (Section 4, propagation on directed graphs): A~ = A^T pushes along
+    out-edges, A~ = A (reverse) along in-edges; D holds the out-degrees, a
+    node without out-arcs counting as out-degree 1."""
+    A = adjacency(g)  # A[u, v] = 1 for the arc u -> v
+    d = np.maximum(A.sum(axis=1), 1.0)
+    At = A if reverse else A.T
+    return (d ** (-a))[:, None] * At * (d ** (-b))[None, :]
+
+
+def horner_directed(g, a: float, b: float, w, x, reverse: bool = False) -> np.ndarray:
+    """sum_{i=0}^{L} w_i P^i x with the directed P of transition_directed."""
+    P = transition_directed(g, a, b, reverse)
+    w = np.asarray(w, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    acc = w[-1] * x
+    for i in range(w.size - 2, -1, -1):
+        acc = w[i] * x + P @ acc
+    return acc
+
+
 def horner_sparse(g, a: float, b: float, w, x) -> np.ndarray:
     """sum_{i=0}^{L} w_i P^i x as horner(), with P = D^-a A D^-b held as a
     scipy CSR matrix (for graphs too large for a dense n x n matrix)."""

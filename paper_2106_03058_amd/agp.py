@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libagp.so")
 
 AGP_OK, AGP_EINVAL, AGP_ENOMEM, AGP_EDEVICE, AGP_ERANGE, AGP_ENOTSUP = 0, 1, 2, 3, 4, 5
 AGP_PENDING, AGP_ENOENT, AGP_EBUSY = 6, 7, 8
-AGP_HOST_PTRS, AGP_VALIDATE, AGP_ADD_SELF_LOOPS = 1, 2, 4
+AGP_HOST_PTRS, AGP_VALIDATE, AGP_ADD_SELF_LOOPS, AGP_DIRECTED, AGP_REVERSE = 1, 2, 4, 8, 16
 MAX_LEVELS = 255
 
 EXPORTED = [
@@ -106,9 +106,13 @@ class Graph:
     """A graph resident on the GPU with degree-sorted adjacency lists."""
 
     def __init__(self, row_ptr, col, *, validate: bool = False, self_loops: bool = False,
-                 stream=None):
-        """row_ptr / col: host arrays, or CUDA tensors (int64 / int32) on the device."""
-        flags = (AGP_VALIDATE if validate else 0) | (AGP_ADD_SELF_LOOPS if self_loops else 0)
+                 directed: bool = False, reverse: bool = False, stream=None):
+        """row_ptr / col: host arrays, or CUDA tensors (int64 / int32) on the device.
+
+        directed: rows are out-neighbour lists of a directed graph and pushes
+        follow out-edges; reverse (with directed): pushes follow in-edges."""
+        flags = ((AGP_VALIDATE if validate else 0) | (AGP_ADD_SELF_LOOPS if self_loops else 0) |
+                 (AGP_DIRECTED if directed else 0) | (AGP_REVERSE if reverse else 0))
         if hasattr(row_ptr, "is_cuda") and row_ptr.is_cuda:
             import torch
 

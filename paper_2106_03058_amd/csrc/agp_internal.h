@@ -68,19 +68,21 @@ struct agp_tune_key {
 struct agp_graph {
   int64_t n = 0;
   int64_t nnz = 0;
-  int32_t max_degree = 0;
+  int32_t max_degree = 0;       // longest row
+  int32_t max_fdeg = 0;         // largest factor degree
   int device = 0;
-  int64_t* row_ptr = nullptr;   // device int64[n + 1]
-  uint32_t* col = nullptr;      // device uint32[nnz], rows sorted by (degree, id)
-  uint32_t* ndeg = nullptr;     // device uint32[nnz], degree of col[j]
-  int32_t* degree = nullptr;    // device int32[n]
-  std::map<double, double*> pow_tables;  // exponent e -> device d^-e, d = 0..max_degree
+  int64_t* row_ptr = nullptr;   // device int64[n + 1], rows in the push direction
+  uint32_t* col = nullptr;      // device uint32[nnz], rows sorted by (factor degree, id)
+  uint32_t* ndeg = nullptr;     // device uint32[nnz], factor degree of col[j]
+  int32_t* degree = nullptr;    // device int32[n], row lengths
+  int32_t* fdeg = nullptr;      // device int32[n], degree in the factors d^-a, d^-b (>= 1)
+  std::map<double, double*> pow_tables;  // exponent e -> device d^-e, d = 0..max_fdeg
   std::map<agp_tune_key, agp_tuning_t> tuning;  // autotuned execution choices
   std::mutex mu;
   agp::Scratch scratch;
 };
 
 namespace agp {
-// Device table of d^-e for d = 0..max_degree (0 at d = 0), cached per graph.
+// Device table of d^-e for d = 0..max_fdeg (0 at d = 0), cached per graph.
 int pow_table(agp_graph* g, double e, const double** out);
 }  // namespace agp

@@ -77,7 +77,7 @@ int pow_table(agp_graph* g, double e, const double** out) {
     *out = it->second;
     return AGP_OK;
   }
-  const size_t cnt = static_cast<size_t>(g->max_degree) + 1;
+  const size_t cnt = static_cast<size_t>(g->max_fdeg) + 1;
   std::vector<double> host(cnt);
   for (size_t d = 0; d < cnt; ++d) host[d] = degree_power(static_cast<int64_t>(d), e);
   double* dev = nullptr;

@@ -141,6 +141,36 @@ __global__ void k_degree(const int64_t* __restrict__ rp, int64_t n, int32_t* __r
   atomicMax(max_deg, local);
 }
 
+// Degree in the factors d^-a, d^-b: the row length of the given matrix
+// (out-degree of a directed graph), a node without arcs counting as 1.
+__global__ void k_factor_degree(const int64_t* __restrict__ rp, int64_t n, int32_t* __restrict__ fdeg,
+                                int* __restrict__ max_f) {
+  int local = 0;
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int d = (int)(rp[u + 1] - rp[u]);
+    const int f = d < 1 ? 1 : d;
+    fdeg[u] = f;
+    local = max(local, f);
+  }
+  atomicMax(max_f, local);
+}
+
+// Transpose of a CSR: in-degree counts, then every arc u -> v placed in row v
+// (order inside a row is fixed later by the row sort).
+__global__ void k_in_count(const int32_t* __restrict__ col, int64_t nnz, unsigned long long* __restrict__ cnt) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz;
+       j += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(cnt + col[j], 1ull);
+}
+
+__global__ void k_transpose_scatter(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t n,
+                                    unsigned long long* __restrict__ cursor, int32_t* __restrict__ tcol) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t j = rp[u]; j < rp[u + 1]; ++j) tcol[atomicAdd(cursor + col[j], 1ull)] = (int32_t)u;
+}
+
 __global__ void k_make_keys(const int32_t* __restrict__ col, const int32_t* __restrict__ deg,
                             int64_t nnz, uint64_t* __restrict__ keys) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz;
@@ -360,6 +390,27 @@ int build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* c
   }
   if (nnz >= ((int64_t)1 << 40)) return fail(AGP_EINVAL, "too many arcs");
 
+  // factor degrees from the given rows (out-degrees when directed)
+  int32_t* fdeg = nullptr;
+  int* fmax = nullptr;
+  if ((rc = al.get(&fdeg, (size_t)n)) || (rc = al.get(&fmax, 1))) return rc;
+  AGP_HIP(hipMemsetAsync(fmax, 0, sizeof(int), s));
+  k_factor_degree<<<grid_for(n, 256), 256, 0, s>>>(rp, n, fdeg, fmax);
+  if (flags & AGP_REVERSE) {  // pushes follow in-edges: rows of the transpose
+    unsigned long long* cnt = nullptr;
+    int64_t* trp = nullptr;
+    int32_t* tcol = nullptr;
+    if ((rc = al.get(&cnt, (size_t)n)) || (rc = al.get(&trp, (size_t)n + 1)) || (rc = al.get(&tcol, (size_t)nnz)))
+      return rc;
+    AGP_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (size_t)n, s));
+    k_in_count<<<grid_for(nnz, 256), 256, 0, s>>>(col, nnz, cnt);
+    if ((rc = exclusive_scan(reinterpret_cast<const int64_t*>(cnt), n, trp, s))) return rc;
+    AGP_HIP(hipMemcpyAsync(cnt, trp, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    k_transpose_scatter<<<grid_for(n, 256), 256, 0, s>>>(rp, col, n, cnt, tcol);
+    rp = trp;
+    col = tcol;
+  }
+
   int32_t* deg = nullptr;
   int* dmax = nullptr;
   uint64_t* keys = nullptr;
@@ -367,7 +418,7 @@ int build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* c
     return rc;
   AGP_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
   k_degree<<<grid_for(n, 256), 256, 0, s>>>(rp, n, deg, dmax);
-  k_make_keys<<<grid_for(nnz, 256), 256, 0, s>>>(col, deg, nnz, keys);
+  k_make_keys<<<grid_for(nnz, 256), 256, 0, s>>>(col, fdeg, nnz, keys);
   if (n > 0) {
     const unsigned rows_grid = (unsigned)std::min<int64_t>(n, 1 << 20);
     k_sort_small_rows<<<rows_grid, kSortThreads, 0, s>>>(rp, n, keys);
@@ -387,31 +438,35 @@ int build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* c
   }
   if (flags & AGP_VALIDATE) {
     AGP_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
-    k_validate_sorted<<<grid_for(n, 256), 256, 0, s>>>(rp, keys, deg, n, dflag);
+    k_validate_sorted<<<grid_for(n, 256), 256, 0, s>>>(rp, keys, fdeg, n, dflag);
     AGP_HIP(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     AGP_HIP(hipStreamSynchronize(s));
     if (hflag & 4) return fail(AGP_EINVAL, "duplicate arcs in a row");
-    if (hflag & 8) return fail(AGP_EINVAL, "the matrix is not symmetric");
+    if ((hflag & 8) && !(flags & AGP_DIRECTED)) return fail(AGP_EINVAL, "the matrix is not symmetric");
   }
   uint32_t *scol = nullptr, *snd = nullptr;
   if ((rc = al.get(&scol, (size_t)nnz)) || (rc = al.get(&snd, (size_t)nnz))) return rc;
   k_split_keys<<<grid_for(nnz, 256), 256, 0, s>>>(keys, nnz, scol, snd);
-  int maxd = 0;
+  int maxd = 0, maxf = 0;
   AGP_HIP(hipMemcpyAsync(&maxd, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
+  AGP_HIP(hipMemcpyAsync(&maxf, fmax, sizeof(int), hipMemcpyDeviceToHost, s));
   AGP_HIP(hipGetLastError());
   AGP_HIP(hipStreamSynchronize(s));
 
   g->n = n;
   g->nnz = nnz;
   g->max_degree = maxd;
+  g->max_fdeg = maxf;
   g->row_ptr = rp;
   g->col = scol;
   g->ndeg = snd;
   g->degree = deg;
+  g->fdeg = fdeg;
   al.keep(rp);
   al.keep(scol);
   al.keep(snd);
   al.keep(deg);
+  al.keep(fdeg);
   return AGP_OK;
 }
 
@@ -426,8 +481,10 @@ int agp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32
   *out = nullptr;
   if (n < 0 || n >= ((int64_t)1 << 31) - 1 || nnz < 0 || !row_ptr || (nnz > 0 && !col_idx))
     return agp::fail(AGP_EINVAL, "agp_graph_create: need 0 <= n < 2^31 - 1, nnz >= 0, non-NULL arrays");
-  if (flags & ~(AGP_HOST_PTRS | AGP_VALIDATE | AGP_ADD_SELF_LOOPS))
+  if (flags & ~(AGP_HOST_PTRS | AGP_VALIDATE | AGP_ADD_SELF_LOOPS | AGP_DIRECTED | AGP_REVERSE))
     return agp::fail(AGP_EINVAL, "agp_graph_create: unknown flag");
+  if ((flags & AGP_REVERSE) && !(flags & AGP_DIRECTED))
+    return agp::fail(AGP_EINVAL, "agp_graph_create: AGP_REVERSE needs AGP_DIRECTED");
   if ((flags & AGP_HOST_PTRS) && (row_ptr[0] != 0 || row_ptr[n] != nnz))
     return agp::fail(AGP_EINVAL, "agp_graph_create: row_ptr[0] must be 0 and row_ptr[n] = nnz");
   agp_graph* g = new (std::nothrow) agp_graph();
@@ -476,6 +533,7 @@ int agp_graph_destroy(agp_graph_t* g) {
     (void)hipFree(g->col);
     (void)hipFree(g->ndeg);
     (void)hipFree(g->degree);
+    (void)hipFree(g->fdeg);
   }
   delete g;
   return AGP_OK;

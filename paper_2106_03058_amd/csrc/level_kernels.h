@@ -78,7 +78,8 @@ struct LevelArgs {
   const int64_t* rp;
   const uint32_t* col;
   const uint32_t* nd;
-  const int32_t* deg;
+  const int32_t* deg;   // row lengths (neighbours to push to)
+  const int32_t* fdeg;  // degrees in the factors d^-a, d^-b
   const ColParams* cp;
   long long su, sc;  // cell = u * su + c * sc
   long long xld;     // level 0 of a batched call: x[u * xld + c]
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
             if (ed > 0) {
               const double absr = fabs(static_cast<double>(r));
               const double t0 = cp.rho * absr;
-              ecv = t0 * cp.db[ed];
+              ecv = t0 * cp.db[A.fdeg[eu]];
               const double eth = cp.theta;
               erp = A.rp[eu];
               double inc0 = ecv;
@@ -696,7 +697,7 @@ __global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __r
     } else {
       absr = 0.0;  // binary64 calls are never binned
     }
-    const double cv = cp.rho * absr * cp.db[d];
+    const double cv = cp.rho * absr * cp.db[A.fdeg[u]];
     sum += cv >= cp.theta ? static_cast<double>(d) : static_cast<double>(d) * (cv / cp.theta);
   }
 #pragma unroll

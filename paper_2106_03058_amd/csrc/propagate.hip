@@ -244,6 +244,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   A.col = g->col;
   A.nd = g->ndeg;
   A.deg = g->degree;
+  A.fdeg = g->fdeg;
   A.cp = cp;
   A.su = C;
   A.sc = 1;

@@ -246,6 +246,7 @@ int step(agp_server* s) {
   A.col = s->g->col;
   A.nd = s->g->ndeg;
   A.deg = s->g->degree;
+  A.fdeg = s->g->fdeg;
   A.cp = s->cp.as<ColParams>();
   A.su = 1;
   A.sc = s->n;

@@ -144,6 +144,35 @@ def erdos_renyi(n: int, p: float, seed: int, *, self_loops: bool = False) -> Gra
     return csr_from_pairs(n, iu[keep], ju[keep], self_loops=self_loops)
 
 
+def directed_from_pairs(n: int, src: np.ndarray, dst: np.ndarray) -> Graph:
+    """Out-adjacency CSR of the arcs src -> dst (loops and duplicates dropped,
+    no symmetrisation): row u lists the out-neighbours of u."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    keep = src != dst
+    key = np.unique(src[keep] * n + dst[keep])
+    rows = key // n
+    col = (key - rows * n).astype(np.int32)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    return Graph(n, row_ptr, col)
+
+
+def directed_chung_lu(n: int, mean_degree: float, gamma: float, seed: int, *, pair_factor: float = 1.0) -> Graph:
+    """Directed power-law graph: n * mean_degree * pair_factor arcs whose tail
+    and head are drawn independently with probability proportional to the
+    Chung-Lu weights (node 0 heaviest); some nodes end up without out-arcs."""
+    rng = np.random.default_rng(seed)
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (gamma - 1.0))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    m = int(round(n * mean_degree * pair_factor))
+    src = np.minimum(np.searchsorted(cdf, rng.random(m), side="right"), n - 1)
+    dst = np.minimum(np.searchsorted(cdf, rng.random(m), side="right"), n - 1)
+    perm = rng.permutation(n)  # tails and heads get independent hub orders
+    return directed_from_pairs(n, src, perm[dst])
+
+
 def toy_graph(k: int) -> Graph:
     """The bad case for pruned propagation in Section 4 (Figure 1).
 

@@ -356,3 +356,80 @@ def test_sparse_horner_matches_dense():
         for a, b, w in ((0.0, 1.0, inputs.weights_ppr(0.2, 12)), (0.5, 0.5, inputs.weights_hkpr(4.0, 9)),
                         (1.0, 0.0, inputs.weights_tp(5)), (0.3, 0.7, inputs.weights_ppr(0.1, 7))):
             assert np.allclose(dense.horner_sparse(g, a, b, w, x), dense.horner(g, a, b, w, x), rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------------------------ directed graphs
+# Section 4, propagation on directed graphs: pi = sum_i w_i (D^-a A~ D^-b)^i x
+# with D the out-degrees; A~ = A^T for PPR / HKPR / Katz (pushes along
+# out-edges), A~ = A for single-target proximity (pushes along in-edges).
+
+def _directed_graphs():
+    return {
+        "dcl": inputs.directed_chung_lu(60, 3, 2.3, seed=21),
+        "dcl2": inputs.directed_chung_lu(90, 5, 2.6, seed=22),
+    }
+
+
+@pytest.mark.parametrize("gname", list(_directed_graphs().keys()))
+@pytest.mark.parametrize("model", ["ppr", "hkpr", "katz", "general", "single_target"])
+@pytest.mark.parametrize("reverse", [False, True])
+def test_directed_eps0_is_the_truncated_sum(orc, gname, model, reverse):
+    g = _directed_graphs()[gname]
+    assert np.any(np.diff(g.row_ptr) == 0)  # nodes without out-arcs are covered
+    a, b, w = MODELS[model]
+    x = _signal(g, "signed", np.random.default_rng(2))
+    ref = dense.horner_directed(g, a, b, w, x, reverse)
+    sg = orc.directed(g, reverse)
+    got, _ = orc.propagate(sg, a, b, w, x, 0.0, seed=1, wp=64)
+    assert np.abs(got - ref).max() <= 1e-12 * (np.abs(ref).max() + 1e-300)
+
+
+def test_directed_ppr_closed_form(orc):
+    """Directed PPR (A~ = A^T, a = 0, b = 1) against alpha (I - (1 - alpha)
+    A^T D^-1)^-1 x within the tail (1 - alpha)^(L+1)."""
+    g = _directed_graphs()["dcl2"]
+    alpha, L = 0.2, 60
+    x = inputs.one_hot(g.n, [3])[:, 0].astype(np.float64)
+    A = dense.adjacency(g)
+    d = np.maximum(A.sum(axis=1), 1.0)
+    exact = alpha * np.linalg.solve(np.eye(g.n) - (1 - alpha) * (A.T / d[None, :]), x)
+    sg = orc.directed(g)
+    got, _ = orc.propagate(sg, 0.0, 1.0, inputs.weights_ppr(alpha, L), x, 0.0, seed=1, wp=64)
+    assert np.abs(got - exact).max() <= (1 - alpha) ** (L + 1) + 1e-12
+
+
+def test_directed_single_target_is_the_transposed_ppr(orc):
+    """Single-target PPR on a directed graph (A~ = A, a = 1, b = 0) at v equals
+    the forward PPR (A~ = A^T, a = 0, b = 1) from source v evaluated at the
+    target: (D^-1 A)^T = A^T D^-1.  Two pushes in opposite directions."""
+    g = _directed_graphs()["dcl"]
+    w = inputs.weights_ppr(0.2, 25)
+    t = 5
+    st, _ = orc.propagate(orc.directed(g, reverse=True), 1.0, 0.0, w,
+                          inputs.one_hot(g.n, [t])[:, 0].astype(np.float64), 0.0, seed=1, wp=64)
+    fwd = orc.directed(g)
+    X = np.eye(g.n)
+    pp, _ = orc.propagate(fwd, 0.0, 1.0, w, X, 0.0, seed=1, wp=64)  # column v: PPR from v
+    assert np.abs(st - pp[t, :]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("reverse", [False, True])
+def test_directed_unbiased(orc, reverse):
+    """Lemma 3.1 on a directed graph: the mean over independent streams is the
+    exact truncated sum."""
+    R = 3000
+    eps = 2e-3
+    g = inputs.directed_chung_lu(150, 5, 2.4, seed=23)
+    a, b = (1.0, 0.0) if reverse else (0.0, 1.0)
+    w = inputs.weights_ppr(0.2, 8)
+    s = int(np.argmax(np.bincount(g.col, minlength=g.n))) if reverse else int(np.argmax(np.diff(g.row_ptr)))
+    x = inputs.one_hot(g.n, [s])[:, 0].astype(np.float64)
+    exact = dense.horner_directed(g, a, b, w, x, reverse)
+    est, cnt = orc.propagate(orc.directed(g, reverse), a, b, w, np.repeat(x[:, None], R, axis=1), eps,
+                             seed=9, wp=64)
+    L = len(w) - 1
+    S = sum(w)
+    bound = L * (L + 1) * eps / 2 * np.abs(exact) / S
+    band = 5 * np.sqrt(np.maximum(bound, 1e-18) / R) + 1e-12
+    assert np.all(np.abs(est.mean(axis=1) / S - exact / S) <= band)
+    assert cnt["cand"].sum() > 0

@@ -19,6 +19,9 @@ Other workloads:
     node) generated on the GPU; the columns are processed in tiles that fit
     the free memory.  Use --steps 1 --warmup 0.
   `--workload serve`: a served query stream on R-MAT scale 24.
+  `--workload directed`: PPR from 256 sources along out-edges and
+    single-target PPR to 256 targets along in-edges (alpha = 0.2, L = 20,
+    eps = 1e-7) on a directed R-MAT scale 22 (arcs as generated).
 The value is edge pushes (deterministic + accepted sampled pushes, the cost
 unit of Theorem 3.3) per second over the timed steps, inputs resident in HBM.
 
@@ -179,6 +182,75 @@ def workload_gnn_hkpr(args):
     return host_workload(g, signal, models, cfg, "columns")
 
 
+def workload_directed(args):
+    """Directed proximity on R-MAT scale 22 (16 arcs per node, arcs kept as
+    generated): PPR from 256 sources along out-edges (A~ = A^T) and
+    single-target PPR to 256 targets along in-edges (A~ = A)."""
+    import torch
+
+    from paper_2106_03058_amd import agp, inputs
+
+    g, _ = cached(args.cache, "rmat22_ef16_s2_directed",
+                  lambda: (inputs.rmat(22, 16, 0.57, 0.19, 0.19, seed=2, directed=True), {}))
+    C = min(args.columns, 256)
+    outdeg = np.diff(g.row_ptr)
+    indeg = np.bincount(g.col, minlength=g.n)
+    rng = np.random.default_rng(102)
+    src = rng.choice(np.flatnonzero(outdeg >= 1), size=C, replace=False)
+    tgt = rng.choice(np.flatnonzero(indeg >= 1), size=C, replace=False)
+    models = [
+        dict(name="ppr", a=0.0, b=1.0, w=inputs.weights_ppr(0.2, 20), eps=1e-7,
+             qids=np.arange(C, dtype=np.uint32), reverse=False, units=src),
+        dict(name="single_target", a=1.0, b=0.0, w=inputs.weights_ppr(0.2, 20), eps=1e-7,
+             qids=np.arange(256, 256 + C, dtype=np.uint32), reverse=True, units=tgt),
+    ]
+    keep = set(args.models.split(","))
+    if not keep & {"ppr", "single_target"}:
+        keep = {"ppr", "single_target"}
+    models = [m for m in models if m["name"] in keep]
+    state = {}
+
+    def make_graph():
+        # one handle per direction; each model uses its own
+        state["G"] = {r: agp.Graph.from_inputs(g, directed=True, reverse=r) for r in {m["reverse"] for m in models}}
+        return state["G"][models[0]["reverse"]]
+
+    def signal_device():
+        # one-hot columns: sources for the forward model, targets for the reverse one
+        state["x"] = {}
+        state["dx"] = {}
+        for r, units in ((False, src), (True, tgt)):
+            x = np.zeros((g.n, C), dtype=np.float32)
+            x[units, np.arange(C)] = 1.0
+            state["x"][r] = x
+            state["dx"][r] = torch.from_numpy(x).to("cuda:0")
+        return state["dx"][models[0]["reverse"]]
+
+    def oracle_inputs(cols):
+        return g, {r: np.ascontiguousarray(state["x"][r][:, cols]) for r in (False, True)}
+
+    def oracle_graph_of(gh, m):
+        import oracle
+
+        return oracle.directed(gh, m["reverse"])
+
+    def exact_of(gh, m, x):
+        from oracle import dense
+
+        return dense.horner_sparse_directed(gh, m["a"], m["b"], m["w"], x, m["reverse"])
+
+    cfg = {"workload": "directed " + "+".join(m["name"] for m in models) + f", {C} sources/targets each, "
+                       "rmat scale 22 (arcs as generated)",
+           "graph": g.describe(), "columns_per_call": C,
+           "models": {m["name"]: {"a": m["a"], "b": m["b"], "L": len(m["w"]) - 1, "eps": m["eps"],
+                                  "pushes_along": "in-edges" if m["reverse"] else "out-edges"} for m in models}}
+    return dict(n=g.n, make_graph=make_graph, signal_device=signal_device, models=models, cfg=cfg,
+                unit="queries", oracle_inputs=oracle_inputs, state=state,
+                graph_of=lambda m: state["G"][m["reverse"]], signal_of=lambda m: state["dx"][m["reverse"]],
+                oracle_graph_of=oracle_graph_of, oracle_signal_of=lambda xh, m: xh[m["reverse"]],
+                exact_of=exact_of)
+
+
 def workload_gnn_ppr_large(args):
     """PPR (APPNP) feature propagation at the scale of a 111M-node citation
     graph: Chung-Lu, exponent 2.2, ~1.6e9 arcs plus a loop per node, generated
@@ -223,7 +295,8 @@ def workload_gnn_ppr_large(args):
                 oracle_inputs=oracle_inputs, state=state)
 
 
-WORKLOADS = {"katz-tp": workload_katz_tp, "gnn-hkpr": workload_gnn_hkpr, "gnn-ppr-large": workload_gnn_ppr_large}
+WORKLOADS = {"katz-tp": workload_katz_tp, "gnn-hkpr": workload_gnn_hkpr, "gnn-ppr-large": workload_gnn_ppr_large,
+             "directed": workload_directed}
 
 
 def run_serve(args) -> dict:
@@ -394,22 +467,26 @@ def main() -> int:
     X = W["signal_device"]()
     if "state" in W:
         W["state"]["X"] = X
-        cfg["graph"] = W["state"].get("desc", {})
+        if "desc" in W["state"]:
+            cfg["graph"] = W["state"]["desc"]
     C = X.shape[1]
-    outs = [torch.empty_like(X) for _ in models]
+    # per model: its graph handle and signal (the same for most workloads)
+    Gs = [W["graph_of"](m) if "graph_of" in W else G for m in models]
+    Xs = [W["signal_of"](m) if "signal_of" in W else X for m in models]
+    outs = [torch.empty_like(Xm) for Xm in Xs]
 
     tunings = {}
     if args.tune:
-        for m, o in zip(models, outs):
-            tunings[m["name"]] = agp.autotune(G, m["a"], m["b"], m["w"], X, m["eps"], args.seed,
+        for m, o, Gm, Xm in zip(models, outs, Gs, Xs):
+            tunings[m["name"]] = agp.autotune(Gm, m["a"], m["b"], m["w"], Xm, m["eps"], args.seed,
                                               qids=m["qids"], out=o)
         log(f"autotuned: {tunings}")
 
     def step(stats: bool):
         res = []
-        for m, o in zip(models, outs):
+        for m, o, Gm, Xm in zip(models, outs, Gs, Xs):
             t0 = time.perf_counter()
-            _, st = agp.propagate(G, m["a"], m["b"], m["w"], X, m["eps"], args.seed, qids=m["qids"],
+            _, st = agp.propagate(Gm, m["a"], m["b"], m["w"], Xm, m["eps"], args.seed, qids=m["qids"],
                                   out=o, stats=stats)
             res.append((st, (time.perf_counter() - t0) * 1e3))
         return res
@@ -460,12 +537,12 @@ def main() -> int:
     nq = args.single // max(len(models), 1)
     one = torch.empty((n, 1), dtype=torch.float32, device=dev)
     single_ok = True
-    for m, o in zip(models, outs):
+    for m, o, Gm, Xm in zip(models, outs, Gs, Xs):
         for c in range(min(nq, C)):
-            xc = X[:, c:c + 1].contiguous()
+            xc = Xm[:, c:c + 1].contiguous()
             torch.cuda.synchronize()
             ts = time.perf_counter()
-            agp.propagate(G, m["a"], m["b"], m["w"], xc, m["eps"], args.seed, qids=m["qids"][c:c + 1], out=one)
+            agp.propagate(Gm, m["a"], m["b"], m["w"], xc, m["eps"], args.seed, qids=m["qids"][c:c + 1], out=one)
             lat_s.append((time.perf_counter() - ts) * 1e3)
             single_ok &= bool(torch.equal(one[:, 0], o[:, c]))
     lat_s = np.array(lat_s) if lat_s else np.zeros(1)
@@ -521,12 +598,17 @@ def main() -> int:
         threads = min(k * len(models), 16, os.cpu_count() or 1)
         gh, xh = W["oracle_inputs"](cols)
         t = time.time()
-        sg = oracle.degree_sort(gh)
+        if "oracle_graph_of" in W:
+            sgs = [W["oracle_graph_of"](gh, m) for m in models]
+        else:
+            sg = oracle.degree_sort(gh)
+            sgs = [sg for _ in models]
+        xhs = [W["oracle_signal_of"](xh, m) if "oracle_signal_of" in W else xh for m in models]
         log(f"oracle degree sort {time.time() - t:.1f}s")
         results = {}
 
         def run(mi, m):
-            results[mi] = oracle.propagate(sg, m["a"], m["b"], m["w"], xh, m["eps"], args.seed,
+            results[mi] = oracle.propagate(sgs[mi], m["a"], m["b"], m["w"], xhs[mi], m["eps"], args.seed,
                                            qids=m["qids"][cols], threads=max(threads // len(models), 1))
 
         t = time.time()
@@ -565,7 +647,10 @@ def main() -> int:
             errs = {}
             ke = min(args.exact_units, k)
             for mi, m in enumerate(models):
-                exact = dense.horner_sparse(gh, m["a"], m["b"], m["w"], xh[:, :ke])
+                if "exact_of" in W:
+                    exact = W["exact_of"](gh, m, xhs[mi][:, :ke])
+                else:
+                    exact = dense.horner_sparse(gh, m["a"], m["b"], m["w"], xhs[mi][:, :ke])
                 got = outs[mi][:, torch.from_numpy(cols[:ke]).to(dev)].cpu().numpy().astype(np.float64)
                 diff = np.abs(got - exact)
                 errs[m["name"]] = {"columns": cols[:ke].tolist(), "eps": m["eps"], "max_abs": float(diff.max()),

@@ -87,6 +87,24 @@ def horner_sparse(g, a: float, b: float, w, x) -> np.ndarray:
     return acc
 
 
+def horner_sparse_directed(g, a: float, b: float, w, x, reverse: bool = False) -> np.ndarray:
+    """horner_directed with a scipy CSR P (large directed graphs)."""
+    import scipy.sparse as sp
+
+    n = g.n
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    A = sp.csr_matrix((np.ones(len(g.col)), np.asarray(g.col), rp), shape=(n, n))  # A[u, v]: u -> v
+    d = np.maximum(np.diff(rp), 1).astype(np.float64)
+    At = A if reverse else A.T
+    P = sp.diags(d ** (-a)) @ At @ sp.diags(d ** (-b))
+    w = np.asarray(w, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    acc = w[-1] * x
+    for i in range(w.size - 2, -1, -1):
+        acc = w[i] * x + P @ acc
+    return acc
+
+
 def level_norms(g, a: float, b: float, w, x) -> np.ndarray:
     """||Y_i P^i x||_1 for i = 0..L, with Y_i = sum_{k >= i} w_k (Definition 3.2)."""
     P = transition(g, a, b)

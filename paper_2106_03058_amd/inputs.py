@@ -102,11 +102,12 @@ def chung_lu(n: int, mean_degree: float, gamma: float, seed: int, *,
 
 
 def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
-         *, permute: bool = True, self_loops: bool = False) -> Graph:
+         *, permute: bool = True, self_loops: bool = False, directed: bool = False) -> Graph:
     """R-MAT graph with 2^scale nodes and edge_factor * 2^scale generated edges.
 
     Node labels are shuffled by a seeded permutation so that hubs are not
-    clustered at small ids.
+    clustered at small ids.  directed: the arcs are kept as generated
+    (out-adjacency, loops and duplicates dropped) instead of symmetrised.
     """
     rng = np.random.default_rng(seed)
     n = 1 << scale
@@ -133,6 +134,8 @@ def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
         perm = rng.permutation(n).astype(np.int64)
         src = perm[src]
         dst = perm[dst]
+    if directed:  # arcs src -> dst as generated (out-adjacency)
+        return directed_from_pairs(n, src, dst)
     return csr_from_pairs(n, src, dst, self_loops=self_loops)
 
 

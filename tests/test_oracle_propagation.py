@@ -433,3 +433,13 @@ def test_directed_unbiased(orc, reverse):
     band = 5 * np.sqrt(np.maximum(bound, 1e-18) / R) + 1e-12
     assert np.all(np.abs(est.mean(axis=1) / S - exact / S) <= band)
     assert cnt["cand"].sum() > 0
+
+
+def test_sparse_directed_horner_matches_dense():
+    g = inputs.directed_chung_lu(80, 4, 2.4, seed=24)
+    x = inputs.features_normal(g.n, 2, seed=3)
+    for reverse in (False, True):
+        for a, b, w in ((0.0, 1.0, inputs.weights_ppr(0.2, 10)), (1.0, 0.0, inputs.weights_ppr(0.2, 10)),
+                        (0.3, 0.7, inputs.weights_hkpr(2.0, 6))):
+            assert np.allclose(dense.horner_sparse_directed(g, a, b, w, x, reverse),
+                               dense.horner_directed(g, a, b, w, x, reverse), rtol=1e-12, atol=1e-14)

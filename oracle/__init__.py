@@ -44,6 +44,7 @@ def lib():
         u32p = ct.POINTER(ct.c_uint32)
         u64p = ct.POINTER(ct.c_uint64)
         dp = ct.POINTER(ct.c_double)
+        L.orc_sweep.argtypes = [ct.c_int64, i64p, i32p, dp, i32p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
         L.orc_degree_sort.argtypes = [ct.c_int64, i64p, i32p, i32p, i32p, i32p, i32p]
         L.orc_level_tables.argtypes = [dp, ct.c_int32, dp, dp, dp, dp]
         L.orc_theta.argtypes = [dp, ct.c_int64, ct.c_double]
@@ -182,3 +183,19 @@ def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, 
     res = out.T
     counters = {name: cnt[:, k, :] for k, name in enumerate(COUNTER_NAMES)}
     return (res[:, 0].copy() if vec else np.ascontiguousarray(res)), counters
+
+
+def sweep(g, pi):
+    """Local clustering sweep of Section 5 on the estimate pi (length n):
+    returns (best_size, best_conductance, order); the cluster is
+    order[:best_size]."""
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    p = np.ascontiguousarray(pi, dtype=np.float64)
+    order = np.empty(g.n, dtype=np.int32)
+    size = ct.c_int64()
+    phi = ct.c_double()
+    rc = lib().orc_sweep(g.n, _p(rp, ct.c_int64), _p(col, ct.c_int32), _p(p, ct.c_double), _p(order, ct.c_int32),
+                         ct.byref(size), ct.byref(phi))
+    assert rc == 0
+    return size.value, phi.value, order

@@ -537,3 +537,72 @@ int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
   pthread_mutex_destroy(&jb.lock);
   return jb.status;
 }
+
+/* ------------------------------------------------------ clustering sweep */
+/* Local clustering sweep (Section 5, the quality of local clusters): nodes
+ * sorted by pi(v) / d_v descending, ties by id, nodes without neighbours
+ * last; then the prefix S_i = {v_1..v_i}, 1 <= i <= n - 1, of minimum
+ * conductance Phi(S) = |cut(S)| / min(vol(S), 2m - vol(S)) (the first such
+ * prefix; Phi undefined, and skipped, where the denominator is 0).  cut(S)
+ * counts the arcs (u, v), u in S, v outside S, of the symmetric CSR (a loop
+ * is never cut); vol(S) sums the row lengths; 2m = rp[n]. */
+
+static const double* g_sw_ratio;
+static const int64_t* g_sw_rp;
+
+static int cmp_sweep(const void* pa, const void* pb) {
+  const int32_t va = *(const int32_t*)pa, vb = *(const int32_t*)pb;
+  const int isoa = g_sw_rp[va + 1] == g_sw_rp[va], isob = g_sw_rp[vb + 1] == g_sw_rp[vb];
+  if (isoa != isob) return isoa < isob ? -1 : 1;
+  const double ra = g_sw_ratio[va], rb = g_sw_ratio[vb];
+  if (ra != rb) return ra > rb ? -1 : 1;
+  return va < vb ? -1 : (va > vb ? 1 : 0);
+}
+
+int orc_sweep(int64_t n, const int64_t* rp, const int32_t* col, const double* pi, int32_t* order,
+              int64_t* best_size, double* best_phi) {
+  if (n < 0) return -1;
+  double* ratio = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  unsigned char* in_s = calloc((size_t)(n > 0 ? n : 1), 1);
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t d = rp[v + 1] - rp[v];
+    double r = d > 0 ? pi[v] / (double)d : 0.0;
+    if (r == 0.0) r = 0.0; /* one zero */
+    ratio[v] = r;
+    order[v] = (int32_t)v;
+  }
+  pthread_mutex_lock(&g_sort_lock);
+  g_sw_ratio = ratio;
+  g_sw_rp = rp;
+  qsort(order, (size_t)n, sizeof(int32_t), cmp_sweep);
+  pthread_mutex_unlock(&g_sort_lock);
+  const int64_t two_m = rp[n];
+  int64_t cut = 0, vol = 0;
+  *best_size = 0;
+  *best_phi = INFINITY;
+  for (int64_t i = 0; i + 1 < n; ++i) { /* S_{i+1} = S_i + v */
+    const int32_t v = order[i];
+    int64_t loops = 0, inside = 0;
+    for (int64_t j = rp[v]; j < rp[v + 1]; ++j) {
+      if (col[j] == v)
+        ++loops;
+      else if (in_s[col[j]])
+        ++inside;
+    }
+    const int64_t d = rp[v + 1] - rp[v];
+    cut += (d - loops) - 2 * inside; /* v's arcs leave S, except those to S */
+    vol += d;
+    in_s[v] = 1;
+    const int64_t denom = vol < two_m - vol ? vol : two_m - vol;
+    if (denom > 0) {
+      const double phi = (double)cut / (double)denom;
+      if (phi < *best_phi) {
+        *best_phi = phi;
+        *best_size = i + 1;
+      }
+    }
+  }
+  free(ratio);
+  free(in_s);
+  return 0;
+}

@@ -79,6 +79,13 @@ int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                        uint64_t seed, const uint32_t* qids, int32_t wp,
                        double* out, uint64_t* counters, int32_t nthreads);
 
+/* Local clustering sweep of pi (Section 5): order gets the nodes sorted by
+ * pi(v)/d_v descending (ties by id, isolated nodes last); best_size is the
+ * first prefix size i in [1, n-1] of minimum conductance, best_phi that
+ * conductance (best_size 0 and +inf when no prefix has one). */
+int orc_sweep(int64_t n, const int64_t* rp, const int32_t* col, const double* pi, int32_t* order,
+              int64_t* best_size, double* best_phi);
+
 #ifdef __cplusplus
 }
 #endif

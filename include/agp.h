@@ -257,6 +257,34 @@ int agp_poll(agp_server_t* s, uint64_t ticket, agp_result_t* res);
  * the server.  Synchronous. */
 int agp_server_destroy(agp_server_t* s);
 
+/* ---------------------------------------------- local clustering sweep */
+
+/* Sweep of a proximity estimate into a local cluster (Section 5, the
+ * quality of local clusters, e.g. a heat kernel PageRank estimate): the
+ * nodes are ordered by pi(v) / d_v descending (d_v = row length; ties by
+ * node id; nodes without arcs last), and the result is the first prefix
+ * S_i = {v_1..v_i}, 1 <= i <= n - 1, of minimum conductance
+ *   Phi(S) = |cut(S)| / min(vol(S), 2m - vol(S)),
+ * cut(S) = arcs from S to the rest (a self-loop is never cut), vol(S) = the
+ * sum of the row lengths in S, 2m = nnz.  Prefixes whose denominator is 0
+ * are skipped.  Cut and volume are exact integers; Phi is their binary64
+ * quotient.
+ *  g            an undirected graph (not built with AGP_DIRECTED)
+ *  pi, ld       device float: the estimate of node v is pi[v * ld] (ld >= 1;
+ *               column c of an n x C agp_propagate result: out + c, ld = C)
+ *  stream       work is enqueued on this stream; the call waits for it
+ *  best_size    host; receives i (0 when no prefix has a conductance)
+ *  best_conductance  host; receives Phi(S_i) (+inf when best_size is 0)
+ *  order        optional device int32[n] (NULL to skip): the node order, so
+ *               that order[0..best_size) is the cluster
+ * Working memory of about 60 n bytes plus the sort's is kept with the graph
+ * (released by agp_graph_destroy); calls on one graph are serialised with
+ * each other and with agp_propagate.  Synchronous on `stream`.
+ * Errors: AGP_EINVAL (NULL argument, ld < 1, directed graph), AGP_ENOMEM,
+ * AGP_EDEVICE. */
+int agp_sweep(const agp_graph_t* g, const float* pi, int64_t ld, void* stream, int64_t* best_size,
+              double* best_conductance, int32_t* order);
+
 /* ------------------------------------------- weight sequences (Table 1) */
 
 /* w_i = alpha (1 - alpha)^i, i = 0..L (PageRank, PPR, APPNP). */

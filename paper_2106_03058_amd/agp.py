@@ -23,7 +23,7 @@ EXPORTED = [
     "agp_last_error", "agp_graph_create", "agp_graph_info", "agp_graph_export",
     "agp_graph_destroy", "agp_propagate", "agp_propagate_f64", "agp_weights_ppr",
     "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp", "agp_server_create", "agp_submit",
-    "agp_poll", "agp_server_destroy", "agp_autotune", "agp_get_tuning",
+    "agp_poll", "agp_server_destroy", "agp_autotune", "agp_get_tuning", "agp_sweep",
 ]
 
 
@@ -82,6 +82,7 @@ def lib():
         L.agp_weights_hkpr.argtypes = [ct.c_double, ct.c_int32, dp]
         L.agp_weights_katz.argtypes = [ct.c_double, ct.c_int32, dp]
         L.agp_weights_tp.argtypes = [ct.c_int32, dp]
+        L.agp_sweep.argtypes = [vp, vp, ct.c_int64, vp, i64p, dp, vp]
         _lib = L
     return _lib
 
@@ -253,6 +254,27 @@ def get_tuning(graph: Graph, C: int, a: float, b: float) -> dict:
     t = Tuning()
     _check(_tune_lib().agp_get_tuning(graph.handle, int(C), float(a), float(b), ct.byref(t)))
     return t.to_dict()
+
+
+def sweep(graph: Graph, pi, *, order: bool = True, stream=None):
+    """Local clustering sweep (Section 5) of the estimate pi: a float32 CUDA
+    tensor of n values, contiguous or a strided column (e.g. out[:, c] of a
+    row-major n x C result).  Returns (best_size, best_conductance, order)
+    with order an int32 device tensor (None when order=False); the cluster
+    is order[:best_size]."""
+    import torch
+
+    if not pi.is_cuda or pi.dtype != torch.float32 or pi.dim() != 1 or pi.numel() != graph.n:
+        raise ValueError("pi must be a 1-d float32 device tensor of n values")
+    ld = pi.stride(0) if graph.n > 1 else 1
+    if ld < 1:
+        raise ValueError("pi needs a positive stride")
+    o = torch.empty(graph.n, dtype=torch.int32, device=pi.device) if order else None
+    size = ct.c_int64()
+    phi = ct.c_double()
+    _check(lib().agp_sweep(graph.handle, _dptr(pi), ld, _stream_ptr(stream), ct.byref(size), ct.byref(phi),
+                           None if o is None else _dptr(o)))
+    return size.value, phi.value, o
 
 
 def _weights(fn, *args, L: int) -> np.ndarray:

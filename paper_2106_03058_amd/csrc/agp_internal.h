@@ -48,6 +48,9 @@ struct Scratch {
   DevBuf levelinfo;  // per level: contribution mass (double), frontier mode (int)
   DevBuf rec[2];     // binned aggregation: push records, partitioned records
   DevBuf bins;       // bucket counts, offsets, cursors, per-level record counts
+  DevBuf sweep;      // clustering sweep: keys, order, ranks, prefix sums, sort space
+  DevBuf sweep_items;        // clustering sweep: arc-balanced work items of the graph
+  int64_t sweep_nitems = -1; // their number (-1: not built yet)
   hipEvent_t events[2 * (AGP_MAX_LEVELS + 1)] = {};  // level timing, created on demand
   int ensure_events();
   void release();
@@ -71,6 +74,7 @@ struct agp_graph {
   int32_t max_degree = 0;       // longest row
   int32_t max_fdeg = 0;         // largest factor degree
   int device = 0;
+  bool directed = false;        // built with AGP_DIRECTED
   int64_t* row_ptr = nullptr;   // device int64[n + 1], rows in the push direction
   uint32_t* col = nullptr;      // device uint32[nnz], rows sorted by (factor degree, id)
   uint32_t* ndeg = nullptr;     // device uint32[nnz], factor degree of col[j]

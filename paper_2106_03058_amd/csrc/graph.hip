@@ -494,6 +494,7 @@ int agp_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32
     delete g;
     return agp::fail(AGP_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
   }
+  g->directed = (flags & AGP_DIRECTED) != 0;
   const int rc = agp::build_graph(n, nnz, row_ptr, col_idx, flags, (hipStream_t)stream, g);
   if (rc != AGP_OK) {
     delete g;

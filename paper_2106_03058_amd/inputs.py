@@ -356,12 +356,15 @@ def chung_lu_device(n: int, mean_degree: float, gamma: float, seed: int, *, targ
 
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
-    w = (torch.arange(n, dtype=torch.float64, device=device) + 1.0) ** (-1.0 / (gamma - 1.0))
+    # the weights and their CDF on the host: a device scan may add in an
+    # order that changes from run to run, and with it the sampled graph
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (gamma - 1.0))
     w *= mean_degree * n / float(w.sum())
-    w.clamp_(max=math.sqrt(n * mean_degree))
-    cdf = torch.cumsum(w, 0)
-    cdf /= cdf[-1].clone()
+    np.minimum(w, math.sqrt(n * mean_degree), out=w)
+    cdf = np.cumsum(w)
     del w
+    cdf /= cdf[-1]
+    cdf = torch.from_numpy(cdf).to(device)
 
     def draw(m):
         keys = []

@@ -46,7 +46,7 @@ def lib():
         dp = ct.POINTER(ct.c_double)
         L.orc_sweep.argtypes = [ct.c_int64, i64p, i32p, dp, i32p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
         L.orc_degree_sort.argtypes = [ct.c_int64, i64p, i32p, i32p, i32p, i32p, i32p]
-        L.orc_level_tables.argtypes = [dp, ct.c_int32, dp, dp, dp, dp]
+        L.orc_level_tables.argtypes = [dp, ct.c_int32, ct.c_int32, dp, dp, dp, dp]
         L.orc_theta.argtypes = [dp, ct.c_int64, ct.c_double]
         L.orc_theta.restype = ct.c_double
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
@@ -57,7 +57,7 @@ def lib():
         L.orc_exact_sum.argtypes = [dp, ct.c_int64, ct.c_int32]
         L.orc_exact_sum.restype = ct.c_double
         L.orc_propagate_many.argtypes = [ct.c_int64, i64p, i32p, i32p, ct.c_double, ct.c_double,
-                                         dp, ct.c_int32, dp, ct.c_int32, ct.c_double, ct.c_uint64,
+                                         dp, ct.c_int32, ct.c_int32, dp, ct.c_int32, ct.c_double, ct.c_uint64,
                                          u32p, ct.c_int32, dp, u64p, ct.c_int32]
         _lib = L
     return _lib
@@ -112,15 +112,18 @@ def directed(g, reverse: bool = False) -> SortedGraph:
     return degree_sort(gt, outdeg)
 
 
-def level_tables(w):
+def level_tables(w, tail: bool = False):
+    """S, Y_0..Y_{L+1}, rho, kappa (tail: the infinite-tail reading of Y_i)."""
     w = np.ascontiguousarray(w, dtype=np.float64)
     L = w.size - 1
     S = ct.c_double()
     Y = np.empty(L + 2)
     rho = np.empty(L + 1)
     kappa = np.empty(L + 1)
-    lib().orc_level_tables(_p(w, ct.c_double), L, ct.byref(S), _p(Y, ct.c_double),
-                           _p(rho, ct.c_double), _p(kappa, ct.c_double))
+    rc = lib().orc_level_tables(_p(w, ct.c_double), L, int(bool(tail)), ct.byref(S), _p(Y, ct.c_double),
+                                _p(rho, ct.c_double), _p(kappa, ct.c_double))
+    if rc != 0:
+        raise ValueError("weights rejected")
     return S.value, Y, rho, kappa
 
 
@@ -153,14 +156,45 @@ def exact_sum(vals, wp: int) -> float:
 COUNTER_NAMES = ("frontier", "hash", "det", "cand", "acc")
 
 
+SPLIT_QID_BIT = 1 << 23
+
+
 def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, *,
-              wp: int = 32, qids=None, threads: int | None = None):
+              wp: int = 32, qids=None, threads: int | None = None, tail: bool = False,
+              split_signs: bool = False):
     """Run Algorithm 2 on every column of x (n x C, or a length-n vector).
 
     Returns (out, counters): out has the shape of x (float64 values that are
     binary32 values when wp == 32); counters maps each counter name to a
     C x (L + 1) uint64 array.
+
+    tail: the paper-literal Y_i = 1 - sum_{k<i} w_k (weights summing to at
+    most 1, no rescaling), see orc_level_tables.
+
+    split_signs: the literal treatment of signed signals (Section 3,
+    assumption on the graph signal): x+ (the positive entries) and x- (the
+    negative ones) are propagated as separate signals, each with its own
+    threshold eps * ||x+-||_1, column c's x- part drawing from the random
+    stream of query id qid_c + 2^23; the estimate is pi+ + pi- rounded once to
+    the working precision, and the counters are those of both passes added.
     """
+    if split_signs:
+        X = np.asarray(x, dtype=np.float64).reshape(sg.n, -1)
+        C = X.shape[1]
+        q = np.arange(C, dtype=np.uint32) if qids is None else np.ascontiguousarray(qids, dtype=np.uint32)
+        if q.size != C or (q >= SPLIT_QID_BIT).any():
+            raise ValueError("split_signs needs one qid per column, each below 2^23")
+        xp = np.where(X > 0.0, X, 0.0)
+        xn = np.where(X < 0.0, X, 0.0)
+        op, cp = propagate(sg, a, b, w, xp, eps, seed, wp=wp, qids=q, threads=threads, tail=tail)
+        on, cn = propagate(sg, a, b, w, xn, eps, seed, wp=wp, qids=q + np.uint32(SPLIT_QID_BIT), threads=threads,
+                           tail=tail)
+        if wp == 32:
+            res = (op.astype(np.float32) + on.astype(np.float32)).astype(np.float64)
+        else:
+            res = op + on
+        counters = {k: cp[k] + cn[k] for k in cp}
+        return (res[:, 0].copy() if np.asarray(x).ndim == 1 else res), counters
     w = np.ascontiguousarray(w, dtype=np.float64)
     L = w.size - 1
     x = np.asarray(x)
@@ -175,7 +209,7 @@ def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, 
         threads = min(C, os.cpu_count() or 1)
     rc = lib().orc_propagate_many(
         sg.n, _p(sg.row_ptr, ct.c_int64), _p(sg.col, ct.c_int32), _p(sg.fdeg, ct.c_int32),
-        float(a), float(b), _p(w, ct.c_double), L, _p(xc, ct.c_double), C, float(eps),
+        float(a), float(b), _p(w, ct.c_double), L, int(bool(tail)), _p(xc, ct.c_double), C, float(eps),
         ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), None if q is None else _p(q, ct.c_uint32), wp,
         _p(out, ct.c_double), _p(cnt, ct.c_uint64), max(1, int(threads)))
     if rc != 0:

@@ -87,15 +87,31 @@ int orc_degree_sort(int64_t n, const int64_t* rp, const int32_t* col, const int3
 
 /* Partial sums Y_i = sum_{k>=i} w_k (Definition 3.2), with w_k = 0 for k > L,
  * added from k = L downwards; rho_i = Y_{i+1}/Y_i (recursion for r^(i+1));
- * kappa_i = (S * w_i) / Y_i (reserve q^(i) = (w_i/Y_i) r^(i), rescaled by S). */
-int orc_level_tables(const double* w, int32_t L, double* S, double* Y,
+ * kappa_i = (S * w_i) / Y_i (reserve q^(i) = (w_i/Y_i) r^(i), rescaled by S).
+ *
+ * tail != 0: the paper-literal infinite tail.  The weights are the first
+ * terms of a sequence whose infinite sum is 1 (Section 3, assumptions on
+ * w_i), so the terms beyond L hold T = 1 - (w_0 + ... + w_L) (the sum taken
+ * from k = 0 upwards, T floored at 0) and Y_i = T + sum_{k=i..L} w_k, added
+ * from k = L downwards onto Y_{L+1} = T; S = Y_0 (1 up to rounding), kappa
+ * as above, rho_i = Y_{i+1}/Y_i for i < L and rho_L = 0: the last level keeps
+ * (w_L / Y_L) r^(L) and drops the rest (Algorithm 2, final step).  Needs
+ * w_0 + ... + w_L <= 1 + 1e-9.  With T = 0 the tables equal the default ones. */
+int orc_level_tables(const double* w, int32_t L, int32_t tail, double* S, double* Y,
                      double* rho, double* kappa) {
   if (L < 0) return -1;
-  Y[L + 1] = 0.0;
+  double T = 0.0;
+  if (tail) {
+    double total = 0.0;
+    for (int32_t k = 0; k <= L; ++k) total += w[k];
+    if (!(total <= 1.0 + 1e-9)) return -1;
+    T = total < 1.0 ? 1.0 - total : 0.0;
+  }
+  Y[L + 1] = T;
   for (int32_t k = L; k >= 0; --k) Y[k] = Y[k + 1] + w[k];
   *S = Y[0];
   for (int32_t i = 0; i <= L; ++i) {
-    rho[i] = (Y[i] == 0.0) ? 0.0 : Y[i + 1] / Y[i];
+    rho[i] = (Y[i] == 0.0 || i == L) ? 0.0 : Y[i + 1] / Y[i];
     kappa[i] = (Y[i] == 0.0) ? 0.0 : ((*S) * w[i]) / Y[i];
   }
   return 0;
@@ -327,7 +343,7 @@ static int group_of(int32_t d) { return 31 - __builtin_clz((unsigned)d); }
 
 int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                   const int32_t* deg, double a, double b, const double* w,
-                  int32_t L, const double* x, double eps, uint64_t seed,
+                  int32_t L, int32_t tail, const double* x, double eps, uint64_t seed,
                   uint32_t qid, int32_t wp, double* out, orc_counters* cnt) {
   if (n < 0 || L < 0 || L > 255 || !(a >= 0.0 && a <= 1.0) || !(b >= 0.0 && b <= 1.0) ||
       !(eps >= 0.0) || (wp != 32 && wp != 64))
@@ -348,7 +364,14 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
   double* Y = malloc(sizeof(double) * ((size_t)L + 2));
   double* rho = malloc(sizeof(double) * ((size_t)L + 1));
   double* kappa = malloc(sizeof(double) * ((size_t)L + 1));
-  orc_level_tables(w, L, &S, Y, &rho[0], &kappa[0]);
+  if (orc_level_tables(w, L, tail, &S, Y, &rho[0], &kappa[0])) {
+    free(da);
+    free(db);
+    free(Y);
+    free(rho);
+    free(kappa);
+    return -1;
+  }
 
   const double theta = orc_theta(x, n, eps);
   const double theta_w = fl_w(theta, wp);
@@ -476,6 +499,7 @@ typedef struct many_job {
   double a, b;
   const double* w;
   int32_t L;
+  int32_t tail;
   const double* x;
   int32_t C;
   double eps;
@@ -509,7 +533,7 @@ static void* many_worker(void* arg) {
       pc = &cn;
     }
     uint32_t qid = jb->qids ? jb->qids[c] : (uint32_t)c;
-    int rc = orc_propagate(jb->n, jb->rp, jb->col, jb->deg, jb->a, jb->b, jb->w, jb->L,
+    int rc = orc_propagate(jb->n, jb->rp, jb->col, jb->deg, jb->a, jb->b, jb->w, jb->L, jb->tail,
                            jb->x + (size_t)c * (size_t)jb->n, jb->eps, jb->seed, qid, jb->wp,
                            jb->out + (size_t)c * (size_t)jb->n, pc);
     if (rc) {
@@ -523,11 +547,11 @@ static void* many_worker(void* arg) {
 
 int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                        const int32_t* deg, double a, double b, const double* w,
-                       int32_t L, const double* x, int32_t C, double eps,
+                       int32_t L, int32_t tail, const double* x, int32_t C, double eps,
                        uint64_t seed, const uint32_t* qids, int32_t wp,
                        double* out, uint64_t* counters, int32_t nthreads) {
   if (C < 0 || nthreads < 1) return -1;
-  many_job jb = {n, rp, col_sorted, deg, a, b, w, L, x, C, eps, seed, qids, wp, out, counters, 0, 0};
+  many_job jb = {n, rp, col_sorted, deg, a, b, w, L, tail, x, C, eps, seed, qids, wp, out, counters, 0, 0};
   pthread_mutex_init(&jb.lock, NULL);
   if (nthreads > C) nthreads = C > 0 ? C : 1;
   pthread_t* th = malloc(sizeof(pthread_t) * (size_t)nthreads);

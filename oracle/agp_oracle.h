@@ -42,8 +42,10 @@ typedef struct orc_counters {
 int orc_degree_sort(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* fdeg_in,
                     int32_t* out_col, int32_t* deg, int32_t* fdeg);
 
-/* S, Y_0..Y_{L+1}, rho_0..rho_L, kappa_0..kappa_L from w_0..w_L. */
-int orc_level_tables(const double* w, int32_t L, double* S, double* Y,
+/* S, Y_0..Y_{L+1}, rho_0..rho_L, kappa_0..kappa_L from w_0..w_L; tail != 0
+ * takes the paper-literal infinite tail Y_i = 1 - sum_{k<i} w_k (returns -1
+ * when w_0 + ... + w_L > 1 + 1e-9). */
+int orc_level_tables(const double* w, int32_t L, int32_t tail, double* S, double* Y,
                      double* rho, double* kappa);
 
 /* theta = eps * ||x||_1 with the fixed blocked summation order. */
@@ -61,13 +63,13 @@ uint64_t orc_splitmix64(uint64_t x);
 /* Exact sum of vals[0..k) rounded once to binary32 (wp = 32) or binary64. */
 double orc_exact_sum(const double* vals, int64_t k, int32_t wp);
 
-/* One column of Algorithm 2. x and out hold n values; with wp = 32 every x
+/* One column of Algorithm 2 (tail as in orc_level_tables). x and out hold n values; with wp = 32 every x
  * must be a binary32 value; deg holds the factor degrees (fdeg of
  * orc_degree_sort), the rows come from rp.  Returns 0, or -1 on invalid
  * arguments. */
 int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                   const int32_t* deg, double a, double b, const double* w,
-                  int32_t L, const double* x, double eps, uint64_t seed,
+                  int32_t L, int32_t tail, const double* x, double eps, uint64_t seed,
                   uint32_t qid, int32_t wp, double* out, orc_counters* cnt);
 
 /* Columns c = 0..C-1 of column-major x/out (x + c*n), spread over nthreads
@@ -75,7 +77,7 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
  * C x 5 x (L+1) uint64 array (frontier, hash, det, cand, acc per column). */
 int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                        const int32_t* deg, double a, double b, const double* w,
-                       int32_t L, const double* x, int32_t C, double eps,
+                       int32_t L, int32_t tail, const double* x, int32_t C, double eps,
                        uint64_t seed, const uint32_t* qids, int32_t wp,
                        double* out, uint64_t* counters, int32_t nthreads);
 

@@ -170,6 +170,39 @@ int agp_propagate_f64(const agp_graph_t* g, double a, double b, const double* w,
                       const double* x, int32_t C, double eps, uint64_t seed,
                       const uint32_t* qids, double* out, void* stream, agp_stats_t* stats);
 
+/* Paper-literal variants of the propagation (agp_propagate_variant). */
+#define AGP_VARIANT_INFINITE_TAIL 1u /* Y_i over the infinite weight sequence */
+#define AGP_VARIANT_SPLIT_SIGNS 2u   /* x+ and x- propagated separately     */
+
+/* agp_propagate with the paper-literal readings that the default replaces
+ * (same arguments and errors, plus `variant`, a set of AGP_VARIANT_* flags;
+ * 0 gives exactly agp_propagate):
+ *  AGP_VARIANT_INFINITE_TAIL  the weights are the first L + 1 terms of a
+ *     sequence whose infinite sum is 1 (Section 3, assumptions on w_i):
+ *     Y_i = T + sum_{k=i..L} w_k with T = 1 - (w_0 + ... + w_L) the mass
+ *     beyond level L (Definition 3.2), and the last level keeps only
+ *     (w_L / Y_L) r^(L) (Algorithm 2, final step); no rescaling.  Needs
+ *     w_0 + ... + w_L <= 1 (AGP_EINVAL otherwise).  Residues are larger than
+ *     with the default truncated Y_i, so the same eps costs more pushes.
+ *  AGP_VARIANT_SPLIT_SIGNS  signed signals as in Section 3 (assumption on
+ *     the graph signal): x = x+ + x-, each part propagated as its own signal
+ *     with its own threshold eps * ||x+-[:, c]||_1; column c's x+ part draws
+ *     from the random stream of query id qid_c, its x- part from that of
+ *     qid_c + 2^23 (so qids must be < 2^23); out = pi+ + pi-, rounded once.
+ *     Temporary device memory of 4 n C elements (in column tiles that fit a
+ *     quarter of the free memory) is allocated for the call.
+ * Counters in stats add up both passes of the split. */
+int agp_propagate_variant(const agp_graph_t* g, double a, double b, const double* w, int32_t L,
+                          const float* x, int32_t C, double eps, uint64_t seed,
+                          const uint32_t* qids, uint32_t variant, float* out, void* stream,
+                          agp_stats_t* stats);
+
+/* The same in binary64 (x and out are device double[n*C]). */
+int agp_propagate_variant_f64(const agp_graph_t* g, double a, double b, const double* w, int32_t L,
+                              const double* x, int32_t C, double eps, uint64_t seed,
+                              const uint32_t* qids, uint32_t variant, double* out, void* stream,
+                              agp_stats_t* stats);
+
 /* ------------------------------------------------------------------ tuning */
 
 /* Execution choices of agp_propagate that never change its results. */

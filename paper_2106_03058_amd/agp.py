@@ -24,7 +24,9 @@ EXPORTED = [
     "agp_graph_destroy", "agp_propagate", "agp_propagate_f64", "agp_weights_ppr",
     "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp", "agp_server_create", "agp_submit",
     "agp_poll", "agp_server_destroy", "agp_autotune", "agp_get_tuning", "agp_sweep",
+    "agp_propagate_variant", "agp_propagate_variant_f64",
 ]
+AGP_VARIANT_INFINITE_TAIL, AGP_VARIANT_SPLIT_SIGNS = 1, 2
 
 
 class AGPError(RuntimeError):
@@ -78,6 +80,9 @@ def lib():
                 ct.c_uint64, u32p, vp, vp, ct.POINTER(Stats)]
         L.agp_propagate.argtypes = prop
         L.agp_propagate_f64.argtypes = prop
+        var = prop[:10] + [ct.c_uint32] + prop[10:]
+        L.agp_propagate_variant.argtypes = var
+        L.agp_propagate_variant_f64.argtypes = var
         L.agp_weights_ppr.argtypes = [ct.c_double, ct.c_int32, dp]
         L.agp_weights_hkpr.argtypes = [ct.c_double, ct.c_int32, dp]
         L.agp_weights_katz.argtypes = [ct.c_double, ct.c_int32, dp]
@@ -169,12 +174,13 @@ class Graph:
 
 
 def propagate(graph: Graph, a: float, b: float, w, x, eps: float, seed: int, *, qids=None,
-              out=None, stream=None, stats: bool = False):
+              out=None, stream=None, stats: bool = False, tail: bool = False, split_signs: bool = False):
     """Run the randomized propagation on every column of x.
 
     x: CUDA tensor (n,) or (n, C), float32 (binary32 path) or float64.
     Returns (out, stats) where out has the shape and dtype of x and stats is
-    a dict of per-level counters (or None).
+    a dict of per-level counters (or None).  tail / split_signs select the
+    paper-literal variants (agp_propagate_variant).
     """
     import torch
 
@@ -198,13 +204,20 @@ def propagate(graph: Graph, a: float, b: float, w, x, eps: float, seed: int, *, 
         if q.size != C:
             raise ValueError("need one qid per column")
     st = Stats() if stats else None
-    fn = {torch.float32: lib().agp_propagate, torch.float64: lib().agp_propagate_f64}.get(X.dtype)
-    if fn is None:
+    variant = (AGP_VARIANT_INFINITE_TAIL if tail else 0) | (AGP_VARIANT_SPLIT_SIGNS if split_signs else 0)
+    if X.dtype == torch.float32:
+        fn = lib().agp_propagate_variant if variant else lib().agp_propagate
+    elif X.dtype == torch.float64:
+        fn = lib().agp_propagate_variant_f64 if variant else lib().agp_propagate_f64
+    else:
         raise ValueError("x must be float32 or float64")
-    _check(fn(graph.handle, float(a), float(b), w.ctypes.data_as(ct.POINTER(ct.c_double)), L,
-              _dptr(X), C, float(eps), ct.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF),
-              None if q is None else q.ctypes.data_as(ct.POINTER(ct.c_uint32)), _dptr(o),
-              _stream_ptr(stream), ct.byref(st) if st is not None else None))
+    args = [graph.handle, float(a), float(b), w.ctypes.data_as(ct.POINTER(ct.c_double)), L,
+            _dptr(X), C, float(eps), ct.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF),
+            None if q is None else q.ctypes.data_as(ct.POINTER(ct.c_uint32))]
+    if variant:
+        args.append(variant)
+    args += [_dptr(o), _stream_ptr(stream), ct.byref(st) if st is not None else None]
+    _check(fn(*args))
     res = o.reshape(-1) if vec else o
     return res, (st.to_dict() if st is not None else None)
 

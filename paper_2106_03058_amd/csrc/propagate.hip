@@ -25,6 +25,9 @@
 namespace agp {
 namespace {
 
+// query-id offset of the x- part of a column under the literal sign split
+constexpr uint32_t kSplitQid = 1u << 23;
+
 using namespace lvl;
 
 // ---------------------------------------------------------- thresholds
@@ -374,7 +377,8 @@ int32_t column_tile(agp_graph* g, int32_t C, bool binned) {
 template <typename T>
 int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L, const T* x,
                    int32_t C, double eps, uint64_t seed, const uint32_t* qids, T* out,
-                   hipStream_t s, agp_stats_t* stats, const agp_tuning_t* force = nullptr) {
+                   hipStream_t s, agp_stats_t* stats, const agp_tuning_t* force = nullptr,
+                   bool tail = false) {
   const char* fn = sizeof(T) == 4 ? "agp_propagate" : "agp_propagate_f64";
   if (!g) return fail(AGP_EINVAL, std::string(fn) + ": NULL graph");
   if (!(a >= 0.0 && a <= 1.0) || !(b >= 0.0 && b <= 1.0))
@@ -399,14 +403,26 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   if (n > 0 && cells / static_cast<size_t>(n) != static_cast<size_t>(C))
     return fail(AGP_EINVAL, std::string(fn) + ": n * C overflows");
 
-  // level tables in binary64: Y_i = sum_{k=i..L} w_k added from k = L down,
-  // S = Y_0, rho_i = Y_{i+1} / Y_i, kappa_i = (S w_i) / Y_i
+  // level tables in binary64: Y_i = Y_{L+1} + sum_{k=i..L} w_k added from
+  // k = L down, S = Y_0, rho_i = Y_{i+1} / Y_i (0 at i = L), kappa_i =
+  // (S w_i) / Y_i.  Y_{L+1} = 0 (weights beyond L are 0), or with the
+  // infinite tail the mass 1 - (w_0 + ... + w_L) of the terms beyond L
+  // (Definition 3.2 for a sequence summing to 1), dropped after level L.
+  double tail_mass = 0.0;
+  if (tail) {
+    double total = 0.0;
+    for (int32_t k = 0; k <= L; ++k) total += w[k];
+    if (!(total <= 1.0 + 1e-9))
+      return fail(AGP_EINVAL, std::string(fn) + ": the infinite tail needs w_0 + ... + w_L <= 1");
+    tail_mass = total < 1.0 ? 1.0 - total : 0.0;
+  }
   std::vector<double> Y(static_cast<size_t>(L) + 2, 0.0), rho(static_cast<size_t>(L) + 1),
       kappa(static_cast<size_t>(L) + 1);
+  Y[static_cast<size_t>(L) + 1] = tail_mass;
   for (int32_t k = L; k >= 0; --k) Y[k] = Y[k + 1] + w[k];
   const double S = Y[0];
   for (int32_t i = 0; i <= L; ++i) {
-    rho[i] = (Y[i] == 0.0) ? 0.0 : Y[i + 1] / Y[i];
+    rho[i] = (Y[i] == 0.0 || i == L) ? 0.0 : Y[i + 1] / Y[i];
     kappa[i] = (Y[i] == 0.0) ? 0.0 : (S * w[i]) / Y[i];
   }
 
@@ -427,6 +443,124 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
     stats->columns = C;
   }
   return AGP_OK;
+}
+
+// ------------------------------------------------- literal sign split
+// x (n x C, rows ld apart) -> x2 (n x 2C): columns [0, C) hold the positive
+// entries, [C, 2C) the negative ones (zeros elsewhere).
+template <typename T>
+__global__ void k_split_signs(const T* __restrict__ x, long long ld, int64_t n, int C, T* __restrict__ x2) {
+  const int64_t total = n * C;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = i / C;
+    const int c = static_cast<int>(i - u * C);
+    const T v = x[u * ld + c];
+    T* row = x2 + u * (2 * static_cast<int64_t>(C));
+    row[c] = v > T(0) ? v : T(0);
+    row[C + c] = v < T(0) ? v : T(0);
+  }
+}
+
+// out[u, c] = o2[u, c] + o2[u, C + c], rounded once.
+template <typename T>
+__global__ void k_join_signs(const T* __restrict__ o2, int64_t n, int C, T* __restrict__ out, long long ld) {
+  const int64_t total = n * C;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = i / C;
+    const int c = static_cast<int>(i - u * C);
+    const T* row = o2 + u * (2 * static_cast<int64_t>(C));
+    out[u * ld + c] = row[c] + row[C + c];
+  }
+}
+
+void add_stats(agp_stats_t* into, const agp_stats_t& part) {
+  for (int i = 0; i <= AGP_MAX_LEVELS; ++i) {
+    into->frontier[i] += part.frontier[i];
+    into->hash[i] += part.hash[i];
+    into->det[i] += part.det[i];
+    into->cand[i] += part.cand[i];
+    into->acc[i] += part.acc[i];
+    into->level_ms[i] += part.level_ms[i];
+  }
+  into->device_ms += part.device_ms;
+}
+
+// The literal treatment of signed signals (Section 3, assumption on the
+// graph signal): per tile of columns, x+ and x- as 2 ct columns of one
+// batched call (column c's x- part on the stream of query id qid_c + 2^23),
+// then pi = pi+ + pi-.
+template <typename T>
+int propagate_split(agp_graph* g, double a, double b, const double* w, int32_t L, const T* x, int32_t C,
+                    double eps, uint64_t seed, const uint32_t* qids, T* out, hipStream_t s, agp_stats_t* stats,
+                    bool tail) {
+  const char* fn = sizeof(T) == 4 ? "agp_propagate_variant" : "agp_propagate_variant_f64";
+  if (!g || !x || !out || !w) return fail(AGP_EINVAL, std::string(fn) + ": NULL argument");
+  if (C < 1) return fail(AGP_EINVAL, std::string(fn) + ": need C >= 1");
+  if (qids) {
+    for (int32_t c = 0; c < C; ++c)
+      if (qids[c] >= kSplitQid) return fail(AGP_EINVAL, std::string(fn) + ": the sign split needs qids < 2^23");
+  } else if (C > static_cast<int32_t>(kSplitQid)) {
+    return fail(AGP_EINVAL, std::string(fn) + ": the sign split needs C <= 2^23 without qids");
+  }
+  const int64_t n = g->n;
+  if (n == 0) return propagate_impl<T>(g, a, b, w, L, x, C, eps, seed, qids, out, s, stats, nullptr, tail);
+  // tiles of columns whose doubled signal and result take at most a quarter
+  // of the free memory
+  size_t free_b = 0, total_b = 0;
+  AGP_HIP(hipMemGetInfo(&free_b, &total_b));
+  const double per_col = 4.0 * static_cast<double>(n) * sizeof(T);
+  int32_t tile = static_cast<int32_t>(std::min<double>(C, std::max(1.0, 0.25 * free_b / per_col)));
+  DevBuf x2, o2;
+  int rc;
+  if ((rc = x2.reserve(static_cast<size_t>(n) * 2 * tile * sizeof(T), false, s)) ||
+      (rc = o2.reserve(static_cast<size_t>(n) * 2 * tile * sizeof(T), false, s))) {
+    x2.release();
+    o2.release();
+    return rc;
+  }
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  std::vector<uint32_t> q2(2 * static_cast<size_t>(tile));
+  for (int32_t c0 = 0; c0 < C && rc == AGP_OK; c0 += tile) {
+    const int32_t ct = std::min(tile, C - c0);
+    for (int32_t c = 0; c < ct; ++c) {
+      const uint32_t q = qids ? qids[c0 + c] : static_cast<uint32_t>(c0 + c);
+      q2[c] = q;
+      q2[ct + c] = q + kSplitQid;
+    }
+    const unsigned grid = static_cast<unsigned>(std::min<int64_t>((n * ct + 255) / 256, 65536));
+    k_split_signs<T><<<grid, 256, 0, s>>>(x + c0, static_cast<long long>(C), n, ct, x2.as<T>());
+    agp_stats_t part;
+    rc = propagate_impl<T>(g, a, b, w, L, x2.as<T>(), 2 * ct, eps, seed, q2.data(), o2.as<T>(), s,
+                           stats ? &part : nullptr, nullptr, tail);
+    if (rc != AGP_OK) break;
+    k_join_signs<T><<<grid, 256, 0, s>>>(o2.as<T>(), n, ct, out + c0, static_cast<long long>(C));
+    if (stats) add_stats(stats, part);
+  }
+  if (rc == AGP_OK) {
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(AGP_EDEVICE, std::string(fn) + ": " + hipGetErrorString(e));
+  }
+  x2.release();
+  o2.release();
+  if (rc == AGP_OK && stats) {
+    stats->levels = L;
+    stats->columns = C;
+  }
+  return rc;
+}
+
+template <typename T>
+int propagate_variant(const agp_graph_t* g, double a, double b, const double* w, int32_t L, const T* x, int32_t C,
+                      double eps, uint64_t seed, const uint32_t* qids, uint32_t variant, T* out, void* stream,
+                      agp_stats_t* stats) {
+  const char* fn = sizeof(T) == 4 ? "agp_propagate_variant" : "agp_propagate_variant_f64";
+  if (variant & ~(AGP_VARIANT_INFINITE_TAIL | AGP_VARIANT_SPLIT_SIGNS))
+    return fail(AGP_EINVAL, std::string(fn) + ": unknown variant flag");
+  const bool tail = (variant & AGP_VARIANT_INFINITE_TAIL) != 0;
+  agp_graph* gg = const_cast<agp_graph*>(g);
+  if (variant & AGP_VARIANT_SPLIT_SIGNS)
+    return propagate_split<T>(gg, a, b, w, L, x, C, eps, seed, qids, out, (hipStream_t)stream, stats, tail);
+  return propagate_impl<T>(gg, a, b, w, L, x, C, eps, seed, qids, out, (hipStream_t)stream, stats, nullptr, tail);
 }
 
 }  // namespace
@@ -496,6 +630,18 @@ int agp_propagate_f64(const agp_graph_t* g, double a, double b, const double* w,
                       double* out, void* stream, agp_stats_t* stats) {
   return agp::propagate_impl<double>(const_cast<agp_graph_t*>(g), a, b, w, L, x, C, eps, seed, qids, out,
                                      (hipStream_t)stream, stats);
+}
+
+int agp_propagate_variant(const agp_graph_t* g, double a, double b, const double* w, int32_t L, const float* x,
+                          int32_t C, double eps, uint64_t seed, const uint32_t* qids, uint32_t variant, float* out,
+                          void* stream, agp_stats_t* stats) {
+  return agp::propagate_variant<float>(g, a, b, w, L, x, C, eps, seed, qids, variant, out, stream, stats);
+}
+
+int agp_propagate_variant_f64(const agp_graph_t* g, double a, double b, const double* w, int32_t L,
+                              const double* x, int32_t C, double eps, uint64_t seed, const uint32_t* qids,
+                              uint32_t variant, double* out, void* stream, agp_stats_t* stats) {
+  return agp::propagate_variant<double>(g, a, b, w, L, x, C, eps, seed, qids, variant, out, stream, stats);
 }
 
 }  // extern "C"

@@ -1,0 +1,144 @@
+"""Paper-literal variants on the HIP path, through the C ABI: the infinite-tail
+Y_i (Definition 3.2 for a weight sequence summing to 1, Algorithm 2's final
+step) and signed signals split into x+ and x- (Section 3, assumption on the
+graph signal).  Estimates and counters bit-exact with the oracle."""
+import ctypes as ct
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_03058_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_03058_amd import agp
+
+    agp.lib()
+    g = inputs.chung_lu(6000, 8, 2.2, seed=41)
+    G = agp.Graph.from_inputs(g)
+    return torch, agp, g, G, oracle.degree_sort(g)
+
+
+MODELS = {
+    # (a, b, weights, eps)
+    "ppr": (0.0, 1.0, inputs.weights_ppr(0.2, 15), 1e-5),
+    "hkpr": (0.0, 1.0, inputs.weights_hkpr(5.0, 20), 1e-5),
+    "appnp": (0.5, 0.5, inputs.weights_ppr(0.1, 10), 1e-4),
+    "general": (0.3, 0.6, inputs.weights_hkpr(3.0, 12), 1e-4),
+}
+
+
+def _signal(g, kind, C, seed):
+    if kind == "onehot":
+        src = np.random.default_rng(seed).choice(np.flatnonzero(np.diff(g.row_ptr) > 0), size=C, replace=False)
+        return inputs.one_hot(g.n, src)
+    return inputs.features_normal(g.n, C, seed=seed)
+
+
+def _check(st, cnt, L):
+    for k in ("frontier", "hash", "det", "cand", "acc"):
+        assert np.array_equal(st[k][: L + 1], cnt[k].sum(axis=0).astype(np.uint64)[: L + 1]), k
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("tail,split", [(True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("C", [1, 7])
+def test_variant_parity(env, name, tail, split, C):
+    torch, agp, g, G, sg = env
+    a, b, w, eps = MODELS[name]
+    x = _signal(g, "normal" if split or name in ("appnp", "general") else "onehot", C, seed=C + 3)
+    qids = np.array([5 * c + 2 for c in range(C)], dtype=np.uint32)
+    X = torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+    out, st = agp.propagate(G, a, b, w, X, eps, 29, qids=qids, stats=True, tail=tail, split_signs=split)
+    got = out.cpu().numpy().astype(np.float64)
+    ref, cnt = oracle.propagate(sg, a, b, w, x.astype(np.float32), eps, 29, wp=32, qids=qids, tail=tail,
+                                split_signs=split)
+    assert np.array_equal(got, ref), f"max diff {np.abs(got - ref).max()}"
+    _check(st, cnt, len(w) - 1)
+    assert st["cand"].sum() > 0
+
+
+@pytest.mark.parametrize("tail,split", [(True, False), (False, True), (True, True)])
+def test_variant_parity_binary64(env, tail, split):
+    torch, agp, g, G, sg = env
+    a, b, w, eps = MODELS["general"]
+    x = _signal(g, "normal", 3, seed=77)
+    out, st = agp.propagate(G, a, b, w, torch.from_numpy(x.astype(np.float64)).to("cuda:0"), eps, 5, stats=True,
+                            tail=tail, split_signs=split)
+    ref, cnt = oracle.propagate(sg, a, b, w, x.astype(np.float64), eps, 5, wp=64, tail=tail, split_signs=split)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    _check(st, cnt, len(w) - 1)
+
+
+def test_variant_zero_is_the_default_call(env):
+    torch, agp, g, G, sg = env
+    a, b, w, eps = MODELS["appnp"]
+    X = torch.from_numpy(_signal(g, "normal", 4, seed=9)).to("cuda:0")
+    ref, _ = agp.propagate(G, a, b, w, X, eps, 8)
+    out = torch.empty_like(X)
+    L = agp.lib()
+    wd = np.ascontiguousarray(w, dtype=np.float64)
+    rc = L.agp_propagate_variant(G.handle, a, b, wd.ctypes.data_as(ct.POINTER(ct.c_double)), len(w) - 1,
+                                 X.data_ptr(), 4, eps, ct.c_uint64(8), None, 0, out.data_ptr(),
+                                 torch.cuda.current_stream().cuda_stream, None)
+    torch.cuda.synchronize()
+    assert rc == 0 and torch.equal(out, ref)
+
+
+def test_split_of_a_nonnegative_signal_is_the_default(env):
+    torch, agp, g, G, sg = env
+    a, b, w, eps = MODELS["ppr"]
+    X = torch.from_numpy(_signal(g, "onehot", 5, seed=2)).to("cuda:0")
+    ref, st0 = agp.propagate(G, a, b, w, X, eps, 3, stats=True)
+    out, st1 = agp.propagate(G, a, b, w, X, eps, 3, stats=True, split_signs=True)
+    assert torch.equal(out, ref)
+    for k in ("det", "acc", "cand", "frontier"):
+        assert np.array_equal(st0[k], st1[k])
+
+
+def test_tail_equals_the_default_for_weights_summing_to_one(env):
+    torch, agp, g, G, sg = env
+    X = torch.from_numpy(_signal(g, "onehot", 3, seed=4)).to("cuda:0")
+    for w in (inputs.weights_tp(6), np.array([0.25, 0.25, 0.25, 0.25])):
+        ref, _ = agp.propagate(G, 0.0, 1.0, w, X, 1e-5, 12)
+        out, _ = agp.propagate(G, 0.0, 1.0, w, X, 1e-5, 12, tail=True)
+        assert torch.equal(out, ref)
+
+
+def test_variant_errors(env):
+    torch, agp, g, G, sg = env
+    X = torch.from_numpy(_signal(g, "onehot", 2, seed=4)).to("cuda:0")
+    with pytest.raises(agp.AGPError) as e:  # Katz weights do not sum to at most 1
+        agp.propagate(G, 0.0, 0.0, inputs.weights_katz(0.5, 10), X, 1e-5, 1, tail=True)
+    assert e.value.code == agp.AGP_EINVAL
+    with pytest.raises(agp.AGPError) as e:  # the x- streams need the top qid bit free
+        agp.propagate(G, 0.0, 1.0, inputs.weights_ppr(0.2, 5), X, 1e-5, 1, qids=[1, 1 << 23], split_signs=True)
+    assert e.value.code == agp.AGP_EINVAL
+    w = np.ascontiguousarray(inputs.weights_ppr(0.2, 5))
+    out = torch.empty_like(X)
+    rc = agp.lib().agp_propagate_variant(G.handle, 0.0, 1.0, w.ctypes.data_as(ct.POINTER(ct.c_double)), 5,
+                                         X.data_ptr(), 2, 1e-5, ct.c_uint64(1), None, 4, out.data_ptr(),
+                                         torch.cuda.current_stream().cuda_stream, None)
+    assert rc == agp.AGP_EINVAL
+
+
+def test_split_in_column_tiles(env, monkeypatch):
+    """Many columns: the split call equals column-by-column split calls
+    (results depend on the column's own query id only)."""
+    torch, agp, g, G, sg = env
+    a, b, w, eps = MODELS["appnp"]
+    x = _signal(g, "normal", 24, seed=31)
+    X = torch.from_numpy(x).to("cuda:0")
+    q = np.arange(100, 124, dtype=np.uint32)
+    out, _ = agp.propagate(G, a, b, w, X, eps, 6, qids=q, split_signs=True)
+    for c in (0, 11, 23):
+        one, _ = agp.propagate(G, a, b, w, X[:, c:c + 1].contiguous(), eps, 6, qids=q[c:c + 1], split_signs=True)
+        assert torch.equal(one[:, 0], out[:, c])

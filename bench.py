@@ -22,6 +22,8 @@ Other workloads:
   `--workload cluster`: local clustering, heat kernel PageRank (t = 5,
     L = 20, eps = 1e-7) from 64 seeds and the minimum-conductance sweep of
     each, on an Orkut-shaped Chung-Lu graph (3.07M nodes, 117M edges).
+  `--workload variants`: the paper-literal x+/x- split and infinite-tail
+    Y_i against the defaults (time, pushes, error against the exact sum).
   `--workload directed`: PPR from 256 sources along out-edges and
     single-target PPR to 256 targets along in-edges (alpha = 0.2, L = 20,
     eps = 1e-7) on a directed R-MAT scale 22 (arcs as generated).
@@ -530,13 +532,102 @@ def run_cluster(args) -> dict:
     return result
 
 
+def run_variants(args) -> dict:
+    """The paper-literal variants against the defaults, each at the same eps,
+    on a Chung-Lu graph generated on the GPU (n = 2.4M, mean degree 50,
+    exponent 2.5, one loop per node):
+      * signed features (GNN heat kernel, a = b = 1/2, t = 5, L = 10,
+        eps = 1e-7, 32 N(0,1) columns): one signed pass against x+ and x-
+        propagated separately;
+      * PPR (alpha = 0.2, L = 20, a = 0, b = 1, eps = 1e-7) from 64 sources:
+        truncated Y_i against the infinite-tail Y_i.
+    Reported per case: time and edge pushes per call, and the error against
+    the exact FP64 sum of Eq. 1 on two columns (sparse Horner on the host)."""
+    import torch
+
+    from oracle import dense
+    from paper_2106_03058_amd import agp, inputs
+
+    dev = torch.device("cuda:0")
+    n = 2_400_000
+    t = time.time()
+    _, rp, col = inputs.chung_lu_device(n, 50.0, 2.5, seed=3, target_edges=n * 25, device=dev)
+    host = inputs.add_self_loops(n, rp.cpu().numpy(), col.cpu().numpy())
+    G = agp.Graph(rp, col, self_loops=True)
+    deg = (rp[1:] - rp[:-1]).cpu().numpy()
+    del rp, col
+    torch.cuda.empty_cache()
+    log(f"chung-lu n={n} with loops: {G.nnz} arcs in {time.time() - t:.1f}s")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(303)
+    Xf = torch.randn((n, 32), generator=gen, device=dev, dtype=torch.float32)
+    src = np.random.default_rng(102).choice(np.flatnonzero(deg >= 1), size=64, replace=False)
+    Xs = torch.zeros((n, 64), dtype=torch.float32, device=dev)
+    Xs[torch.from_numpy(src).to(dev), torch.arange(64, device=dev)] = 1.0
+    cases = [
+        ("signed_one_pass", Xf, 0.5, 0.5, inputs.weights_hkpr(5.0, 10), {}),
+        ("signed_split", Xf, 0.5, 0.5, inputs.weights_hkpr(5.0, 10), {"split_signs": True}),
+        ("ppr_truncated_Y", Xs, 0.0, 1.0, inputs.weights_ppr(0.2, 20), {}),
+        ("ppr_infinite_tail", Xs, 0.0, 1.0, inputs.weights_ppr(0.2, 20), {"tail": True}),
+    ]
+    res = {}
+    exact_cache = {}
+    for name, X, a, b, w, kw in cases:
+        out = torch.empty_like(X)
+        for _ in range(args.warmup):
+            agp.propagate(G, a, b, w, X, 1e-7, args.seed, out=out, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, st = agp.propagate(G, a, b, w, X, 1e-7, args.seed, out=out, stats=True, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        cols = [0, 1]
+        got = out[:, cols].cpu().numpy().astype(np.float64)
+        xh = X[:, cols].cpu().numpy().astype(np.float64)
+        te = time.time()
+        key = (id(X), a, b, len(w))
+        if key not in exact_cache:  # both cases of a pair share the exact sum
+            exact_cache[key] = dense.horner_sparse(host, a, b, w, xh)
+        exact = exact_cache[key]
+        diff = np.abs(got - exact)
+        res[name] = {"ms_per_call": ms, "columns": X.shape[1], "edge_pushes": int(st["pushes"]),
+                     "edge_pushes_per_s": st["pushes"] / (ms / 1e3),
+                     "max_abs_err": float(diff.max()),
+                     "rel_l1_err": float(diff.sum() / np.abs(exact).sum()),
+                     "rel_l2_err": float(np.sqrt((diff ** 2).sum() / (exact ** 2).sum()))}
+        log(f"{name}: {ms:.1f} ms, {st['pushes']:.3e} pushes, rel l1 {res[name]['rel_l1_err']:.3e} "
+            f"(exact {time.time() - te:.1f}s)")
+    base = res["signed_one_pass"]
+    return {
+        "metric": "edge-pushes/s (default one-pass signed propagation; variants alongside)",
+        "value": base["edge_pushes_per_s"],
+        "unit": "edge-pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": base["ms_per_call"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "paper-literal variants vs defaults at eps=1e-7: split signs (gnn hkpr, 32 N(0,1) "
+                               "columns) and infinite-tail Y_i (ppr from 64 sources), chung-lu n=2.4M d=50 + loops",
+                   "graph": {"n": n, "arcs": G.nnz}},
+        "cases": res,
+        "split_cost_ratio": res["signed_split"]["ms_per_call"] / base["ms_per_call"],
+        "tail_cost_ratio": res["ppr_infinite_tail"]["ms_per_call"] / res["ppr_truncated_Y"]["ms_per_call"],
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2021)
-    ap.add_argument("--workload", default="katz-tp", choices=sorted(WORKLOADS) + ["serve", "cluster"])
+    ap.add_argument("--workload", default="katz-tp", choices=sorted(WORKLOADS) + ["serve", "cluster", "variants"])
     ap.add_argument("--queries", type=int, default=1024, help="serve: queries in the stream")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: offered arrivals per second")
     ap.add_argument("--slots", type=int, default=64, help="serve: server slots")
@@ -570,6 +661,9 @@ def main() -> int:
         return 0
     if args.workload == "cluster":
         print(json.dumps(run_cluster(args)), flush=True)
+        return 0
+    if args.workload == "variants":
+        print(json.dumps(run_variants(args)), flush=True)
         return 0
     W = WORKLOADS[args.workload](args)
     models, cfg, unit_name, n = W["models"], W["cfg"], W["unit"], W["n"]

@@ -598,6 +598,22 @@ def run_variants(args) -> dict:
                      "rel_l2_err": float(np.sqrt((diff ** 2).sum() / (exact ** 2).sum()))}
         log(f"{name}: {ms:.1f} ms, {st['pushes']:.3e} pushes, rel l1 {res[name]['rel_l1_err']:.3e} "
             f"(exact {time.time() - te:.1f}s)")
+    # full-size parity of one sampled column of each variant against the oracle
+    import oracle
+
+    t = time.time()
+    sg = oracle.degree_sort(host)
+    parity = {}
+    for name, X, a, b, w, kw in cases:
+        if not kw:
+            continue
+        c = int(np.random.default_rng(55).integers(X.shape[1]))
+        out = torch.empty_like(X)
+        agp.propagate(G, a, b, w, X, 1e-7, args.seed, out=out, **kw)
+        xc = X[:, c].cpu().numpy().astype(np.float64)
+        ref, _ = oracle.propagate(sg, a, b, w, xc, 1e-7, args.seed, qids=[c], **kw)
+        parity[name] = {"column": c, "bit_exact": bool(np.array_equal(out[:, c].cpu().numpy().astype(np.float64), ref))}
+    log(f"variant parity {parity} in {time.time() - t:.1f}s")
     base = res["signed_one_pass"]
     return {
         "metric": "edge-pushes/s (default one-pass signed propagation; variants alongside)",
@@ -616,6 +632,7 @@ def run_variants(args) -> dict:
                                "columns) and infinite-tail Y_i (ppr from 64 sources), chung-lu n=2.4M d=50 + loops",
                    "graph": {"n": n, "arcs": G.nnz}},
         "cases": res,
+        "parity_full_size": parity,
         "split_cost_ratio": res["signed_split"]["ms_per_call"] / base["ms_per_call"],
         "tail_cost_ratio": res["ppr_infinite_tail"]["ms_per_call"] / res["ppr_truncated_Y"]["ms_per_call"],
     }

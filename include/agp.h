@@ -318,6 +318,18 @@ int agp_server_destroy(agp_server_t* s);
 int agp_sweep(const agp_graph_t* g, const float* pi, int64_t ld, void* stream, int64_t* best_size,
               double* best_conductance, int32_t* order);
 
+/* agp_sweep of C estimates at once: column c is pi[v * ld + c] (1 <= C <=
+ * ld; e.g. an n x C agp_propagate result with ld = C).  best_size and
+ * best_conductance are host arrays of C entries, each what agp_sweep gives
+ * for that column.  Columns are processed in groups of up to 64 (fewer when
+ * a group's working memory of about 40 n bytes per column would exceed a
+ * quarter of the free memory), each column with its own sort and each group
+ * with one pass over the arcs.  Working memory is kept with the graph like
+ * agp_sweep's.  Synchronous on `stream`.  Errors: AGP_EINVAL (NULL argument,
+ * C < 1 or ld < C, directed graph), AGP_ENOMEM, AGP_EDEVICE. */
+int agp_sweep_batch(const agp_graph_t* g, const float* pi, int64_t ld, int32_t C, void* stream,
+                    int64_t* best_size, double* best_conductance);
+
 /* ------------------------------------------- weight sequences (Table 1) */
 
 /* w_i = alpha (1 - alpha)^i, i = 0..L (PageRank, PPR, APPNP). */

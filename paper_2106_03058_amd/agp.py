@@ -24,7 +24,7 @@ EXPORTED = [
     "agp_graph_destroy", "agp_propagate", "agp_propagate_f64", "agp_weights_ppr",
     "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp", "agp_server_create", "agp_submit",
     "agp_poll", "agp_server_destroy", "agp_autotune", "agp_get_tuning", "agp_sweep",
-    "agp_propagate_variant", "agp_propagate_variant_f64",
+    "agp_propagate_variant", "agp_propagate_variant_f64", "agp_sweep_batch",
 ]
 AGP_VARIANT_INFINITE_TAIL, AGP_VARIANT_SPLIT_SIGNS = 1, 2
 
@@ -88,6 +88,7 @@ def lib():
         L.agp_weights_katz.argtypes = [ct.c_double, ct.c_int32, dp]
         L.agp_weights_tp.argtypes = [ct.c_int32, dp]
         L.agp_sweep.argtypes = [vp, vp, ct.c_int64, vp, i64p, dp, vp]
+        L.agp_sweep_batch.argtypes = [vp, vp, ct.c_int64, ct.c_int32, vp, i64p, dp]
         _lib = L
     return _lib
 
@@ -288,6 +289,27 @@ def sweep(graph: Graph, pi, *, order: bool = True, stream=None):
     _check(lib().agp_sweep(graph.handle, _dptr(pi), ld, _stream_ptr(stream), ct.byref(size), ct.byref(phi),
                            None if o is None else _dptr(o)))
     return size.value, phi.value, o
+
+
+def sweep_batch(graph: Graph, pis, *, stream=None):
+    """Sweeps of many estimates at once: pis is a float32 CUDA tensor of
+    shape (n, C) whose rows are contiguous (e.g. an agp_propagate result or
+    a slice of its columns).  Returns (best_size, best_conductance) as host
+    arrays of C entries, each equal to sweep() of that column."""
+    import torch
+
+    if not pis.is_cuda or pis.dtype != torch.float32 or pis.dim() != 2 or pis.shape[0] != graph.n:
+        raise ValueError("pis must be a 2-d float32 device tensor with n rows")
+    C = pis.shape[1]
+    if C < 1 or (graph.n > 1 and pis.stride(1) != 1):
+        raise ValueError("pis needs at least one column and contiguous rows")
+    ld = pis.stride(0) if graph.n > 1 else C
+    size = np.zeros(C, dtype=np.int64)
+    phi = np.zeros(C, dtype=np.float64)
+    _check(lib().agp_sweep_batch(graph.handle, _dptr(pis), max(ld, C), C, _stream_ptr(stream),
+                                 size.ctypes.data_as(ct.POINTER(ct.c_int64)),
+                                 phi.ctypes.data_as(ct.POINTER(ct.c_double))))
+    return size, phi
 
 
 def _weights(fn, *args, L: int) -> np.ndarray:

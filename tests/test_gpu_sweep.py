@@ -161,3 +161,51 @@ def test_sweep_of_strided_columns(env):
         s2, p2, o2 = agp.sweep(G, P[:, c].contiguous())
         assert (s1, p1) == (s2, p2) and torch.equal(o1, o2)
         _assert_same((s1, p1, o1.cpu().numpy()), oracle.sweep(g, P[:, c].cpu().numpy().astype(np.float64)))
+
+
+@pytest.mark.parametrize("n,C,loops", [(300, 5, False), (4000, 64, True), (20000, 70, False)])
+def test_sweep_batch_equals_the_oracle(env, n, C, loops):
+    """The batched sweep (groups of up to 64 columns, one segmented sort and
+    one arc pass per group) gives every column's size and Phi bit-exact."""
+    torch, agp = env
+    g = inputs.chung_lu(n, 6, 2.3, seed=C)
+    G = agp.Graph.from_inputs(g, self_loops=loops)
+    og = inputs.add_self_loops(g.n, g.row_ptr, g.col) if loops else g
+    P = np.stack([_sparse_pi(n, 100 + c, density=0.05 + 0.9 * (c % 3) / 2) for c in range(C)], axis=1)
+    P[:, 1] = 0.0  # a column without estimate: all ties, order by id
+    size, phi = agp.sweep_batch(G, torch.from_numpy(P).to("cuda:0"))
+    for c in range(C):
+        rs, rphi, _ = oracle.sweep(og, P[:, c].astype(np.float64))
+        assert (size[c], phi[c]) == (rs, rphi) or (size[c] == rs == 0 and math.isinf(phi[c])), c
+
+
+def test_sweep_batch_of_propagation_columns(env):
+    """Heat-kernel estimates of 40 seeds (computed by the oracle) swept in
+    one call, as strided columns of the n x 48 block they sit in."""
+    torch, agp = env
+    g = inputs.chung_lu(30000, 10, 2.1, seed=9)
+    s = np.random.default_rng(3).choice(np.flatnonzero(np.diff(g.row_ptr) > 0), size=48, replace=False)
+    ref, _ = oracle.propagate(oracle.degree_sort(g), 0.0, 1.0, inputs.weights_hkpr(5.0, 15),
+                              inputs.one_hot(g.n, s), 1e-5, 4, wp=32)
+    G = agp.Graph.from_inputs(g)
+    X = torch.from_numpy(ref.astype(np.float32)).to("cuda:0")
+    size, phi = agp.sweep_batch(G, X[:, 8:48])
+    for c in range(40):
+        rs, rphi, _ = oracle.sweep(g, ref[:, 8 + c])
+        assert (size[c], phi[c]) == (rs, rphi), c
+
+
+def test_sweep_batch_full_size(env):
+    """64 sparse estimates on a 2^20-node power-law graph: size and Phi of
+    every column against the oracle (a sample of 8) and against agp_sweep."""
+    torch, agp = env
+    g = inputs.chung_lu(1 << 20, 12, 2.1, seed=17)
+    G = agp.Graph.from_inputs(g)
+    P = torch.from_numpy(np.stack([_sparse_pi(g.n, 500 + c, density=0.1) for c in range(64)], axis=1)).to("cuda:0")
+    size, phi = agp.sweep_batch(G, P)
+    for c in range(64):
+        s1, p1, _ = agp.sweep(G, P[:, c], order=False)
+        assert (size[c], phi[c]) == (s1, p1), c
+    for c in range(0, 64, 8):
+        rs, rphi, _ = oracle.sweep(g, P[:, c].cpu().numpy().astype(np.float64))
+        assert (size[c], phi[c]) == (rs, rphi), c

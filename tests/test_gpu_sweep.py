@@ -209,3 +209,20 @@ def test_sweep_batch_full_size(env):
     for c in range(0, 64, 8):
         rs, rphi, _ = oracle.sweep(g, P[:, c].cpu().numpy().astype(np.float64))
         assert (size[c], phi[c]) == (rs, rphi), c
+
+
+def test_sweep_batch_degenerate(env):
+    torch, agp = env
+    g1 = inputs.Graph(1, np.array([0, 0]), np.array([], dtype=np.int32))
+    size, phi = agp.sweep_batch(agp.Graph.from_inputs(g1), torch.ones((1, 3), device="cuda:0"))
+    assert list(size) == [0, 0, 0] and np.all(np.isinf(phi))
+    g0 = inputs.Graph(4, np.zeros(5, dtype=np.int64), np.array([], dtype=np.int32))
+    size, phi = agp.sweep_batch(agp.Graph.from_inputs(g0), torch.ones((4, 2), device="cuda:0"))
+    assert list(size) == [0, 0] and np.all(np.isinf(phi))
+    g = inputs.chung_lu(500, 4, 2.5, seed=2)
+    G = agp.Graph.from_inputs(g)
+    with pytest.raises(ValueError):
+        agp.sweep_batch(G, torch.ones((500, 4), device="cuda:0").t())  # columns not contiguous in rows
+    d = inputs.directed_chung_lu(300, 4, 2.5, seed=6)
+    with pytest.raises(agp.AGPError):
+        agp.sweep_batch(agp.Graph.from_inputs(d, directed=True), torch.zeros((300, 2), device="cuda:0"))

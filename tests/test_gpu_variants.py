@@ -142,3 +142,16 @@ def test_split_in_column_tiles(env, monkeypatch):
     for c in (0, 11, 23):
         one, _ = agp.propagate(G, a, b, w, X[:, c:c + 1].contiguous(), eps, 6, qids=q[c:c + 1], split_signs=True)
         assert torch.equal(one[:, 0], out[:, c])
+
+
+def test_variants_at_level_zero_and_one(env):
+    """L = 0 (the estimate is w_0 x: no push) and L = 1, both variants."""
+    torch, agp, g, G, sg = env
+    x = _signal(g, "normal", 3, seed=12)
+    X = torch.from_numpy(x).to("cuda:0")
+    for w in (np.array([0.4]), np.array([0.3, 0.5])):
+        for tail, split in ((True, False), (False, True), (True, True)):
+            out, _ = agp.propagate(G, 0.5, 0.5, w, X, 1e-4, 2, tail=tail, split_signs=split)
+            ref, _ = oracle.propagate(sg, 0.5, 0.5, w, x.astype(np.float32), 1e-4, 2, wp=32, tail=tail,
+                                      split_signs=split)
+            assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)

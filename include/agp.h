@@ -229,9 +229,16 @@ int agp_get_tuning(const agp_graph_t* g, int32_t C, double a, double b, agp_tuni
 
 /* ----------------------------------------------------------------- serving */
 
-/* A single-source proximity query: x = e_source (||x||_1 = 1, so theta = eps).
- * PPR, heat kernel PageRank, Katz and L-hop transition probability are the
- * models of Table 1 with x = e_s. */
+/* A proximity query: x = e_source (||x||_1 = 1, so theta = eps), or, with
+ * x_nnz > 0, the sparse signal x = sum_k x_val[k] e_{x_idx[k]} (theta = eps
+ * ||x||_1, summed as agp_propagate sums a column).  PPR, heat kernel
+ * PageRank, Katz and L-hop transition probability are the models of Table 1
+ * with x = e_s; a sparse x gives, e.g., a personalised vector over a seed
+ * set.  The result equals agp_propagate of the dense x with the same seed
+ * and qid = query_id.  Sparse entries must be distinct ids in [0, n), finite,
+ * with at least one non-zero, and every non-zero must be a multiple of the
+ * column's unit ulp(fl32(theta)) (true for every entry of magnitude at least
+ * theta); zeros are ignored.  The arrays are copied by agp_submit. */
 typedef struct agp_query {
   int64_t source;    /* node id, 0 <= source < n                                */
   double a, b;       /* exponents in [0, 1]                                     */
@@ -241,6 +248,9 @@ typedef struct agp_query {
   uint64_t seed;     /* key of the query's random streams                       */
   uint32_t query_id; /* < 2^24; with seed selects the random streams            */
   float* out;        /* device float[n]: receives pi_hat                        */
+  int64_t x_nnz;        /* 0: x = e_source; > 0: entries of a sparse x          */
+  const int64_t* x_idx; /* host int64[x_nnz]: node ids (source is then unused)  */
+  const float* x_val;   /* host float[x_nnz]: values                            */
 } agp_query_t;
 
 typedef struct agp_server_config {

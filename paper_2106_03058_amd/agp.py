@@ -339,7 +339,8 @@ def weights_tp(L: int) -> np.ndarray:
 class Query(ct.Structure):
     _fields_ = [("source", ct.c_int64), ("a", ct.c_double), ("b", ct.c_double), ("L", ct.c_int32),
                 ("w", ct.POINTER(ct.c_double)), ("eps", ct.c_double), ("seed", ct.c_uint64),
-                ("query_id", ct.c_uint32), ("out", ct.c_void_p)]
+                ("query_id", ct.c_uint32), ("out", ct.c_void_p), ("x_nnz", ct.c_int64),
+                ("x_idx", ct.POINTER(ct.c_int64)), ("x_val", ct.POINTER(ct.c_float))]
 
 
 class ServerConfig(ct.Structure):
@@ -379,10 +380,21 @@ class Server:
         _check(L.agp_server_create(graph.handle, ct.byref(cfg), ct.byref(h)))
         self._h = h
 
-    def submit(self, source: int, a: float, b: float, w, eps: float, seed: int, query_id: int, out) -> int:
+    def submit(self, source: int, a: float, b: float, w, eps: float, seed: int, query_id: int, out,
+               x=None) -> int:
+        """Queue a query with signal e_source, or with the sparse signal
+        x = (ids, values) when x is given (source is then ignored)."""
         w = np.ascontiguousarray(w, dtype=np.float64)
         q = Query(int(source), float(a), float(b), w.size - 1, w.ctypes.data_as(ct.POINTER(ct.c_double)),
                   float(eps), ct.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(query_id), _dptr(out))
+        if x is not None:
+            idx = np.ascontiguousarray(x[0], dtype=np.int64)
+            val = np.ascontiguousarray(x[1], dtype=np.float32)
+            if idx.size != val.size:
+                raise ValueError("x needs as many ids as values")
+            q.x_nnz = idx.size
+            q.x_idx = idx.ctypes.data_as(ct.POINTER(ct.c_int64))
+            q.x_val = val.ctypes.data_as(ct.POINTER(ct.c_float))
         t = ct.c_uint64()
         _check(_server_lib().agp_submit(self._h, ct.byref(q), ct.byref(t)))
         return t.value

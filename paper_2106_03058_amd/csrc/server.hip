@@ -28,8 +28,8 @@
 namespace agp {
 namespace srv {
 struct AdmitItem {
-  long long units;  // the initial residue 1.0 in the column's units
-  uint32_t source;
+  long long units;  // an initial residue (x value) in the column's units
+  uint32_t node;
   uint32_t slot;
 };
 }  // namespace srv
@@ -39,8 +39,8 @@ namespace {
 using namespace lvl;
 using srv::AdmitItem;
 
-// New slots: seed the residue of the source, append it to the frontier, clear
-// the slot's counters.
+// New slots: seed the residues of the signal's entries, append them to the
+// frontier, clear the slots' counters (every item of a slot clears them).
 __global__ void k_admit(const AdmitItem* __restrict__ items, int k, long long* __restrict__ acc, int64_t n,
                         uint64_t* __restrict__ F, unsigned long long* __restrict__ cnt,
                         unsigned long long* __restrict__ counters, double* __restrict__ mass,
@@ -48,9 +48,9 @@ __global__ void k_admit(const AdmitItem* __restrict__ items, int k, long long* _
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k) return;
   const AdmitItem it = items[i];
-  acc[static_cast<size_t>(it.slot) * static_cast<size_t>(n) + it.source] = it.units;
+  acc[static_cast<size_t>(it.slot) * static_cast<size_t>(n) + it.node] = it.units;
   const unsigned long long pos = atomicAdd(cnt, 1ull);
-  F[pos] = (static_cast<uint64_t>(it.source) << 32) | it.slot;
+  F[pos] = (static_cast<uint64_t>(it.node) << 32) | it.slot;
   for (int j = 0; j < kNumCounters; ++j) counters[static_cast<size_t>(it.slot) * kNumCounters + j] = 0;
   mass[it.slot] = 0.0;
   err[it.slot] = 0;
@@ -77,6 +77,10 @@ struct QueryRec {
   agp_query_t q;
   std::vector<double> w;
   std::vector<double> rho, kappa;
+  double theta = 0.0;                // eps ||x||_1
+  std::vector<uint32_t> xi;          // sparse signal: ascending node ids
+  std::vector<long long> xu;         //   and values in units of ulp(fl32(theta))
+  bool signed_x = false;             // some entry is negative
   double estimate = 0.0;
   int slot = -1;
   int level = 0;
@@ -115,7 +119,7 @@ struct agp_server {
   std::thread worker;
   // pinned staging
   ColParams* h_cp = nullptr;
-  agp::srv::AdmitItem* h_admit = nullptr;
+  std::vector<agp::srv::AdmitItem> h_admit;  // the step's admissions (kept until the step syncs)
   unsigned long long* h_counters = nullptr;
   double* h_mass = nullptr;
   int* h_err = nullptr;
@@ -141,7 +145,17 @@ void unit_of(double theta, int* ue, double* scale, long long* dtheta) {
 
 int validate(const agp_server* s, const agp_query_t* q) {
   if (!q) return fail(AGP_EINVAL, "agp_submit: NULL query");
-  if (q->source < 0 || q->source >= s->n) return fail(AGP_EINVAL, "agp_submit: source out of range");
+  if (q->x_nnz < 0) return fail(AGP_EINVAL, "agp_submit: x_nnz < 0");
+  if (q->x_nnz == 0 && (q->source < 0 || q->source >= s->n))
+    return fail(AGP_EINVAL, "agp_submit: source out of range");
+  if (q->x_nnz > 0) {
+    if (!q->x_idx || !q->x_val) return fail(AGP_EINVAL, "agp_submit: NULL sparse signal");
+    if (q->x_nnz > s->n) return fail(AGP_EINVAL, "agp_submit: more entries than nodes");
+    for (int64_t k = 0; k < q->x_nnz; ++k) {
+      if (q->x_idx[k] < 0 || q->x_idx[k] >= s->n) return fail(AGP_EINVAL, "agp_submit: signal id out of range");
+      if (!std::isfinite(q->x_val[k])) return fail(AGP_EINVAL, "agp_submit: non-finite signal value");
+    }
+  }
   if (!(q->a >= 0.0 && q->a <= 1.0) || !(q->b >= 0.0 && q->b <= 1.0))
     return fail(AGP_EINVAL, "agp_submit: a and b must lie in [0, 1]");
   if (q->L < 0 || q->L > AGP_MAX_LEVELS) return fail(AGP_EINVAL, "agp_submit: need 0 <= L <= 255");
@@ -151,11 +165,56 @@ int validate(const agp_server* s, const agp_query_t* q) {
   for (int32_t i = 0; i <= q->L; ++i)
     if (!(q->w[i] >= 0.0) || !std::isfinite(q->w[i]))
       return fail(AGP_EINVAL, "agp_submit: weights must be finite and >= 0");
+  return AGP_OK;
+}
+
+// theta = eps ||x||_1 summed as the batched path sums a column (ascending
+// rows, in blocks of kThetaRows, then over the blocks), and the signal in
+// units of ulp(fl32(theta)).
+int signal_of(const agp_query_t* q, QueryRec* r) {
   int ue;
   double scale;
   long long dth;
-  unit_of(q->eps, &ue, &scale, &dth);
-  if (-ue > 61) return fail(AGP_EINVAL, "agp_submit: eps below the exact-accumulator range (2^-38)");
+  if (q->x_nnz == 0) {
+    r->theta = q->eps;  // ||e_s||_1 = 1
+    unit_of(r->theta, &ue, &scale, &dth);
+    if (-ue > 61) return fail(AGP_EINVAL, "agp_submit: eps below the exact-accumulator range (2^-38)");
+    r->xi.assign(1, static_cast<uint32_t>(q->source));
+    r->xu.assign(1, static_cast<long long>(std::ldexp(1.0, -ue)));
+    return AGP_OK;
+  }
+  std::vector<std::pair<int64_t, float>> e;
+  e.reserve(static_cast<size_t>(q->x_nnz));
+  for (int64_t k = 0; k < q->x_nnz; ++k) e.emplace_back(q->x_idx[k], q->x_val[k]);
+  std::sort(e.begin(), e.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+  for (size_t k = 1; k < e.size(); ++k)
+    if (e[k].first == e[k - 1].first) return fail(AGP_EINVAL, "agp_submit: repeated signal id");
+  double total = 0.0, part = 0.0;
+  int64_t block = e.front().first / lvl::kThetaRows;
+  for (const auto& x : e) {
+    if (x.first / lvl::kThetaRows != block) {
+      total = total + part;
+      part = 0.0;
+      block = x.first / lvl::kThetaRows;
+    }
+    part = part + std::fabs(static_cast<double>(x.second));
+  }
+  total = total + part;
+  if (!(total > 0.0)) return fail(AGP_EINVAL, "agp_submit: the signal has no non-zero entry");
+  r->theta = q->eps * total;
+  unit_of(r->theta, &ue, &scale, &dth);
+  if (-ue > 61) return fail(AGP_EINVAL, "agp_submit: eps ||x||_1 below the exact-accumulator range (2^-38)");
+  r->xi.clear();
+  r->xu.clear();
+  for (const auto& x : e) {
+    if (x.second == 0.0f) continue;
+    const double u = std::ldexp(static_cast<double>(x.second), -ue);
+    if (u != std::nearbyint(u) || !(std::fabs(u) < 4.0e18))
+      return fail(AGP_EINVAL, "agp_submit: a signal value is not a multiple of the unit ulp(fl32(eps ||x||_1))");
+    r->xi.push_back(static_cast<uint32_t>(x.first));
+    r->xu.push_back(static_cast<long long>(u));
+    if (x.second < 0.0f) r->signed_x = true;
+  }
   return AGP_OK;
 }
 
@@ -163,7 +222,8 @@ int validate(const agp_server* s, const agp_query_t* q) {
 int step(agp_server* s) {
   hipStream_t st = s->stream;
   std::vector<uint64_t> admitted;
-  int nadmit = 0;
+  s->h_admit.clear();
+  bool positive = true;
   {
     std::unique_lock<std::mutex> lk(s->mu);
     for (int c = 0; c < s->S && !s->pending.empty(); ++c) {
@@ -191,7 +251,8 @@ int step(agp_server* s) {
       }
       QueryRec& r = s->recs[t];
       const int i = r.level;
-      p.theta = r.q.eps;  // ||e_s||_1 = 1
+      if (r.signed_x) positive = false;
+      p.theta = r.theta;
       unit_of(p.theta, &p.ue, &p.scale, &p.dtheta);
       p.theta_w = static_cast<float>(p.theta);
       p.rho = r.rho[i];
@@ -205,10 +266,8 @@ int step(agp_server* s) {
       p.flags = (i == r.q.L ? kLastLevel : 0) | (r.q.a == 0.0 ? kAZero : 0) | (r.failed ? kDrop : 0);
       if (r.fresh) {
         r.fresh = false;
-        s->h_admit[nadmit].units = static_cast<long long>(std::ldexp(1.0, -p.ue));
-        s->h_admit[nadmit].source = static_cast<uint32_t>(r.q.source);
-        s->h_admit[nadmit].slot = static_cast<uint32_t>(c);
-        ++nadmit;
+        for (size_t k = 0; k < r.xi.size(); ++k)
+          s->h_admit.push_back(srv::AdmitItem{r.xu[k], r.xi[k], static_cast<uint32_t>(c)});
       }
     }
   }
@@ -234,8 +293,11 @@ int step(agp_server* s) {
   long long* acc[2] = {s->acc[0].as<long long>(), s->acc[1].as<long long>()};
   uint64_t* F[2] = {s->F[0].as<uint64_t>(), s->F[1].as<uint64_t>()};
   AGP_HIP(hipMemcpyAsync(s->cp.ptr, s->h_cp, sizeof(ColParams) * s->S, hipMemcpyHostToDevice, st));
+  const int nadmit = static_cast<int>(s->h_admit.size());
   if (nadmit) {
-    AGP_HIP(hipMemcpyAsync(s->admit.ptr, s->h_admit, sizeof(srv::AdmitItem) * nadmit, hipMemcpyHostToDevice, st));
+    if (int rc = s->admit.reserve(sizeof(srv::AdmitItem) * static_cast<size_t>(nadmit), false, st)) return rc;
+    AGP_HIP(hipMemcpyAsync(s->admit.ptr, s->h_admit.data(), sizeof(srv::AdmitItem) * nadmit, hipMemcpyHostToDevice,
+                           st));
     k_admit<<<grid_for(nadmit, 64), 64, 0, st>>>(s->admit.as<srv::AdmitItem>(), nadmit, acc[cur], s->n, F[cur],
                                                   counts + cur, s->counters.as<unsigned long long>(),
                                                   s->mass.as<double>(), s->err.as<int>());
@@ -258,7 +320,7 @@ int step(agp_server* s) {
   A.counters = s->counters.as<unsigned long long>();
   A.mass = s->mass.as<double>();
   A.err = s->err.as<int>();
-  A.positive = 1;
+  A.positive = positive ? 1 : 0;  // first-touch appends need residues that cannot cancel
   A.dense_cut = std::max<unsigned long long>(1ull, static_cast<unsigned long long>(s->n) * s->S / 32);
   A.mode_out = s->mode.as<int>();
   A.rec = nullptr;
@@ -450,7 +512,6 @@ int agp_server_create(const agp_graph_t* g, const agp_server_config_t* cfg, agp_
   }
   if (!rc) {
     if (hipHostMalloc(reinterpret_cast<void**>(&s->h_cp), sizeof(ColParams) * s->S) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&s->h_admit), sizeof(srv::AdmitItem) * s->S) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&s->h_counters),
                       sizeof(unsigned long long) * lvl::kNumCounters * s->S) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&s->h_mass), sizeof(double) * s->S) != hipSuccess ||
@@ -475,6 +536,10 @@ int agp_submit(agp_server_t* s, const agp_query_t* q, uint64_t* ticket) {
   if (rc) return rc;
   QueryRec r;
   r.q = *q;
+  rc = signal_of(q, &r);
+  if (rc) return rc;
+  r.q.x_idx = nullptr;  // copied into r.xi / r.xu
+  r.q.x_val = nullptr;
   r.w.assign(q->w, q->w + q->L + 1);
   r.q.w = r.w.data();
   // level tables: Y_i = sum_{k=i..L} w_k from k = L down; rho, kappa as in
@@ -532,7 +597,6 @@ int agp_server_destroy(agp_server_t* s) {
                   &s->cp, &s->admit, &s->mode, &s->rec[0], &s->rec[1], &s->bins})
     b->release();
   if (s->h_cp) (void)hipHostFree(s->h_cp);
-  if (s->h_admit) (void)hipHostFree(s->h_admit);
   if (s->h_counters) (void)hipHostFree(s->h_counters);
   if (s->h_mass) (void)hipHostFree(s->h_mass);
   if (s->h_err) (void)hipHostFree(s->h_err);

@@ -54,7 +54,7 @@ def _oracle_one(g, sg, q):
 def _serve(torch, agp, G, qs, *, slots, budget=0.0):
     srv = agp.Server(G, max_slots=slots, queue_capacity=len(qs) + 4, work_budget=budget)
     outs = [torch.full((G.n,), float("nan"), dtype=torch.float32, device="cuda:0") for _ in qs]
-    tickets = [srv.submit(q["source"], q["a"], q["b"], q["w"], q["eps"], q["seed"], q["qid"], o)
+    tickets = [srv.submit(q["source"], q["a"], q["b"], q["w"], q["eps"], q["seed"], q["qid"], o, x=q.get("x"))
                for q, o in zip(qs, outs)]
     res = [None] * len(qs)
     t0 = time.time()
@@ -167,3 +167,65 @@ def test_aggregation_modes_serve_the_same_bits(env, monkeypatch):
             assert r["status"] == agp.AGP_OK
             assert np.array_equal(o, ref), f"{mode}: query {q['qid']}"
             assert r["pushes"] == int(cnt["det"].sum() + cnt["acc"].sum())
+
+
+def _dense(g, q):
+    x = np.zeros(g.n, dtype=np.float32)
+    if q.get("x") is None:
+        x[q["source"]] = 1.0
+    else:
+        x[q["x"][0]] = q["x"][1]
+    return x
+
+
+def test_sparse_signal_queries(env):
+    """Queries with sparse signals (seed sets, signed values) served beside
+    single-source ones: each equals the oracle and the batched call on the
+    dense signal with the same (seed, query id); a signed query turns the
+    server's first-touch appends off for the steps it runs in."""
+    torch, agp, g, G, sg, lam = env
+    rng = np.random.default_rng(31)
+    qs = _mix(g, lam, 9, seed=5)
+    for i, q in enumerate(qs):
+        if i % 3 == 1:  # a seed set
+            ids = rng.choice(g.n, size=int(rng.integers(2, 40)), replace=False)
+            vals = rng.uniform(0.5, 2.0, size=ids.size).astype(np.float32)
+            if i == 4:
+                vals[::2] *= -1.0  # signed
+            q["x"] = (ids, vals)
+    outs, res = _serve(torch, agp, G, qs, slots=4)
+    for q, o, r in zip(qs, outs, res):
+        x = _dense(g, q)
+        ref, cnt = oracle.propagate(sg, q["a"], q["b"], q["w"], x, q["eps"], q["seed"], wp=32, qids=[q["qid"]])
+        assert r["status"] == agp.AGP_OK
+        assert np.array_equal(o, ref), f"query {q['qid']}: max diff {np.abs(o - ref).max()}"
+        assert r["pushes"] == int(cnt["det"].sum() + cnt["acc"].sum())
+        X = torch.from_numpy(x[:, None].copy()).to("cuda:0")
+        out, _ = agp.propagate(G, q["a"], q["b"], q["w"], X, q["eps"], q["seed"], qids=[q["qid"]])
+        assert np.array_equal(out[:, 0].cpu().numpy().astype(np.float64), o)
+
+
+def test_sparse_signal_errors(env):
+    torch, agp, g, G, sg, lam = env
+    srv = agp.Server(G, max_slots=2, queue_capacity=8)
+    o = torch.zeros(g.n, dtype=torch.float32, device="cuda:0")
+    w = inputs.weights_ppr(0.2, 5)
+    bad = [
+        (np.array([3, 3]), np.array([1.0, 2.0])),        # repeated id
+        (np.array([g.n]), np.array([1.0])),              # out of range
+        (np.array([1, 2]), np.array([0.0, 0.0])),        # no non-zero entry
+        (np.array([1, 2]), np.array([1.0, np.nan])),     # not finite
+        (np.array([1, 2]), np.array([1.0, 1e-30])),      # below the unit of theta
+    ]
+    for x in bad:
+        with pytest.raises(agp.AGPError) as e:
+            srv.submit(0, 0.0, 1.0, w, 1e-4, 1, 1, o, x=x)
+        assert e.value.code == agp.AGP_EINVAL
+    # a good one still runs
+    t = srv.submit(0, 0.0, 1.0, w, 1e-4, 1, 1, o, x=(np.array([5, 9]), np.array([1.0, -0.5])))
+    t0 = time.time()
+    r = None
+    while r is None and time.time() - t0 < 30:
+        r = srv.poll(t)
+    srv.close()
+    assert r is not None and r["status"] == agp.AGP_OK

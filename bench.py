@@ -324,6 +324,7 @@ def run_serve(args) -> dict:
     log(f"lambda_1 = {lam:.6f} in {time.time() - t:.1f}s")
     G = agp.Graph(rp, col)
     deg = (rp[1:] - rp[:-1]).cpu().numpy().astype(np.float64)
+    host = inputs.Graph(n, rp.cpu().numpy(), col.cpu().numpy()) if args.oracle_queries > 0 else None
     del rp, col
     torch.cuda.empty_cache()
     rng = np.random.default_rng(404)
@@ -345,6 +346,9 @@ def run_serve(args) -> dict:
     pool = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(S + 32)]
     keep = min(args.single, N)
     kept = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(keep)]
+    # queries re-run by the oracle keep their outputs in buffers of their own
+    checked = sorted(np.random.default_rng(77).choice(N, size=min(args.oracle_queries, N), replace=False).tolist())
+    held = {i: torch.empty(n, dtype=torch.float32, device=dev) for i in checked if i >= keep}
     srv = agp.Server(G, max_slots=S, queue_capacity=N + 1)
     free = list(range(len(pool)))
     outstanding = {}
@@ -353,11 +357,11 @@ def run_serve(args) -> dict:
     t0 = time.perf_counter()
     while submitted < N or outstanding:
         now = time.perf_counter() - t0
-        while submitted < N and arrivals[submitted] <= now and (submitted < keep or free):
+        while submitted < N and arrivals[submitted] <= now and (submitted < keep or submitted in held or free):
             i = submitted
             name, a, b, w, eps = qs[i]
-            slot = -1 if i < keep else free.pop()
-            buf = kept[i] if i < keep else pool[slot]
+            slot = -1 if (i < keep or i in held) else free.pop()
+            buf = kept[i] if i < keep else (held[i] if i in held else pool[slot])
             tk = srv.submit(int(src[i]), a, b, w, eps, 5000 + i, i, buf)
             outstanding[tk] = (i, slot)
             submitted += 1
@@ -392,6 +396,34 @@ def run_serve(args) -> dict:
         pushes1 += st["pushes"]
         same &= bool(torch.equal(o[:, 0], kept[i]))
     lat1 = np.array(lat1)
+    oracle_check = None
+    if checked:
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+
+        t = time.time()
+        sg = oracle.degree_sort(host)
+        log(f"oracle degree sort {time.time() - t:.1f}s")
+        t = time.time()
+        ok = []
+
+        def one(i):
+            name, a, b, w, eps = qs[i]
+            x = np.zeros(n, dtype=np.float32)
+            x[int(src[i])] = 1.0
+            ref, _ = oracle.propagate(sg, a, b, w, x, eps, 5000 + i, qids=[i], threads=1)
+            got = (kept[i] if i < keep else held[i]).cpu().numpy().astype(np.float64)
+            return i, bool(np.array_equal(got, ref))
+
+        workers = min(16, os.cpu_count() or 1)
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            for k, (i, eq) in enumerate(ex.map(one, checked)):
+                ok.append(eq)
+                if k % 10 == 0 or not eq:
+                    log(f"oracle query {k + 1}/{len(checked)} (#{i}): {'equal' if eq else 'DIFFERENT'}")
+        oracle_check = {"queries": len(checked), "bit_exact": int(sum(ok)), "threads": workers,
+                        "seconds": time.time() - t}
+        log(f"oracle check {oracle_check}")
     return {
         "metric": METRIC,
         "value": pushes / makespan,
@@ -416,6 +448,7 @@ def run_serve(args) -> dict:
                                       "p99": float(np.percentile(lat1, 99)), "queries": keep},
         "pushes_per_s_one_per_launch": pushes1 / (lat1.sum() / 1e3),
         "served_equals_one_per_launch": same,
+        "oracle_check": oracle_check,
     }
 
 
@@ -660,6 +693,8 @@ def main() -> int:
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: offered arrivals per second")
     ap.add_argument("--slots", type=int, default=64, help="serve: server slots")
     ap.add_argument("--single", type=int, default=16, help="units timed one per launch")
+    ap.add_argument("--oracle-queries", type=int, default=0,
+                    help="serve: queries of the stream re-run by the oracle (random sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="autotune aggregation and grid per model before timing (default: library defaults)")

@@ -130,6 +130,12 @@ int agp_graph_info(const agp_graph_t* g, int64_t* n, int64_t* nnz, int32_t* max_
 int agp_graph_export(const agp_graph_t* g, int64_t* row_ptr, int32_t* col_sorted,
                      int32_t* degree);
 
+/* Degree group of every stored arc (Section 4, subset sampling: the groups
+ * G_k of neighbours with floor(log2 d_v) = k): host uint8[nnz], in the order
+ * of agp_graph_export's col_sorted, floor(log2) of the neighbour's degree in
+ * D (so non-decreasing along each row).  Synchronous (default stream). */
+int agp_graph_groups(const agp_graph_t* g, uint8_t* group_ids);
+
 /* Release a graph and every buffer the library cached for it. */
 int agp_graph_destroy(agp_graph_t* g);
 

@@ -24,7 +24,7 @@ EXPORTED = [
     "agp_graph_destroy", "agp_propagate", "agp_propagate_f64", "agp_weights_ppr",
     "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp", "agp_server_create", "agp_submit",
     "agp_poll", "agp_server_destroy", "agp_autotune", "agp_get_tuning", "agp_sweep",
-    "agp_propagate_variant", "agp_propagate_variant_f64", "agp_sweep_batch",
+    "agp_propagate_variant", "agp_propagate_variant_f64", "agp_sweep_batch", "agp_graph_groups",
 ]
 AGP_VARIANT_INFINITE_TAIL, AGP_VARIANT_SPLIT_SIGNS = 1, 2
 
@@ -75,6 +75,7 @@ def lib():
         L.agp_graph_create.argtypes = [ct.c_int64, ct.c_int64, vp, vp, ct.c_uint32, vp, ct.POINTER(vp)]
         L.agp_graph_info.argtypes = [vp, i64p, i64p, i32p]
         L.agp_graph_export.argtypes = [vp, i64p, i32p, i32p]
+        L.agp_graph_groups.argtypes = [vp, ct.POINTER(ct.c_uint8)]
         L.agp_graph_destroy.argtypes = [vp]
         prop = [vp, ct.c_double, ct.c_double, dp, ct.c_int32, vp, ct.c_int32, ct.c_double,
                 ct.c_uint64, u32p, vp, vp, ct.POINTER(Stats)]
@@ -161,6 +162,12 @@ class Graph:
                                       col.ctypes.data_as(ct.POINTER(ct.c_int32)),
                                       deg.ctypes.data_as(ct.POINTER(ct.c_int32))))
         return rp, col, deg
+
+    def groups(self) -> np.ndarray:
+        """Degree group floor(log2 d) of every arc's neighbour, in export() order."""
+        gid = np.empty(self.nnz, dtype=np.uint8)
+        _check(lib().agp_graph_groups(self.handle, gid.ctypes.data_as(ct.POINTER(ct.c_uint8))))
+        return gid
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:

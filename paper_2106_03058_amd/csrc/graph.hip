@@ -470,6 +470,12 @@ int build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* c
   return AGP_OK;
 }
 
+// degree group of every arc's neighbour: floor(log2 d) of its factor degree
+__global__ void k_groups(const uint32_t* __restrict__ nd, int64_t nnz, uint8_t* __restrict__ out) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz; j += (int64_t)gridDim.x * blockDim.x)
+    out[j] = static_cast<uint8_t>(31 - __clz(nd[j]));
+}
+
 }  // namespace
 }  // namespace agp
 
@@ -520,6 +526,19 @@ int agp_graph_export(const agp_graph_t* g, int64_t* row_ptr, int32_t* col_sorted
     AGP_HIP(hipMemcpy(col_sorted, g->col, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToHost));
   if (degree && g->n)
     AGP_HIP(hipMemcpy(degree, g->degree, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToHost));
+  return AGP_OK;
+}
+
+int agp_graph_groups(const agp_graph_t* g, uint8_t* group_ids) {
+  if (!g || !group_ids) return agp::fail(AGP_EINVAL, "agp_graph_groups: NULL argument");
+  if (g->nnz == 0) return AGP_OK;
+  uint8_t* d = nullptr;
+  AGP_HIP(hipMalloc(&d, static_cast<size_t>(g->nnz)));
+  agp::k_groups<<<agp::grid_for(g->nnz, 256), 256>>>(g->ndeg, g->nnz, d);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(group_ids, d, static_cast<size_t>(g->nnz), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return agp::fail(AGP_EDEVICE, std::string("agp_graph_groups: ") + hipGetErrorString(e));
   return AGP_OK;
 }
 

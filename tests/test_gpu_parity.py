@@ -75,6 +75,12 @@ def test_degree_sorted_csr_is_bit_exact(agp, torch_dev, loops):
     assert np.array_equal(deg, sg.deg)
     assert G.max_degree == int(sg.deg.max())
     assert G.max_degree > 64
+    # degree groups floor(log2 d_v) of every arc, from the oracle's sorted rows
+    gid = G.groups()
+    want = np.floor(np.log2(sg.fdeg[sg.col].astype(np.float64))).astype(np.uint8)
+    assert np.array_equal(gid, want)
+    for u in range(0, g.n, 997):  # non-decreasing along rows
+        assert np.all(np.diff(gid[rp[u]:rp[u + 1]].astype(np.int32)) >= 0)
 
 
 def _pairs(g):

@@ -671,16 +671,21 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
 // ------------------------------------------------- push estimate
 // An upper bound on the pushes of a level (deterministic rows count d_u,
 // sampled rows their expected d_u c / theta with c = rho |r| d_u^-b), summed
-// over the frontier: decides whether the level is worth binning.
+// over the frontier (over a sample of it when it is large): decides whether
+// the level is worth binning.
 template <typename T, bool kFirst>
 __global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __restrict__ x,
                                                        const typename Prec<T>::Cell* __restrict__ acc_cur,
                                                        double* __restrict__ est) {
   const unsigned long long count = *A.cnt_in;
+  // large frontiers: every 16th entry, scaled up (the estimate only chooses
+  // between interchangeable aggregation modes, and levels this large are far
+  // from the choice's threshold)
+  const unsigned long long stride = count >= (1ull << 22) ? 16ull : 1ull;
   double sum = 0.0;
-  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < count;
-       i += (unsigned long long)gridDim.x * blockDim.x) {
-    const uint64_t item = A.fin[i];
+  for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; j * stride < count;
+       j += (unsigned long long)gridDim.x * blockDim.x) {
+    const uint64_t item = A.fin[j * stride];
     const uint32_t u = static_cast<uint32_t>(item >> 32);
     const uint32_t c = static_cast<uint32_t>(item);
     const ColParams& cp = A.cp[c];
@@ -702,7 +707,7 @@ __global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __r
   }
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off);
-  if (lane_id() == 0 && sum != 0.0) atomicAdd(est, sum);
+  if (lane_id() == 0 && sum != 0.0) atomicAdd(est, sum * static_cast<double>(stride));
 }
 
 // ------------------------------------------------- frontier compaction

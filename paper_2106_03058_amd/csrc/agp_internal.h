@@ -78,6 +78,7 @@ struct agp_graph {
   int64_t* row_ptr = nullptr;   // device int64[n + 1], rows in the push direction
   uint32_t* col = nullptr;      // device uint32[nnz], rows sorted by (factor degree, id)
   uint32_t* ndeg = nullptr;     // device uint32[nnz], factor degree of col[j]
+  uint32_t* gend = nullptr;     // device uint32[nnz], row-relative end of arc j's degree group
   int32_t* degree = nullptr;    // device int32[n], row lengths
   int32_t* fdeg = nullptr;      // device int32[n], degree in the factors d^-a, d^-b (>= 1)
   std::map<double, double*> pow_tables;  // exponent e -> device d^-e, d = 0..max_fdeg

@@ -324,6 +324,37 @@ __global__ void k_split_keys(const uint64_t* __restrict__ keys, int64_t nnz, uin
   }
 }
 
+// End of each arc's degree group inside its row (row-relative, exclusive):
+// the first later position whose factor degree reaches the next power of
+// two, else the row length.  Rows ascend in the factor degree, so a run of
+// sampled pushes that starts at position s of a row stays in one group up to
+// gend[s].  One wave per row; each lane binary-searches for its arcs.
+__global__ void k_group_ends(const int64_t* __restrict__ rp, const uint32_t* __restrict__ nd, int64_t n,
+                             uint32_t* __restrict__ gend) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t u = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; u < n; u += nw) {
+    const int64_t r0 = rp[u], r1 = rp[u + 1];
+    for (int64_t j = r0 + lane; j < r1; j += 64) {
+      const int g = 31 - __clz(nd[j]);
+      int64_t lo = r1;
+      if (g < 31) {
+        const uint32_t lim = 1u << (g + 1);
+        lo = j + 1;
+        int64_t hi = r1;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (nd[mid] < lim)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+      }
+      gend[j] = (uint32_t)(lo - r0);
+    }
+  }
+}
+
 unsigned grid_for(int64_t items, int threads) {
   int64_t b = (items + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -444,9 +475,11 @@ int build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* c
     if (hflag & 4) return fail(AGP_EINVAL, "duplicate arcs in a row");
     if ((hflag & 8) && !(flags & AGP_DIRECTED)) return fail(AGP_EINVAL, "the matrix is not symmetric");
   }
-  uint32_t *scol = nullptr, *snd = nullptr;
-  if ((rc = al.get(&scol, (size_t)nnz)) || (rc = al.get(&snd, (size_t)nnz))) return rc;
+  uint32_t *scol = nullptr, *snd = nullptr, *gend = nullptr;
+  if ((rc = al.get(&scol, (size_t)nnz)) || (rc = al.get(&snd, (size_t)nnz)) || (rc = al.get(&gend, (size_t)nnz)))
+    return rc;
   k_split_keys<<<grid_for(nnz, 256), 256, 0, s>>>(keys, nnz, scol, snd);
+  if (n > 0) k_group_ends<<<(unsigned)std::min<int64_t>((n + 3) / 4, 1 << 16), 256, 0, s>>>(rp, snd, n, gend);
   int maxd = 0, maxf = 0;
   AGP_HIP(hipMemcpyAsync(&maxd, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
   AGP_HIP(hipMemcpyAsync(&maxf, fmax, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -460,11 +493,13 @@ int build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* c
   g->row_ptr = rp;
   g->col = scol;
   g->ndeg = snd;
+  g->gend = gend;
   g->degree = deg;
   g->fdeg = fdeg;
   al.keep(rp);
   al.keep(scol);
   al.keep(snd);
+  al.keep(gend);
   al.keep(deg);
   al.keep(fdeg);
   return AGP_OK;
@@ -552,6 +587,7 @@ int agp_graph_destroy(agp_graph_t* g) {
     (void)hipFree(g->row_ptr);
     (void)hipFree(g->col);
     (void)hipFree(g->ndeg);
+    (void)hipFree(g->gend);
     (void)hipFree(g->degree);
     (void)hipFree(g->fdeg);
   }

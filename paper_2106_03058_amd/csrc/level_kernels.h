@@ -78,6 +78,7 @@ struct LevelArgs {
   const int64_t* rp;
   const uint32_t* col;
   const uint32_t* nd;
+  const uint32_t* gend;  // row-relative end of each arc's degree group
   const int32_t* deg;   // row lengths (neighbours to push to)
   const int32_t* fdeg;  // degrees in the factors d^-a, d^-b
   const ColParams* cp;
@@ -575,22 +576,11 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       const uint32_t wnext = ((s >> kSegLog2) + 1u) << kSegLog2;
       const uint32_t wend = wnext < rend ? wnext : rend;
       run_end = wend;
-      if (!azero) {
+      if (!azero) {  // the run also ends with the degree group of position s
         const uint32_t ds = A.nd[rpu + s];
+        const uint32_t ge = A.gend[rpu + s];
         dstart = cpp->da[ds];
-        const int g = 31 - __clz(ds);
-        if (g < 31) {
-          const uint32_t lim = 1u << (g + 1);
-          uint32_t blo = s + 1, bhi = wend;
-          while (blo < bhi) {
-            const uint32_t mid = (blo + bhi) >> 1;
-            if (A.nd[rpu + mid] < lim)
-              blo = mid + 1;
-            else
-              bhi = mid;
-          }
-          run_end = blo;
-        }
+        if (ge < wend) run_end = ge;
         const double num = cv * dstart;
         tab = make_skip_table(num / th);
       }

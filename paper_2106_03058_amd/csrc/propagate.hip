@@ -246,6 +246,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   A.rp = g->row_ptr;
   A.col = g->col;
   A.nd = g->ndeg;
+  A.gend = g->gend;
   A.deg = g->degree;
   A.fdeg = g->fdeg;
   A.cp = cp;

@@ -307,6 +307,7 @@ int step(agp_server* s) {
   A.rp = s->g->row_ptr;
   A.col = s->g->col;
   A.nd = s->g->ndeg;
+  A.gend = s->g->gend;
   A.deg = s->g->degree;
   A.fdeg = s->g->fdeg;
   A.cp = s->cp.as<ColParams>();

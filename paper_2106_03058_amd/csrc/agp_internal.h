@@ -48,6 +48,7 @@ struct Scratch {
   DevBuf levelinfo;  // per level: contribution mass (double), frontier mode (int)
   DevBuf rec[2];     // binned aggregation: push records, partitioned records
   DevBuf bins;       // bucket counts, offsets, cursors, per-level record counts
+  DevBuf big;        // deferred long deterministic rows: per-level counters, then the row list
   DevBuf sweep;      // clustering sweep: keys, order, ranks, prefix sums, sort space
   DevBuf sweep_items;        // clustering sweep: arc-balanced work items of the graph
   int64_t sweep_nitems = -1; // their number (-1: not built yet)

@@ -58,6 +58,7 @@ void Scratch::release() {
   levelinfo.release();
   rec[0].release();
   rec[1].release();
+  big.release();
   sweep.release();
   sweep_items.release();
   sweep_nitems = -1;

@@ -56,6 +56,21 @@ constexpr int kBinLog2 = 13;
 constexpr int kMaxBinsPerBucket = 1024;
 constexpr int kBuckets = 1024;
 
+// Rows with many deterministic pushes (a hub with a large residue) would
+// keep one wave busy while the rest of the grid idles; a batched level
+// defers rows of at least kBigRow deterministic pushes to a list that
+// k_det_big then spreads over the whole grid in chunks of kBigChunk pushes.
+constexpr uint32_t kBigRow = 4096;
+constexpr int kBigChunk = 4096;  // <= kBigRow: a lane's pushes in a chunk cross at most one row boundary
+constexpr int kBigShift = 40;    // list counter: deferred rows << 40 | their pushes (a level's pushes < 2^40)
+
+struct BigRow {
+  unsigned long long off;  // deterministic pushes of the rows deferred before this one
+  int64_t rp;              // first arc of the row
+  double cv;               // c = rho |r| d_u^-b
+  uint32_t c, J, neg, pad;
+};
+
 struct ColParams {
   double theta;          // eps * ||x_c||_1
   double scale;          // 2^-ue (binary32 units)
@@ -103,6 +118,10 @@ struct LevelArgs {
   int bucket_shift;              // cells per bucket = 2^bucket_shift
   const double* bin_est;         // non-null: bin only if *bin_est >= bin_pushes (estimated pushes)
   double bin_pushes;
+  // deferred rows (batched calls; nullptr: every row is pushed by its wave)
+  unsigned long long* big_ctr;   // this level's list counter, zero at the start
+  BigRow* big;
+  unsigned long long big_cap;
 };
 
 // ----------------------------------------------------- working precision
@@ -463,6 +482,27 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
                   (eJ < ed) ? static_cast<long long>(((ed - 1) >> kSegLog2) - (eJ >> kSegLog2) + 1) : 0;
               dwork = eJ;
               iwork = (windows + kWinPerItem - 1) / kWinPerItem;
+              // a long deterministic prefix goes to the deferred list (the
+              // counter is read first so that it never wraps)
+              if (!kServe && A.big_ctr != nullptr && eJ >= kBigRow &&
+                  (__hip_atomic_load(A.big_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> kBigShift) <
+                      A.big_cap) {
+                const unsigned long long old =
+                    atomic_add_ret(A.big_ctr, (1ull << kBigShift) | static_cast<unsigned long long>(eJ));
+                const unsigned long long slot = old >> kBigShift;
+                if (slot < A.big_cap) {
+                  BigRow br;
+                  br.off = old & ((1ull << kBigShift) - 1ull);
+                  br.rp = erp;
+                  br.cv = ecv;
+                  br.c = ec;
+                  br.J = eJ;
+                  br.neg = eneg ? 1u : 0u;
+                  br.pad = 0;
+                  A.big[slot] = br;
+                  dwork = 0;
+                }
+              }
               // bound on the magnitude this entry can add (every contribution
               // is at most max(inc_0, theta)), for the overflow check
               const T big = to_w(inc0 > eth ? inc0 : eth, T());
@@ -656,6 +696,79 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       if (m != 0.0) atomicAdd(A.mass + A.level, m);
     }
   }
+}
+
+// ------------------------------------------------- deferred rows
+// The deterministic pushes of the rows a level deferred, after its k_level
+// launch: a wave takes kBigChunk consecutive pushes of the concatenated rows
+// (lane l pushes l, l + 64, ...), finds its row once by binary search over
+// the rows' offsets and moves to the next row when it crosses its end.  The
+// pushes are computed and accumulated as in k_level (first contributions of
+// a sparse level appended to the next frontier).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_det_big(LevelArgs A, typename Prec<T>::Cell* __restrict__ acc_next) {
+  using P = Prec<T>;
+  using Delta = typename P::Delta;
+  constexpr int kWaves = kThreads / kWave;
+  __shared__ uint64_t s_stage[kWaves][kStage];
+  const unsigned long long ctr = *A.big_ctr;
+  unsigned long long nb = ctr >> kBigShift;
+  if (nb == 0) return;
+  if (nb > A.big_cap) nb = A.big_cap;  // rows beyond the list were pushed by their waves
+  const BigRow* R = A.big;
+  const unsigned long long total = R[nb - 1].off + R[nb - 1].J;
+  const bool sparse = *A.mode_out == kModeSparse;
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  uint64_t* stage = s_stage[wave];
+  int staged = 0;  // wave-uniform
+  const unsigned long long nchunks = (total + kBigChunk - 1) / kBigChunk;
+  for (unsigned long long ch = static_cast<unsigned long long>(blockIdx.x) * kWaves + wave; ch < nchunks;
+       ch += static_cast<unsigned long long>(gridDim.x) * kWaves) {
+    unsigned long long k = ch * kBigChunk + lane;
+    unsigned long long e = 0, hi = nb;  // last row with off <= k
+    while (hi - e > 1) {
+      const unsigned long long mid = (e + hi) >> 1;
+      if (R[mid].off <= k)
+        e = mid;
+      else
+        hi = mid;
+    }
+    unsigned long long off = R[e].off, next = e + 1 < nb ? R[e + 1].off : total;
+    for (int j = 0; j < kBigChunk / kWave; ++j, k += kWave) {
+      bool emit = false;
+      uint32_t v = 0, vc = 0;
+      Delta delta{};
+      if (k < total) {
+        while (k >= next) {
+          ++e;
+          off = next;
+          next = e + 1 < nb ? R[e + 1].off : total;
+        }
+        const BigRow& br = R[e];
+        vc = br.c;
+        const ColParams* cpd = A.cp + vc;
+        const int64_t arc = br.rp + static_cast<int64_t>(k - off);
+        v = A.col[arc];
+        double inc = br.cv;
+        if (!(cpd->flags & kAZero)) inc = inc * cpd->da[A.nd[arc]];
+        T val = to_w(inc, T());
+        if (br.neg) val = -val;
+        emit = P::to_units(val, *cpd, &delta);
+        if (!emit) atomicOr(A.err, 1);
+      }
+      const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(vc) * A.sc;
+      bool first = false;
+      if (emit) {
+        if (sparse)
+          first = P::add_ret(acc_next, vcell, delta);
+        else
+          P::add(acc_next, vcell, delta);
+      }
+      if (sparse) stage_push(stage, staged, (static_cast<uint64_t>(v) << 32) | vc, first, A.fout, A.cnt_out);
+    }
+  }
+  if (sparse) stage_flush(stage, staged, A.fout, A.cnt_out);
 }
 
 // ------------------------------------------------- push estimate

@@ -242,6 +242,25 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   const unsigned cgrid = grid_for(n * (int64_t)(C >= kWave ? kWave : C), kThreads, 8192);
   k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroValue<T>{x, ldc}, n, C, (long long)C, 1ll, F[0], counts, nullptr);
 
+  // rows with long deterministic prefixes, deferred per level to k_det_big
+  constexpr unsigned long long kBigCap = 1ull << 16;
+  unsigned long long big_cap = kBigCap;
+  if (const char* e = std::getenv("AGP_BIG_ROWS")) {  // shorter list (tests); 0: no deferral
+    const unsigned long long v = std::strtoull(e, nullptr, 10);
+    if (v < big_cap) big_cap = v;
+  }
+  unsigned long long* big_ctr = nullptr;
+  BigRow* big_rows = nullptr;
+  if (big_cap > 0 &&
+      sc.big.reserve(sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1) + sizeof(BigRow) * kBigCap, false, s) ==
+          AGP_OK) {
+    big_ctr = sc.big.as<unsigned long long>();
+    big_rows = reinterpret_cast<BigRow*>(big_ctr + AGP_MAX_LEVELS + 1);
+    AGP_HIP(hipMemsetAsync(big_ctr, 0, sizeof(unsigned long long) * (static_cast<size_t>(L) + 1), s));
+  } else {
+    (void)hipGetLastError();  // no room for the list: every row stays with its wave
+  }
+
   LevelArgs A{};
   A.rp = g->row_ptr;
   A.col = g->col;
@@ -278,6 +297,9 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     A.mode_out = mode + i + 1;
     const bool bin_level = binned && i < L;
     A.rec = bin_level ? sc.rec[0].as<uint32_t>() : nullptr;
+    A.big_ctr = (big_ctr != nullptr && i < L) ? big_ctr + i : nullptr;
+    A.big = big_rows;
+    A.big_cap = big_cap;
     A.rec_count = bin_level ? rec_counts + i : nullptr;
     Cell* cur = acc[i & 1];
     Cell* nxt = acc[(i + 1) & 1];
@@ -294,6 +316,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
       k_level<T, true, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
     else
       k_level<T, false, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
+    if (A.big_ctr != nullptr) k_det_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
     if (stats) AGP_HIP(hipEventRecord(ev[2 * i + 1], s));
     if (bin_level) {
       uint32_t* r0 = sc.rec[0].as<uint32_t>();

@@ -866,16 +866,6 @@ __global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int 
   stage_flush(stage, staged, F, cnt);
 }
 
-// x[u * ld + c] != 0 (the signal, row stride ld)
-template <typename T>
-struct NonZeroValue {
-  const T* x;
-  long long ld;
-  __device__ bool operator()(int64_t u, int64_t c, size_t) const {
-    return x[static_cast<size_t>(u) * static_cast<size_t>(ld) + static_cast<size_t>(c)] != T(0);
-  }
-};
-
 template <typename T>
 struct NonZeroCell {
   const typename Prec<T>::Cell* acc;

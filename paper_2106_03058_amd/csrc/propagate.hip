@@ -32,23 +32,41 @@ using namespace lvl;
 
 // ---------------------------------------------------------- thresholds
 // ||x_c||_1 in binary64: sequential over blocks of 4096 rows, then over the
-// block sums.  flags: 1 = non-finite entry, 2 = negative entry.
+// block sums.  flags: 1 = non-finite entry, 2 = negative entry.  The same
+// pass forms the level-0 frontier (the non-zero cells of x, in any order).
+// One wave per (row block, 64 columns); loads are issued 16 rows at a time
+// and summed in row order.
+constexpr int kThetaBatch = 16;
+
 template <typename T>
-__global__ void k_theta_partial(const T* __restrict__ x, long long ldx, int64_t n, int C,
-                                double* __restrict__ partial, int* __restrict__ flags) {
+__global__ __launch_bounds__(kWave) void k_theta_partial(const T* __restrict__ x, long long ldx, int64_t n, int C,
+                                                         double* __restrict__ partial, int* __restrict__ flags,
+                                                         uint64_t* __restrict__ F, unsigned long long* __restrict__ cnt) {
+  __shared__ uint64_t s_stage[kStage];
   const int c = blockIdx.y * blockDim.x + threadIdx.x;
-  if (c >= C) return;
+  const bool live = c < C;
   const int64_t lo = (int64_t)blockIdx.x * kThetaRows;
   const int64_t hi = (lo + kThetaRows) < n ? lo + kThetaRows : n;
   double sum = 0.0;
   int f = 0;
-  for (int64_t i = lo; i < hi; ++i) {
-    const T v = x[static_cast<size_t>(i) * static_cast<size_t>(ldx) + c];
-    if (!isfinite(static_cast<double>(v))) f |= 1;
-    if (v < T(0)) f |= 2;
-    sum = sum + fabs(static_cast<double>(v));
+  int staged = 0;  // wave-uniform
+  for (int64_t i0 = lo; i0 < hi; i0 += kThetaBatch) {
+    T v[kThetaBatch];
+#pragma unroll
+    for (int k = 0; k < kThetaBatch; ++k)
+      v[k] = (live && i0 + k < hi) ? x[static_cast<size_t>(i0 + k) * static_cast<size_t>(ldx) + c] : T(0);
+#pragma unroll
+    for (int k = 0; k < kThetaBatch; ++k) {
+      if (i0 + k >= hi) break;  // wave-uniform
+      if (!isfinite(static_cast<double>(v[k]))) f |= 1;
+      if (v[k] < T(0)) f |= 2;
+      sum = sum + fabs(static_cast<double>(v[k]));
+      stage_push(s_stage, staged, (static_cast<uint64_t>(i0 + k) << 32) | static_cast<uint32_t>(c), v[k] != T(0), F,
+                 cnt);
+    }
   }
-  partial[(size_t)blockIdx.x * C + c] = sum;
+  stage_flush(s_stage, staged, F, cnt);
+  if (live) partial[(size_t)blockIdx.x * C + c] = sum;
   if (f) atomicOr(flags, f);
 }
 
@@ -183,7 +201,8 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   // thresholds theta_c = eps ||x_c||_1 and signal checks
   if (tblocks > 0) {
     dim3 grid((unsigned)tblocks, (unsigned)((C + 63) / 64));
-    k_theta_partial<T><<<grid, 64, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1);
+    k_theta_partial<T><<<grid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
+                                              sc.frontier[0].as<uint64_t>(), counts);
   }
   k_theta_final<T><<<grid_for(C, 64), 64, 0, s>>>(sc.partial.as<double>(), tblocks, C, eps,
                                                   qids ? dq : nullptr, qid_base, cp);
@@ -240,7 +259,6 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   uint64_t* F[2] = {sc.frontier[0].as<uint64_t>(), sc.frontier[1].as<uint64_t>()};
   Cell* acc[2] = {sc.acc[0].as<Cell>(), sc.acc[1].as<Cell>()};
   const unsigned cgrid = grid_for(n * (int64_t)(C >= kWave ? kWave : C), kThreads, 8192);
-  k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroValue<T>{x, ldc}, n, C, (long long)C, 1ll, F[0], counts, nullptr);
 
   // rows with long deterministic prefixes, deferred per level to k_det_big
   constexpr unsigned long long kBigCap = 1ull << 16;

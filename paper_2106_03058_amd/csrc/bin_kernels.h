@@ -97,9 +97,9 @@ __device__ __forceinline__ unsigned int block_scan_1024(const unsigned int* v, u
   return total;
 }
 
-// Partition of the records into buckets: a tile of 16384 records is sorted
+// Partition of the records into buckets: a tile of 32768 records is sorted
 // by bucket in LDS, then every bucket's run is written out contiguously.
-constexpr int kPartPerThread = 32;
+constexpr int kPartPerThread = 64;
 constexpr int kPartTile = kReduceThreads * kPartPerThread;
 
 __global__ __launch_bounds__(kReduceThreads) void k_partition(const uint32_t* __restrict__ rec,
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_bin_scatter(const uint32_t* 
 // acc += count * fl(theta_c) (its deterministic pushes are already in acc);
 // the bin's non-zero cells are gathered in LDS and appended to the next
 // frontier with one atomic per bin.
-constexpr int kSumThreads = 256;
+constexpr int kSumThreads = 512;
 
 __global__ __launch_bounds__(kSumThreads) void k_bin_sum(const uint32_t* __restrict__ tmp,
                                                          const unsigned long long* __restrict__ bin_off,

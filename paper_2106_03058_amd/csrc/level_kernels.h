@@ -780,11 +780,11 @@ template <typename T, bool kFirst>
 __global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __restrict__ x,
                                                        const typename Prec<T>::Cell* __restrict__ acc_cur,
                                                        double* __restrict__ est) {
+  __shared__ double s_part[kThreads / kWave];
   const unsigned long long count = *A.cnt_in;
-  // large frontiers: every 16th entry, scaled up (the estimate only chooses
-  // between interchangeable aggregation modes, and levels this large are far
-  // from the choice's threshold)
-  const unsigned long long stride = count >= (1ull << 22) ? 16ull : 1ull;
+  // large frontiers: an evenly spaced sample of 2^20 to 2^21 entries, scaled
+  // up (the estimate only chooses between interchangeable aggregation modes)
+  const unsigned long long stride = count >= (1ull << 21) ? count >> 20 : 1ull;
   double sum = 0.0;
   for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; j * stride < count;
        j += (unsigned long long)gridDim.x * blockDim.x) {
@@ -810,7 +810,13 @@ __global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __r
   }
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off);
-  if (lane_id() == 0 && sum != 0.0) atomicAdd(est, sum * static_cast<double>(stride));
+  if (lane_id() == 0) s_part[threadIdx.x / kWave] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {  // one atomic per block
+    double b = 0.0;
+    for (int w = 0; w < kThreads / kWave; ++w) b += s_part[w];
+    if (b != 0.0) atomicAdd(est, b * static_cast<double>(stride));
+  }
 }
 
 // ------------------------------------------------- frontier compaction

@@ -34,15 +34,17 @@ using namespace lvl;
 // ||x_c||_1 in binary64: sequential over blocks of 4096 rows, then over the
 // block sums.  flags: 1 = non-finite entry, 2 = negative entry.  The same
 // pass forms the level-0 frontier (the non-zero cells of x, in any order).
-// One wave per (row block, 64 columns); loads are issued 16 rows at a time
-// and summed in row order.
-constexpr int kThetaBatch = 16;
+// One wave per (row block, 64 columns); loads are issued 32 rows at a time
+// and summed in row order; the frontier goes out in chunks of up to kCap
+// entries (one atomic each): 2048 when every wave of the launch fits on the
+// chip at once with 16 KiB of LDS each, else 1024.
+constexpr int kThetaBatch = 32;
 
-template <typename T>
+template <typename T, int kCap>
 __global__ __launch_bounds__(kWave) void k_theta_partial(const T* __restrict__ x, long long ldx, int64_t n, int C,
                                                          double* __restrict__ partial, int* __restrict__ flags,
                                                          uint64_t* __restrict__ F, unsigned long long* __restrict__ cnt) {
-  __shared__ uint64_t s_stage[kStage];
+  __shared__ uint64_t s_stage[kCap];
   const int c = blockIdx.y * blockDim.x + threadIdx.x;
   const bool live = c < C;
   const int64_t lo = (int64_t)blockIdx.x * kThetaRows;
@@ -61,8 +63,8 @@ __global__ __launch_bounds__(kWave) void k_theta_partial(const T* __restrict__ x
       if (!isfinite(static_cast<double>(v[k]))) f |= 1;
       if (v[k] < T(0)) f |= 2;
       sum = sum + fabs(static_cast<double>(v[k]));
-      stage_push(s_stage, staged, (static_cast<uint64_t>(i0 + k) << 32) | static_cast<uint32_t>(c), v[k] != T(0), F,
-                 cnt);
+      stage_push<kCap>(s_stage, staged, (static_cast<uint64_t>(i0 + k) << 32) | static_cast<uint32_t>(c),
+                              v[k] != T(0), F, cnt);
     }
   }
   stage_flush(s_stage, staged, F, cnt);
@@ -201,8 +203,12 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   // thresholds theta_c = eps ||x_c||_1 and signal checks
   if (tblocks > 0) {
     dim3 grid((unsigned)tblocks, (unsigned)((C + 63) / 64));
-    k_theta_partial<T><<<grid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
-                                              sc.frontier[0].as<uint64_t>(), counts);
+    if (tblocks * static_cast<int64_t>(grid.y) <= 2048)
+      k_theta_partial<T, 2048><<<grid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
+                                                      sc.frontier[0].as<uint64_t>(), counts);
+    else
+      k_theta_partial<T, 1024><<<grid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
+                                                      sc.frontier[0].as<uint64_t>(), counts);
   }
   k_theta_final<T><<<grid_for(C, 64), 64, 0, s>>>(sc.partial.as<double>(), tblocks, C, eps,
                                                   qids ? dq : nullptr, qid_base, cp);

@@ -166,6 +166,11 @@ __device__ __forceinline__ unsigned long long bin_of(uint32_t rec) {
   return static_cast<unsigned long long>(rec & kRecCellMask) >> kBinLog2;
 }
 
+// Counts use tiles of kCountTile records (read kBinPerThread per thread at a
+// time): a tile's window of bins is flushed with one global atomic per bin,
+// so larger tiles mean fewer atomics on the same counters.
+constexpr int kCountTile = 8 * kBinTile;
+
 __global__ __launch_bounds__(kReduceThreads) void k_bin_count(const uint32_t* __restrict__ part,
                                                               const unsigned long long* __restrict__ rec_count,
                                                               unsigned long long* __restrict__ bin_count,
@@ -174,26 +179,29 @@ __global__ __launch_bounds__(kReduceThreads) void k_bin_count(const uint32_t* __
   __shared__ unsigned int s_h[kBinWindow];
   const unsigned long long total = *rec_count;
   const unsigned long long bpb = 1ull << (shift - kBinLog2);  // bins per bucket
-  for (unsigned long long lo = (unsigned long long)blockIdx.x * kBinTile; lo < total;
-       lo += (unsigned long long)gridDim.x * kBinTile) {
-    const unsigned long long w0 = (bin_of(part[lo]) / bpb) * bpb;  // first bin of the tile's first bucket
+  for (unsigned long long t0 = (unsigned long long)blockIdx.x * kCountTile; t0 < total;
+       t0 += (unsigned long long)gridDim.x * kCountTile) {
+    const unsigned long long w0 = (bin_of(part[t0]) / bpb) * bpb;  // first bin of the tile's first bucket
+    const unsigned long long t1 = t0 + kCountTile < total ? t0 + kCountTile : total;
     for (int i = threadIdx.x; i < kBinWindow; i += blockDim.x) s_h[i] = 0;
     __syncthreads();
-    uint32_t r[kBinPerThread];
+    for (unsigned long long lo = t0; lo < t1; lo += kBinTile) {
+      uint32_t r[kBinPerThread];
 #pragma unroll
-    for (int k = 0; k < kBinPerThread; ++k) {
-      const unsigned long long i = lo + (unsigned long long)(k * kReduceThreads + threadIdx.x);
-      r[k] = i < total ? part[i] : 0u;
-    }
+      for (int k = 0; k < kBinPerThread; ++k) {
+        const unsigned long long i = lo + (unsigned long long)(k * kReduceThreads + threadIdx.x);
+        r[k] = i < t1 ? part[i] : 0u;
+      }
 #pragma unroll
-    for (int k = 0; k < kBinPerThread; ++k) {
-      const unsigned long long i = lo + (unsigned long long)(k * kReduceThreads + threadIdx.x);
-      if (i < total) {
-        const unsigned long long gb = bin_of(r[k]);
-        if (gb >= w0 && gb - w0 < (unsigned long long)kBinWindow)
-          atomicAdd(&s_h[gb - w0], 1u);
-        else
-          atomicAdd(bin_count + gb, 1ull);
+      for (int k = 0; k < kBinPerThread; ++k) {
+        const unsigned long long i = lo + (unsigned long long)(k * kReduceThreads + threadIdx.x);
+        if (i < t1) {
+          const unsigned long long gb = bin_of(r[k]);
+          if (gb >= w0 && gb - w0 < (unsigned long long)kBinWindow)
+            atomicAdd(&s_h[gb - w0], 1u);
+          else
+            atomicAdd(bin_count + gb, 1ull);
+        }
       }
     }
     __syncthreads();

@@ -109,7 +109,9 @@ const char* agp_last_error(void);
  * out-arcs counts as out-degree 1 in D.
  * The library copies the arrays; the caller may free them on return.  Inside
  * the handle every row (in the push direction) is sorted ascending by
- * (degree of neighbour in D, id).
+ * (degree of neighbour in D, id).  The handle holds 12 bytes of device
+ * memory per arc (neighbour id, its degree in D, the end of its degree group
+ * within the row) and 16 per node, plus the working memory of later calls.
  * Errors: AGP_EINVAL for bad sizes, ids out of range, unknown flags,
  * AGP_REVERSE without AGP_DIRECTED, or (with AGP_VALIDATE) duplicate arcs or
  * (undirected only) an asymmetric matrix; AGP_ENOMEM; AGP_EDEVICE.

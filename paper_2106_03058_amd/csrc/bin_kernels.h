@@ -327,7 +327,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_bin_scatter(const uint32_t* 
 // One block per bin: signed record counts in LDS, then each cell's new value
 // acc += count * fl(theta_c) (its deterministic pushes are already in acc);
 // the bin's non-zero cells are gathered in LDS and appended to the next
-// frontier with one atomic per bin.
+// frontier with one atomic per bin.  With det non-null (a flag per bin that
+// the level's deterministic pushes set), a bin whose flag is clear holds
+// only zeros before its records: it is not read, and without records it has
+// nothing to do.  A set flag is cleared for the next level; a stale set flag
+// only costs the reads.
 constexpr int kSumThreads = 512;
 
 __global__ __launch_bounds__(kSumThreads) void k_bin_sum(const uint32_t* __restrict__ tmp,
@@ -335,7 +339,7 @@ __global__ __launch_bounds__(kSumThreads) void k_bin_sum(const uint32_t* __restr
                                                          const ColParams* __restrict__ cp, long long su, long long sc,
                                                          unsigned long long cells, long long* __restrict__ acc,
                                                          uint64_t* __restrict__ F, unsigned long long* __restrict__ cnt,
-                                                         const int* __restrict__ mode) {
+                                                         const int* __restrict__ mode, uint8_t* __restrict__ det) {
   if (*mode != kModeBinned) return;
   constexpr int kBin = 1 << kBinLog2;
   __shared__ int s_cnt[kBin];
@@ -345,10 +349,12 @@ __global__ __launch_bounds__(kSumThreads) void k_bin_sum(const uint32_t* __restr
   const int lane = lane_id();
   const unsigned long long gb = blockIdx.x;
   const unsigned long long cell0 = gb << kBinLog2;
+  const bool read_acc = det == nullptr || det[gb] != 0;
+  const unsigned long long lo = bin_off[gb], hi = bin_off[gb + 1];
+  if (!read_acc && lo == hi) return;  // the whole block: no record, no deterministic push
   for (int j = threadIdx.x; j < kBin; j += blockDim.x) s_cnt[j] = 0;
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
-  const unsigned long long lo = bin_off[gb], hi = bin_off[gb + 1];
   for (unsigned long long i0 = lo + threadIdx.x; i0 < hi; i0 += (unsigned long long)blockDim.x * 8) {
     uint32_t rr[8];
 #pragma unroll
@@ -367,7 +373,7 @@ __global__ __launch_bounds__(kSumThreads) void k_bin_sum(const uint32_t* __restr
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const unsigned long long cell = cell0 + static_cast<unsigned long long>((k0 + k) * kSumThreads + threadIdx.x);
-      vv[k] = cell < cells ? acc[cell] : 0ll;
+      vv[k] = (read_acc && cell < cells) ? acc[cell] : 0ll;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -393,6 +399,7 @@ __global__ __launch_bounds__(kSumThreads) void k_bin_sum(const uint32_t* __restr
   __syncthreads();
   const unsigned int total = s_n;
   if (threadIdx.x == 0 && total) s_base = atomicAdd(cnt, static_cast<unsigned long long>(total));
+  if (threadIdx.x == 0 && det != nullptr && read_acc) det[gb] = 0;
   __syncthreads();
   for (unsigned int i = threadIdx.x; i < total; i += blockDim.x) {
     const unsigned long long cell = cell0 + s_nz[i];

@@ -122,6 +122,8 @@ struct LevelArgs {
   unsigned long long* big_ctr;   // this level's list counter, zero at the start
   BigRow* big;
   unsigned long long big_cap;
+  // binned levels: deterministic pushes mark their destination bin (nullptr: no marks)
+  uint8_t* det_bins;
 };
 
 // ----------------------------------------------------- working precision
@@ -565,6 +567,8 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
           if (B.neg[e]) val = -val;
           emit = P::to_units(val, *cpd, &delta);
           if (!emit) atomicOr(A.err + (kServe ? vc : 0u), 1);
+          if (binned && A.det_bins != nullptr)
+            A.det_bins[(static_cast<size_t>(v) * A.su + static_cast<size_t>(vc) * A.sc) >> kBinLog2] = 1;
         }
         emit_atomic(emit, v, vc, delta);
       }
@@ -718,6 +722,7 @@ __global__ __launch_bounds__(kThreads) void k_det_big(LevelArgs A, typename Prec
   const BigRow* R = A.big;
   const unsigned long long total = R[nb - 1].off + R[nb - 1].J;
   const bool sparse = *A.mode_out == kModeSparse;
+  uint8_t* const det_bins = *A.mode_out == kModeBinned ? A.det_bins : nullptr;
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   uint64_t* stage = s_stage[wave];
@@ -758,6 +763,7 @@ __global__ __launch_bounds__(kThreads) void k_det_big(LevelArgs A, typename Prec
         if (!emit) atomicOr(A.err, 1);
       }
       const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(vc) * A.sc;
+      if (emit && det_bins != nullptr) det_bins[vcell >> kBinLog2] = 1;
       bool first = false;
       if (emit) {
         if (sparse)

@@ -241,7 +241,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
         sc.rec[1].reserve(rec_cap * sizeof(uint32_t), false, s) ||
         sc.bins.reserve(sizeof(unsigned int) * kBuckets + sizeof(unsigned long long) * (2 * kBuckets + 1) +
                             sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1) +
-                            sizeof(unsigned long long) * (3 * nbins + 1), true, s)) {
+                            sizeof(unsigned long long) * (3 * nbins + 1) + static_cast<size_t>(nbins), true, s)) {
       sc.rec[0].release();  // not enough memory for the record buffers: atomics instead
       sc.rec[1].release();
       binned = false;
@@ -255,6 +255,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   unsigned long long* bin_count = binned ? rec_counts + AGP_MAX_LEVELS + 1 : nullptr;
   unsigned long long* bin_off = binned ? bin_count + nbins : nullptr;
   unsigned long long* bin_cur = binned ? bin_off + nbins + 1 : nullptr;
+  uint8_t* det_bins = binned ? reinterpret_cast<uint8_t*>(bin_cur + nbins) : nullptr;  // any stale value is safe
   if (binned) {
     AGP_HIP(hipMemsetAsync(rec_counts, 0, sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1), s));
     AGP_HIP(hipMemsetAsync(bin_count, 0, sizeof(unsigned long long) * nbins, s));
@@ -321,6 +322,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     A.mode_out = mode + i + 1;
     const bool bin_level = binned && i < L;
     A.rec = bin_level ? sc.rec[0].as<uint32_t>() : nullptr;
+    A.det_bins = bin_level ? det_bins : nullptr;
     A.big_ctr = (big_ctr != nullptr && i < L) ? big_ctr + i : nullptr;
     A.big = big_rows;
     A.big_cap = big_cap;
@@ -353,7 +355,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
       k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(r1, rec_counts + i, bin_cur, r0, mode + i + 1, shift);
       k_bin_sum<<<static_cast<unsigned>(nbins), kSumThreads, 0, s>>>(
           r0, bin_off, cp, (long long)C, 1ll, static_cast<unsigned long long>(cells),
-          reinterpret_cast<long long*>(nxt), F[(i + 1) & 1], counts + i + 1, mode + i + 1);
+          reinterpret_cast<long long*>(nxt), F[(i + 1) & 1], counts + i + 1, mode + i + 1, det_bins);
     }
     if (i < L)
       k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, (long long)C, 1ll, F[(i + 1) & 1],

@@ -341,6 +341,7 @@ int step(agp_server* s) {
     bin_count = reinterpret_cast<unsigned long long*>(est + 1);
     bin_off = bin_count + s->nbins;
     bin_cur = bin_off + s->nbins + 1;
+    A.det_bins = reinterpret_cast<uint8_t*>(bin_cur + s->nbins);  // any stale value is safe
     A.rec = s->rec[0].as<uint32_t>();
     A.rec_count = rec_count;
     A.rec_cap = s->rec_cap;
@@ -364,7 +365,7 @@ int step(agp_server* s) {
     k_bin_scatter<<<2048, kReduceThreads, 0, st>>>(r1, rec_count, bin_cur, r0, mode, s->bucket_shift);
     k_bin_sum<<<static_cast<unsigned>(s->nbins), kSumThreads, 0, st>>>(
         r0, bin_off, A.cp, 1ll, (long long)s->n, static_cast<unsigned long long>(s->n) * s->S, acc[nxt], F[nxt],
-        counts + nxt, mode);
+        counts + nxt, mode, A.det_bins);
   }
   k_compact<<<grid_for(s->n * (int64_t)s->S, kThreads, 8192), kThreads, 0, st>>>(
       NonZeroCell<float>{acc[nxt]}, s->n, s->S, 1ll, (long long)s->n, F[nxt], counts + nxt, s->mode.as<int>());
@@ -501,7 +502,8 @@ int agp_server_create(const agp_graph_t* g, const agp_server_config_t* cfg, agp_
       if (s->rec[0].reserve(s->rec_cap * sizeof(uint32_t), false, s->stream) ||
           s->rec[1].reserve(s->rec_cap * sizeof(uint32_t), false, s->stream) ||
           s->bins.reserve(sizeof(unsigned int) * lvl::kBuckets + sizeof(unsigned long long) * (2 * lvl::kBuckets + 2) +
-                              sizeof(double) + sizeof(unsigned long long) * (3 * s->nbins + 1), true, s->stream)) {
+                              sizeof(double) + sizeof(unsigned long long) * (3 * s->nbins + 1) +
+                              static_cast<size_t>(s->nbins), true, s->stream)) {
         s->rec[0].release();  // not enough memory for the records: atomics only
         s->rec[1].release();
         s->bins.release();

@@ -53,8 +53,8 @@ HBM_PEAK_GBPS = 8000.0
 # --calibrate-copy; FETCH_SIZE is scaled by the factor that makes the 1 GiB
 # copy read 1 GiB.  Valid only for the kernel sources they were taken from.
 TRAFFIC = {
-    "katz-tp": {"sources": "d27807b49a042c3c", "columns": 256, "bytes_per_launch": 11101846014.0,
-                "fetch_bytes": 7455831217.0, "write_bytes": 3646014797.0},
+    "katz-tp": {"sources": "eb4cb502d362e09b", "columns": 256, "bytes_per_launch": 11243650518.0,
+                "fetch_bytes": 7490381975.0, "write_bytes": 3753268544.0},
 }
 KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
                   "paper_2106_03058_amd/csrc/propagate.hip")

@@ -784,9 +784,9 @@ def main() -> int:
     log(f"{ms_per_step:.1f} ms/step, {pushes_step:.3e} pushes/step")
 
     # roofline of the dominant kernel: the level kernel of levels 1..L
-    # (k_level<float, false, false>, timed together with the k_det_big
-    # launch that pushes the level's deferred long rows; level 0 reads the
-    # signal and is a separate instantiation)
+    # (k_level<float, false, false>, timed together with the k_det_big and
+    # k_samp_big launches that make the level's deferred pushes; level 0
+    # reads the signal and is a separate instantiation)
     mid_bytes = mid_ms = 0.0
     launches = 0
     all_bytes = all_ms = 0.0
@@ -856,7 +856,7 @@ def main() -> int:
         "one_per_launch_equals_batched": single_ok,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_level<float, false, false> + k_det_big<float> (levels 1..L)",
+            "kernel": "k_level<float, false, false> + k_det_big<float> + k_samp_big<float> (levels 1..L)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",

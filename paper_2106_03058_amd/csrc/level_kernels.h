@@ -71,6 +71,21 @@ struct BigRow {
   uint32_t c, J, neg, pad;
 };
 
+// Likewise an entry whose sampled suffix makes samp_items (64 by default)
+// or more work items (a hub holding a small residue in some column): its
+// items go to a second list that k_samp_big spreads over the whole grid
+// (one item per lane).
+constexpr long long kBigItems = 64;
+
+struct BigSamp {
+  unsigned long long off;  // work items of the entries deferred before this one
+  int64_t rp;              // first arc of the row
+  double cv;               // c = rho |r| d_u^-b
+  double p0;               // a = 0: the sampling probability of every run
+  uint32_t u, c, J, d;
+  uint32_t neg, items;
+};
+
 struct ColParams {
   double theta;          // eps * ||x_c||_1
   double scale;          // 2^-ue (binary32 units)
@@ -122,6 +137,9 @@ struct LevelArgs {
   unsigned long long* big_ctr;   // this level's list counter, zero at the start
   BigRow* big;
   unsigned long long big_cap;
+  unsigned long long* samp_ctr;  // the same for deferred sampled suffixes (entries << 40 | items)
+  BigSamp* samp;
+  long long samp_items;          // work items from which an entry's sampled suffix is deferred
   // binned levels: deterministic pushes mark their destination bin (nullptr: no marks)
   uint8_t* det_bins;
 };
@@ -505,6 +523,28 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
                   dwork = 0;
                 }
               }
+              if (!kServe && A.samp_ctr != nullptr && iwork >= A.samp_items &&
+                  (__hip_atomic_load(A.samp_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> kBigShift) <
+                      A.big_cap) {
+                const unsigned long long old =
+                    atomic_add_ret(A.samp_ctr, (1ull << kBigShift) | static_cast<unsigned long long>(iwork));
+                const unsigned long long slot = old >> kBigShift;
+                if (slot < A.big_cap) {
+                  BigSamp bs;
+                  bs.off = old & ((1ull << kBigShift) - 1ull);
+                  bs.rp = erp;
+                  bs.cv = ecv;
+                  bs.p0 = ep0;
+                  bs.u = eu;
+                  bs.c = ec;
+                  bs.J = eJ;
+                  bs.d = ed;
+                  bs.neg = eneg ? 1u : 0u;
+                  bs.items = static_cast<uint32_t>(iwork);
+                  A.samp[slot] = bs;
+                  iwork = 0;
+                }
+              }
               // bound on the magnitude this entry can add (every contribution
               // is at most max(inc_0, theta)), for the overflow check
               const T big = to_w(inc0 > eth ? inc0 : eth, T());
@@ -775,6 +815,165 @@ __global__ __launch_bounds__(kThreads) void k_det_big(LevelArgs A, typename Prec
     }
   }
   if (sparse) stage_flush(stage, staged, A.fout, A.cnt_out);
+}
+
+// The sampled work items of the entries a level deferred, after its k_level
+// launch: lane g takes items g, g + G, ... of the concatenated entries (G
+// lanes in the grid), finds an item's entry by binary search over the
+// entries' item offsets and walks its windows exactly as k_level does (the
+// same runs, draws and acceptance tests, so the same pushes); the pushes
+// are emitted as in k_level's mode for the level (records, first-touch
+// appends or plain atomics), and the level's candidate and acceptance
+// counters get this kernel's counts.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Prec<T>::Cell* __restrict__ acc_next) {
+  using P = Prec<T>;
+  using Delta = typename P::Delta;
+  constexpr int kWaves = kThreads / kWave;
+  __shared__ uint64_t s_stage[kWaves][kStage];
+  __shared__ unsigned int s_hist[kBuckets];
+  const unsigned long long ctr = *A.samp_ctr;
+  unsigned long long nb = ctr >> kBigShift;
+  if (nb == 0) return;  // the whole grid
+  if (nb > A.big_cap) nb = A.big_cap;  // entries beyond the list kept their items
+  const BigSamp* R = A.samp;
+  const unsigned long long total = R[nb - 1].off + R[nb - 1].items;
+  const int mode = *A.mode_out;
+  const bool binned = mode == kModeBinned;
+  const bool sparse = mode == kModeSparse;
+  if (binned) {
+    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) s_hist[i] = 0;
+    __syncthreads();
+  }
+  const int wave = threadIdx.x / kWave;
+  uint64_t* stage = s_stage[wave];
+  int staged = 0;  // wave-uniform
+  unsigned long long n_cand = 0, n_acc = 0;
+  const unsigned long long G = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
+  unsigned long long next = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+
+  bool active = false, need_run = false, neg = false, azero = true;
+  uint32_t u = 0, c = 0, s = 0, rend = 0, run_end = 0, pos = 0, t = 0, ctr3 = 0, key0 = 0, key1 = 0;
+  int64_t rpu = 0;
+  double cv = 0.0, dstart = 1.0, th = 0.0;
+  const ColParams* cpp = A.cp;
+  SkipTable tab;
+  for (;;) {
+    if (active && need_run && s >= rend) active = false;
+    if (!active && next < total) {  // the lane's next item
+      unsigned long long e = 0, hi = nb;  // last entry with off <= next
+      while (hi - e > 1) {
+        const unsigned long long mid = (e + hi) >> 1;
+        if (R[mid].off <= next)
+          e = mid;
+        else
+          hi = mid;
+      }
+      const BigSamp& bs = R[e];
+      const uint32_t il = static_cast<uint32_t>(next - bs.off);
+      next += G;
+      u = bs.u;
+      c = bs.c;
+      rpu = bs.rp;
+      cv = bs.cv;
+      neg = bs.neg != 0;
+      const uint32_t J = bs.J, d = bs.d;
+      cpp = A.cp + c;
+      azero = (cpp->flags & kAZero) != 0;
+      th = cpp->theta;
+      ctr3 = (cpp->qid << 8) | static_cast<uint32_t>(cpp->level);
+      key0 = cpp->key0;
+      key1 = cpp->key1;
+      const uint32_t nwin = ((d - 1) >> kSegLog2) - (J >> kSegLog2) + 1;
+      const uint32_t w0 = il * kWinPerItem;
+      const uint32_t w1 = (w0 + kWinPerItem) < nwin ? w0 + kWinPerItem : nwin;
+      const uint32_t ws = ((J >> kSegLog2) + w0) << kSegLog2;
+      const uint32_t we = ((J >> kSegLog2) + w1) << kSegLog2;
+      s = ws > J ? ws : J;
+      rend = we < d ? we : d;
+      if (azero) tab = make_skip_table(bs.p0);
+      active = true;
+      need_run = true;
+    }
+    if (!__any(active)) break;
+    if (active && need_run) {  // a run, as in k_level
+      const uint32_t wnext = ((s >> kSegLog2) + 1u) << kSegLog2;
+      const uint32_t wend = wnext < rend ? wnext : rend;
+      run_end = wend;
+      if (!azero) {
+        const uint32_t ds = A.nd[rpu + s];
+        const uint32_t ge = A.gend[rpu + s];
+        dstart = cpp->da[ds];
+        if (ge < wend) run_end = ge;
+        const double num = cv * dstart;
+        tab = make_skip_table(num / th);
+      }
+      pos = s;
+      t = 0;
+      need_run = false;
+    }
+    bool emit = false;
+    uint32_t v = 0;
+    Delta delta{};
+    if (active && !need_run) {  // one draw, as in k_level
+      const U4 o = philox4x32_10(t, s, u, ctr3, key0, key1);
+      const double V = unit_double(o.x, o.y);
+      const uint32_t cand = pos + static_cast<uint32_t>(geometric_skip(tab, V));
+      if (cand >= run_end) {
+        s = run_end;
+        need_run = true;
+      } else {
+        ++n_cand;
+        const int64_t arc = rpu + cand;
+        bool accept = true;
+        if (!azero) {
+          const double ratio = cpp->da[A.nd[arc]] / dstart;
+          accept = unit_double(o.z, o.w) < ratio;
+        }
+        if (accept) {
+          ++n_acc;
+          v = A.col[arc];
+          emit = true;
+          delta = P::theta_units(*cpp, neg);
+        }
+        pos = cand + 1;
+        ++t;
+      }
+    }
+    if (binned) {
+      uint32_t rec = 0;
+      if (emit) {
+        const uint32_t vcell = v * static_cast<uint32_t>(A.su) + c * static_cast<uint32_t>(A.sc);
+        rec = vcell | (neg ? 0x80000000u : 0u);
+        atomicAdd(&s_hist[vcell >> A.bucket_shift], 1u);
+      }
+      stage_push_records(reinterpret_cast<uint32_t*>(stage), staged, rec, emit, A, acc_next);
+    } else {
+      const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(c) * A.sc;
+      bool first = false;
+      if (emit) {
+        if (sparse)
+          first = P::add_ret(acc_next, vcell, delta);
+        else
+          P::add(acc_next, vcell, delta);
+      }
+      if (sparse) stage_push(stage, staged, (static_cast<uint64_t>(v) << 32) | c, first, A.fout, A.cnt_out);
+    }
+  }
+  if (sparse) stage_flush(stage, staged, A.fout, A.cnt_out);
+  if (binned) {
+    stage_flush_records(reinterpret_cast<uint32_t*>(stage), staged, A, acc_next);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
+      if (s_hist[i]) atomicAdd(A.bucket_count + i, s_hist[i]);
+  }
+  unsigned long long* cnt = A.counters + static_cast<size_t>(A.level) * kNumCounters;
+  const unsigned long long v3 = wave_sum_u64(n_cand);
+  const unsigned long long v4 = wave_sum_u64(n_acc);
+  if (lane_id() == 0) {
+    if (v3) atomicAdd(cnt + 3, v3);
+    if (v4) atomicAdd(cnt + 4, v4);
+  }
 }
 
 // ------------------------------------------------- push estimate

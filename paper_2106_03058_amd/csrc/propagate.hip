@@ -270,18 +270,30 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   // rows with long deterministic prefixes, deferred per level to k_det_big
   constexpr unsigned long long kBigCap = 1ull << 16;
   unsigned long long big_cap = kBigCap;
-  if (const char* e = std::getenv("AGP_BIG_ROWS")) {  // shorter list (tests); 0: no deferral
+  if (const char* e = std::getenv("AGP_BIG_ROWS")) {  // shorter lists (tests); 0: no deferral
     const unsigned long long v = std::strtoull(e, nullptr, 10);
     if (v < big_cap) big_cap = v;
   }
+  long long samp_items = kBigItems;
+  if (const char* e = std::getenv("AGP_BIG_ITEMS")) {  // smaller deferral cut for sampled suffixes (tests)
+    const long long v = std::strtoll(e, nullptr, 10);
+    if (v >= 1) samp_items = v;
+  }
+  // (and entries with many sampled work items, deferred to k_samp_big):
+  // per-level counters of both lists, then the two lists
   unsigned long long* big_ctr = nullptr;
+  unsigned long long* samp_ctr = nullptr;
   BigRow* big_rows = nullptr;
+  BigSamp* samp_rows = nullptr;
   if (big_cap > 0 &&
-      sc.big.reserve(sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1) + sizeof(BigRow) * kBigCap, false, s) ==
-          AGP_OK) {
+      sc.big.reserve(sizeof(unsigned long long) * 2 * (AGP_MAX_LEVELS + 1) + sizeof(BigRow) * kBigCap +
+                         sizeof(BigSamp) * kBigCap,
+                     false, s) == AGP_OK) {
     big_ctr = sc.big.as<unsigned long long>();
-    big_rows = reinterpret_cast<BigRow*>(big_ctr + AGP_MAX_LEVELS + 1);
-    AGP_HIP(hipMemsetAsync(big_ctr, 0, sizeof(unsigned long long) * (static_cast<size_t>(L) + 1), s));
+    samp_ctr = big_ctr + AGP_MAX_LEVELS + 1;
+    big_rows = reinterpret_cast<BigRow*>(samp_ctr + AGP_MAX_LEVELS + 1);
+    samp_rows = reinterpret_cast<BigSamp*>(big_rows + kBigCap);
+    AGP_HIP(hipMemsetAsync(big_ctr, 0, sizeof(unsigned long long) * 2 * (AGP_MAX_LEVELS + 1), s));
   } else {
     (void)hipGetLastError();  // no room for the list: every row stays with its wave
   }
@@ -324,7 +336,10 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     A.rec = bin_level ? sc.rec[0].as<uint32_t>() : nullptr;
     A.det_bins = bin_level ? det_bins : nullptr;
     A.big_ctr = (big_ctr != nullptr && i < L) ? big_ctr + i : nullptr;
+    A.samp_ctr = (samp_ctr != nullptr && i < L) ? samp_ctr + i : nullptr;
     A.big = big_rows;
+    A.samp = samp_rows;
+    A.samp_items = samp_items;
     A.big_cap = big_cap;
     A.rec_count = bin_level ? rec_counts + i : nullptr;
     Cell* cur = acc[i & 1];
@@ -343,6 +358,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     else
       k_level<T, false, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
     if (A.big_ctr != nullptr) k_det_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
+    if (A.samp_ctr != nullptr) k_samp_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
     if (stats) AGP_HIP(hipEventRecord(ev[2 * i + 1], s));
     if (bin_level) {
       uint32_t* r0 = sc.rec[0].as<uint32_t>();

@@ -107,3 +107,42 @@ def test_long_rows_many_columns(env):
     ref, cnt = oracle.propagate(sg, a, b, w, x, eps, 5, wp=32, qids=q)
     out, st = agp.propagate(G, a, b, w, torch.from_numpy(x).to("cuda:0"), eps, 5, qids=q, stats=True)
     _check(out.cpu().numpy().astype(np.float64), st, ref, cnt, len(w) - 1)
+
+
+def test_long_sampled_rows(env, monkeypatch):
+    """Hubs reached with a small residue: their sampled suffixes make 8 or
+    more work items of 16 windows and, with the deferral cut lowered to 8
+    items (AGP_BIG_ITEMS), are deferred to k_samp_big (one item per lane
+    over the grid); bit-exact with the oracle in every mode and list
+    length, and with the default cut."""
+    torch, agp, g, G, sg = env
+    monkeypatch.setenv("AGP_BIG_ITEMS", "8")
+    deg = np.diff(g.row_ptr)
+    rng = np.random.default_rng(3)
+    src = []
+    for h in (2, 3):  # the hubs of 9000 and 12000 neighbours
+        src += [int(v) for v in rng.choice(g.col[g.row_ptr[h]:g.row_ptr[h + 1]], size=3, replace=False)]
+    x = inputs.one_hot(g.n, src)
+    X = torch.from_numpy(x).to("cuda:0")
+    eps = 1e-4
+    # TP: level-1 residue of hub h from source s is 1/d_s, so c = 1/(d_s d_h) < eps: sampled, and the row
+    # makes ceil(ceil(d_h / 64) / 16) >= 8 items
+    for s in src[:1]:
+        h = 2
+        assert 1.0 / (deg[s] * deg[h]) < eps and ((deg[h] + 63) // 64 + 15) // 16 >= 8
+    for a, b, w in ((0.0, 1.0, inputs.weights_tp(6)), (0.5, 0.5, inputs.weights_ppr(0.2, 6))):
+        ref, cnt = oracle.propagate(sg, a, b, w, x, eps, 17, wp=32)
+        assert cnt["cand"].sum() > 0
+        outs = []
+        for env_vars in ({}, {"AGP_BIG_ROWS": "0"}, {"AGP_BIG_ROWS": "1"}, {"AGP_AGGREGATION": "binned"},
+                         {"AGP_AGGREGATION": "atomic"}, {"AGP_BIG_ITEMS": "64"}):
+            for k in ("AGP_BIG_ROWS", "AGP_AGGREGATION"):
+                monkeypatch.delenv(k, raising=False)
+            monkeypatch.setenv("AGP_BIG_ITEMS", "8")
+            for k, v in env_vars.items():
+                monkeypatch.setenv(k, v)
+            out, st = agp.propagate(G, a, b, w, X, eps, 17, stats=True)
+            got = out.cpu().numpy().astype(np.float64)
+            _check(got, st, ref, cnt, len(w) - 1)
+            outs.append(got)
+        assert all(np.array_equal(outs[0], o) for o in outs[1:])

@@ -53,8 +53,8 @@ HBM_PEAK_GBPS = 8000.0
 # --calibrate-copy; FETCH_SIZE is scaled by the factor that makes the 1 GiB
 # copy read 1 GiB.  Valid only for the kernel sources they were taken from.
 TRAFFIC = {
-    "katz-tp": {"sources": "eb4cb502d362e09b", "columns": 256, "bytes_per_launch": 11243650518.0,
-                "fetch_bytes": 7490381975.0, "write_bytes": 3753268544.0},
+    "katz-tp": {"sources": "98d1a1fed2a207ce", "columns": 256, "bytes_per_launch": 11014166009.0,
+                "fetch_bytes": 7261762965.0, "write_bytes": 3752403044.0},
 }
 KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
                   "paper_2106_03058_amd/csrc/propagate.hip")

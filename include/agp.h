@@ -235,6 +235,17 @@ int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int3
  * default (aggregation 2, 4096 workgroups). */
 int agp_get_tuning(const agp_graph_t* g, int32_t C, double a, double b, agp_tuning_t* out);
 
+/* Environment overrides read by every propagation call (for tuning and
+ * tests; none of them changes a result):
+ *   AGP_AGGREGATION=atomic|binned|auto   the aggregation of agp_tuning_t;
+ *   AGP_RECORD_CAP=n     at most n push records per binned level (records
+ *                        beyond it are added with atomics);
+ *   AGP_COLUMN_TILE=n    at most n columns per tile of a call;
+ *   AGP_BIG_ROWS=n       at most n entries per level in each list of deferred
+ *                        work (0: every entry keeps its pushes in its wave);
+ *   AGP_BIG_ITEMS=n      sampled suffixes of n or more work items are
+ *                        deferred (default 64). */
+
 /* ----------------------------------------------------------------- serving */
 
 /* A proximity query: x = e_source (||x||_1 = 1, so theta = eps), or, with

@@ -691,7 +691,7 @@ def main() -> int:
     ap.add_argument("--workload", default="katz-tp", choices=sorted(WORKLOADS) + ["serve", "cluster", "variants"])
     ap.add_argument("--queries", type=int, default=1024, help="serve: queries in the stream")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: offered arrivals per second")
-    ap.add_argument("--slots", type=int, default=64, help="serve: server slots")
+    ap.add_argument("--slots", type=int, default=112, help="serve: server slots")
     ap.add_argument("--single", type=int, default=16, help="units timed one per launch")
     ap.add_argument("--oracle-queries", type=int, default=0,
                     help="serve: queries of the stream re-run by the oracle (random sample)")

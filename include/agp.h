@@ -79,8 +79,13 @@ typedef struct agp_stats {
   uint64_t cand[AGP_MAX_LEVELS + 1];
   uint64_t acc[AGP_MAX_LEVELS + 1];
   double device_ms; /* from the first level kernel's start to the last one's end */
-  /* HIP-event time of the level kernel launched for level i (ms) */
+  /* HIP-event time of the level kernel launched for level i and of the
+   * launches that make its deferred pushes (ms) */
   double level_ms[AGP_MAX_LEVELS + 1];
+  /* HIP-event time of everything level i enqueues (ms): the push estimate,
+   * the level kernels, the aggregation of its pushes and the formation of
+   * the next frontier */
+  double level_total_ms[AGP_MAX_LEVELS + 1];
 } agp_stats_t;
 
 /* Thread-local description of the last error raised on this thread. */
@@ -358,6 +363,27 @@ int agp_sweep(const agp_graph_t* g, const float* pi, int64_t ld, void* stream, i
  * C < 1 or ld < C, directed graph), AGP_ENOMEM, AGP_EDEVICE. */
 int agp_sweep_batch(const agp_graph_t* g, const float* pi, int64_t ld, int32_t C, void* stream,
                     int64_t* best_size, double* best_conductance);
+
+/* ------------------------------------- device random number generators */
+
+/* The device generators that take the propagation's random decisions,
+ * evaluated on host inputs (for known-answer checks).  The subset sampling of
+ * Section 4 draws its uniforms from Philox4x32-10 (Salmon, Moraes, Dror,
+ * Shaw, SC'11: ten rounds of the Philox-4x32 S-box with the published
+ * multipliers and Weyl key increments); the per-level frontier hash sums the
+ * splitmix64 finaliser (Steele, Lea, Flood, OOPSLA'14) of node ids.
+ *  count  number of blocks (>= 0)
+ *  ctr    host uint32[4 * count], counter words c0..c3 of each block
+ *  key    host uint32[2 * count], key words k0, k1 of each block
+ *  out    host uint32[4 * count], receives the four output words
+ * Synchronous (default stream); temporary device memory is allocated.
+ * Errors: AGP_EINVAL (count < 0 or a NULL array with count > 0),
+ * AGP_ENOMEM, AGP_EDEVICE. */
+int agp_device_philox4x32_10(int64_t count, const uint32_t* ctr, const uint32_t* key, uint32_t* out);
+
+/* splitmix64 finaliser of in[i] into out[i], i < count (host arrays);
+ * as agp_device_philox4x32_10. */
+int agp_device_splitmix64(int64_t count, const uint64_t* in, uint64_t* out);
 
 /* ------------------------------------------- weight sequences (Table 1) */
 

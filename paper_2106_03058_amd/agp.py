@@ -25,6 +25,7 @@ EXPORTED = [
     "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp", "agp_server_create", "agp_submit",
     "agp_poll", "agp_server_destroy", "agp_autotune", "agp_get_tuning", "agp_sweep",
     "agp_propagate_variant", "agp_propagate_variant_f64", "agp_sweep_batch", "agp_graph_groups",
+    "agp_device_philox4x32_10", "agp_device_splitmix64",
 ]
 AGP_VARIANT_INFINITE_TAIL, AGP_VARIANT_SPLIT_SIGNS = 1, 2
 
@@ -45,6 +46,7 @@ class Stats(ct.Structure):
         ("acc", ct.c_uint64 * (MAX_LEVELS + 1)),
         ("device_ms", ct.c_double),
         ("level_ms", ct.c_double * (MAX_LEVELS + 1)),
+        ("level_total_ms", ct.c_double * (MAX_LEVELS + 1)),
     ]
 
     def to_dict(self) -> dict:
@@ -55,6 +57,7 @@ class Stats(ct.Structure):
         d["columns"] = self.columns
         d["device_ms"] = float(self.device_ms)
         d["level_ms"] = np.array(self.level_ms[: L + 1], dtype=np.float64)
+        d["level_total_ms"] = np.array(self.level_total_ms[: L + 1], dtype=np.float64)
         d["pushes"] = int(d["det"].sum() + d["acc"].sum())
         return d
 
@@ -90,6 +93,8 @@ def lib():
         L.agp_weights_tp.argtypes = [ct.c_int32, dp]
         L.agp_sweep.argtypes = [vp, vp, ct.c_int64, vp, i64p, dp, vp]
         L.agp_sweep_batch.argtypes = [vp, vp, ct.c_int64, ct.c_int32, vp, i64p, dp]
+        L.agp_device_philox4x32_10.argtypes = [ct.c_int64, vp, vp, vp]
+        L.agp_device_splitmix64.argtypes = [ct.c_int64, vp, vp]
         _lib = L
     return _lib
 
@@ -317,6 +322,24 @@ def sweep_batch(graph: Graph, pis, *, stream=None):
                                  size.ctypes.data_as(ct.POINTER(ct.c_int64)),
                                  phi.ctypes.data_as(ct.POINTER(ct.c_double))))
     return size, phi
+
+
+def device_philox4x32_10(ctr, key) -> np.ndarray:
+    """The device Philox4x32-10 blocks of ctr (k x 4) under key (k x 2)."""
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(-1, 4))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(-1, 2))
+    if c.shape[0] != k.shape[0]:
+        raise ValueError("one key per counter block")
+    out = np.empty_like(c)
+    _check(lib().agp_device_philox4x32_10(c.shape[0], c.ctypes.data, k.ctypes.data, out.ctypes.data))
+    return out
+
+
+def device_splitmix64(values) -> np.ndarray:
+    v = np.ascontiguousarray(np.asarray(values, dtype=np.uint64).ravel())
+    out = np.empty_like(v)
+    _check(lib().agp_device_splitmix64(v.size, v.ctypes.data, out.ctypes.data))
+    return out
 
 
 def _weights(fn, *args, L: int) -> np.ndarray:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libagp.so")
-SOURCES = ["common.cpp", "graph.hip", "propagate.hip", "server.hip", "sweep.hip"]
+SOURCES = ["common.cpp", "graph.hip", "propagate.hip", "server.hip", "sweep.hip", "generators.hip"]
 ARCH = os.environ.get("AGP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

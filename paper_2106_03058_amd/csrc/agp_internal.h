@@ -52,7 +52,9 @@ struct Scratch {
   DevBuf sweep;      // clustering sweep: keys, order, ranks, prefix sums, sort space
   DevBuf sweep_items;        // clustering sweep: arc-balanced work items of the graph
   int64_t sweep_nitems = -1; // their number (-1: not built yet)
-  hipEvent_t events[2 * (AGP_MAX_LEVELS + 1)] = {};  // level timing, created on demand
+  // level timing, created on demand: per level its start, the level kernel's
+  // start and end, and the end of the level's next frontier
+  hipEvent_t events[4 * (AGP_MAX_LEVELS + 1)] = {};
   int ensure_events();
   void release();
 };

@@ -345,6 +345,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     Cell* cur = acc[i & 1];
     Cell* nxt = acc[(i + 1) & 1];
     A.bin_est = nullptr;
+    if (stats) AGP_HIP(hipEventRecord(ev[4 * i], s));
     if (bin_level && tune.aggregation == 2) {
       A.bin_est = est + i;
       if (i == 0)
@@ -352,14 +353,14 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
       else
         k_estimate<T, false><<<1024, kThreads, 0, s>>>(A, x, cur, est + i);
     }
-    if (stats) AGP_HIP(hipEventRecord(ev[2 * i], s));
+    if (stats) AGP_HIP(hipEventRecord(ev[4 * i + 1], s));
     if (i == 0)
       k_level<T, true, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
     else
       k_level<T, false, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
     if (A.big_ctr != nullptr) k_det_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
     if (A.samp_ctr != nullptr) k_samp_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
-    if (stats) AGP_HIP(hipEventRecord(ev[2 * i + 1], s));
+    if (stats) AGP_HIP(hipEventRecord(ev[4 * i + 2], s));
     if (bin_level) {
       uint32_t* r0 = sc.rec[0].as<uint32_t>();
       uint32_t* r1 = sc.rec[1].as<uint32_t>();
@@ -376,6 +377,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     if (i < L)
       k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, (long long)C, 1ll, F[(i + 1) & 1],
                                            counts + i + 1, mode + i + 1);
+    if (stats) AGP_HIP(hipEventRecord(ev[4 * i + 3], s));
   }
   AGP_HIP(hipGetLastError());
   std::vector<double> hmass(static_cast<size_t>(L) + 1);
@@ -406,10 +408,12 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     }
     float ms = 0.0f;
     for (int32_t i = 0; i <= L; ++i) {
-      AGP_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      AGP_HIP(hipEventElapsedTime(&ms, ev[4 * i + 1], ev[4 * i + 2]));
       stats->level_ms[i] += ms;
+      AGP_HIP(hipEventElapsedTime(&ms, ev[4 * i], ev[4 * i + 3]));
+      stats->level_total_ms[i] += ms;
     }
-    AGP_HIP(hipEventElapsedTime(&ms, ev[0], ev[2 * L + 1]));
+    AGP_HIP(hipEventElapsedTime(&ms, ev[0], ev[4 * L + 3]));
     stats->device_ms += ms;
   }
   return AGP_OK;
@@ -547,6 +551,7 @@ void add_stats(agp_stats_t* into, const agp_stats_t& part) {
     into->cand[i] += part.cand[i];
     into->acc[i] += part.acc[i];
     into->level_ms[i] += part.level_ms[i];
+    into->level_total_ms[i] += part.level_total_ms[i];
   }
   into->device_ms += part.device_ms;
 }

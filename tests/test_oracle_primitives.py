@@ -148,6 +148,30 @@ def test_philox_statistics(orc):
     assert not np.array_equal(orc.philox([1, 2, 3, 4], key), orc.philox([1, 2, 3, 4], key + 1))
 
 
+def _kat():
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.json")) as f:
+        return json.load(f)
+
+
+def test_philox_known_answers(orc):
+    """The published Philox4x32-10 vectors (tests/golden/philox4x32_10_kat.json):
+    a wrong multiplier, Weyl increment, round count or word exchange changes
+    every one of them."""
+    for v in _kat()["vectors"]:
+        ctr = np.array([int(h, 16) for h in v["ctr"]], dtype=np.uint32)
+        key = np.array([int(h, 16) for h in v["key"]], dtype=np.uint32)
+        out = [int(h, 16) for h in v["out"]]
+        assert orc.philox(ctr, key).tolist() == out
+
+
+def test_splitmix64_known_answer(orc):
+    for v in _kat()["splitmix64"]["vectors"]:
+        assert orc.splitmix64(int(v["in"], 16)) == int(v["out"], 16)
+
+
 def test_splitmix_no_collisions(orc):
     hs = {orc.splitmix64(i) for i in range(20000)}
     assert len(hs) == 20000

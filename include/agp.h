@@ -224,32 +224,59 @@ typedef struct agp_tuning {
                            1: push records binned by destination, summed in LDS;
                            2: records on dense levels, atomics on sparse ones  */
   int32_t level_blocks; /* workgroups of the level kernel (>= 256)               */
+  int32_t dense;        /* node-major levels with one lane per column (binary32):
+                           0 never, 1 always, 2 when at least a quarter of the
+                           signal's entries are non-zero and C >= 16           */
+  int32_t tile_columns; /* columns per tile; 0: the widest tile that fits       */
+  int32_t big_row;      /* deterministic pushes from which an entry's row is
+                           deferred to a grid-wide kernel; 0: 4096              */
+  int32_t big_items;    /* sampled work items (16 windows each) from which an
+                           entry's sampled suffix is deferred; 0: 64            */
+  int32_t sparse_shift; /* a level whose frontier holds fewer than n C / 2^k
+                           entries appends first contributions directly; 0: 5 */
+  int32_t bin_shift;    /* (aggregation 2) a level whose estimated pushes reach
+                           n C / 2^k is binned; 0: 3                            */
 } agp_tuning_t;
 
 /* Autotuner: runs the propagation of the arguments (as agp_propagate) once
- * per candidate choice, timing each with HIP events on `stream`, and keeps
- * the fastest for later agp_propagate calls on g with the same column count
- * and exponents (a, b).  `out` holds the result on return (identical for
- * every candidate).  *best (nullable) receives the choice.  Errors as
- * agp_propagate. */
+ * with the defaults (untimed), then once per candidate, timing each with HIP
+ * events on `stream`: a coordinate descent over dense (0, 1), aggregation
+ * (0, 1, 2), level_blocks (1024 .. 8192), tile_columns (all, C/2, C/4) and,
+ * unless the dense levels won, big_row, big_items, sparse_shift and
+ * bin_shift.  The fastest choice is kept for later agp_propagate calls on g
+ * with the same column count and exponents (a, b).  `out` holds the result
+ * on return (identical for every candidate).  *best (nullable) receives the
+ * choice.  Errors as agp_propagate. */
 int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int32_t L,
                  const float* x, int32_t C, double eps, uint64_t seed, const uint32_t* qids,
                  float* out, void* stream, agp_tuning_t* best);
 
-/* The choice agp_propagate uses for (g, C, a, b): the tuned one, else the
- * default (aggregation 2, 4096 workgroups). */
+/* The choice agp_propagate uses for (g, C, a, b): the tuned or set one,
+ * else the default (aggregation 2, 4096 workgroups, dense 2, the other
+ * fields at their stated defaults), with the environment overrides below
+ * applied. */
 int agp_get_tuning(const agp_graph_t* g, int32_t C, double a, double b, agp_tuning_t* out);
+
+/* Pin the choice for later calls on g with C columns and exponents (a, b),
+ * replacing an autotuned one (zero fields take their defaults, out-of-range
+ * ones are clamped); t == NULL forgets it.  Results never depend on it. */
+int agp_set_tuning(const agp_graph_t* g, int32_t C, double a, double b, const agp_tuning_t* t);
 
 /* Environment overrides read by every propagation call (for tuning and
  * tests; none of them changes a result):
  *   AGP_AGGREGATION=atomic|binned|auto   the aggregation of agp_tuning_t;
- *   AGP_RECORD_CAP=n     at most n push records per binned level (records
- *                        beyond it are added with atomics);
+ *   AGP_DENSE=0|1|auto   the dense field of agp_tuning_t;
+ *   AGP_RECORD_CAP=n     at most n push records per binned level (per record
+ *                        group on dense levels; records beyond it are added
+ *                        with atomics);
  *   AGP_COLUMN_TILE=n    at most n columns per tile of a call;
  *   AGP_BIG_ROWS=n       at most n entries per level in each list of deferred
  *                        work (0: every entry keeps its pushes in its wave);
- *   AGP_BIG_ITEMS=n      sampled suffixes of n or more work items are
- *                        deferred (default 64). */
+ *   AGP_BIG_ITEMS=n      the big_items field;
+ *   AGP_DENSE_GROUP_SHIFT=k  dense levels: records grouped by 2^k columns;
+ *   AGP_CHECK_ZERO=1     dense levels: after each tile, check on the host
+ *                        that the scratch sums and residues are all-zero
+ *                        again (AGP_EDEVICE otherwise; slow). */
 
 /* ----------------------------------------------------------------- serving */
 

@@ -25,7 +25,7 @@ EXPORTED = [
     "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp", "agp_server_create", "agp_submit",
     "agp_poll", "agp_server_destroy", "agp_autotune", "agp_get_tuning", "agp_sweep",
     "agp_propagate_variant", "agp_propagate_variant_f64", "agp_sweep_batch", "agp_graph_groups",
-    "agp_device_philox4x32_10", "agp_device_splitmix64",
+    "agp_device_philox4x32_10", "agp_device_splitmix64", "agp_set_tuning",
 ]
 AGP_VARIANT_INFINITE_TAIL, AGP_VARIANT_SPLIT_SIGNS = 1, 2
 
@@ -235,12 +235,33 @@ def propagate(graph: Graph, a: float, b: float, w, x, eps: float, seed: int, *, 
     return res, (st.to_dict() if st is not None else None)
 
 
+TUNING_FIELDS = ("aggregation", "level_blocks", "dense", "tile_columns", "big_row", "big_items",
+                 "sparse_shift", "bin_shift")
+
+
 class Tuning(ct.Structure):
-    _fields_ = [("aggregation", ct.c_int32), ("level_blocks", ct.c_int32)]
+    _fields_ = [(name, ct.c_int32) for name in TUNING_FIELDS]
 
     def to_dict(self) -> dict:
         names = {0: "atomic", 1: "binned", 2: "auto"}
-        return {"aggregation": names.get(self.aggregation, str(self.aggregation)), "level_blocks": self.level_blocks}
+        d = {k: int(getattr(self, k)) for k in TUNING_FIELDS}
+        d["aggregation"] = names.get(self.aggregation, str(self.aggregation))
+        d["dense"] = {0: "never", 1: "always", 2: "auto"}.get(self.dense, str(self.dense))
+        return d
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Tuning":
+        t = cls()
+        agg = {"atomic": 0, "binned": 1, "auto": 2}
+        den = {"never": 0, "always": 1, "auto": 2}
+        for k in TUNING_FIELDS:
+            v = d.get(k, 0)
+            if k == "aggregation" and isinstance(v, str):
+                v = agg[v]
+            if k == "dense" and isinstance(v, str):
+                v = den[v]
+            setattr(t, k, int(v))
+        return t
 
 
 def _tune_lib():
@@ -251,6 +272,7 @@ def _tune_lib():
                                    ct.c_int32, ct.c_double, ct.c_uint64, ct.POINTER(ct.c_uint32), vp, vp,
                                    ct.POINTER(Tuning)]
         L.agp_get_tuning.argtypes = [vp, ct.c_int32, ct.c_double, ct.c_double, ct.POINTER(Tuning)]
+        L.agp_set_tuning.argtypes = [vp, ct.c_int32, ct.c_double, ct.c_double, ct.POINTER(Tuning)]
         L._tune_ready = True
     return L
 
@@ -280,6 +302,14 @@ def get_tuning(graph: Graph, C: int, a: float, b: float) -> dict:
     t = Tuning()
     _check(_tune_lib().agp_get_tuning(graph.handle, int(C), float(a), float(b), ct.byref(t)))
     return t.to_dict()
+
+
+def set_tuning(graph: Graph, C: int, a: float, b: float, tuning: dict | None) -> None:
+    """Pin execution choices (a dict of agp_tuning_t fields; missing ones take
+    the defaults) for calls with C columns and exponents a, b; None forgets."""
+    t = None if tuning is None else Tuning.from_dict(tuning)
+    _check(_tune_lib().agp_set_tuning(graph.handle, int(C), float(a), float(b),
+                                      None if t is None else ct.byref(t)))
 
 
 def sweep(graph: Graph, pi, *, order: bool = True, stream=None):

@@ -52,6 +52,10 @@ struct Scratch {
   DevBuf sweep;      // clustering sweep: keys, order, ranks, prefix sums, sort space
   DevBuf sweep_items;        // clustering sweep: arc-balanced work items of the graph
   int64_t sweep_nitems = -1; // their number (-1: not built yet)
+  DevBuf dense_items;        // dense levels: arc-balanced work items (node ranges, long-row pieces)
+  DevBuf dense_rows;         // dense levels: the long rows (cut into pieces)
+  int64_t dense_nitems = -1; // number of items (-1: not built yet)
+  int64_t dense_nrows = 0;   // number of long rows
   // level timing, created on demand: per level its start, the level kernel's
   // start and end, and the end of the level's next frontier
   hipEvent_t events[4 * (AGP_MAX_LEVELS + 1)] = {};

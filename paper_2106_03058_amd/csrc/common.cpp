@@ -62,6 +62,10 @@ void Scratch::release() {
   sweep.release();
   sweep_items.release();
   sweep_nitems = -1;
+  dense_items.release();
+  dense_rows.release();
+  dense_nitems = -1;
+  dense_nrows = 0;
   bins.release();
 }
 

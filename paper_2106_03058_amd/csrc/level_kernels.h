@@ -14,12 +14,16 @@
 // atomics that add contributions commute and the result does not depend on
 // the order in which pushes land.
 //
-// Per tile of up to 256 frontier entries a block converts each residue,
-// updates the reserve (pi(u) += kappa_i r(u)), finds the deterministic prefix
-// J of the degree-sorted row by binary search (increment >= theta) and counts
-// the 64-position windows of the sampled suffix; a block-wide scan spreads
-// single pushes and windows over the lanes, which walk the Philox /
-// geometric-skip chains in lockstep per wave.
+// A wave takes batches of up to 64 frontier entries (u, c): each lane
+// converts one entry's residue, updates the reserve (pi(u) += kappa_i r(u)),
+// finds the deterministic prefix J of the degree-sorted row (increment >=
+// theta, by binary search) and counts the work items of its sampled suffix;
+// the wave then makes the batch's deterministic pushes with all lanes (a
+// wave-wide scan spreads them) and lanes draw sampled work items (runs of
+// 64-position windows) from a per-wave queue, walking their Philox /
+// geometric-skip chains.  Rows with long deterministic prefixes and entries
+// with many sampled work items are deferred to grid-wide kernels
+// (k_det_big, k_samp_big) that run right after the level.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -58,10 +62,11 @@ constexpr int kBuckets = 1024;
 
 // Rows with many deterministic pushes (a hub with a large residue) would
 // keep one wave busy while the rest of the grid idles; a batched level
-// defers rows of at least kBigRow deterministic pushes to a list that
-// k_det_big then spreads over the whole grid in chunks of kBigChunk pushes.
+// defers rows of at least big_row (default kBigRow) deterministic pushes to a
+// list that k_det_big then spreads over the whole grid in chunks of kBigChunk
+// pushes.
 constexpr uint32_t kBigRow = 4096;
-constexpr int kBigChunk = 4096;  // <= kBigRow: a lane's pushes in a chunk cross at most one row boundary
+constexpr int kBigChunk = 4096;  // a lane walks from row to row inside its chunk
 constexpr int kBigShift = 40;    // list counter: deferred rows << 40 | their pushes (a level's pushes < 2^40)
 
 struct BigRow {
@@ -134,6 +139,7 @@ struct LevelArgs {
   const double* bin_est;         // non-null: bin only if *bin_est >= bin_pushes (estimated pushes)
   double bin_pushes;
   // deferred rows (batched calls; nullptr: every row is pushed by its wave)
+  uint32_t big_row;              // deterministic pushes from which an entry's row is deferred
   unsigned long long* big_ctr;   // this level's list counter, zero at the start
   BigRow* big;
   unsigned long long big_cap;
@@ -504,7 +510,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
               iwork = (windows + kWinPerItem - 1) / kWinPerItem;
               // a long deterministic prefix goes to the deferred list (the
               // counter is read first so that it never wraps)
-              if (!kServe && A.big_ctr != nullptr && eJ >= kBigRow &&
+              if (!kServe && A.big_ctr != nullptr && eJ >= A.big_row &&
                   (__hip_atomic_load(A.big_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> kBigShift) <
                       A.big_cap) {
                 const unsigned long long old =

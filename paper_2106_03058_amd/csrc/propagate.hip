@@ -13,13 +13,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <initializer_list>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "agp_internal.h"
 #include "bin_kernels.h"
+#include "dense_kernels.h"
 #include "level_kernels.h"
 
 namespace agp {
@@ -72,13 +75,55 @@ __global__ __launch_bounds__(kWave) void k_theta_partial(const T* __restrict__ x
   if (f) atomicOr(flags, f);
 }
 
+// The same sums as k_theta_partial without forming a frontier; counts the
+// non-zero entries of x instead (their share decides the dense path).
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_theta_scan(const T* __restrict__ x, long long ldx, int64_t n, int C,
+                                                      double* __restrict__ partial, int* __restrict__ flags,
+                                                      unsigned long long* __restrict__ nnz) {
+  const int c = blockIdx.y * blockDim.x + threadIdx.x;
+  const bool live = c < C;
+  const int64_t lo = (int64_t)blockIdx.x * kThetaRows;
+  const int64_t hi = (lo + kThetaRows) < n ? lo + kThetaRows : n;
+  double sum = 0.0;
+  int f = 0;
+  unsigned long long cnt = 0;
+  for (int64_t i0 = lo; i0 < hi; i0 += kThetaBatch) {
+    T v[kThetaBatch];
+#pragma unroll
+    for (int k = 0; k < kThetaBatch; ++k)
+      v[k] = (live && i0 + k < hi) ? x[static_cast<size_t>(i0 + k) * static_cast<size_t>(ldx) + c] : T(0);
+#pragma unroll
+    for (int k = 0; k < kThetaBatch; ++k) {
+      if (i0 + k >= hi) break;  // wave-uniform
+      if (!isfinite(static_cast<double>(v[k]))) f |= 1;
+      if (v[k] < T(0)) f |= 2;
+      sum = sum + fabs(static_cast<double>(v[k]));
+      cnt += v[k] != T(0) ? 1ull : 0ull;
+    }
+  }
+  if (live) partial[(size_t)blockIdx.x * C + c] = sum;
+  if (f) atomicOr(flags, f);
+  const unsigned long long tot = wave_sum_u64(cnt);
+  if (lane_id() == 0 && tot) atomicAdd(nnz, tot);
+}
+
 template <typename T>
 __global__ void k_theta_final(const double* __restrict__ partial, int64_t nblocks, int C, double eps,
                               const uint32_t* __restrict__ qids, uint32_t qid_base, ColParams* __restrict__ cp) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
   double total = 0.0;
-  for (int64_t b = 0; b < nblocks; ++b) total = total + partial[(size_t)b * C + c];
+  constexpr int kInFlight = 16;  // loads issued together, added in block order
+  int64_t b = 0;
+  for (; b + kInFlight <= nblocks; b += kInFlight) {
+    double v[kInFlight];
+#pragma unroll
+    for (int k = 0; k < kInFlight; ++k) v[k] = partial[(size_t)(b + k) * C + c];
+#pragma unroll
+    for (int k = 0; k < kInFlight; ++k) total = total + v[k];
+  }
+  for (; b < nblocks; ++b) total = total + partial[(size_t)b * C + c];
   ColParams p = cp[c];
   p.theta = eps * total;
   p.qid = qids ? qids[c] : qid_base + static_cast<uint32_t>(c);
@@ -129,15 +174,41 @@ __global__ void k_set_level(ColParams* __restrict__ cp, int C, int level, double
 }
 
 // ------------------------------------------------------------ driver
+constexpr int kSparseShift = 5;  // sparse levels: frontier below n C / 32
+constexpr int kBinShift = 3;     // binned levels: estimated pushes reach n C / 8
+
 agp_tuning_t default_tuning() {
-  agp_tuning_t t;
+  agp_tuning_t t{};
   t.aggregation = 2;  // records on levels with many pushes, atomics elsewhere
   t.level_blocks = kLevelBlocks;
+  t.dense = 2;
+  t.tile_columns = 0;
+  t.big_row = static_cast<int32_t>(kBigRow);
+  t.big_items = static_cast<int32_t>(kBigItems);
+  t.sparse_shift = kSparseShift;
+  t.bin_shift = kBinShift;
+  return t;
+}
+
+// Zero fields of a caller's tuning take the defaults; out-of-range values
+// are clamped.
+agp_tuning_t normalize_tuning(agp_tuning_t t) {
+  const agp_tuning_t d = default_tuning();
+  if (t.aggregation < 0 || t.aggregation > 2) t.aggregation = d.aggregation;
+  if (t.level_blocks < 256) t.level_blocks = t.level_blocks <= 0 ? d.level_blocks : 256;
+  if (t.level_blocks > 65536) t.level_blocks = 65536;
+  if (t.dense < 0 || t.dense > 2) t.dense = d.dense;
+  if (t.tile_columns < 0) t.tile_columns = 0;
+  if (t.big_row <= 0) t.big_row = d.big_row;
+  if (t.big_items <= 0) t.big_items = d.big_items;
+  if (t.sparse_shift <= 0 || t.sparse_shift > 30) t.sparse_shift = d.sparse_shift;
+  if (t.bin_shift <= 0 || t.bin_shift > 30) t.bin_shift = d.bin_shift;
   return t;
 }
 
 // The tuning in force for a call: an explicit one, else the autotuned one,
-// else the default; AGP_AGGREGATION=atomic|binned|auto overrides the aggregation.
+// else the default; environment variables (include/agp.h) override single
+// fields.
 agp_tuning_t tuning_for(agp_graph* g, int32_t C, double a, double b, const agp_tuning_t* force) {
   agp_tuning_t t = default_tuning();
   if (force) {
@@ -146,12 +217,25 @@ agp_tuning_t tuning_for(agp_graph* g, int32_t C, double a, double b, const agp_t
     auto it = g->tuning.find(agp_tune_key{C, a, b});
     if (it != g->tuning.end()) t = it->second;
   }
+  t = normalize_tuning(t);
   if (const char* e = std::getenv("AGP_AGGREGATION")) {
     if (std::strcmp(e, "atomic") == 0) t.aggregation = 0;
     if (std::strcmp(e, "binned") == 0) t.aggregation = 1;
     if (std::strcmp(e, "auto") == 0) t.aggregation = 2;
   }
-  if (t.level_blocks < 256) t.level_blocks = 256;
+  if (const char* e = std::getenv("AGP_DENSE")) {
+    if (std::strcmp(e, "0") == 0) t.dense = 0;
+    if (std::strcmp(e, "1") == 0) t.dense = 1;
+    if (std::strcmp(e, "auto") == 0) t.dense = 2;
+  }
+  if (const char* e = std::getenv("AGP_COLUMN_TILE")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v > 0) t.tile_columns = static_cast<int32_t>(v);
+  }
+  if (const char* e = std::getenv("AGP_BIG_ITEMS")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 1) t.big_items = static_cast<int32_t>(v);
+  }
   return t;
 }
 
@@ -259,6 +343,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   if (binned) {
     AGP_HIP(hipMemsetAsync(rec_counts, 0, sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1), s));
     AGP_HIP(hipMemsetAsync(bin_count, 0, sizeof(unsigned long long) * nbins, s));
+    AGP_HIP(hipMemsetAsync(bucket_count, 0, sizeof(unsigned int) * kBuckets, s));  // the dense path shares the buffer
   }
 
   hipEvent_t* ev = sc.events;
@@ -274,11 +359,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     const unsigned long long v = std::strtoull(e, nullptr, 10);
     if (v < big_cap) big_cap = v;
   }
-  long long samp_items = kBigItems;
-  if (const char* e = std::getenv("AGP_BIG_ITEMS")) {  // smaller deferral cut for sampled suffixes (tests)
-    const long long v = std::strtoll(e, nullptr, 10);
-    if (v >= 1) samp_items = v;
-  }
+  const long long samp_items = tune.big_items;
   // (and entries with many sampled work items, deferred to k_samp_big):
   // per-level counters of both lists, then the two lists
   unsigned long long* big_ctr = nullptr;
@@ -313,14 +394,15 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   A.mass = mass;
   A.err = flags;
   A.positive = positive ? 1 : 0;
-  A.dense_cut = std::max<unsigned long long>(1ull, static_cast<unsigned long long>(cells / 32));
+  A.dense_cut = std::max<unsigned long long>(1ull, static_cast<unsigned long long>(cells >> tune.sparse_shift));
+  A.big_row = static_cast<uint32_t>(tune.big_row);
   A.rec = nullptr;
   A.rec_count = nullptr;
   A.rec_cap = rec_cap;
   A.bucket_count = bucket_count;
   A.bucket_shift = shift;
   A.bin_est = nullptr;
-  A.bin_pushes = static_cast<double>(cells) / 8.0;  // auto: bin levels with at least n C / 8 pushes
+  A.bin_pushes = std::ldexp(static_cast<double>(cells), -tune.bin_shift);  // auto: bin levels with n C / 2^k pushes
   const uint32_t key0 = static_cast<uint32_t>(seed), key1 = static_cast<uint32_t>(seed >> 32);
   for (int32_t i = 0; i <= L; ++i) {
     const int lflags = (i == L ? kLastLevel : 0) | (a == 0.0 ? kAZero : 0);
@@ -424,11 +506,8 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
 // memory (plus what the scratch already holds), else the widest tile that
 // does; AGP_COLUMN_TILE forces a width (tests).
 template <typename T>
-int32_t column_tile(agp_graph* g, int32_t C, bool binned) {
-  if (const char* e = std::getenv("AGP_COLUMN_TILE")) {
-    const long v = std::strtol(e, nullptr, 10);
-    if (v > 0 && v < C) return static_cast<int32_t>(v);
-  }
+int32_t column_tile(agp_graph* g, int32_t C, bool binned, const agp_tuning_t& tune) {
+  if (tune.tile_columns > 0) return std::min(tune.tile_columns, C);
   const size_t cell_bytes = sizeof(typename Prec<T>::Cell) * (sizeof(T) == 4 ? 1 : 2);
   // two accumulators and two frontier lists per cell (+ two record buffers of 4 records)
   const size_t per_cell = 2 * cell_bytes + 2 * sizeof(uint64_t) + (binned ? 2 * 4 * sizeof(uint32_t) : 0);
@@ -442,6 +521,376 @@ int32_t column_tile(agp_graph* g, int32_t C, bool binned) {
   const double fit = budget / per_col;
   if (fit >= static_cast<double>(C)) return C;
   return fit < 1.0 ? 1 : static_cast<int32_t>(fit);
+}
+
+// ------------------------------------------------------------ dense levels
+// Work items of the dense level kernel, built once per graph on the host
+// from the row lengths: runs of up to 64 consecutive nodes holding at most
+// dense::kItemArcs arcs, and rows longer than that cut into pieces of 64
+// windows (4096 arcs).  The long rows are also listed (their residues are
+// cleared after each level).
+int dense_items(agp_graph* g, hipStream_t s) {
+  Scratch& sc = g->scratch;
+  if (sc.dense_nitems >= 0) return AGP_OK;
+  const int64_t n = g->n;
+  std::vector<int32_t> deg(static_cast<size_t>(n));
+  if (n > 0) {
+    AGP_HIP(hipMemcpyAsync(deg.data(), g->degree, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    AGP_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<uint64_t> items;
+  std::vector<uint32_t> rows;
+  items.reserve(static_cast<size_t>(n / 16 + 16));
+  for (int64_t u = 0; u < n;) {
+    const int64_t d = deg[u];
+    if (d > dense::kItemArcs) {
+      const int64_t nwin = (d + kSeg - 1) / kSeg;
+      if (nwin >= (1ll << 20)) return fail(AGP_ENOTSUP, "dense levels: a row longer than 2^26 arcs");
+      for (int64_t w0 = 0; w0 < nwin; w0 += 64) {
+        const uint64_t cnt = static_cast<uint64_t>(std::min<int64_t>(64, nwin - w0));
+        items.push_back(dense::kItemLong | (cnt << 52) | (static_cast<uint64_t>(w0) << 32) | static_cast<uint64_t>(u));
+      }
+      rows.push_back(static_cast<uint32_t>(u));
+      ++u;
+      continue;
+    }
+    const int64_t start = u;
+    int64_t arcs = 0, cnt = 0;
+    while (u < n && cnt < dense::kItemNodes && deg[u] <= dense::kItemArcs && arcs + deg[u] <= dense::kItemArcs) {
+      arcs += deg[u];
+      ++cnt;
+      ++u;
+    }
+    items.push_back((static_cast<uint64_t>(cnt) << 32) | static_cast<uint64_t>(start));
+  }
+  int rc;
+  if ((rc = sc.dense_items.reserve(sizeof(uint64_t) * std::max<size_t>(items.size(), 1), false, s)) ||
+      (rc = sc.dense_rows.reserve(sizeof(uint32_t) * std::max<size_t>(rows.size(), 1), false, s)))
+    return rc;
+  if (!items.empty())
+    AGP_HIP(hipMemcpyAsync(sc.dense_items.ptr, items.data(), sizeof(uint64_t) * items.size(), hipMemcpyHostToDevice, s));
+  if (!rows.empty())
+    AGP_HIP(hipMemcpyAsync(sc.dense_rows.ptr, rows.data(), sizeof(uint32_t) * rows.size(), hipMemcpyHostToDevice, s));
+  AGP_HIP(hipStreamSynchronize(s));
+  sc.dense_nitems = static_cast<int64_t>(items.size());
+  sc.dense_nrows = static_cast<int64_t>(rows.size());
+  return AGP_OK;
+}
+
+// Memory plan of a dense call: Ct columns per tile (at most 64, tiles of
+// equal width), record groups of 2^gshift columns (n 2^gshift <= 2^31), and
+// the record buffers' capacity per group.
+struct DensePlan {
+  int32_t Ct = 0;
+  int gshift = 6;
+  int ng = 1;
+  unsigned long long rec_cap = 0;  // per group; 0: atomics only
+};
+
+DensePlan dense_plan(agp_graph* g, int32_t C, const agp_tuning_t& tune, bool binned) {
+  DensePlan p;
+  const int64_t n = g->n > 0 ? g->n : 1;
+  int32_t want = tune.tile_columns > 0 ? std::min(tune.tile_columns, dense::kMaxCols) : dense::kMaxCols;
+  want = std::min(want, C);
+  size_t free_b = 0, total_b = 0;
+  (void)hipMemGetInfo(&free_b, &total_b);
+  Scratch& sc = g->scratch;
+  const size_t held = sc.acc[0].bytes + sc.acc[1].bytes + sc.frontier[0].bytes + sc.frontier[1].bytes +
+                      sc.rec[0].bytes + sc.rec[1].bytes;
+  const double budget = 0.9 * static_cast<double>(free_b + held);
+  // 8 B exact sum + 4 B residue per cell, 2 flag bytes per node; records
+  // (two buffers of 4 B) take at least a quarter record per cell
+  auto fits = [&](int32_t ct, double rpc) {
+    return static_cast<double>(n) * (ct * (12.0 + (binned ? 8.0 * rpc : 0.0)) + 2.0) <= budget;
+  };
+  int32_t ct = want;
+  while (ct > 1 && !fits(ct, 0.25)) --ct;
+  const int32_t ntiles = (C + ct - 1) / ct;
+  p.Ct = (C + ntiles - 1) / ntiles;  // equal tiles
+  int gshift = 6;
+  while (gshift > 0 && static_cast<double>(n) * static_cast<double>(1 << gshift) > 2147483648.0) --gshift;
+  if (const char* e = std::getenv("AGP_DENSE_GROUP_SHIFT")) {  // narrower record groups (tests)
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 0 && v < gshift) gshift = static_cast<int>(v);
+  }
+  p.gshift = gshift;
+  p.ng = (p.Ct + (1 << gshift) - 1) >> gshift;
+  if (p.ng > dense::kMaxGroups) p.ng = 0;  // not addressable in 4 groups (n > 2^31 / 16)
+  if (binned && p.ng > 0) {
+    const double cells = static_cast<double>(n) * p.Ct;
+    double room = (budget - static_cast<double>(n) * (12.0 * p.Ct + 2.0)) / 8.0;  // records per buffer
+    room = std::min(room, 1.5 * cells);
+    if (const char* e = std::getenv("AGP_RECORD_CAP")) {
+      const double v = std::strtod(e, nullptr);
+      if (v > 0 && v < room * p.ng) room = v * p.ng;
+    }
+    p.rec_cap = room >= 1024.0 * p.ng ? static_cast<unsigned long long>(room / p.ng) : 0ull;
+  }
+  return p;
+}
+
+// One dense tile of Ct columns (x, out: the tile's first column, rows ldc
+// apart; cpt: the tile's column parameters with theta, units and qids set).
+// The caller holds g->mu.
+int propagate_dense_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, const DensePlan& plan, double a,
+                         double b, const std::vector<double>& rho, const std::vector<double>& kappa, int32_t L,
+                         const float* x, long long ldc, int32_t Ct, const ColParams* cpt, uint64_t seed, float* out,
+                         hipStream_t s, agp_stats_t* stats) {
+  using namespace dense;
+  const int64_t n = g->n;
+  const size_t cells = static_cast<size_t>(n) * static_cast<size_t>(Ct);
+  int rc;
+  const double *da = nullptr, *db = nullptr;
+  if ((rc = pow_table(g, a, &da)) || (rc = pow_table(g, b, &db))) return rc;
+  if ((rc = dense_items(g, s))) return rc;
+  Scratch& sc = g->scratch;
+  const int ng = plan.ng;
+  const int gw = 1 << plan.gshift;
+  const bool binned = plan.rec_cap > 0 && tune.aggregation != 0;
+  // group cells: n * width of group 0 (the widest)
+  const unsigned long long gcells0 = static_cast<unsigned long long>(n) * static_cast<unsigned long long>(std::min(gw, Ct));
+  int shift = kBinLog2;
+  while (shift < 32 && (gcells0 > 0 ? gcells0 - 1ull : 0ull) >> shift >= (unsigned long long)kBuckets) ++shift;
+  const long long nbins_g = static_cast<long long>(((gcells0 > 0 ? gcells0 : 1) - 1) >> kBinLog2) + 1;
+  if ((rc = sc.acc[0].reserve(cells * sizeof(long long), true, s)) ||
+      (rc = sc.acc[1].reserve(cells * sizeof(float), true, s)) ||
+      (rc = sc.frontier[0].reserve(2 * static_cast<size_t>(n) + 64, false, s)) ||
+      (rc = sc.counters.reserve(sizeof(unsigned long long) * kNumCounters * (AGP_MAX_LEVELS + 1), false, s)) ||
+      (rc = sc.flags.reserve(sizeof(int) * 4, false, s)) ||
+      (rc = sc.levelinfo.reserve((2 * sizeof(double) + sizeof(int)) * (AGP_MAX_LEVELS + 2), false, s)))
+    return rc;
+  if (binned) {
+    const size_t bins_bytes = sizeof(unsigned int) * kBuckets * ng + sizeof(unsigned long long) * (kBuckets + 1) * ng +
+                              sizeof(unsigned long long) * kBuckets * ng +
+                              sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1) * ng +
+                              sizeof(unsigned long long) * (3 * nbins_g + 1) + static_cast<size_t>(nbins_g) * ng;
+    if ((rc = sc.rec[0].reserve(plan.rec_cap * ng * sizeof(uint32_t), false, s)) ||
+        (rc = sc.rec[1].reserve(plan.rec_cap * ng * sizeof(uint32_t), false, s)) ||
+        (rc = sc.bins.reserve(bins_bytes, true, s)))
+      return rc;
+  }
+  long long* acc = sc.acc[0].as<long long>();
+  float* r = sc.acc[1].as<float>();
+  uint8_t* flags2[2] = {sc.frontier[0].as<uint8_t>(), sc.frontier[0].as<uint8_t>() + n};
+  unsigned long long* counters = sc.counters.as<unsigned long long>();
+  int* errf = sc.flags.as<int>();
+  double* mass = sc.levelinfo.as<double>();
+  int* mode = reinterpret_cast<int*>(mass + 2 * (AGP_MAX_LEVELS + 2));
+  unsigned int* bucket_count = binned ? sc.bins.as<unsigned int>() : nullptr;
+  unsigned long long* bucket_off = binned ? reinterpret_cast<unsigned long long*>(bucket_count + kBuckets * ng) : nullptr;
+  unsigned long long* cursor = binned ? bucket_off + (kBuckets + 1) * ng : nullptr;
+  unsigned long long* rec_counts = binned ? cursor + kBuckets * ng : nullptr;
+  unsigned long long* bin_count = binned ? rec_counts + (AGP_MAX_LEVELS + 1) * ng : nullptr;
+  unsigned long long* bin_off = binned ? bin_count + nbins_g : nullptr;
+  unsigned long long* bin_cur = binned ? bin_off + nbins_g + 1 : nullptr;
+  uint8_t* det_bins = binned ? reinterpret_cast<uint8_t*>(bin_cur + nbins_g) : nullptr;
+  AGP_HIP(hipMemsetAsync(sc.levelinfo.ptr, 0, sc.levelinfo.bytes, s));
+  AGP_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * kNumCounters * (L + 1), s));
+  AGP_HIP(hipMemsetAsync(errf, 0, sizeof(int), s));
+  if (binned) {  // counters that the bin kernels expect at zero (the layout moves with ng and nbins_g)
+    AGP_HIP(hipMemsetAsync(rec_counts, 0, sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1) * ng, s));
+    AGP_HIP(hipMemsetAsync(bucket_count, 0, sizeof(unsigned int) * kBuckets * ng, s));
+    AGP_HIP(hipMemsetAsync(bin_count, 0, sizeof(unsigned long long) * nbins_g, s));
+  }
+  // every level starts binned (records beyond the buffers switch it to the fallback)
+  k_fill_i32<<<1, 256, 0, s>>>(mode, L + 2, binned ? kModeBinned : kModeCompact);
+  hipEvent_t* ev = sc.events;
+  if (stats && (rc = sc.ensure_events())) return rc;
+
+  DenseArgs D{};
+  D.rp = g->row_ptr;
+  D.col = g->col;
+  D.nd = g->ndeg;
+  D.deg = g->degree;
+  D.fdeg = g->fdeg;
+  D.da = da;
+  D.db = db;
+  D.items = sc.dense_items.as<uint64_t>();
+  D.nitems = sc.dense_nitems;
+  D.cp = cpt;
+  D.Ct = Ct;
+  D.x = x;
+  D.xld = ldc;
+  D.r = r;
+  D.out = out;
+  D.old = ldc;
+  D.acc = acc;
+  D.key0 = static_cast<uint32_t>(seed);
+  D.key1 = static_cast<uint32_t>(seed >> 32);
+  D.err = errf;
+  D.rec_cap = plan.rec_cap;
+  D.bucket_shift = shift;
+  D.gshift = plan.gshift;
+  D.nbins_g = nbins_g;
+  const unsigned fgrid = grid_for(n, 256, 4096);
+  const unsigned cgrid = grid_for(static_cast<int64_t>(cells), 256, 8192);
+  for (int32_t i = 0; i <= L; ++i) {
+    uint8_t* fcur = flags2[i & 1];
+    uint8_t* fnext = flags2[(i + 1) & 1];
+    D.rho = rho[i];
+    D.kappa = kappa[i];
+    D.level = i;
+    D.lflags = (i == L ? kLastLevel : 0) | (a == 0.0 ? kAZero : 0);
+    D.counters = counters + static_cast<size_t>(i) * kNumCounters;
+    D.mass = mass + i;
+    D.flag_in = fcur;
+    const bool bin_level = binned && i < L;
+    D.rec = bin_level ? sc.rec[0].as<uint32_t>() : nullptr;
+    D.rec_count = bin_level ? rec_counts + static_cast<size_t>(i) * ng : nullptr;
+    D.bucket_count = bin_level ? bucket_count : nullptr;
+    D.det_bins = bin_level ? det_bins : nullptr;
+    if (stats) AGP_HIP(hipEventRecord(ev[4 * i], s));
+    if (i < L) k_fill_u8<<<fgrid, 256, 0, s>>>(fnext, static_cast<size_t>(n), 0);
+    if (stats) AGP_HIP(hipEventRecord(ev[4 * i + 1], s));
+    if (i == 0)
+      k_dense_level<true><<<tune.level_blocks, dense::kThreads, 0, s>>>(D);
+    else
+      k_dense_level<false><<<tune.level_blocks, dense::kThreads, 0, s>>>(D);
+    if (stats) AGP_HIP(hipEventRecord(ev[4 * i + 2], s));
+    if (i > 0 && sc.dense_nrows > 0)
+      k_dense_clear_rows<<<grid_for(sc.dense_nrows * Ct, 256, 1024), 256, 0, s>>>(sc.dense_rows.as<uint32_t>(),
+                                                                                   sc.dense_nrows, Ct, r);
+    if (i < L) {
+      if (bin_level) {
+        int* md = mode + i;
+        k_dense_bins_scan<<<ng, kBuckets, 0, s>>>(bucket_count, bucket_off, cursor, D.rec_count, plan.rec_cap, md);
+        for (int gi = 0; gi < ng; ++gi) {
+          const int wgi = std::min(gw, Ct - gi * gw);
+          const unsigned long long gcells = static_cast<unsigned long long>(n) * static_cast<unsigned long long>(wgi);
+          const long long nbins = static_cast<long long>(((gcells > 0 ? gcells : 1) - 1) >> kBinLog2) + 1;
+          uint32_t* r0 = sc.rec[0].as<uint32_t>() + static_cast<size_t>(gi) * plan.rec_cap;
+          uint32_t* r1 = sc.rec[1].as<uint32_t>() + static_cast<size_t>(gi) * plan.rec_cap;
+          const unsigned long long* rc_g = D.rec_count + gi;
+          k_partition<<<1024, kReduceThreads, 0, s>>>(r0, rc_g, cursor + static_cast<size_t>(gi) * kBuckets, r1, md,
+                                                      shift);
+          k_bin_count<<<2048, kReduceThreads, 0, s>>>(r1, rc_g, bin_count, md, shift);
+          k_bin_scan<<<1, 1024, 0, s>>>(bin_count, nbins, bin_off, bin_cur, md);
+          k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(r1, rc_g, bin_cur, r0, md, shift);
+          k_dense_bin_sum<<<static_cast<unsigned>(nbins), dense::kSumThreads, 0, s>>>(
+              r0, bin_off, cpt, Ct, gi * gw, wgi, gcells, acc, r, fnext, md, det_bins + static_cast<size_t>(gi) * nbins_g);
+        }
+        k_dense_apply_overflow<<<2048, 256, 0, s>>>(D, ng, md);
+        k_dense_finish<<<cgrid, 256, 0, s>>>(cpt, n, Ct, acc, r, fnext, md);
+      } else {
+        k_dense_finish<<<cgrid, 256, 0, s>>>(cpt, n, Ct, acc, r, fnext, nullptr);
+      }
+    }
+    if (stats) AGP_HIP(hipEventRecord(ev[4 * i + 3], s));
+  }
+  AGP_HIP(hipGetLastError());
+  int herr = 0;
+  std::vector<double> hmass(static_cast<size_t>(L) + 1);
+  AGP_HIP(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, s));
+  AGP_HIP(hipMemcpyAsync(hmass.data(), mass, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, s));
+  AGP_HIP(hipStreamSynchronize(s));
+  for (int32_t i = 0; i <= L; ++i)
+    if (!(hmass[i] < 0x1p61)) herr |= 1;
+  if (herr) {  // restore the all-zero invariant of the sums and residues
+    AGP_HIP(hipMemsetAsync(sc.acc[0].ptr, 0, sc.acc[0].bytes, s));
+    AGP_HIP(hipMemsetAsync(sc.acc[1].ptr, 0, sc.acc[1].bytes, s));
+    AGP_HIP(hipStreamSynchronize(s));
+    return fail(AGP_ERANGE, std::string(fn) + ": a residue outgrew the exact accumulator range");
+  }
+  if (std::getenv("AGP_CHECK_ZERO")) {  // debugging aid: the sums and residues must be all-zero again
+    std::vector<long long> ha(cells);
+    std::vector<float> hr(cells);
+    AGP_HIP(hipMemcpy(ha.data(), acc, cells * sizeof(long long), hipMemcpyDeviceToHost));
+    AGP_HIP(hipMemcpy(hr.data(), r, cells * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < cells; ++k)
+      if (ha[k] != 0 || hr[k] != 0.0f)
+        return fail(AGP_EDEVICE, std::string(fn) + ": scratch not cleared at cell " + std::to_string(k) +
+                                     " (acc " + std::to_string(ha[k]) + ", r " + std::to_string(hr[k]) + ")");
+  }
+  if (stats) {
+    std::vector<unsigned long long> h(static_cast<size_t>(kNumCounters) * (L + 1));
+    AGP_HIP(hipMemcpy(h.data(), counters, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (int32_t i = 0; i <= L; ++i) {
+      stats->frontier[i] += h[i * kNumCounters + 0];
+      stats->hash[i] += h[i * kNumCounters + 1];
+      stats->det[i] += h[i * kNumCounters + 2];
+      stats->cand[i] += h[i * kNumCounters + 3];
+      stats->acc[i] += h[i * kNumCounters + 4];
+    }
+    float ms = 0.0f;
+    for (int32_t i = 0; i <= L; ++i) {
+      AGP_HIP(hipEventElapsedTime(&ms, ev[4 * i + 1], ev[4 * i + 2]));
+      stats->level_ms[i] += ms;
+      AGP_HIP(hipEventElapsedTime(&ms, ev[4 * i], ev[4 * i + 3]));
+      stats->level_total_ms[i] += ms;
+    }
+    AGP_HIP(hipEventElapsedTime(&ms, ev[0], ev[4 * L + 3]));
+    stats->device_ms += ms;
+  }
+  return AGP_OK;
+}
+
+// Thresholds of all C columns (theta, units, qids) into cp and the number of
+// non-zero entries of x; synchronous.  flags_out gets the signal flags
+// (1: non-finite entry, 2: negative entry).
+template <typename T>
+int all_thresholds(agp_graph* g, const T* x, int32_t C, double eps, const uint32_t* qids, ColParams* cp,
+                   uint32_t* dq, hipStream_t s, unsigned long long* nnz_out, int* flags_out) {
+  Scratch& sc = g->scratch;
+  const int64_t n = g->n;
+  const int64_t tblocks = (n + kThetaRows - 1) / kThetaRows;
+  int rc;
+  if ((rc = sc.partial.reserve(sizeof(double) * (size_t)std::max<int64_t>(tblocks, 1) * C, false, s)) ||
+      (rc = sc.flags.reserve(sizeof(int) * 4, false, s)) || (rc = sc.counts.reserve(sizeof(unsigned long long) * 4, false, s)))
+    return rc;
+  int* flags = sc.flags.as<int>();
+  unsigned long long* nnz = sc.counts.as<unsigned long long>();
+  AGP_HIP(hipMemsetAsync(flags, 0, sc.flags.bytes, s));
+  AGP_HIP(hipMemsetAsync(nnz, 0, sizeof(unsigned long long), s));
+  if (qids) AGP_HIP(hipMemcpyAsync(dq, qids, sizeof(uint32_t) * C, hipMemcpyHostToDevice, s));
+  if (tblocks > 0) {
+    dim3 grid((unsigned)tblocks, (unsigned)((C + 63) / 64));
+    k_theta_scan<T><<<grid, kWave, 0, s>>>(x, static_cast<long long>(C), n, C, sc.partial.as<double>(), flags + 1, nnz);
+  }
+  k_theta_final<T><<<grid_for(C, 64), 64, 0, s>>>(sc.partial.as<double>(), tblocks, C, eps, qids ? dq : nullptr, 0u,
+                                                  cp);
+  AGP_HIP(hipGetLastError());
+  int hflags[4] = {0, 0, 0, 0};
+  unsigned long long hnnz = 0;
+  AGP_HIP(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+  AGP_HIP(hipMemcpyAsync(&hnnz, nnz, sizeof(hnnz), hipMemcpyDeviceToHost, s));
+  AGP_HIP(hipStreamSynchronize(s));
+  *nnz_out = hnnz;
+  *flags_out = hflags[1];
+  return AGP_OK;
+}
+
+// The dense path of a binary32 call: thresholds of all columns, then (when
+// the tuning asks for it, or at least a quarter of x is non-zero) dense
+// tiles.  Returns kNotDense to leave the call to the frontier-list path.
+constexpr int kNotDense = -1;
+
+int propagate_dense(agp_graph* g, const char* fn, const agp_tuning_t& tune, double a, double b,
+                    const std::vector<double>& rho, const std::vector<double>& kappa, int32_t L, const float* x,
+                    int32_t C, double eps, uint64_t seed, const uint32_t* qids, float* out, hipStream_t s,
+                    agp_stats_t* stats) {
+  const int64_t n = g->n;
+  if (n == 0) return kNotDense;
+  const bool may_bin = tune.aggregation == 1 || tune.aggregation == 2;
+  const DensePlan plan = dense_plan(g, C, tune, may_bin);
+  if (plan.ng == 0 || plan.Ct < 1) return kNotDense;
+  Scratch& sc = g->scratch;
+  int rc;
+  if ((rc = sc.colparams.reserve(sizeof(ColParams) * C + sizeof(uint32_t) * C, false, s))) return rc;
+  ColParams* cp = sc.colparams.as<ColParams>();
+  uint32_t* dq = reinterpret_cast<uint32_t*>(cp + C);
+  unsigned long long nnz = 0;
+  int xflags = 0;
+  if ((rc = all_thresholds<float>(g, x, C, eps, qids, cp, dq, s, &nnz, &xflags))) return rc;
+  if (xflags & 1) return fail(AGP_EINVAL, std::string(fn) + ": x holds a non-finite value");
+  const double cells = static_cast<double>(n) * static_cast<double>(C);
+  if (tune.dense == 2 && static_cast<double>(nnz) < 0.25 * cells) return kNotDense;
+  for (int32_t c0 = 0; c0 < C; c0 += plan.Ct) {
+    const int32_t ct = std::min(plan.Ct, C - c0);
+    rc = propagate_dense_tile(g, fn, tune, plan, a, b, rho, kappa, L, x + c0, static_cast<long long>(C), ct, cp + c0,
+                              seed, out + c0, s, stats);
+    if (rc != AGP_OK) return rc;
+  }
+  return AGP_OK;
 }
 
 template <typename T>
@@ -498,10 +947,22 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
 
   std::lock_guard<std::mutex> lk(g->mu);
   const agp_tuning_t tune = tuning_for(g, C, a, b, force);
-  const bool may_bin = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4;
-  const int32_t tile = column_tile<T>(g, C, may_bin);
-  AGP_HIP(hipMemsetAsync(out, 0, cells * sizeof(T), s));
   if (stats) std::memset(stats, 0, sizeof(*stats));
+  if constexpr (std::is_same<T, float>::value) {
+    if (tune.dense == 1 || (tune.dense == 2 && C >= 16)) {
+      const int rc = propagate_dense(g, fn, tune, a, b, rho, kappa, L, x, C, eps, seed, qids, out, s, stats);
+      if (rc != kNotDense) {
+        if (rc == AGP_OK && stats) {
+          stats->levels = L;
+          stats->columns = C;
+        }
+        return rc;
+      }
+    }
+  }
+  const bool may_bin = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4;
+  const int32_t tile = column_tile<T>(g, C, may_bin, tune);
+  AGP_HIP(hipMemsetAsync(out, 0, cells * sizeof(T), s));
   for (int32_t c0 = 0; c0 < C; c0 += tile) {
     const int32_t ct = std::min(tile, C - c0);
     const int rc = propagate_tile<T>(g, fn, tune, a, b, rho, kappa, L, x + c0, static_cast<long long>(C), ct, eps,
@@ -649,33 +1110,55 @@ int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int3
   hipEvent_t e0, e1;
   AGP_HIP(hipEventCreate(&e0));
   AGP_HIP(hipEventCreate(&e1));
-  agp_tuning_t cands[6];
-  int nc = 0;
-  for (int agg = 0; agg < 3; ++agg)
-    for (int blocks : {2048, 4096}) cands[nc++] = agp_tuning_t{agg, blocks};
-  float best_ms = 0.0f;
+  // one untimed call with the defaults (allocations, graph work items)
   agp_tuning_t pick = default_tuning();
-  int rc = AGP_OK;
-  for (int k = 0; k < nc && rc == AGP_OK; ++k) {
+  int rc = propagate_impl<float>(gg, a, b, w, L, x, C, eps, seed, qids, out, s, nullptr, &pick);
+  auto timed = [&](const agp_tuning_t& t, float* ms) {
     (void)hipEventRecord(e0, s);
-    rc = propagate_impl<float>(gg, a, b, w, L, x, C, eps, seed, qids, out, s, nullptr, &cands[k]);
+    const int r = propagate_impl<float>(gg, a, b, w, L, x, C, eps, seed, qids, out, s, nullptr, &t);
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (rc == AGP_OK && (k == 0 || ms < best_ms)) {
-      best_ms = ms;
-      pick = cands[k];
+    *ms = 0.0f;
+    (void)hipEventElapsedTime(ms, e0, e1);
+    return r;
+  };
+  float best_ms = 0.0f;
+  if (rc == AGP_OK) rc = timed(pick, &best_ms);
+  // coordinate descent: each field's candidates with the others fixed at the
+  // best so far (every candidate gives the same bits)
+  auto field = [&](int32_t agp_tuning_t::*f, std::initializer_list<int32_t> vals) {
+    for (int32_t v : vals) {
+      if (rc != AGP_OK) return;
+      agp_tuning_t t = pick;
+      if (t.*f == v) continue;
+      t.*f = v;
+      float ms = 0.0f;
+      rc = timed(t, &ms);
+      if (rc == AGP_OK && ms < best_ms) {
+        best_ms = ms;
+        pick = t;
+      }
     }
+  };
+  if (C >= 2) field(&agp_tuning_t::dense, {0, 1});
+  field(&agp_tuning_t::aggregation, {0, 1, 2});
+  field(&agp_tuning_t::level_blocks, {1024, 2048, 4096, 8192});
+  if (C >= 4) field(&agp_tuning_t::tile_columns, {0, (C + 1) / 2, (C + 3) / 4});
+  if (pick.dense != 1) {  // cut-offs of the frontier-list levels
+    field(&agp_tuning_t::big_row, {1024, 4096, 16384});
+    field(&agp_tuning_t::big_items, {16, 64, 256});
+    field(&agp_tuning_t::sparse_shift, {3, 5, 7});
+    if (pick.aggregation == 2) field(&agp_tuning_t::bin_shift, {2, 3, 5});
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != AGP_OK) return rc;
+  pick = normalize_tuning(pick);
   {
     std::lock_guard<std::mutex> lk(gg->mu);
     gg->tuning[agp_tune_key{C, a, b}] = pick;
   }
-  // leave `out` with the result (every candidate gives the same bits)
+  // `out` holds the result of the last candidate (identical for every one)
   if (best) *best = pick;
   return AGP_OK;
 }
@@ -686,6 +1169,18 @@ int agp_get_tuning(const agp_graph_t* g, int32_t C, double a, double b, agp_tuni
   agp_graph* gg = const_cast<agp_graph*>(g);
   std::lock_guard<std::mutex> lk(gg->mu);
   *out = tuning_for(gg, C, a, b, nullptr);
+  return AGP_OK;
+}
+
+int agp_set_tuning(const agp_graph_t* g, int32_t C, double a, double b, const agp_tuning_t* t) {
+  using namespace agp;
+  if (!g) return fail(AGP_EINVAL, "agp_set_tuning: NULL graph");
+  agp_graph* gg = const_cast<agp_graph*>(g);
+  std::lock_guard<std::mutex> lk(gg->mu);
+  if (t)
+    gg->tuning[agp_tune_key{C, a, b}] = normalize_tuning(*t);
+  else
+    gg->tuning.erase(agp_tune_key{C, a, b});
   return AGP_OK;
 }
 

@@ -48,6 +48,7 @@ using lvl::kBinLog2;
 using lvl::kBuckets;
 using lvl::kLastLevel;
 using lvl::kNumCounters;
+using lvl::wave_sync;
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
@@ -55,7 +56,7 @@ constexpr int kMaxCols = 64;       // columns of a tile (one lane each)
 constexpr int kMaxGroups = 4;      // record groups of a tile
 constexpr int kItemArcs = 4096;    // arcs of a work item (rows above it are cut by windows)
 constexpr int kItemNodes = 64;     // nodes of a work item
-constexpr int kStageRecs = 1024;   // records staged per wave (split over the groups)
+constexpr int kStageRecs = 512;    // records staged per wave (split over the groups)
 
 // Work item: bits 0..31 first node; bit 63 set for a piece of one long row
 // (bits 32..51 first window, bits 52..58 window count, 1..64), else bits
@@ -135,70 +136,71 @@ __device__ __forceinline__ void apply_group_record(const DenseArgs& D, int g, ui
                           static_cast<unsigned long long>(dt));
 }
 
-// Per-wave staging of group records: group g owns kStageRecs / ng slots.
-struct GroupStage {
-  uint32_t* base;  // the wave's kStageRecs slots
-  int per;         // slots per group
-  int n[kMaxGroups];
+// ------------------------------------------------------------ the level
+// Per work item (a run of consecutive nodes, or a piece of one long row) the
+// wave first loads the row pointer, degree and d_u^-b of every node (one lane
+// per node).  Each node with a non-zero residue is then set up with one lane
+// per column (residue, reserve, c = rho |r| d_u^-b, the deterministic prefix
+// J) and its row is taken 64 arcs (one window) at a time: the window's
+// neighbour ids, degree factors and run boundaries (degree groups cut at the
+// window) go to LDS, and the (column, run) pairs of the window -- every run
+// after each column's deterministic prefix -- are numbered and handed out 64
+// at a time, one pair per lane.  A lane builds the skip table of its pair's
+// run and walks the run's Philox / geometric-skip chain, reading candidates'
+// neighbours from LDS, so lanes stay busy whether a node has one active
+// column or 64 and however many degree groups its row holds.  The next
+// node's residues and first window are loaded while the current node draws.
+struct WaveLds {
+  int64_t rp[kItemNodes];       // the item's nodes: first arc
+  uint32_t d[kItemNodes];       //   degree
+  double db[kItemNodes];        //   d_u^-b
+  uint32_t col[kWave];          // the window's neighbour ids
+  double da[kWave];             //   their factors d^-a (1 when a = 0)
+  uint32_t rstart[kWave + 1];   //   run starts (window-relative); rstart[R] = window length
+  uint32_t pre[kWave];          // per column: pairs of the columns before it
+  uint32_t k0[kWave];           // per column: its first run in the window
+  double cv[kWave];             // per column of the node: c = rho |r| d_u^-b
+  uint32_t J[kWave];            // per column of the node: deterministic prefix (row-relative)
+  int nst[kMaxGroups];          // records staged per group
+  uint32_t stage[kStageRecs];   // staged records, kStageRecs / ng per group
 };
 
-__device__ __forceinline__ void group_flush(GroupStage& st, int g, const DenseArgs& D) {
-  const int cnt = st.n[g];
-  if (cnt == 0) return;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  unsigned long long b0 = 0;
-  if (lane_id() == 0) b0 = atomicAdd(D.rec_count + g, static_cast<unsigned long long>(cnt));
-  b0 = __shfl(b0, 0);
-  const uint32_t* src = st.base + g * st.per;
-  uint32_t* dst = D.rec + static_cast<size_t>(g) * D.rec_cap;
-  for (int i = lane_id(); i < cnt; i += kWave) {
-    if (b0 + i < D.rec_cap)
-      dst[b0 + i] = src[i];
-    else
-      apply_group_record(D, g, src[i]);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  st.n[g] = 0;
-}
-
-// ------------------------------------------------------------ the level
-// kFirst: level 0 (residues read from x, the reserve written without a read,
-// every node visited).  Work items are taken round-robin by the waves of the
-// grid; items are balanced by arc count when the graph's items are built.
 template <bool kFirst>
 __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
-  __shared__ uint32_t s_stage[kWaves][kStageRecs];
+  __shared__ WaveLds s_w[kWaves];
   __shared__ unsigned int s_hist[kMaxGroups][kBuckets];
+  __shared__ double s_theta[kMaxCols];
+  __shared__ long long s_dth[kMaxCols];
+  __shared__ uint32_t s_ctr3[kMaxCols];
 
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
   const bool binned = D.rec != nullptr;
   const int ng = (D.Ct + (1 << D.gshift) - 1) >> D.gshift;
-  if (binned) {
-    for (int i = threadIdx.x; i < ng * kBuckets; i += blockDim.x) (&s_hist[0][0])[i] = 0;
-    __syncthreads();
+  const int per = kStageRecs / ng;
+  WaveLds& W = s_w[wave];
+  for (int i = threadIdx.x; i < D.Ct; i += blockDim.x) {
+    const ColParams& p = D.cp[i];
+    s_theta[i] = p.theta;
+    s_dth[i] = p.dtheta;
+    s_ctr3[i] = (p.qid << 8) | static_cast<uint32_t>(D.level);
   }
-  GroupStage st;
-  st.base = s_stage[wave];
-  st.per = kStageRecs / ng;
-#pragma unroll
-  for (int g = 0; g < kMaxGroups; ++g) st.n[g] = 0;
+  if (binned)
+    for (int i = threadIdx.x; i < ng * kBuckets; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+  if (lane < kMaxGroups) W.nst[lane] = 0;
+  __syncthreads();
 
-  // the lane's column
+  // the lane's column during the per-node setup
   const int c = lane;
   const bool live = c < D.Ct;
   const int my_g = c >> D.gshift;
   const int my_w = live ? group_width(D.Ct, D.gshift, my_g) : 1;
   const int my_cl = c - (my_g << D.gshift);
   double th = 1.0, scale = 1.0;
-  long long dth = 0;
-  uint32_t ctr3 = 0;
   if (live) {
-    const ColParams& p = D.cp[c];
-    th = p.theta;
-    scale = p.scale;
-    dth = p.dtheta;
-    ctr3 = (p.qid << 8) | static_cast<uint32_t>(D.level);
+    th = D.cp[c].theta;
+    scale = D.cp[c].scale;
   }
   const bool azero = (D.lflags & kAZero) != 0;
   const bool last = (D.lflags & kLastLevel) != 0;
@@ -207,30 +209,44 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
   unsigned long long n_front = 0, n_hash = 0, n_det = 0, n_cand = 0, n_acc = 0;
   double mass = 0.0;
 
-  // one sampled push of -/+ fl(theta_c) to (v, c) for the lanes with emit
-  auto emit_sampled = [&](bool emit, uint32_t v, bool neg) {
+  // records of group g to the level's buffer (all lanes together)
+  auto flush = [&](int g) {
+    const int cnt = W.nst[g];
+    if (cnt == 0) return;
+    unsigned long long b0 = 0;
+    if (lane == 0) b0 = atomicAdd(D.rec_count + g, static_cast<unsigned long long>(cnt));
+    b0 = __shfl(b0, 0);
+    const uint32_t* src = W.stage + g * per;
+    uint32_t* dst = D.rec + static_cast<size_t>(g) * D.rec_cap;
+    for (int i = lane; i < cnt; i += kWave) {
+      if (b0 + i < D.rec_cap)
+        dst[b0 + i] = src[i];
+      else
+        apply_group_record(D, g, src[i]);
+    }
+    wave_sync();
+    if (lane == 0) W.nst[g] = 0;
+    wave_sync();
+  };
+  // a sampled push of -/+ fl(theta_ec) to (v, ec) for the lanes with e (all
+  // lanes together): a staged record, or an integer atomic without records
+  auto emit = [&](bool e, uint32_t v, int ec, bool neg) {
+    if (__ballot(e) == 0ull) return;
     if (binned) {
-      const uint32_t gcell = v * static_cast<uint32_t>(my_w) + static_cast<uint32_t>(my_cl);
-      if (emit) atomicAdd(&s_hist[my_g][gcell >> D.bucket_shift], 1u);
-      const unsigned long long mask = __ballot(emit);
-      if (mask == 0ull) return;
-#pragma unroll
-      for (int g = 0; g < kMaxGroups; ++g) {
-        if (g >= ng) break;
-        const int lo = g << D.gshift;
-        const unsigned long long gm = (lo >= kWave) ? 0ull : (mask >> lo) << lo;  // lanes >= lo
-        const int hi = lo + (1 << D.gshift);
-        const unsigned long long inside = gm & (hi >= kWave ? ~0ull : ((1ull << hi) - 1ull));
-        if (inside == 0ull) continue;
-        if (emit && my_g == g)
-          st.base[g * st.per + st.n[g] + __popcll(inside & ((1ull << lane) - 1ull))] =
-              gcell | (neg ? 0x80000000u : 0u);
-        st.n[g] += __popcll(inside);
-        if (st.n[g] > st.per - kWave) group_flush(st, g, D);
+      if (e) {
+        const int eg = ec >> D.gshift;
+        const int ew = group_width(D.Ct, D.gshift, eg);
+        const uint32_t gcell = v * static_cast<uint32_t>(ew) + static_cast<uint32_t>(ec - (eg << D.gshift));
+        atomicAdd(&s_hist[eg][gcell >> D.bucket_shift], 1u);
+        const int slot = atomicAdd(&W.nst[eg], 1);
+        W.stage[eg * per + slot] = gcell | (neg ? 0x80000000u : 0u);
       }
-    } else if (emit) {
-      const long long dt = neg ? -dth : dth;
-      lvl::atomic_add_relaxed(reinterpret_cast<unsigned long long*>(D.acc + static_cast<size_t>(v) * D.Ct + c),
+      wave_sync();
+      for (int g = 0; g < ng; ++g)
+        if (W.nst[g] > per - kWave) flush(g);
+    } else if (e) {
+      const long long dt = neg ? -s_dth[ec] : s_dth[ec];
+      lvl::atomic_add_relaxed(reinterpret_cast<unsigned long long*>(D.acc + static_cast<size_t>(v) * D.Ct + ec),
                               static_cast<unsigned long long>(dt));
     }
   };
@@ -249,66 +265,119 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
     } else {
       nodes = static_cast<int>((it >> 32) & 0xFFull);
     }
-    unsigned long long todo;
-    if (kFirst) {
-      todo = nodes >= kWave ? ~0ull : ((1ull << nodes) - 1ull);
-    } else {
-      const bool f = lane < nodes && D.flag_in[u0 + lane] != 0;
-      todo = __ballot(f);
+    // the item's nodes (lane = node)
+    bool f = false;
+    if (lane < nodes) {
+      const uint32_t uu = u0 + static_cast<uint32_t>(lane);
+      f = kFirst || D.flag_in[uu] != 0;
+      if (f) {
+        W.rp[lane] = D.rp[uu];
+        W.d[lane] = static_cast<uint32_t>(D.deg[uu]);
+        W.db[lane] = pushes ? D.db[D.fdeg[uu]] : 0.0;
+      }
     }
+    unsigned long long todo = __ballot(f);
+    wave_sync();
     // the first piece of a long row owns the row's per-node work (reserve,
     // frontier counters, mass); the row's residues are cleared after the
     // level (every piece reads them)
     const bool owner = !longrow || wlo == 0;
+    const uint32_t ws0 = wlo << kSegLog2;
+    // loads of a node's residues (lane = column) and first window (lane = arc)
+    float r_n = 0.0f;
+    uint32_t col_n = 0, nd_n = 0;
+    auto prefetch = [&](int bb) {
+      const uint32_t uu = u0 + static_cast<uint32_t>(bb);
+      r_n = 0.0f;
+      if (live) r_n = kFirst ? D.x[static_cast<size_t>(uu) * static_cast<size_t>(D.xld) + c]
+                             : D.r[static_cast<size_t>(uu) * static_cast<size_t>(D.Ct) + c];
+      col_n = nd_n = 0;
+      if (pushes) {
+        const uint32_t j = ws0 + static_cast<uint32_t>(lane);
+        if (j < W.d[bb]) {
+          const int64_t a = W.rp[bb] + j;
+          col_n = D.col[a];
+          nd_n = D.nd[a];
+        }
+      }
+    };
+    if (todo) prefetch(__ffsll(static_cast<long long>(todo)) - 1);
     while (todo) {
       const int b = __ffsll(static_cast<long long>(todo)) - 1;
       todo &= todo - 1ull;
       const uint32_t u = u0 + static_cast<uint32_t>(b);
-      const size_t ucell = static_cast<size_t>(u) * static_cast<size_t>(D.Ct) + c;
-      float r = 0.0f;
-      if (live) r = kFirst ? D.x[static_cast<size_t>(u) * static_cast<size_t>(D.xld) + c] : D.r[ucell];
+      const float r = r_n;
+      const uint32_t colw0 = col_n, ndw0 = nd_n;
+      const uint32_t d = W.d[b];
+      const int64_t rp = W.rp[b];
       const bool nz = live && r != 0.0f;
-      if (!kFirst && !longrow && nz) D.r[ucell] = 0.0f;
+      // dependent loads of this node before the next node's prefetch
+      const bool valid0 = ws0 + static_cast<uint32_t>(lane) < d;
+      double daw0 = 1.0;
+      if (pushes && !azero && valid0) daw0 = D.da[ndw0];
+      float* o = D.out + static_cast<size_t>(u) * static_cast<size_t>(D.old) + c;
+      float o_old = 0.0f;
+      if (!kFirst && owner && nz && D.kappa != 0.0) o_old = *o;
+      if (todo) prefetch(__ffsll(static_cast<long long>(todo)) - 1);
+      // ---- per-column setup (lane = column)
+      if (!kFirst && !longrow && nz) D.r[static_cast<size_t>(u) * static_cast<size_t>(D.Ct) + c] = 0.0f;
       if (owner) {
         if (nz) {
           ++n_front;
           n_hash += splitmix64(u);
         }
-        float* o = D.out + static_cast<size_t>(u) * static_cast<size_t>(D.old) + c;
         if (kFirst) {  // pi starts at +0: pi = +0 + fl(kappa r)
           if (live) *o = nz ? 0.0f + static_cast<float>(D.kappa * static_cast<double>(r)) : 0.0f;
         } else if (nz && D.kappa != 0.0) {
-          *o = *o + static_cast<float>(D.kappa * static_cast<double>(r));
+          *o = o_old + static_cast<float>(D.kappa * static_cast<double>(r));
         }
       }
-      if (!pushes || !__any(nz)) continue;
-      const uint32_t d = static_cast<uint32_t>(D.deg[u]);
-      if (d == 0) continue;
-      const int64_t rp = D.rp[u];
+      if (!pushes || d == 0 || !__any(nz)) continue;
       const bool neg = r < 0.0f;
-      // c = (rho |r|) d_u^-b and the deterministic prefix J (increment >= theta)
+      // c = (rho |r|) d_u^-b and the deterministic prefix J (increment >= theta):
+      // the increments fall along the degree-sorted row
       const double absr = fabs(static_cast<double>(r));
       const double t0 = D.rho * absr;
-      const double cv = t0 * D.db[D.fdeg[u]];
+      const double cv = t0 * W.db[b];
       uint32_t J = 0;
-      double inc0 = cv, p0 = 0.0;
+      double inc0 = cv;
+      const bool onewin = d - ws0 <= static_cast<uint32_t>(kWave);  // the piece's first window ends the row
       if (azero) {
         J = (nz && cv >= th) ? d : 0u;
-        const double num = cv * 1.0;
-        p0 = num / th;
       } else {
-        inc0 = cv * D.da[D.nd[rp]];
+        const double da_first = wlo == 0 ? shfl_f64(daw0, 0) : D.da[D.nd[rp]];
+        inc0 = cv * da_first;
+        double da_last;
+        if (wlo == 0 && onewin)
+          da_last = shfl_f64(daw0, static_cast<int>(d - 1));
+        else
+          da_last = D.da[D.nd[rp + d - 1]];
         uint32_t lo = 0, hi = d;
         if (!nz || !(inc0 >= th))
           hi = 0;
-        else if (cv * D.da[D.nd[rp + d - 1]] >= th)
+        else if (cv * da_last >= th)
           lo = d;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (cv * D.da[D.nd[rp + mid]] >= th)
-            lo = mid + 1;
-          else
-            hi = mid;
+        if (__any(lo < hi)) {
+          if (wlo == 0 && onewin) {  // the row is in registers: search by lane exchanges
+            for (int step = 0; step < 7; ++step) {
+              const uint32_t mid = (lo + hi) >> 1;
+              const double dm = shfl_f64(daw0, static_cast<int>(mid < d ? mid : 0u));
+              if (lo < hi) {
+                if (cv * dm >= th)
+                  lo = mid + 1;
+                else
+                  hi = mid;
+              }
+            }
+          } else {
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi) >> 1;
+              if (cv * D.da[D.nd[rp + mid]] >= th)
+                lo = mid + 1;
+              else
+                hi = mid;
+            }
+          }
         }
         J = lo;
       }
@@ -319,30 +388,35 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
       const uint32_t nwin = ((d - 1) >> kSegLog2) + 1;
       const uint32_t w1 = whi < nwin ? whi : nwin;
       if (nz) {  // deterministic pushes of this piece: positions [jlo, min(J, jhi))
-        const uint32_t jlo = wlo << kSegLog2, jhi = (w1 << kSegLog2) < d ? (w1 << kSegLog2) : d;
+        const uint32_t jlo = ws0, jhi = (w1 << kSegLog2) < d ? (w1 << kSegLog2) : d;
         n_det += (J > jlo ? (J < jhi ? J : jhi) - jlo : 0u);
       }
       const uint32_t Jmax = wave_max_u32(nz ? J : 0u);
-      SkipTable tab0;
-      if (azero) tab0 = make_skip_table(p0);
+      const unsigned long long negmask = __ballot(nz && neg);
+      wave_sync();  // the previous node's pairs have been read
+      W.cv[lane] = cv;
+      W.J[lane] = nz ? J : 0xFFFFFFFFu;
       for (uint32_t w = wlo; w < w1; ++w) {
         const uint32_t ws = w << kSegLog2;
         const uint32_t we = (ws + kSeg) < d ? ws + kSeg : d;
-        const bool need_samp = __any(nz && J < we);
+        const bool has = nz && J < we;  // the column samples in this window
+        const bool need_samp = __any(has);
         const bool need_det = Jmax > ws;
         if (!need_samp && !need_det) continue;
-        // the window's arcs, one per lane
-        const uint32_t j = ws + static_cast<uint32_t>(lane);
-        const bool valid = j < we;
-        const uint32_t colw = valid ? D.col[rp + j] : 0u;
-        double daw = 1.0;
-        int gw = 0;
-        if (!azero && valid) {
-          const uint32_t ndw = D.nd[rp + j];
-          daw = D.da[ndw];
-          gw = 31 - __clz(ndw);
+        // ---- the window's arcs (lane = arc)
+        const bool valid = ws + static_cast<uint32_t>(lane) < we;
+        uint32_t colw = colw0;
+        double daw = daw0;
+        if (w != wlo) {
+          colw = 0u;
+          daw = 1.0;
+          if (valid) {
+            const int64_t a = rp + ws + static_cast<uint32_t>(lane);
+            colw = D.col[a];
+            if (!azero) daw = D.da[D.nd[a]];
+          }
         }
-        // deterministic pushes at positions [ws, min(Jmax, we))
+        // deterministic pushes at positions [ws, min(Jmax, we)) (lane = column)
         if (need_det) {
           const uint32_t jd = Jmax < we ? Jmax : we;
           for (uint32_t q = ws; q < jd; ++q) {
@@ -370,71 +444,97 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
           }
         }
         if (!need_samp) continue;
-        // runs: the window start and every change of degree group (a > 0)
+        // runs: the window start and every change of degree group (a > 0);
+        // floor(log2) of d^-a's degree is read back from the factor's bits
         unsigned long long runs;
         if (azero) {
           runs = 1ull;
         } else {
+          const uint32_t ndv = valid ? (w == wlo ? ndw0 : D.nd[rp + ws + static_cast<uint32_t>(lane)]) : 1u;
+          const int gw = 31 - __clz(ndv);
           const int gprev = __shfl(gw, lane > 0 ? lane - 1 : 0);
           runs = __ballot(valid && (lane == 0 || gw != gprev));
         }
-        const int wlen = static_cast<int>(we - ws);
-        while (runs) {
-          const int s0 = __ffsll(static_cast<long long>(runs)) - 1;
-          runs &= runs - 1ull;
-          const int e0 = runs ? __ffsll(static_cast<long long>(runs)) - 1 : wlen;
-          // the lane's run: from max(s0, J) to e0 (only if it is non-empty)
-          const int jrel = J > ws ? static_cast<int>(J - ws) : 0;
-          bool active = nz && jrel < e0;
-          const int sl = jrel > s0 ? jrel : s0;
-          const int slc = sl < kWave ? sl : kWave - 1;
-          double dstart = 1.0;
-          SkipTable tab;
-          if (azero) {
-            tab = tab0;
-          } else {
-            dstart = shfl_f64(daw, slc);
-            const double num = cv * dstart;
-            tab = make_skip_table(num / th);
-          }
-          const uint32_t s_abs = ws + static_cast<uint32_t>(sl);
-          int pos = sl;
-          uint32_t t = 0;
+        const int R = __popcll(runs);
+        const uint32_t wlen = we - ws;
+        // per column: its first run (runs ending at or before its prefix are
+        // deterministic) and its number of (column, run) pairs
+        const uint32_t jr = J > ws ? J - ws : 0u;
+        int k0 = 0, cnt = 0;
+        if (has) {
+          const unsigned long long upto = jr >= 63u ? ~0ull : ((2ull << jr) - 1ull);
+          k0 = __popcll(runs & upto & ~1ull);
+          cnt = R - k0;
+        }
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+          const int tv = __shfl_up(incl, off);
+          if (lane >= off) incl += tv;
+        }
+        const int total = __shfl(incl, kWave - 1);
+        wave_sync();  // the previous window's pairs have been read
+        W.col[lane] = colw;
+        W.da[lane] = daw;
+        if ((runs >> lane) & 1ull) W.rstart[__popcll(runs & lt_mask)] = static_cast<uint32_t>(lane);
+        if (lane == 0) W.rstart[R] = wlen;
+        W.pre[lane] = static_cast<uint32_t>(incl - cnt);
+        W.k0[lane] = static_cast<uint32_t>(k0);
+        wave_sync();
+        // ---- the window's (column, run) pairs, 64 at a time (lane = pair)
+        for (int base = 0; base < total; base += kWave) {
+          const int i = base + lane;
+          bool active = i < total;
+          int pc = 0;  // the pair's column: the last column whose first pair is at or before i
+#pragma unroll
+          for (int step = kWave / 2; step > 0; step >>= 1)
+            if (W.pre[pc + step] <= static_cast<uint32_t>(i)) pc += step;
+          const int k = static_cast<int>(W.k0[pc]) + (i - static_cast<int>(W.pre[pc]));
+          const int kk = active ? k : 0;
+          const uint32_t rs = W.rstart[kk];
+          const uint32_t pJ = W.J[pc];
+          const uint32_t pj = pJ > ws ? pJ - ws : 0u;
+          const uint32_t s = rs > pj ? rs : pj;
+          const uint32_t e = W.rstart[kk + 1];
+          const uint32_t sc = s < static_cast<uint32_t>(kWave) ? s : 0u;
+          const double dstart = azero ? 1.0 : W.da[sc];
+          const double num = W.cv[pc] * dstart;
+          const SkipTable tab = make_skip_table(num / s_theta[pc]);
+          const bool pneg = ((negmask >> pc) & 1ull) != 0;
+          const uint32_t ctr3 = s_ctr3[pc];
+          const uint32_t s_abs = ws + s;
+          uint32_t pos = s, t = 0;
           while (__any(active)) {
             const U4 o = philox4x32_10(t, s_abs, u, ctr3, D.key0, D.key1);
             const double V = unit_double(o.x, o.y);
-            const int cand = pos + geometric_skip(tab, V);
-            const bool hit = active && cand < e0;
+            const uint32_t cand = pos + static_cast<uint32_t>(geometric_skip(tab, V));
+            const bool hit = active && cand < e;
             if (active && !hit) active = false;
-            const int cidx = hit ? cand : 0;
-            const uint32_t vcand = static_cast<uint32_t>(__shfl(static_cast<int>(colw), cidx));
-            const double dcand = azero ? 1.0 : shfl_f64(daw, cidx);
-            bool emit = false;
+            bool e_push = false;
+            uint32_t vcand = 0;
             if (hit) {
               ++n_cand;
               bool accept = true;
               if (!azero) {
-                const double ratio = dcand / dstart;
+                const double ratio = W.da[cand] / dstart;
                 accept = unit_double(o.z, o.w) < ratio;
               }
               if (accept) {
                 ++n_acc;
-                emit = true;
+                e_push = true;
+                vcand = W.col[cand];
               }
               pos = cand + 1;
               ++t;
             }
-            emit_sampled(emit, vcand, neg);
+            emit(e_push, vcand, pc, pneg);
           }
         }
       }
     }
   }
   if (binned) {
-    for (int g = 0; g < kMaxGroups; ++g) {
-      if (g >= ng) break;
-      group_flush(st, g, D);
-    }
+    for (int g = 0; g < ng; ++g) flush(g);
     __syncthreads();
     for (int i = threadIdx.x; i < ng * kBuckets; i += blockDim.x) {
       const unsigned int h = (&s_hist[0][0])[i];

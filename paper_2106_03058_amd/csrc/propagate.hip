@@ -625,6 +625,11 @@ DensePlan dense_plan(agp_graph* g, int32_t C, const agp_tuning_t& tune, bool bin
       if (v > 0 && v < room * p.ng) room = v * p.ng;
     }
     p.rec_cap = room >= 1024.0 * p.ng ? static_cast<unsigned long long>(room / p.ng) : 0ull;
+    // keep record buffers that hold at least 90% of that: the free memory
+    // moves a little between calls, and growing them means freeing and
+    // allocating tens of GB
+    const unsigned long long have = std::min(sc.rec[0].bytes, sc.rec[1].bytes) / (sizeof(uint32_t) * p.ng);
+    if (p.rec_cap > 0 && have >= p.rec_cap / 10 * 9) p.rec_cap = std::min<unsigned long long>(have, 2 * p.rec_cap);
   }
   return p;
 }

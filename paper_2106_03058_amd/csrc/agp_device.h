@@ -44,6 +44,29 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
   return U4{c0, c1, c2, c3};
 }
 
+// The same generator for a key held in scalar registers (the same key for the
+// whole wave).  The key schedule is recomputed round by round with two scalar
+// adds; the empty asm statement only hides the key's value from the compiler,
+// which would otherwise keep all twenty round keys live for the whole kernel.
+__device__ __forceinline__ U4 philox4x32_10_skey(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t y0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t y2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+    c0 = y0;
+    c1 = static_cast<uint32_t>(p1);
+    c2 = y2;
+    c3 = static_cast<uint32_t>(p0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    __asm__ volatile("" : "+s"(k0), "+s"(k1));
+  }
+  return U4{c0, c1, c2, c3};
+}
+
 // 53 random bits (32 from `hi`, the top 21 of `lo`) as a double in [0, 1).
 __device__ __forceinline__ double unit_double(uint32_t hi, uint32_t lo) {
   // hi * 2^21 + (lo >> 11) is an integer below 2^53: both terms and the sum

@@ -155,13 +155,13 @@ __device__ __forceinline__ void apply_group_record(const DenseArgs& D, int g, ui
 // So lanes stay busy whether a node has one active column or 64, however
 // many degree groups its rows hold, and however long each chain runs.
 struct Slot {
-  uint32_t col[kWave];         // neighbour ids of the window's arcs
-  double da[kWave];            // their factors d^-a (1 when a = 0)
-  uint32_t rstart[kWave + 1];  // run starts (window-relative); rstart[R] = window length
-  uint32_t pre[kWave];         // per column: pairs of the columns before it
-  uint32_t k0[kWave];          // per column: its first run in the window
-  double cv[kWave];            // per column: c = rho |r| d_u^-b
-  uint32_t J[kWave];           // per column: deterministic prefix (row-relative)
+  uint32_t col[kWave];       // neighbour ids of the window's arcs
+  double da[kWave];          // their factors d^-a (1 when a = 0)
+  uint32_t rs[kWave + 1];    // run starts (window-relative); rs[R] = window length
+  uint32_t meta[kWave];      // per sampling column, by rank: column | k0 << 8 | jr << 16 | sign << 31,
+                             // k0 its first run, jr its deterministic prefix in the window
+  double cv[kWave];          // per sampling column, by rank: c = rho |r| d_u^-b
+  uint32_t R, M, u, ws;      // runs, ceil(2^32 / R), node, window start (row-relative)
 };
 
 struct WaveLds {
@@ -180,6 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
   __shared__ double s_theta[kMaxCols];
   __shared__ long long s_dth[kMaxCols];
   __shared__ uint32_t s_ctr3[kMaxCols];
+  __shared__ uint32_t s_magic[kWave + 1];  // ceil(2^32 / R) for R = 2..64 (R = 1: 2^32 - 1)
 
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
@@ -188,6 +189,10 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
   const int ng = (D.Ct + (1 << D.gshift) - 1) >> D.gshift;
   const int per = kStageRecs / ng;
   WaveLds& W = s_w[wave];
+  for (int i = threadIdx.x; i <= kWave; i += blockDim.x)
+    s_magic[i] = i <= 1 ? 0xFFFFFFFFu
+                        : static_cast<uint32_t>((0x100000000ull + static_cast<unsigned long long>(i) - 1ull) /
+                                                static_cast<unsigned long long>(i));
   for (int i = threadIdx.x; i < D.Ct; i += blockDim.x) {
     const ColParams& p = D.cp[i];
     s_theta[i] = p.theta;
@@ -247,7 +252,6 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
   bool longrow = false;
   uint32_t pu = 0, pd = 0, pw = 0, pw1 = 0, pJmax = 0;  // the node being produced
   int64_t prp = 0;
-  unsigned long long pneg = 0;
   bool nz = false, neg = false;  // per column
   double cv = 0.0;
   uint32_t J = 0;
@@ -272,11 +276,8 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
       }
     }
   };
-  // ---- slots: hs = the older one; avail[], taken[] and total[] per slot
-  int hs = 0;
-  int total[2] = {0, 0}, taken[2] = {0, 0};
-  uint32_t sl_u[2] = {0, 0}, sl_ws[2] = {0, 0};
-  unsigned long long sl_neg[2] = {0, 0};
+  // ---- slots: pairs handed out and pairs of each slot (wave-uniform)
+  int tot0 = 0, tot1 = 0, tk0 = 0, tk1 = 0;
   // ---- consumer state (per lane)
   bool active = false;
   int cs = 0;  // the lane's slot
@@ -351,9 +352,13 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
         nz = live && r != 0.0f;
         if (!kFirst && !longrow && nz) D.r[ucell] = 0.0f;
         if (owner) {
-          if (nz) {
-            ++n_front;
-            n_hash += splitmix64(pu);
+          // frontier counters: (node, column) pairs with a non-zero residue
+          // and their hash, counted once per node (lane 0)
+          const unsigned long long nzm = __ballot(nz);
+          if (lane == 0 && nzm) {
+            const unsigned long long k = static_cast<unsigned long long>(__popcll(nzm));
+            n_front += k;
+            n_hash += k * splitmix64(pu);
           }
           if (kFirst) {  // pi starts at +0: pi = +0 + fl(kappa r)
             if (live) *o = nz ? 0.0f + static_cast<float>(D.kappa * static_cast<double>(r)) : 0.0f;
@@ -420,7 +425,6 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
           n_det += (J > jlo ? (J < jhi ? J : jhi) - jlo : 0u);
         }
         pJmax = wave_max_u32(nz ? J : 0u);
-        pneg = __ballot(nz && neg);
         pnode = true;
       }
       // ---- window pw of the node being produced
@@ -490,111 +494,109 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
       // per column: its first run (runs ending at or before its prefix are
       // deterministic) and its number of (column, run) pairs
       const uint32_t jr = J > ws ? J - ws : 0u;
-      int k0 = 0, cnt = 0;
+      int k0 = 0;
       if (has) {
         const unsigned long long upto = jr >= 63u ? ~0ull : ((2ull << jr) - 1ull);
         k0 = __popcll(runs & upto & ~1ull);
-        cnt = R - k0;
       }
-      int incl = cnt;
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-        const int tv = __shfl_up(incl, off);
-        if (lane >= off) incl += tv;
-      }
+      const unsigned long long hasm = __ballot(has);
+      const int m = __popcll(hasm);
       Slot& S = W.slot[fs];
       S.col[lane] = colw;
       S.da[lane] = daw;
-      if ((runs >> lane) & 1ull) S.rstart[__popcll(runs & lt_mask)] = static_cast<uint32_t>(lane);
-      if (lane == 0) S.rstart[R] = we - ws;
-      S.pre[lane] = static_cast<uint32_t>(incl - cnt);
-      S.k0[lane] = static_cast<uint32_t>(k0);
-      S.cv[lane] = cv;
-      S.J[lane] = nz ? J : 0xFFFFFFFFu;
-      total[fs] = __shfl(incl, kWave - 1);
-      taken[fs] = 0;
-      sl_u[fs] = pu;
-      sl_ws[fs] = ws;
-      sl_neg[fs] = pneg;
+      if ((runs >> lane) & 1ull) S.rs[__popcll(runs & lt_mask)] = static_cast<uint32_t>(lane);
+      if (has) {
+        const int rk = __popcll(hasm & lt_mask);
+        S.meta[rk] = static_cast<uint32_t>(c) | (static_cast<uint32_t>(k0) << 8) | (jr << 16) | (neg ? 0x80000000u : 0u);
+        S.cv[rk] = cv;
+      }
+      if (lane == 0) {
+        S.rs[R] = we - ws;
+        S.R = static_cast<uint32_t>(R);
+        S.M = s_magic[R];
+        S.u = pu;
+        S.ws = ws;
+      }
+      if (fs == 0) {
+        tot0 = m * R;
+        tk0 = 0;
+      } else {
+        tot1 = m * R;
+        tk1 = 0;
+      }
       wave_sync();
       return true;
     }
   };
 
+  int cur = 0;  // the older slot; both start empty and are filled by the retire step below
   for (;;) {
-    const int ts = hs ^ 1;
-    const int avail = (total[hs] - taken[hs]) + (total[ts] - taken[ts]);
-    // the older slot is free once its pairs are taken and their chains ended
-    if (taken[hs] == total[hs] && !__any(active && cs == hs)) {
-      if (total[ts] > taken[ts] || __any(active && cs == ts)) {
-        hs = ts;  // the newer slot becomes the older one
-        continue;
-      }
-      total[hs] = taken[hs] = 0;
-    }
-    const int fs = (total[hs] == 0 && !__any(active && cs == hs)) ? hs
-                   : ((total[ts] == taken[ts] && !__any(active && cs == ts)) ? ts : -1);
-    if (!pdone && avail < kWave && fs >= 0) {
-      produce(fs);
-      continue;
-    }
-    if (avail == 0 && !__any(active)) {
-      if (pdone) break;
-      continue;
-    }
     // ---- refill: idle lanes take the next pairs, older slot first
     const unsigned long long idle = __ballot(!active);
-    if (idle != 0ull && avail > 0) {
+    const int remc = cur == 0 ? tot0 - tk0 : tot1 - tk1;
+    const int remn = cur == 0 ? tot1 - tk1 : tot0 - tk0;
+    if (idle != 0ull && remc + remn > 0) {
+      const int nidle = __popcll(idle);
       const int rank = __popcll(idle & lt_mask);
-      const int remh = total[hs] - taken[hs];
-      int take_s = -1, idx = 0;
+      int ts = -1;
+      uint32_t idx = 0;
       if (!active) {
-        if (rank < remh) {
-          take_s = hs;
-          idx = taken[hs] + rank;
-        } else if (rank - remh < total[ts] - taken[ts]) {
-          take_s = ts;
-          idx = taken[ts] + (rank - remh);
+        const int tkc = cur == 0 ? tk0 : tk1, tkn = cur == 0 ? tk1 : tk0;
+        if (rank < remc) {
+          ts = cur;
+          idx = static_cast<uint32_t>(tkc + rank);
+        } else if (rank - remc < remn) {
+          ts = cur ^ 1;
+          idx = static_cast<uint32_t>(tkn + (rank - remc));
         }
       }
-      const int nidle = __popcll(idle);
-      const int th_ = nidle < remh ? nidle : remh;
-      taken[hs] += th_;
-      const int rest = nidle - th_;
-      const int remt = total[ts] - taken[ts];
-      taken[ts] += rest < remt ? rest : remt;
-      if (take_s >= 0) {
-        const Slot& S = W.slot[take_s];
-        int q = 0;  // the pair's column: the last column whose first pair is at or before idx
-#pragma unroll
-        for (int step = kWave / 2; step > 0; step >>= 1)
-          if (S.pre[q + step] <= static_cast<uint32_t>(idx)) q += step;
-        const int k = static_cast<int>(S.k0[q]) + (idx - static_cast<int>(S.pre[q]));
-        const uint32_t ws = sl_ws[take_s];
-        const uint32_t rs = S.rstart[k];
-        const uint32_t pJ = S.J[q];
-        const uint32_t pj = pJ > ws ? pJ - ws : 0u;
-        const uint32_t s0 = rs > pj ? rs : pj;
-        e = S.rstart[k + 1];
-        dstart = azero ? 1.0 : S.da[s0];
-        const double num = S.cv[q] * dstart;
-        tab = make_skip_table(num / s_theta[q]);
-        cneg = ((sl_neg[take_s] >> q) & 1ull) != 0;
-        ctr3 = s_ctr3[q];
-        cu = sl_u[take_s];
-        s_abs = ws + s0;
-        pos = s0;
-        t = 0;
-        pc = q;
-        cs = take_s;
-        active = true;
+      const int gc = nidle < remc ? nidle : remc;
+      const int gn = (nidle - gc) < remn ? (nidle - gc) : remn;
+      if (cur == 0) {
+        tk0 += gc;
+        tk1 += gn;
+      } else {
+        tk1 += gc;
+        tk0 += gn;
+      }
+      if (ts >= 0) {
+        const Slot& S = W.slot[ts];
+        // pair idx = rank * R + run, column-major over the sampling columns
+        const uint32_t R = S.R;
+        uint32_t cr = __umulhi(idx, S.M);
+        uint32_t k = idx - cr * R;
+        if (k >= R) {
+          k -= R;
+          ++cr;
+        }
+        const uint32_t meta = S.meta[cr];
+        const uint32_t k0 = (meta >> 8) & 0xFFu;
+        if (k >= k0) {  // runs before k0 lie in the column's deterministic prefix
+          const int q = static_cast<int>(meta & 0xFFu);
+          const uint32_t jr = (meta >> 16) & 0x7Fu;
+          const uint32_t rs = S.rs[k];
+          const uint32_t s0 = rs > jr ? rs : jr;
+          e = S.rs[k + 1];
+          dstart = azero ? 1.0 : S.da[s0];
+          const double num = S.cv[cr] * dstart;
+          tab = make_skip_table(num / s_theta[q]);
+          cneg = (meta >> 31) != 0;
+          ctr3 = s_ctr3[q];
+          cu = S.u;
+          s_abs = S.ws + s0;
+          pos = s0;
+          t = 0;
+          pc = q;
+          cs = ts;
+          active = true;
+        }
       }
     }
     // ---- one draw of every active chain
     bool e_push = false;
     uint32_t vcand = 0;
     if (active) {
-      const U4 o = philox4x32_10(t, s_abs, cu, ctr3, D.key0, D.key1);
+      const U4 o = philox4x32_10_skey(t, s_abs, cu, ctr3, D.key0, D.key1);
       const double V = unit_double(o.x, o.y);
       const uint32_t cand = pos + static_cast<uint32_t>(geometric_skip(tab, V));
       if (cand < e) {
@@ -638,6 +640,19 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
             reinterpret_cast<unsigned long long*>(D.acc + static_cast<size_t>(vcand) * D.Ct + pc),
             static_cast<unsigned long long>(dt));
       }
+    }
+    // ---- the older slot is free once its pairs are handed out and their
+    // chains have ended: refill it with the next window (it becomes the newer)
+    const bool cur_done = (cur == 0 ? tk0 == tot0 : tk1 == tot1) && !__any(active && cs == cur);
+    if (cur_done) {
+      const bool nxt_done = (cur == 0 ? tk1 == tot1 : tk0 == tot0) && !__any(active && cs != cur);
+      if (pdone && nxt_done) break;
+      if (cur == 0)
+        tot0 = tk0 = 0;
+      else
+        tot1 = tk1 = 0;
+      if (!pdone) produce(cur);
+      cur ^= 1;
     }
   }
   if (binned) {

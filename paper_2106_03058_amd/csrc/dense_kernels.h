@@ -137,44 +137,37 @@ __device__ __forceinline__ void apply_group_record(const DenseArgs& D, int g, ui
 }
 
 // ------------------------------------------------------------ the level
-// Every wave runs a small producer / consumer loop.
-//  * The producer walks the wave's work items (runs of consecutive nodes, or
-//    pieces of one long row).  For a node with a non-zero residue it does the
-//    per-column work with one lane per column (residue, reserve, c = rho |r|
-//    d_u^-b, the deterministic prefix J), then takes the row 64 arcs (one
-//    window) at a time: the deterministic pushes of the window are made
-//    at once (lane = column), and the window's neighbour ids, degree
-//    factors, run boundaries (degree groups cut at the window) and the
-//    numbering of its (column, run) pairs -- every run after each column's
-//    deterministic prefix -- go to one of two LDS slots.
-//  * The consumer gives every idle lane the next pair of the older slot
-//    (then of the newer one); a lane builds its run's skip table and walks the
-//    run's Philox / geometric-skip chain one draw per iteration, reading
-//    candidates' neighbours from the slot.  A slot is refilled once all of its
-//    pairs have been taken and their chains have ended.
-// So lanes stay busy whether a node has one active column or 64, however
-// many degree groups its rows hold, and however long each chain runs.
-struct Slot {
-  uint32_t col[kWave];       // neighbour ids of the window's arcs
-  double da[kWave];          // their factors d^-a (1 when a = 0)
-  uint32_t rs[kWave + 1];    // run starts (window-relative); rs[R] = window length
-  uint32_t meta[kWave];      // per sampling column, by rank: column | k0 << 8 | jr << 16 | sign << 31,
-                             // k0 its first run, jr its deterministic prefix in the window
-  double cv[kWave];          // per sampling column, by rank: c = rho |r| d_u^-b
-  uint32_t R, M, u, ws;      // runs, ceil(2^32 / R), node, window start (row-relative)
-};
-
+// Per work item (a run of consecutive nodes, or a piece of one long row) the
+// wave first loads the row pointer, degree and d_u^-b of every node (one lane
+// per node).  Each node with a non-zero residue is then set up with one lane
+// per column (residue, reserve, c = rho |r| d_u^-b, the deterministic prefix
+// J) and its row is taken 64 arcs (one window) at a time: the window's
+// neighbour ids, degree factors and run boundaries (degree groups cut at the
+// window) go to LDS, and the (column, run) pairs of the window -- every run
+// after each column's deterministic prefix -- are numbered column by column
+// and handed out to the lanes: a lane builds the skip table of its pair's
+// run and walks the run's Philox / geometric-skip chain one draw per step,
+// reading candidates' neighbours from LDS, and takes the next pair of the
+// window as soon as its chain ends.  So lanes stay busy whether a node has
+// one active column or 64, however many degree groups its row holds and
+// however long each chain runs.  The next node's residues and first window
+// are loaded while the current node draws.
 struct WaveLds {
-  int64_t rp[kItemNodes];       // the current item's nodes: first arc
+  int64_t rp[kItemNodes];       // the item's nodes: first arc
   uint32_t d[kItemNodes];       //   degree
   double db[kItemNodes];        //   d_u^-b
-  Slot slot[2];
+  uint32_t col[kWave];          // the window's neighbour ids
+  double da[kWave];             //   their factors d^-a (1 when a = 0)
+  uint32_t rs[kWave + 1];       //   run starts (window-relative); rs[R] = window length
+  uint32_t meta[kWave];         // per sampling column, by rank: column | k0 << 8 | jr << 16 | sign << 31
+                                // (k0 its first run, jr its deterministic prefix in the window)
+  double cv[kWave];             // per sampling column, by rank: c = rho |r| d_u^-b
   int nst[kMaxGroups];          // records staged per group
   uint32_t stage[kStageRecs];   // staged records, kStageRecs / ng per group
 };
 
 template <bool kFirst>
-__global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
+__global__ __launch_bounds__(kThreads, 4) void k_dense_level(DenseArgs D) {
   __shared__ WaveLds s_w[kWaves];
   __shared__ unsigned int s_hist[kMaxGroups][kBuckets];
   __shared__ double s_theta[kMaxCols];
@@ -204,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
   if (lane < kMaxGroups) W.nst[lane] = 0;
   __syncthreads();
 
-  // the lane's column in the producer
+  // the lane's column during the per-node setup
   const int c = lane;
   const bool live = c < D.Ct;
   const int my_g = c >> D.gshift;
@@ -241,418 +234,329 @@ __global__ __launch_bounds__(kThreads) void k_dense_level(DenseArgs D) {
     if (lane == 0) W.nst[g] = 0;
     wave_sync();
   };
-
-  // ---- producer state (wave-uniform, except the per-column node values)
-  const long long nwaves = static_cast<long long>(gridDim.x) * kWaves;
-  long long item = static_cast<long long>(blockIdx.x) * kWaves + wave;
-  bool pdone = false;          // no node left
-  bool pnode = false;          // a node is being produced
-  unsigned long long todo = 0; // nodes of the current item still to visit
-  uint32_t u0 = 0, wlo = 0, whi = 0;
-  bool longrow = false;
-  uint32_t pu = 0, pd = 0, pw = 0, pw1 = 0, pJmax = 0;  // the node being produced
-  int64_t prp = 0;
-  bool nz = false, neg = false;  // per column
-  double cv = 0.0;
-  uint32_t J = 0;
-  // loads of the next node's residues (lane = column) and first window (lane = arc)
-  float r_n = 0.0f;
-  uint32_t col_n = 0, nd_n = 0;
-  uint32_t colw0 = 0, ndw0 = 0;  // the current node's first window
-  double pdaw0 = 1.0;
-  auto prefetch = [&](int bb) {
-    const uint32_t uu = u0 + static_cast<uint32_t>(bb);
-    r_n = 0.0f;
-    if (live) r_n = kFirst ? D.x[static_cast<size_t>(uu) * static_cast<size_t>(D.xld) + c]
-                           : D.r[static_cast<size_t>(uu) * static_cast<size_t>(D.Ct) + c];
-    col_n = 0;
-    nd_n = 1;
-    if (pushes) {
-      const uint32_t j = (wlo << kSegLog2) + static_cast<uint32_t>(lane);
-      if (j < W.d[bb]) {
-        const int64_t a = W.rp[bb] + j;
-        col_n = D.col[a];
-        nd_n = D.nd[a];
+  // a sampled push of -/+ fl(theta_ec) to (v, ec) for the lanes with e (all
+  // lanes together): a staged record, or an integer atomic without records
+  auto emit = [&](bool e, uint32_t v, int ec, bool neg) {
+    if (__ballot(e) == 0ull) return;
+    if (binned) {
+      if (e) {
+        const int eg = ec >> D.gshift;
+        const int ew = group_width(D.Ct, D.gshift, eg);
+        const uint32_t gcell = v * static_cast<uint32_t>(ew) + static_cast<uint32_t>(ec - (eg << D.gshift));
+        atomicAdd(&s_hist[eg][gcell >> D.bucket_shift], 1u);
+        const int slot = atomicAdd(&W.nst[eg], 1);
+        W.stage[eg * per + slot] = gcell | (neg ? 0x80000000u : 0u);
       }
+      wave_sync();
+      for (int g = 0; g < ng; ++g)
+        if (W.nst[g] > per - kWave) flush(g);
+    } else if (e) {
+      const long long dt = neg ? -s_dth[ec] : s_dth[ec];
+      lvl::atomic_add_relaxed(reinterpret_cast<unsigned long long*>(D.acc + static_cast<size_t>(v) * D.Ct + ec),
+                              static_cast<unsigned long long>(dt));
     }
   };
-  // ---- slots: pairs handed out and pairs of each slot (wave-uniform)
-  int tot0 = 0, tot1 = 0, tk0 = 0, tk1 = 0;
-  // ---- consumer state (per lane)
-  bool active = false;
-  int cs = 0;  // the lane's slot
-  int pc = 0;  // the lane's column
-  uint32_t cu = 0, s_abs = 0, pos = 0, e = 0, t = 0, ctr3 = 0;
-  bool cneg = false;
-  double dstart = 1.0;
-  SkipTable tab;
 
-  // Produce one window into the free slot fs (or finish the producer);
-  // returns true if the slot received pairs.
-  auto produce = [&](int fs) -> bool {
-    for (;;) {
-      if (!pnode) {
-        // next node with a non-zero residue
-        while (todo == 0ull) {
-          if (item >= D.nitems) {
-            pdone = true;
-            return false;
-          }
-          const uint64_t it = D.items[item];
-          item += nwaves;
-          longrow = (it & kItemLong) != 0;
-          u0 = static_cast<uint32_t>(it);
-          int nodes;
-          wlo = 0;
-          whi = 0xFFFFFFFFu;
-          if (longrow) {
-            nodes = 1;
-            wlo = static_cast<uint32_t>((it >> 32) & 0xFFFFFull);
-            whi = wlo + static_cast<uint32_t>((it >> 52) & 0x7Full);
-          } else {
-            nodes = static_cast<int>((it >> 32) & 0xFFull);
-          }
-          bool f = false;
-          wave_sync();  // the previous item's node table has been read
-          if (lane < nodes) {
-            const uint32_t uu = u0 + static_cast<uint32_t>(lane);
-            f = kFirst || D.flag_in[uu] != 0;
-            if (f) {
-              W.rp[lane] = D.rp[uu];
-              W.d[lane] = static_cast<uint32_t>(D.deg[uu]);
-              W.db[lane] = pushes ? D.db[D.fdeg[uu]] : 0.0;
-            }
-          }
-          todo = __ballot(f);
-          wave_sync();
-          if (todo) prefetch(__ffsll(static_cast<long long>(todo)) - 1);
+  const long long nwaves = static_cast<long long>(gridDim.x) * kWaves;
+  for (long long item = static_cast<long long>(blockIdx.x) * kWaves + wave; item < D.nitems; item += nwaves) {
+    const uint64_t it = D.items[item];
+    const bool longrow = (it & kItemLong) != 0;
+    const uint32_t u0 = static_cast<uint32_t>(it);
+    int nodes;
+    uint32_t wlo = 0, whi = 0xFFFFFFFFu;
+    if (longrow) {
+      nodes = 1;
+      wlo = static_cast<uint32_t>((it >> 32) & 0xFFFFFull);
+      whi = wlo + static_cast<uint32_t>((it >> 52) & 0x7Full);
+    } else {
+      nodes = static_cast<int>((it >> 32) & 0xFFull);
+    }
+    // the item's nodes (lane = node)
+    bool f = false;
+    if (lane < nodes) {
+      const uint32_t uu = u0 + static_cast<uint32_t>(lane);
+      f = kFirst || D.flag_in[uu] != 0;
+      if (f) {
+        W.rp[lane] = D.rp[uu];
+        W.d[lane] = static_cast<uint32_t>(D.deg[uu]);
+        W.db[lane] = pushes ? D.db[D.fdeg[uu]] : 0.0;
+      }
+    }
+    unsigned long long todo = __ballot(f);
+    wave_sync();
+    // the first piece of a long row owns the row's per-node work (reserve,
+    // frontier counters, mass); the row's residues are cleared after the
+    // level (every piece reads them)
+    const bool owner = !longrow || wlo == 0;
+    const uint32_t ws0 = wlo << kSegLog2;
+    // loads of a node's residues (lane = column) and first window (lane = arc)
+    float r_n = 0.0f;
+    uint32_t col_n = 0, nd_n = 0;
+    auto prefetch = [&](int bb) {
+      const uint32_t uu = u0 + static_cast<uint32_t>(bb);
+      r_n = 0.0f;
+      if (live) r_n = kFirst ? D.x[static_cast<size_t>(uu) * static_cast<size_t>(D.xld) + c]
+                             : D.r[static_cast<size_t>(uu) * static_cast<size_t>(D.Ct) + c];
+      col_n = nd_n = 0;
+      if (pushes) {
+        const uint32_t j = ws0 + static_cast<uint32_t>(lane);
+        if (j < W.d[bb]) {
+          const int64_t a = W.rp[bb] + j;
+          col_n = D.col[a];
+          nd_n = D.nd[a];
         }
-        const int b = __ffsll(static_cast<long long>(todo)) - 1;
-        todo &= todo - 1ull;
-        pu = u0 + static_cast<uint32_t>(b);
-        pd = W.d[b];
-        prp = W.rp[b];
-        const double dbv = W.db[b];
-        const float r = r_n;
-        colw0 = col_n;
-        ndw0 = nd_n;
-        // the first window's factors before the next node's loads are issued
-        const bool valid0 = (wlo << kSegLog2) + static_cast<uint32_t>(lane) < pd;
-        double daw0 = 1.0;
-        if (pushes && !azero && valid0) daw0 = D.da[ndw0];
-        const bool owner = !longrow || wlo == 0;
-        float* o = D.out + static_cast<size_t>(pu) * static_cast<size_t>(D.old) + c;
-        float o_old = 0.0f;
-        if (!kFirst && owner && live && r != 0.0f && D.kappa != 0.0) o_old = *o;
-        if (todo) prefetch(__ffsll(static_cast<long long>(todo)) - 1);
-        // the first piece of a long row owns the row's per-node work
-        // (reserve, frontier counters, mass); the row's residues are cleared
-        // after the level (every piece reads them)
-        const size_t ucell = static_cast<size_t>(pu) * static_cast<size_t>(D.Ct) + c;
-        nz = live && r != 0.0f;
-        if (!kFirst && !longrow && nz) D.r[ucell] = 0.0f;
-        if (owner) {
-          // frontier counters: (node, column) pairs with a non-zero residue
-          // and their hash, counted once per node (lane 0)
-          const unsigned long long nzm = __ballot(nz);
-          if (lane == 0 && nzm) {
-            const unsigned long long k = static_cast<unsigned long long>(__popcll(nzm));
-            n_front += k;
-            n_hash += k * splitmix64(pu);
-          }
-          if (kFirst) {  // pi starts at +0: pi = +0 + fl(kappa r)
-            if (live) *o = nz ? 0.0f + static_cast<float>(D.kappa * static_cast<double>(r)) : 0.0f;
-          } else if (nz && D.kappa != 0.0) {
-            *o = o_old + static_cast<float>(D.kappa * static_cast<double>(r));
-          }
+      }
+    };
+    if (todo) prefetch(__ffsll(static_cast<long long>(todo)) - 1);
+    while (todo) {
+      const int b = __ffsll(static_cast<long long>(todo)) - 1;
+      todo &= todo - 1ull;
+      const uint32_t u = u0 + static_cast<uint32_t>(b);
+      const float r = r_n;
+      const uint32_t colw0 = col_n, ndw0 = nd_n;
+      const uint32_t d = W.d[b];
+      const int64_t rp = W.rp[b];
+      const bool nz = live && r != 0.0f;
+      // dependent loads of this node before the next node's prefetch
+      const bool valid0 = ws0 + static_cast<uint32_t>(lane) < d;
+      double daw0 = 1.0;
+      if (pushes && !azero && valid0) daw0 = D.da[ndw0];
+      float* o = D.out + static_cast<size_t>(u) * static_cast<size_t>(D.old) + c;
+      float o_old = 0.0f;
+      if (!kFirst && owner && nz && D.kappa != 0.0) o_old = *o;
+      if (todo) prefetch(__ffsll(static_cast<long long>(todo)) - 1);
+      // ---- per-column setup (lane = column)
+      if (!kFirst && !longrow && nz) D.r[static_cast<size_t>(u) * static_cast<size_t>(D.Ct) + c] = 0.0f;
+      if (owner) {
+        // frontier counters: (node, column) pairs with a non-zero residue and
+        // their hash, counted once per node (lane 0)
+        const unsigned long long nzm = __ballot(nz);
+        if (lane == 0 && nzm) {
+          const unsigned long long kk = static_cast<unsigned long long>(__popcll(nzm));
+          n_front += kk;
+          n_hash += kk * splitmix64(u);
         }
-        pdaw0 = daw0;
-        if (!pushes || pd == 0 || !__any(nz)) continue;
-        neg = r < 0.0f;
-        // c = (rho |r|) d_u^-b and the deterministic prefix J (increment >= theta)
-        const double absr = fabs(static_cast<double>(r));
-        const double t0 = D.rho * absr;
-        cv = t0 * dbv;
-        J = 0;
-        double inc0 = cv;
-        if (azero) {
-          J = (nz && cv >= th) ? pd : 0u;
-        } else {
-          // the increments fall along the degree-sorted row; a row of at most
-          // 64 arcs is in registers (its first window)
-          const bool inreg = wlo == 0 && pd <= static_cast<uint32_t>(kWave);
-          const double da_first = wlo == 0 ? shfl_f64(daw0, 0) : D.da[D.nd[prp]];
-          inc0 = cv * da_first;
-          const double da_last = inreg ? shfl_f64(daw0, static_cast<int>(pd - 1)) : D.da[D.nd[prp + pd - 1]];
-          uint32_t lo = 0, hi = pd;
-          if (!nz || !(inc0 >= th))
-            hi = 0;
-          else if (cv * da_last >= th)
-            lo = pd;
-          if (__any(lo < hi)) {
-            if (inreg) {
-              for (int step = 0; step < 7; ++step) {
-                const uint32_t mid = (lo + hi) >> 1;
-                const double dm = shfl_f64(daw0, static_cast<int>(mid < pd ? mid : 0u));
-                if (lo < hi) {
-                  if (cv * dm >= th)
-                    lo = mid + 1;
-                  else
-                    hi = mid;
-                }
-              }
-            } else {
-              while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (cv * D.da[D.nd[prp + mid]] >= th)
+        if (kFirst) {  // pi starts at +0: pi = +0 + fl(kappa r)
+          if (live) *o = nz ? 0.0f + static_cast<float>(D.kappa * static_cast<double>(r)) : 0.0f;
+        } else if (nz && D.kappa != 0.0) {
+          *o = o_old + static_cast<float>(D.kappa * static_cast<double>(r));
+        }
+      }
+      if (!pushes || d == 0 || !__any(nz)) continue;
+      const bool neg = r < 0.0f;
+      // c = (rho |r|) d_u^-b and the deterministic prefix J (increment >= theta):
+      // the increments fall along the degree-sorted row
+      const double absr = fabs(static_cast<double>(r));
+      const double t0 = D.rho * absr;
+      const double cv = t0 * W.db[b];
+      uint32_t J = 0;
+      double inc0 = cv;
+      const bool onewin = d - ws0 <= static_cast<uint32_t>(kWave);  // the piece's first window ends the row
+      if (azero) {
+        J = (nz && cv >= th) ? d : 0u;
+      } else {
+        const double da_first = wlo == 0 ? shfl_f64(daw0, 0) : D.da[D.nd[rp]];
+        inc0 = cv * da_first;
+        double da_last;
+        if (wlo == 0 && onewin)
+          da_last = shfl_f64(daw0, static_cast<int>(d - 1));
+        else
+          da_last = D.da[D.nd[rp + d - 1]];
+        uint32_t lo = 0, hi = d;
+        if (!nz || !(inc0 >= th))
+          hi = 0;
+        else if (cv * da_last >= th)
+          lo = d;
+        if (__any(lo < hi)) {
+          if (wlo == 0 && onewin) {  // the row is in registers: search by lane exchanges
+            for (int step = 0; step < 7; ++step) {
+              const uint32_t mid = (lo + hi) >> 1;
+              const double dm = shfl_f64(daw0, static_cast<int>(mid < d ? mid : 0u));
+              if (lo < hi) {
+                if (cv * dm >= th)
                   lo = mid + 1;
                 else
                   hi = mid;
               }
             }
-          }
-          J = lo;
-        }
-        if (nz && owner) {
-          const float big = static_cast<float>(inc0 > th ? inc0 : th);
-          mass += static_cast<double>(pd) * (fabs(static_cast<double>(big)) * scale);
-        }
-        const uint32_t nwin = ((pd - 1) >> kSegLog2) + 1;
-        pw = wlo;
-        pw1 = whi < nwin ? whi : nwin;
-        if (nz) {  // deterministic pushes of this piece: positions [jlo, min(J, jhi))
-          const uint32_t jlo = wlo << kSegLog2, jhi = (pw1 << kSegLog2) < pd ? (pw1 << kSegLog2) : pd;
-          n_det += (J > jlo ? (J < jhi ? J : jhi) - jlo : 0u);
-        }
-        pJmax = wave_max_u32(nz ? J : 0u);
-        pnode = true;
-      }
-      // ---- window pw of the node being produced
-      const uint32_t ws = pw << kSegLog2;
-      const uint32_t we = (ws + kSeg) < pd ? ws + kSeg : pd;
-      ++pw;
-      if (pw >= pw1) pnode = false;
-      const bool has = nz && J < we;  // the column samples in this window
-      const bool need_samp = __any(has);
-      const bool need_det = pJmax > ws;
-      if (!need_samp && !need_det) continue;
-      const bool valid = ws + static_cast<uint32_t>(lane) < we;
-      uint32_t colw = 0u, ndw = 1u;
-      double daw = 1.0;
-      if (ws == (wlo << kSegLog2)) {  // the prefetched first window
-        if (valid) {
-          colw = colw0;
-          ndw = ndw0;
-          daw = pdaw0;
-        }
-      } else if (valid) {
-        const int64_t a = prp + ws + static_cast<uint32_t>(lane);
-        colw = D.col[a];
-        if (!azero) {
-          ndw = D.nd[a];
-          daw = D.da[ndw];
-        }
-      }
-      // deterministic pushes at positions [ws, min(Jmax, we)) (lane = column)
-      if (need_det) {
-        const uint32_t jd = pJmax < we ? pJmax : we;
-        for (uint32_t q = ws; q < jd; ++q) {
-          const int src = static_cast<int>(q - ws);
-          const uint32_t v = static_cast<uint32_t>(__shfl(static_cast<int>(colw), src));
-          const double dav = azero ? 1.0 : shfl_f64(daw, src);
-          if (nz && q < J) {
-            double inc = cv;
-            if (!azero) inc = inc * dav;
-            float val = static_cast<float>(inc);
-            if (neg) val = -val;
-            long long units;
-            if (f32_to_units(val, scale, &units)) {
-              lvl::atomic_add_relaxed(
-                  reinterpret_cast<unsigned long long*>(D.acc + static_cast<size_t>(v) * D.Ct + c),
-                  static_cast<unsigned long long>(units));
-              if (D.det_bins) {
-                const uint32_t gcell = v * static_cast<uint32_t>(my_w) + static_cast<uint32_t>(my_cl);
-                D.det_bins[static_cast<size_t>(my_g) * D.nbins_g + (gcell >> kBinLog2)] = 1;
-              }
-            } else {
-              atomicOr(D.err, 1);
+          } else {
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi) >> 1;
+              if (cv * D.da[D.nd[rp + mid]] >= th)
+                lo = mid + 1;
+              else
+                hi = mid;
             }
           }
         }
+        J = lo;
       }
-      if (!need_samp) continue;
-      // runs: the window start and every change of degree group (a > 0)
-      unsigned long long runs;
-      if (azero) {
-        runs = 1ull;
-      } else {
-        const int gw = 31 - __clz(ndw);
-        const int gprev = __shfl(gw, lane > 0 ? lane - 1 : 0);
-        runs = __ballot(valid && (lane == 0 || gw != gprev));
+      if (nz && owner) {
+        const float big = static_cast<float>(inc0 > th ? inc0 : th);
+        mass += static_cast<double>(d) * (fabs(static_cast<double>(big)) * scale);
       }
-      const int R = __popcll(runs);
-      // per column: its first run (runs ending at or before its prefix are
-      // deterministic) and its number of (column, run) pairs
-      const uint32_t jr = J > ws ? J - ws : 0u;
-      int k0 = 0;
-      if (has) {
-        const unsigned long long upto = jr >= 63u ? ~0ull : ((2ull << jr) - 1ull);
-        k0 = __popcll(runs & upto & ~1ull);
+      const uint32_t nwin = ((d - 1) >> kSegLog2) + 1;
+      const uint32_t w1 = whi < nwin ? whi : nwin;
+      if (nz) {  // deterministic pushes of this piece: positions [jlo, min(J, jhi))
+        const uint32_t jlo = ws0, jhi = (w1 << kSegLog2) < d ? (w1 << kSegLog2) : d;
+        n_det += (J > jlo ? (J < jhi ? J : jhi) - jlo : 0u);
       }
-      const unsigned long long hasm = __ballot(has);
-      const int m = __popcll(hasm);
-      Slot& S = W.slot[fs];
-      S.col[lane] = colw;
-      S.da[lane] = daw;
-      if ((runs >> lane) & 1ull) S.rs[__popcll(runs & lt_mask)] = static_cast<uint32_t>(lane);
-      if (has) {
-        const int rk = __popcll(hasm & lt_mask);
-        S.meta[rk] = static_cast<uint32_t>(c) | (static_cast<uint32_t>(k0) << 8) | (jr << 16) | (neg ? 0x80000000u : 0u);
-        S.cv[rk] = cv;
-      }
-      if (lane == 0) {
-        S.rs[R] = we - ws;
-        S.R = static_cast<uint32_t>(R);
-        S.M = s_magic[R];
-        S.u = pu;
-        S.ws = ws;
-      }
-      if (fs == 0) {
-        tot0 = m * R;
-        tk0 = 0;
-      } else {
-        tot1 = m * R;
-        tk1 = 0;
-      }
-      wave_sync();
-      return true;
-    }
-  };
-
-  int cur = 0;  // the older slot; both start empty and are filled by the retire step below
-  for (;;) {
-    // ---- refill: idle lanes take the next pairs, older slot first
-    const unsigned long long idle = __ballot(!active);
-    const int remc = cur == 0 ? tot0 - tk0 : tot1 - tk1;
-    const int remn = cur == 0 ? tot1 - tk1 : tot0 - tk0;
-    if (idle != 0ull && remc + remn > 0) {
-      const int nidle = __popcll(idle);
-      const int rank = __popcll(idle & lt_mask);
-      int ts = -1;
-      uint32_t idx = 0;
-      if (!active) {
-        const int tkc = cur == 0 ? tk0 : tk1, tkn = cur == 0 ? tk1 : tk0;
-        if (rank < remc) {
-          ts = cur;
-          idx = static_cast<uint32_t>(tkc + rank);
-        } else if (rank - remc < remn) {
-          ts = cur ^ 1;
-          idx = static_cast<uint32_t>(tkn + (rank - remc));
+      const uint32_t Jmax = wave_max_u32(nz ? J : 0u);
+      for (uint32_t w = wlo; w < w1; ++w) {
+        const uint32_t ws = w << kSegLog2;
+        const uint32_t we = (ws + kSeg) < d ? ws + kSeg : d;
+        const bool has = nz && J < we;  // the column samples in this window
+        const bool need_samp = __any(has);
+        const bool need_det = Jmax > ws;
+        if (!need_samp && !need_det) continue;
+        // ---- the window's arcs (lane = arc)
+        const bool valid = ws + static_cast<uint32_t>(lane) < we;
+        uint32_t colw = colw0;
+        double daw = daw0;
+        if (w != wlo) {
+          colw = 0u;
+          daw = 1.0;
+          if (valid) {
+            const int64_t a = rp + ws + static_cast<uint32_t>(lane);
+            colw = D.col[a];
+            if (!azero) daw = D.da[D.nd[a]];
+          }
         }
-      }
-      const int gc = nidle < remc ? nidle : remc;
-      const int gn = (nidle - gc) < remn ? (nidle - gc) : remn;
-      if (cur == 0) {
-        tk0 += gc;
-        tk1 += gn;
-      } else {
-        tk1 += gc;
-        tk0 += gn;
-      }
-      if (ts >= 0) {
-        const Slot& S = W.slot[ts];
-        // pair idx = rank * R + run, column-major over the sampling columns
-        const uint32_t R = S.R;
-        uint32_t cr = __umulhi(idx, S.M);
-        uint32_t k = idx - cr * R;
-        if (k >= R) {
-          k -= R;
-          ++cr;
+        // deterministic pushes at positions [ws, min(Jmax, we)) (lane = column)
+        if (need_det) {
+          const uint32_t jd = Jmax < we ? Jmax : we;
+          for (uint32_t q = ws; q < jd; ++q) {
+            const int src = static_cast<int>(q - ws);
+            const uint32_t v = static_cast<uint32_t>(__shfl(static_cast<int>(colw), src));
+            const double dav = azero ? 1.0 : shfl_f64(daw, src);
+            if (nz && q < J) {
+              double inc = cv;
+              if (!azero) inc = inc * dav;
+              float val = static_cast<float>(inc);
+              if (neg) val = -val;
+              long long units;
+              if (f32_to_units(val, scale, &units)) {
+                lvl::atomic_add_relaxed(
+                    reinterpret_cast<unsigned long long*>(D.acc + static_cast<size_t>(v) * D.Ct + c),
+                    static_cast<unsigned long long>(units));
+                if (D.det_bins) {
+                  const uint32_t gcell = v * static_cast<uint32_t>(my_w) + static_cast<uint32_t>(my_cl);
+                  D.det_bins[static_cast<size_t>(my_g) * D.nbins_g + (gcell >> kBinLog2)] = 1;
+                }
+              } else {
+                atomicOr(D.err, 1);
+              }
+            }
+          }
         }
-        const uint32_t meta = S.meta[cr];
-        const uint32_t k0 = (meta >> 8) & 0xFFu;
-        if (k >= k0) {  // runs before k0 lie in the column's deterministic prefix
-          const int q = static_cast<int>(meta & 0xFFu);
-          const uint32_t jr = (meta >> 16) & 0x7Fu;
-          const uint32_t rs = S.rs[k];
-          const uint32_t s0 = rs > jr ? rs : jr;
-          e = S.rs[k + 1];
-          dstart = azero ? 1.0 : S.da[s0];
-          const double num = S.cv[cr] * dstart;
-          tab = make_skip_table(num / s_theta[q]);
-          cneg = (meta >> 31) != 0;
-          ctr3 = s_ctr3[q];
-          cu = S.u;
-          s_abs = S.ws + s0;
-          pos = s0;
-          t = 0;
-          pc = q;
-          cs = ts;
-          active = true;
+        if (!need_samp) continue;
+        // runs: the window start and every change of degree group (a > 0);
+        // floor(log2) of d^-a's degree is read back from the factor's bits
+        unsigned long long runs;
+        if (azero) {
+          runs = 1ull;
+        } else {
+          const uint32_t ndv = valid ? (w == wlo ? ndw0 : D.nd[rp + ws + static_cast<uint32_t>(lane)]) : 1u;
+          const int gw = 31 - __clz(ndv);
+          const int gprev = __shfl(gw, lane > 0 ? lane - 1 : 0);
+          runs = __ballot(valid && (lane == 0 || gw != gprev));
         }
-      }
-    }
-    // ---- one draw of every active chain
-    bool e_push = false;
-    uint32_t vcand = 0;
-    if (active) {
-      const U4 o = philox4x32_10_skey(t, s_abs, cu, ctr3, D.key0, D.key1);
-      const double V = unit_double(o.x, o.y);
-      const uint32_t cand = pos + static_cast<uint32_t>(geometric_skip(tab, V));
-      if (cand < e) {
-        ++n_cand;
-        const Slot& S = W.slot[cs];
-        bool accept = true;
-        if (!azero) {
-          const double ratio = S.da[cand] / dstart;
-          accept = unit_double(o.z, o.w) < ratio;
+        const int R = __popcll(runs);
+        // per sampling column: its first run (runs ending at or before its
+        // prefix are deterministic) and its prefix inside the window
+        const uint32_t jr = J > ws ? J - ws : 0u;
+        int k0 = 0;
+        if (has) {
+          const unsigned long long upto = jr >= 63u ? ~0ull : ((2ull << jr) - 1ull);
+          k0 = __popcll(runs & upto & ~1ull);
         }
-        if (accept) {
-          ++n_acc;
-          e_push = true;
-          vcand = S.col[cand];
-        }
-        pos = cand + 1;
-        ++t;
-      } else {
-        active = false;
-      }
-    }
-    // a sampled push of -/+ fl(theta_pc) to (vcand, pc): a staged record, or
-    // an integer atomic without records
-    if (__ballot(e_push) != 0ull) {
-      if (binned) {
-        if (e_push) {
-          const int eg = pc >> D.gshift;
-          const int ew = group_width(D.Ct, D.gshift, eg);
-          const uint32_t gcell =
-              vcand * static_cast<uint32_t>(ew) + static_cast<uint32_t>(pc - (eg << D.gshift));
-          atomicAdd(&s_hist[eg][gcell >> D.bucket_shift], 1u);
-          const int slot = atomicAdd(&W.nst[eg], 1);
-          W.stage[eg * per + slot] = gcell | (cneg ? 0x80000000u : 0u);
+        const unsigned long long hasm = __ballot(has);
+        const uint32_t total = static_cast<uint32_t>(__popcll(hasm) * R);
+        const uint32_t magic = s_magic[R];
+        wave_sync();  // the previous window's pairs have been read
+        W.col[lane] = colw;
+        W.da[lane] = daw;
+        if ((runs >> lane) & 1ull) W.rs[__popcll(runs & lt_mask)] = static_cast<uint32_t>(lane);
+        if (lane == 0) W.rs[R] = we - ws;
+        if (has) {
+          const int rk = __popcll(hasm & lt_mask);
+          W.meta[rk] = static_cast<uint32_t>(c) | (static_cast<uint32_t>(k0) << 8) | (jr << 16) |
+                       (neg ? 0x80000000u : 0u);
+          W.cv[rk] = cv;
         }
         wave_sync();
-        for (int g = 0; g < ng; ++g)
-          if (W.nst[g] > per - kWave) flush(g);
-      } else if (e_push) {
-        const long long dt = cneg ? -s_dth[pc] : s_dth[pc];
-        lvl::atomic_add_relaxed(
-            reinterpret_cast<unsigned long long*>(D.acc + static_cast<size_t>(vcand) * D.Ct + pc),
-            static_cast<unsigned long long>(dt));
+        // ---- the window's (column, run) pairs: pair idx = rank * R + run; a
+        // lane takes the next pair as soon as its chain has ended (lane = pair)
+        uint32_t next = 0;
+        bool active = false;
+        int pc = 0;
+        bool pneg = false;
+        uint32_t ctr3 = 0, s_abs = 0, pos = 0, e = 0, t = 0;
+        double dstart = 1.0;
+        SkipTable tab;
+        for (;;) {
+          const unsigned long long idle = __ballot(!active);
+          if (idle != 0ull && next < total) {
+            const uint32_t idx = next + static_cast<uint32_t>(__popcll(idle & lt_mask));
+            next += static_cast<uint32_t>(__popcll(idle));
+            if (!active && idx < total) {
+              uint32_t cr = __umulhi(idx, magic);
+              uint32_t k = idx - cr * static_cast<uint32_t>(R);
+              if (k >= static_cast<uint32_t>(R)) {
+                k -= static_cast<uint32_t>(R);
+                ++cr;
+              }
+              const uint32_t meta = W.meta[cr];
+              if (k >= ((meta >> 8) & 0xFFu)) {  // runs before k0 lie in the deterministic prefix
+                const int q = static_cast<int>(meta & 0xFFu);
+                const uint32_t pjr = (meta >> 16) & 0x7Fu;
+                const uint32_t rs0 = W.rs[k];
+                const uint32_t s0 = rs0 > pjr ? rs0 : pjr;
+                e = W.rs[k + 1];
+                dstart = azero ? 1.0 : W.da[s0];
+                const double num = W.cv[cr] * dstart;
+                tab = make_skip_table(num / s_theta[q]);
+                pneg = (meta >> 31) != 0;
+                ctr3 = s_ctr3[q];
+                s_abs = ws + s0;
+                pos = s0;
+                t = 0;
+                pc = q;
+                active = true;
+              }
+            }
+          }
+          if (!__any(active)) {
+            if (next >= total) break;
+            continue;
+          }
+          bool e_push = false;
+          uint32_t vcand = 0;
+          if (active) {
+            const U4 o = philox4x32_10_skey(t, s_abs, u, ctr3, D.key0, D.key1);
+            const double V = unit_double(o.x, o.y);
+            const uint32_t cand = pos + static_cast<uint32_t>(geometric_skip(tab, V));
+            if (cand < e) {
+              ++n_cand;
+              bool accept = true;
+              if (!azero) {
+                const double ratio = W.da[cand] / dstart;
+                accept = unit_double(o.z, o.w) < ratio;
+              }
+              if (accept) {
+                ++n_acc;
+                e_push = true;
+                vcand = W.col[cand];
+              }
+              pos = cand + 1;
+              ++t;
+            } else {
+              active = false;
+            }
+          }
+          emit(e_push, vcand, pc, pneg);
+        }
       }
-    }
-    // ---- the older slot is free once its pairs are handed out and their
-    // chains have ended: refill it with the next window (it becomes the newer)
-    const bool cur_done = (cur == 0 ? tk0 == tot0 : tk1 == tot1) && !__any(active && cs == cur);
-    if (cur_done) {
-      const bool nxt_done = (cur == 0 ? tk1 == tot1 : tk0 == tot0) && !__any(active && cs != cur);
-      if (pdone && nxt_done) break;
-      if (cur == 0)
-        tot0 = tk0 = 0;
-      else
-        tot1 = tk1 = 0;
-      if (!pdone) produce(cur);
-      cur ^= 1;
     }
   }
   if (binned) {

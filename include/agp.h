@@ -69,6 +69,10 @@ typedef struct agp_graph agp_graph_t;
  *  det[i]       deterministic pushes made at level i           (i < L)
  *  cand[i]      sampled candidate positions drawn at level i    (i < L)
  *  acc[i]       accepted sampled pushes at level i              (i < L)
+ *  runs[i]      sampling runs at level i (a run is a range of one degree
+ *               group inside a 64-position window of a sampled suffix; each
+ *               starts one geometric-skip chain, so the random draws of the
+ *               level number runs[i] + cand[i])                  (i < L)
  * An edge push is det + acc. */
 typedef struct agp_stats {
   int32_t levels;  /* L of the call */
@@ -78,6 +82,7 @@ typedef struct agp_stats {
   uint64_t det[AGP_MAX_LEVELS + 1];
   uint64_t cand[AGP_MAX_LEVELS + 1];
   uint64_t acc[AGP_MAX_LEVELS + 1];
+  uint64_t runs[AGP_MAX_LEVELS + 1];
   double device_ms; /* from the first level kernel's start to the last one's end */
   /* HIP-event time of the level kernel launched for level i and of the
    * launches that make its deferred pushes (ms) */

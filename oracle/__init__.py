@@ -58,7 +58,7 @@ def lib():
         L.orc_exact_sum.restype = ct.c_double
         L.orc_propagate_many.argtypes = [ct.c_int64, i64p, i32p, i32p, ct.c_double, ct.c_double,
                                          dp, ct.c_int32, ct.c_int32, dp, ct.c_int32, ct.c_double, ct.c_uint64,
-                                         u32p, ct.c_int32, dp, u64p, ct.c_int32]
+                                         u32p, ct.c_int32, dp, u64p, ct.c_int32, ct.c_int32]
         _lib = L
     return _lib
 
@@ -153,7 +153,7 @@ def exact_sum(vals, wp: int) -> float:
     return lib().orc_exact_sum(_p(v, ct.c_double), v.size, wp)
 
 
-COUNTER_NAMES = ("frontier", "hash", "det", "cand", "acc")
+COUNTER_NAMES = ("frontier", "hash", "det", "cand", "acc", "runs")
 
 
 SPLIT_QID_BIT = 1 << 23
@@ -161,7 +161,7 @@ SPLIT_QID_BIT = 1 << 23
 
 def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, *,
               wp: int = 32, qids=None, threads: int | None = None, tail: bool = False,
-              split_signs: bool = False):
+              split_signs: bool = False, stop_level: int = -1):
     """Run Algorithm 2 on every column of x (n x C, or a length-n vector).
 
     Returns (out, counters): out has the shape of x (float64 values that are
@@ -170,6 +170,10 @@ def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, 
 
     tail: the paper-literal Y_i = 1 - sum_{k<i} w_k (weights summing to at
     most 1, no rescaling), see orc_level_tables.
+
+    stop_level: stop after that level (a bounded timing sample: the output
+    then holds the reserves of the levels done, the counters of those
+    levels are complete).
 
     split_signs: the literal treatment of signed signals (Section 3,
     assumption on the graph signal): x+ (the positive entries) and x- (the
@@ -203,7 +207,7 @@ def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, 
     C = X.shape[1]
     xc = np.ascontiguousarray(X.T, dtype=np.float64)  # column-major
     out = np.empty_like(xc)
-    cnt = np.zeros((C, 5, L + 1), dtype=np.uint64)
+    cnt = np.zeros((C, len(COUNTER_NAMES), L + 1), dtype=np.uint64)
     q = None if qids is None else np.ascontiguousarray(qids, dtype=np.uint32)
     if threads is None:
         threads = min(C, os.cpu_count() or 1)
@@ -211,7 +215,7 @@ def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, 
         sg.n, _p(sg.row_ptr, ct.c_int64), _p(sg.col, ct.c_int32), _p(sg.fdeg, ct.c_int32),
         float(a), float(b), _p(w, ct.c_double), L, int(bool(tail)), _p(xc, ct.c_double), C, float(eps),
         ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), None if q is None else _p(q, ct.c_uint32), wp,
-        _p(out, ct.c_double), _p(cnt, ct.c_uint64), max(1, int(threads)))
+        _p(out, ct.c_double), _p(cnt, ct.c_uint64), max(1, int(threads)), int(stop_level))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     res = out.T

@@ -345,6 +345,12 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                   const int32_t* deg, double a, double b, const double* w,
                   int32_t L, int32_t tail, const double* x, double eps, uint64_t seed,
                   uint32_t qid, int32_t wp, double* out, orc_counters* cnt) {
+  return orc_propagate_levels(n, rp, col_sorted, deg, a, b, w, L, tail, x, eps, seed, qid, wp, out, cnt, -1);
+}
+
+int orc_propagate_levels(int64_t n, const int64_t* rp, const int32_t* col_sorted, const int32_t* deg, double a,
+                         double b, const double* w, int32_t L, int32_t tail, const double* x, double eps,
+                         uint64_t seed, uint32_t qid, int32_t wp, double* out, orc_counters* cnt, int32_t stop) {
   if (n < 0 || L < 0 || L > 255 || !(a >= 0.0 && a <= 1.0) || !(b >= 0.0 && b <= 1.0) ||
       !(eps >= 0.0) || (wp != 32 && wp != 64))
     return -1;
@@ -389,7 +395,7 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
   }
 
   for (int32_t i = 0; i <= L; ++i) {
-    uint64_t nf = 0, hs = 0, ndet = 0, ncand = 0, nacc = 0;
+    uint64_t nf = 0, hs = 0, ndet = 0, ncand = 0, nacc = 0, nruns = 0;
     int64_t ntouched = 0;
     for (int64_t u = 0; u < n; ++u) { /* each u with non-zero residue */
       double ru = r[u];
@@ -424,6 +430,7 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
         while (e < du && (e % seg) != 0 &&
                (a == 0.0 || group_of(deg[nb[e]]) == group_of(deg[nb[s]])))
           ++e;
+        ++nruns;
         const double dstart = da[deg[nb[s]]];
         const double pstar = (c * dstart) / theta;
         int64_t pos = s;
@@ -460,6 +467,7 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
         cnt->det[i] = ndet;
         cnt->cand[i] = ncand;
         cnt->acc[i] = nacc;
+        cnt->runs[i] = nruns;
       }
     }
     if (getenv("ORC_PROGRESS")) { /* long runs: one line per level on stderr */
@@ -467,7 +475,7 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
               (long long)nf, (unsigned long long)(ndet + nacc));
       fflush(stderr);
     }
-    if (i == L) break;
+    if (i == L || i == stop) break;
     /* empty level i; r^(i+1) is the rounded exact sum of what arrived */
     for (int64_t u = 0; u < n; ++u) r[u] = 0.0;
     for (int64_t k = 0; k < ntouched; ++k) {
@@ -508,6 +516,7 @@ typedef struct many_job {
   int32_t wp;
   double* out;
   uint64_t* counters;
+  int32_t stop;
   int next;
   int status;
   pthread_mutex_t lock;
@@ -523,19 +532,20 @@ static void* many_worker(void* arg) {
     if (c >= jb->C) break;
     orc_counters cn, *pc = NULL;
     if (jb->counters) {
-      uint64_t* base = jb->counters + (size_t)c * 5 * L1;
+      uint64_t* base = jb->counters + (size_t)c * ORC_NUM_COUNTERS * L1;
       cn.frontier = base;
       cn.hash = base + L1;
       cn.det = base + 2 * L1;
       cn.cand = base + 3 * L1;
       cn.acc = base + 4 * L1;
-      memset(base, 0, sizeof(uint64_t) * 5 * L1);
+      cn.runs = base + 5 * L1;
+      memset(base, 0, sizeof(uint64_t) * ORC_NUM_COUNTERS * L1);
       pc = &cn;
     }
     uint32_t qid = jb->qids ? jb->qids[c] : (uint32_t)c;
-    int rc = orc_propagate(jb->n, jb->rp, jb->col, jb->deg, jb->a, jb->b, jb->w, jb->L, jb->tail,
-                           jb->x + (size_t)c * (size_t)jb->n, jb->eps, jb->seed, qid, jb->wp,
-                           jb->out + (size_t)c * (size_t)jb->n, pc);
+    int rc = orc_propagate_levels(jb->n, jb->rp, jb->col, jb->deg, jb->a, jb->b, jb->w, jb->L, jb->tail,
+                                  jb->x + (size_t)c * (size_t)jb->n, jb->eps, jb->seed, qid, jb->wp,
+                                  jb->out + (size_t)c * (size_t)jb->n, pc, jb->stop);
     if (rc) {
       pthread_mutex_lock(&jb->lock);
       jb->status = rc;
@@ -549,9 +559,9 @@ int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                        const int32_t* deg, double a, double b, const double* w,
                        int32_t L, int32_t tail, const double* x, int32_t C, double eps,
                        uint64_t seed, const uint32_t* qids, int32_t wp,
-                       double* out, uint64_t* counters, int32_t nthreads) {
+                       double* out, uint64_t* counters, int32_t nthreads, int32_t stop) {
   if (C < 0 || nthreads < 1) return -1;
-  many_job jb = {n, rp, col_sorted, deg, a, b, w, L, tail, x, C, eps, seed, qids, wp, out, counters, 0, 0};
+  many_job jb = {n, rp, col_sorted, deg, a, b, w, L, tail, x, C, eps, seed, qids, wp, out, counters, stop, 0, 0};
   pthread_mutex_init(&jb.lock, NULL);
   if (nthreads > C) nthreads = C > 0 ? C : 1;
   pthread_t* th = malloc(sizeof(pthread_t) * (size_t)nthreads);

@@ -26,13 +26,15 @@ extern "C" {
 #define ORC_SEG_LOG2 6
 
 /* Per-level counters of one propagation (one column). Arrays have L + 1
- * entries; det/cand/acc use entries 0..L-1, frontier/hash use 0..L. */
+ * entries; det/cand/acc/runs use entries 0..L-1, frontier/hash use 0..L. */
+#define ORC_NUM_COUNTERS 6
 typedef struct orc_counters {
   uint64_t* frontier; /* |{u : r^(i)(u) != 0}|                        */
   uint64_t* hash;     /* sum of splitmix64(u) over that set, mod 2^64 */
   uint64_t* det;      /* deterministic pushes                         */
   uint64_t* cand;     /* sampled candidates                           */
   uint64_t* acc;      /* accepted sampled pushes                      */
+  uint64_t* runs;     /* sampling runs (each starts one skip chain)   */
 } orc_counters;
 
 /* Sort every adjacency list ascending by (factor degree of neighbour, id).
@@ -72,14 +74,21 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                   int32_t L, int32_t tail, const double* x, double eps, uint64_t seed,
                   uint32_t qid, int32_t wp, double* out, orc_counters* cnt);
 
+/* orc_propagate that stops after level `stop` (stop < 0: never): out then
+ * holds the reserves of levels 0..stop only (a bounded timing sample). */
+int orc_propagate_levels(int64_t n, const int64_t* rp, const int32_t* col_sorted, const int32_t* deg, double a,
+                         double b, const double* w, int32_t L, int32_t tail, const double* x, double eps,
+                         uint64_t seed, uint32_t qid, int32_t wp, double* out, orc_counters* cnt, int32_t stop);
+
 /* Columns c = 0..C-1 of column-major x/out (x + c*n), spread over nthreads
  * host threads; qids may be NULL (qid = c).  counters, if not NULL, is a
- * C x 5 x (L+1) uint64 array (frontier, hash, det, cand, acc per column). */
+ * C x 6 x (L+1) uint64 array (frontier, hash, det, cand, acc, runs per
+ * column).  stop as in orc_propagate_levels. */
 int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                        const int32_t* deg, double a, double b, const double* w,
                        int32_t L, int32_t tail, const double* x, int32_t C, double eps,
                        uint64_t seed, const uint32_t* qids, int32_t wp,
-                       double* out, uint64_t* counters, int32_t nthreads);
+                       double* out, uint64_t* counters, int32_t nthreads, int32_t stop);
 
 /* Local clustering sweep of pi (Section 5): order gets the nodes sorted by
  * pi(v)/d_v descending (ties by id, isolated nodes last); best_size is the

@@ -44,6 +44,7 @@ class Stats(ct.Structure):
         ("det", ct.c_uint64 * (MAX_LEVELS + 1)),
         ("cand", ct.c_uint64 * (MAX_LEVELS + 1)),
         ("acc", ct.c_uint64 * (MAX_LEVELS + 1)),
+        ("runs", ct.c_uint64 * (MAX_LEVELS + 1)),
         ("device_ms", ct.c_double),
         ("level_ms", ct.c_double * (MAX_LEVELS + 1)),
         ("level_total_ms", ct.c_double * (MAX_LEVELS + 1)),
@@ -52,7 +53,7 @@ class Stats(ct.Structure):
     def to_dict(self) -> dict:
         L = self.levels
         d = {k: np.array(getattr(self, k)[: L + 1], dtype=np.uint64)
-             for k in ("frontier", "hash", "det", "cand", "acc")}
+             for k in ("frontier", "hash", "det", "cand", "acc", "runs")}
         d["levels"] = L
         d["columns"] = self.columns
         d["device_ms"] = float(self.device_ms)

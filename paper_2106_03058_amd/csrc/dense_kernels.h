@@ -88,7 +88,7 @@ struct DenseArgs {
   double rho, kappa;
   int level, lflags;
   uint32_t key0, key1;
-  unsigned long long* counters;  // this level's 5 counters
+  unsigned long long* counters;  // this level's counters (frontier, hash, det, cand, acc, runs)
   double* mass;                  // this level's contribution mass
   int* err;
   // records (rec == nullptr: sampled pushes are added with atomics)
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_dense_level(DenseArgs D) {
   const bool last = (D.lflags & kLastLevel) != 0;
   const bool pushes = !last && D.rho != 0.0;
 
-  unsigned long long n_front = 0, n_hash = 0, n_det = 0, n_cand = 0, n_acc = 0;
+  unsigned long long n_front = 0, n_hash = 0, n_det = 0, n_cand = 0, n_acc = 0, n_runs = 0;
   double mass = 0.0;
 
   // records of group g to the level's buffer (all lanes together)
@@ -508,6 +508,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_dense_level(DenseArgs D) {
               }
               const uint32_t meta = W.meta[cr];
               if (k >= ((meta >> 8) & 0xFFu)) {  // runs before k0 lie in the deterministic prefix
+                ++n_runs;
                 const int q = static_cast<int>(meta & 0xFFu);
                 const uint32_t pjr = (meta >> 16) & 0x7Fu;
                 const uint32_t rs0 = W.rs[k];
@@ -572,6 +573,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_dense_level(DenseArgs D) {
   const unsigned long long v2 = wave_sum_u64(n_det);
   const unsigned long long v3 = wave_sum_u64(n_cand);
   const unsigned long long v4 = wave_sum_u64(n_acc);
+  const unsigned long long v5 = wave_sum_u64(n_runs);
   double m = mass;
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) m += __shfl_down(m, off);
@@ -581,6 +583,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_dense_level(DenseArgs D) {
     if (v2) atomicAdd(D.counters + 2, v2);
     if (v3) atomicAdd(D.counters + 3, v3);
     if (v4) atomicAdd(D.counters + 4, v4);
+    if (v5) atomicAdd(D.counters + 5, v5);
     if (m != 0.0) atomicAdd(D.mass, m);
   }
 }
@@ -665,6 +668,7 @@ __global__ __launch_bounds__(kSumThreads) void k_dense_bin_sum(const uint32_t* _
   }
   __syncthreads();
   constexpr int kCellsPer = kBin / kSumThreads;
+  const uint32_t uwg = static_cast<uint32_t>(wg);
 #pragma unroll 4
   for (int k = 0; k < kCellsPer; ++k) {
     const int j = k * kSumThreads + threadIdx.x;
@@ -672,8 +676,9 @@ __global__ __launch_bounds__(kSumThreads) void k_dense_bin_sum(const uint32_t* _
     if (gcell >= gcells) continue;
     const int kc = s_cnt[j];
     if (!read_acc && kc == 0) continue;
-    const unsigned long long u = gcell / static_cast<unsigned long long>(wg);
-    const int c = cbase + static_cast<int>(gcell - u * static_cast<unsigned long long>(wg));
+    const uint32_t g32 = static_cast<uint32_t>(gcell);  // group cells stay below 2^31
+    const uint32_t u = g32 / uwg;
+    const int c = cbase + static_cast<int>(g32 - u * uwg);
     const size_t idx = static_cast<size_t>(u) * static_cast<size_t>(Ct) + static_cast<size_t>(c);
     long long a = 0;
     if (read_acc) a = acc[idx];

@@ -37,7 +37,7 @@ namespace lvl {
 
 constexpr int kThreads = 256;
 constexpr int kLevelBlocks = 4096;
-constexpr int kNumCounters = 5;   // frontier, hash, det, cand, acc
+constexpr int kNumCounters = 6;   // frontier, hash, det, cand, acc, runs
 constexpr int kThetaRows = 4096;  // rows per partial sum of ||x||_1
 constexpr int kServeLdsSlots = 128;  // server columns whose counters a block sums in LDS
 
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   uint64_t* stage = s_stage[wave];
   int staged = 0;  // wave-uniform
 
-  unsigned long long n_front = 0, n_hash = 0, n_det = 0, n_cand = 0, n_acc = 0;
+  unsigned long long n_front = 0, n_hash = 0, n_det = 0, n_cand = 0, n_acc = 0, n_runs = 0;
   double mass = 0.0;
 
   // One contribution per lane (or none), in exact units of the next
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   // lane state: the sampled work item in progress
   bool active = false, need_run = false, neg = false, azero = true;
   uint32_t u = 0, c = 0, s = 0, rend = 0, run_end = 0, pos = 0, t = 0, ctr3 = 0, key0 = 0, key1 = 0;
-  uint32_t it_cand = 0, it_acc = 0;
+  uint32_t it_cand = 0, it_acc = 0, it_runs = 0;
   int64_t rpu = 0;
   double cv = 0.0, dstart = 1.0, th = 0.0;
   const ColParams* cpp = A.cp;
@@ -433,9 +433,14 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
     // (a) a lane whose item has no window left becomes idle
     if (active && need_run && s >= rend) {
       active = false;
-      if (kServe && it_cand) {
-        serve_count(A, s_scnt, c, 3, static_cast<unsigned long long>(it_cand));
-        if (it_acc) serve_count(A, s_scnt, c, 4, static_cast<unsigned long long>(it_acc));
+      if (kServe) {
+        if (it_cand) {
+          serve_count(A, s_scnt, c, 3, static_cast<unsigned long long>(it_cand));
+          if (it_acc) serve_count(A, s_scnt, c, 4, static_cast<unsigned long long>(it_acc));
+        }
+        if (it_runs) serve_count(A, s_scnt, c, 5, static_cast<unsigned long long>(it_runs));
+      } else {
+        n_runs += it_runs;
       }
     }
     // (b) the queue is empty and a lane is idle: set up the next batch
@@ -651,7 +656,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
           if (azero) tab = make_skip_table(B.p0[e]);
           active = true;
           need_run = true;
-          it_cand = it_acc = 0;
+          it_cand = it_acc = it_runs = 0;
         }
       }
       it_next += __popcll(idle);
@@ -663,6 +668,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
     }
     // (d) a run: the rest of the current window, or (a > 0) of its degree group
     if (active && need_run) {
+      ++it_runs;
       const uint32_t wnext = ((s >> kSegLog2) + 1u) << kSegLog2;
       const uint32_t wend = wnext < rend ? wnext : rend;
       run_end = wend;
@@ -734,6 +740,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
     const unsigned long long v2 = wave_sum_u64(n_det);
     const unsigned long long v3 = wave_sum_u64(n_cand);
     const unsigned long long v4 = wave_sum_u64(n_acc);
+    const unsigned long long v5 = wave_sum_u64(n_runs);
     double m = mass;
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) m += __shfl_down(m, off);
@@ -743,6 +750,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       if (v2) atomicAdd(cnt + 2, v2);
       if (v3) atomicAdd(cnt + 3, v3);
       if (v4) atomicAdd(cnt + 4, v4);
+      if (v5) atomicAdd(cnt + 5, v5);
       if (m != 0.0) atomicAdd(A.mass + A.level, m);
     }
   }
@@ -854,7 +862,7 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
   const int wave = threadIdx.x / kWave;
   uint64_t* stage = s_stage[wave];
   int staged = 0;  // wave-uniform
-  unsigned long long n_cand = 0, n_acc = 0;
+  unsigned long long n_cand = 0, n_acc = 0, n_runs = 0;
   const unsigned long long G = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
   unsigned long long next = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
 
@@ -903,6 +911,7 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
     }
     if (!__any(active)) break;
     if (active && need_run) {  // a run, as in k_level
+      ++n_runs;
       const uint32_t wnext = ((s >> kSegLog2) + 1u) << kSegLog2;
       const uint32_t wend = wnext < rend ? wnext : rend;
       run_end = wend;
@@ -976,9 +985,11 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
   unsigned long long* cnt = A.counters + static_cast<size_t>(A.level) * kNumCounters;
   const unsigned long long v3 = wave_sum_u64(n_cand);
   const unsigned long long v4 = wave_sum_u64(n_acc);
+  const unsigned long long v5 = wave_sum_u64(n_runs);
   if (lane_id() == 0) {
     if (v3) atomicAdd(cnt + 3, v3);
     if (v4) atomicAdd(cnt + 4, v4);
+    if (v5) atomicAdd(cnt + 5, v5);
   }
 }
 

@@ -487,6 +487,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
       stats->det[i] += h[i * kNumCounters + 2];
       stats->cand[i] += h[i * kNumCounters + 3];
       stats->acc[i] += h[i * kNumCounters + 4];
+      stats->runs[i] += h[i * kNumCounters + 5];
     }
     float ms = 0.0f;
     for (int32_t i = 0; i <= L; ++i) {
@@ -815,6 +816,7 @@ int propagate_dense_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune,
       stats->det[i] += h[i * kNumCounters + 2];
       stats->cand[i] += h[i * kNumCounters + 3];
       stats->acc[i] += h[i * kNumCounters + 4];
+      stats->runs[i] += h[i * kNumCounters + 5];
     }
     float ms = 0.0f;
     for (int32_t i = 0; i <= L; ++i) {
@@ -1016,6 +1018,7 @@ void add_stats(agp_stats_t* into, const agp_stats_t& part) {
     into->det[i] += part.det[i];
     into->cand[i] += part.cand[i];
     into->acc[i] += part.acc[i];
+    into->runs[i] += part.runs[i];
     into->level_ms[i] += part.level_ms[i];
     into->level_total_ms[i] += part.level_total_ms[i];
   }

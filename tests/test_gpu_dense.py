@@ -90,7 +90,7 @@ def _check(torch, agp, G, sg, a, b, w, x, eps, seed, monkeypatch, *, env_vars=No
     bad = ~np.isclose(got, ref, rtol=1e-5, atol=1e-9)
     assert not bad.any(), f"{bad.sum()} entries outside tolerance, max diff {np.abs(got - ref).max()}"
     assert np.array_equal(got, ref), f"not bit-identical: max diff {np.abs(got - ref).max()}"
-    for k in ("frontier", "hash", "det", "cand", "acc"):
+    for k in ("frontier", "hash", "det", "cand", "acc", "runs"):
         want = cnt[k].sum(axis=0).astype(np.uint64)
         assert np.array_equal(st[k][: L + 1], want[: L + 1]), f"counter {k}: {st[k][:L + 1]} vs {want}"
     return got, st
@@ -134,7 +134,7 @@ def test_dense_equals_frontier_lists(env, monkeypatch):
     monkeypatch.setenv("AGP_DENSE", "auto")
     o2, s2 = agp.propagate(G, a, b, w, X, eps, 5, stats=True)
     assert torch.equal(o1, o2)
-    for k in ("frontier", "hash", "det", "cand", "acc"):
+    for k in ("frontier", "hash", "det", "cand", "acc", "runs"):
         assert np.array_equal(s1[k], s2[k])
 
 

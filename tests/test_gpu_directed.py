@@ -67,7 +67,7 @@ def test_directed_parity(env, name, C):
     ref, cnt = oracle.propagate(oracle.directed(g, reverse), a, b, w, x.astype(np.float32), eps, 17, wp=32)
     assert np.array_equal(got, ref), f"max diff {np.abs(got - ref).max()}"
     L = len(w) - 1
-    for k in ("frontier", "hash", "det", "cand", "acc"):
+    for k in ("frontier", "hash", "det", "cand", "acc", "runs"):
         assert np.array_equal(st[k][: L + 1], cnt[k].sum(axis=0).astype(np.uint64)[: L + 1]), k
     assert st["cand"].sum() > 0
 

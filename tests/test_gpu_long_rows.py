@@ -61,7 +61,7 @@ def _x(g, kind):
 
 def _check(got, st, ref, cnt, L):
     assert np.array_equal(got, ref), f"max diff {np.abs(got - ref).max()}"
-    for k in ("frontier", "hash", "det", "cand", "acc"):
+    for k in ("frontier", "hash", "det", "cand", "acc", "runs"):
         assert np.array_equal(st[k][: L + 1], cnt[k].sum(axis=0).astype(np.uint64)[: L + 1]), k
 
 

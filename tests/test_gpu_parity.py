@@ -56,7 +56,7 @@ def _assert_parity(got, st, ref, cnt, L):
     bad = ~np.isclose(got, ref, rtol=RTOL, atol=ATOL)
     assert not bad.any(), f"{bad.sum()} entries outside tolerance, max diff {np.abs(got - ref).max()}"
     assert np.array_equal(got, ref), f"not bit-identical: max diff {np.abs(got - ref).max()}"
-    for k in ("frontier", "hash", "det", "cand", "acc"):
+    for k in ("frontier", "hash", "det", "cand", "acc", "runs"):
         want = cnt[k].sum(axis=0).astype(np.uint64)  # summed over columns (hash mod 2^64)
         assert np.array_equal(st[k][: L + 1], want[: L + 1]), f"counter {k}: {st[k]} vs {want}"
 

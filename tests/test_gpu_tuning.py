@@ -68,7 +68,7 @@ def test_every_tuning_candidate_keeps_the_bits(env, workload):
                                                             {0: "atomic", 1: "binned", 2: "auto"}.get(v))
                 out, st = agp.propagate(G, a, b, w, X, eps, 31, stats=True)
                 assert np.array_equal(out.cpu().numpy().astype(np.float64), ref), f"{name}={v}"
-                for k in ("frontier", "hash", "det", "cand", "acc"):
+                for k in ("frontier", "hash", "det", "cand", "acc", "runs"):
                     assert np.array_equal(st[k], cnt[k].sum(axis=0).astype(np.uint64)), f"{name}={v}: {k}"
     finally:
         agp.set_tuning(G, C, a, b, None)

@@ -44,7 +44,7 @@ def _signal(g, kind, C, seed):
 
 
 def _check(st, cnt, L):
-    for k in ("frontier", "hash", "det", "cand", "acc"):
+    for k in ("frontier", "hash", "det", "cand", "acc", "runs"):
         assert np.array_equal(st[k][: L + 1], cnt[k].sum(axis=0).astype(np.uint64)[: L + 1]), k
 
 

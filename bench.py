@@ -1,23 +1,21 @@
 """Benchmark of the randomized level push on one MI355X.
 
-Default workload, `--workload katz-tp` (one step = one pass of the whole hot
-path over one batch):
-  R-MAT graph, scale 22 (4,194,304 nodes), 16 generated edges per node,
-  (a, b, c) = (0.57, 0.19, 0.19), symmetrised, deduplicated, loops dropped;
-  256 sources drawn uniformly among nodes of degree >= 1;
-  * Katz: a = b = 0, w_i = 0.85 beta^i with beta = 0.85 / lambda_1 (lambda_1 by
-    FP64 power iteration), L = 30, eps = 1e-7, the 256 sources in one call;
-  * 10-step transition probability: a = 0, b = 1, w_10 = 1, L = 10,
-    eps = 1e-7, the same 256 sources in one call.
+Default workload, `--workload gnn-ppr-large` (one step = one pass of the
+whole hot path over one batch): PPR feature propagation (alpha = 0.1,
+L = 10, a = b = 1/2, eps = 1e-8) of a 111,059,956 x 128 U[-1, 1] binary32
+feature matrix on a Chung-Lu graph (n = 111,059,956, exponent 2.2, ~1.6e9
+arcs plus one loop per node) generated on the GPU; graph and features stay
+resident in HBM, the 128 columns run as tiles of node-major dense levels.
 Other workloads:
+  `--workload katz-tp`: R-MAT graph, scale 22 (4,194,304 nodes), 16
+    generated edges per node, (a, b, c) = (0.57, 0.19, 0.19), symmetrised,
+    deduplicated, loops dropped; 256 sources drawn uniformly among nodes of
+    degree >= 1; Katz (a = b = 0, w_i = 0.85 beta^i, beta = 0.85 / lambda_1,
+    L = 30, eps = 1e-7) and 10-step transition probability (a = 0, b = 1,
+    w_10 = 1, eps = 1e-7), the 256 sources in one call each.
   `--workload gnn-hkpr`: heat-kernel feature propagation (t = 5, L = 10,
     a = b = 1/2, eps = 1e-7) of a 2.4M x 128 N(0,1) matrix on a Chung-Lu
     graph (n = 2.4M, mean degree 50, exponent 2.5, one self-loop per node).
-  `--workload gnn-ppr-large`: PPR feature propagation (alpha = 0.1, L = 10,
-    a = b = 1/2, eps = 1e-8) of a 111M x 128 U[-1, 1] matrix on a Chung-Lu
-    graph (n = 111,059,956, exponent 2.2, ~1.6e9 arcs plus one loop per
-    node) generated on the GPU; the columns are processed in tiles that fit
-    the free memory.  Use --steps 1 --warmup 0.
   `--workload serve`: a served query stream on R-MAT scale 24.
   `--workload cluster`: local clustering, heat kernel PageRank (t = 5,
     L = 20, eps = 1e-7) from 64 seeds and the minimum-conductance sweep of
@@ -47,6 +45,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# Vector ALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# = 39.32e12 lane-instructions/s (32-bit integer, binary32 and binary64
+# adds/multiplies/FMAs all issue at this rate on gfx950).  One random draw of
+# the sampling step is at least 103 such instructions: Philox4x32-10 (42,
+# with 32x32->64 multiply-adds), two 53-bit uniforms and the 7-step lifted
+# geometric skip (61), counted in the gfx950 assembly of a draw-only loop;
+# the skip table of each run, the acceptance test of each candidate and every
+# memory access come on top.  A level whose time goes to its draws is bound
+# by ALU_PEAK_DRAWS draws/s.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+VALU_PER_DRAW = 103
+ALU_PEAK_GDRAWS = VALU_LANE_OPS / VALU_PER_DRAW / 1e9
 
 # HBM bytes per launch of the level kernel (levels 1..L), from two rocprofv3
 # --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) with
@@ -57,7 +67,7 @@ TRAFFIC = {
                 "fetch_bytes": 7261762965.0, "write_bytes": 3752403044.0},
 }
 KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
-                  "paper_2106_03058_amd/csrc/propagate.hip")
+                  "paper_2106_03058_amd/csrc/dense_kernels.h", "paper_2106_03058_amd/csrc/propagate.hip")
 
 
 def kernel_sources_sha() -> str:
@@ -242,7 +252,8 @@ def workload_directed(args):
     def exact_of(gh, m, x):
         from oracle import dense
 
-        return dense.horner_sparse_directed(gh, m["a"], m["b"], m["w"], x, m["reverse"])
+        return (dense.horner_sparse_directed(gh, m["a"], m["b"], m["w"], x, m["reverse"]),
+                np.diff(gh.row_ptr))  # MaxError of a directed graph divides by out-degrees
 
     cfg = {"workload": "directed " + "+".join(m["name"] for m in models) + f", {C} sources/targets each, "
                        "rmat scale 22 (arcs as generated)",
@@ -274,8 +285,12 @@ def workload_gnn_ppr_large(args):
         state["desc"] = {"n": n, "arcs_without_loops": int(rp[-1].item()),
                          "max_degree_without_loops": int((rp[1:] - rp[:-1]).max().item())}
         log(f"chung-lu n={n}: {state['desc']} in {time.time() - t:.1f}s")
-        if not args.no_cpu_baseline:
-            state["rp"], state["col"] = rp.cpu().numpy(), col.cpu().numpy()
+        if args.host_leg:  # the same graph with its loops, for the oracle and the exact sums
+            t = time.time()
+            rpl, coll = inputs.add_self_loops_device(n, rp, col)
+            state["host"] = inputs.Graph(n, rpl.cpu().numpy(), coll.cpu().numpy())
+            del rpl, coll
+            log(f"host copy of the graph with loops {time.time() - t:.1f}s")
         G = agp.Graph(rp, col, self_loops=True)
         del rp, col
         torch.cuda.empty_cache()
@@ -285,10 +300,8 @@ def workload_gnn_ppr_large(args):
         return inputs.features_uniform_device(n, 128, -1.0, 1.0, seed=505)
 
     def oracle_inputs(cols):
-        t = time.time()
-        g = inputs.add_self_loops(n, state.pop("rp"), state.pop("col"))
-        log(f"host graph with loops {time.time() - t:.1f}s")
-        return g, np.ascontiguousarray(state["X"][:, cols].cpu().numpy())
+        return state["host"], np.ascontiguousarray(state["X"][:, torch.from_numpy(cols).to(state["X"].device)]
+                                                   .cpu().numpy())
 
     models = [dict(name="ppr", a=0.5, b=0.5, w=inputs.weights_ppr(0.1, 10), eps=1e-8,
                    qids=np.arange(128, dtype=np.uint32))]
@@ -297,7 +310,8 @@ def workload_gnn_ppr_large(args):
            "graph": state, "columns_per_call": 128,
            "models": {"ppr": {"a": 0.5, "b": 0.5, "L": 10, "alpha": 0.1, "eps": 1e-8}}}
     return dict(n=n, make_graph=make_graph, signal_device=signal_device, models=models, cfg=cfg, unit="columns",
-                oracle_inputs=oracle_inputs, state=state)
+                oracle_inputs=oracle_inputs, state=state, cpu_sample=dict(stop_level=0, stride=8, units=4),
+                single=2)
 
 
 WORKLOADS = {"katz-tp": workload_katz_tp, "gnn-hkpr": workload_gnn_hkpr, "gnn-ppr-large": workload_gnn_ppr_large,
@@ -682,38 +696,112 @@ def run_variants(args) -> dict:
     }
 
 
+def copy_probe_gbps(dev) -> float:
+    """Device-to-device copy of 4 GiB (read + write bytes over the copy's
+    HIP-event time): the HBM rate a plain streaming kernel reaches."""
+    import torch
+
+    src = torch.ones(1 << 30, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = 0.0
+    for _ in range(5):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2.0 * src.numel() * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
+def level_roofline(runs, models, args, C) -> dict:
+    """Roofline object of the level kernel over the timed steps.
+
+    Node-major dense levels (feature propagation): the kernel is bound by its
+    random draws (runs + candidates), so `achieved` is draws per launch over
+    the launch's HIP-event time against ALU_PEAK_GDRAWS; levels 0..L-1, one
+    launch per level and column tile (level L only converts residues).
+    Frontier-list levels: algorithmic bytes of the launches of levels 1..L
+    against the HBM peak.  Both report the algorithmic HBM rate and, while the
+    kernel sources hash to the profiled ones, the measured traffic."""
+    dense = all(st["dense"] for r in runs for st, _ in r)
+    draws = lvl_ms = alg = 0.0
+    launches = 0
+    for r in runs:
+        for (st, _), m in zip(r, models):
+            L = st["levels"]
+            lv = range(0, L) if dense else range(1, L + 1)
+            for i in lv:
+                draws += float(st["runs"][i]) + float(st["cand"][i])
+                lvl_ms += float(st["level_ms"][i])
+            alg += alg_bytes(st, lv, m["a"] == 0.0)
+            launches += len(lv) * max(int(st["tiles"]), 1)
+    avg_s = lvl_ms / 1e3 / max(launches, 1)
+    alg_gbps = alg / (lvl_ms / 1e3) / 1e9
+    rec = TRAFFIC.get(args.workload)
+    traffic = None
+    if rec and rec["sources"] == kernel_sources_sha() and rec["columns"] == C and not args.tune:
+        traffic = rec["bytes_per_launch"] / avg_s / 1e9
+    hbm = {"alg_bytes_per_launch": alg / max(launches, 1), "alg_gbps": alg_gbps,
+           "traffic_bytes_per_launch": rec["bytes_per_launch"] if traffic is not None else None,
+           "traffic_gbps": traffic, "traffic_over_alg": (traffic / alg_gbps) if traffic else None}
+    if dense:
+        achieved = draws / max(launches, 1) / avg_s / 1e9
+        return {"bound": "alu", "kernel": "k_dense_level (levels 0..L-1, one launch per level and column tile)",
+                "achieved": achieved, "peak": ALU_PEAK_GDRAWS, "unit": "Gdraw/s", "frac": achieved / ALU_PEAK_GDRAWS,
+                "traffic": traffic, "traffic_unit": "GB/s",
+                "draws_per_launch": draws / max(launches, 1), "avg_launch_ms": avg_s * 1e3, "launches": launches,
+                "peak_derivation": f"{VALU_LANE_OPS:.4g} VALU lane-ops/s / {VALU_PER_DRAW} per draw",
+                "hbm": hbm}
+    return {"bound": "hbm", "kernel": "k_level<float, false, false> + k_det_big<float> + k_samp_big<float> "
+                                      "(levels 1..L)",
+            "achieved": alg_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": alg_gbps / HBM_PEAK_GBPS,
+            "traffic": traffic, "traffic_bytes_per_launch": hbm["traffic_bytes_per_launch"],
+            "avg_launch_ms": avg_s * 1e3, "alg_bytes_per_launch": hbm["alg_bytes_per_launch"], "launches": launches}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2021)
-    ap.add_argument("--workload", default="katz-tp", choices=sorted(WORKLOADS) + ["serve", "cluster", "variants"])
+    ap.add_argument("--workload", default="gnn-ppr-large",
+                    choices=sorted(WORKLOADS) + ["serve", "cluster", "variants"])
     ap.add_argument("--queries", type=int, default=1024, help="serve: queries in the stream")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: offered arrivals per second")
     ap.add_argument("--slots", type=int, default=112, help="serve: server slots")
-    ap.add_argument("--single", type=int, default=16, help="units timed one per launch")
+    ap.add_argument("--single", type=int, default=None, help="units timed one per launch")
     ap.add_argument("--oracle-queries", type=int, default=0,
                     help="serve: queries of the stream re-run by the oracle (random sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true",
-                    help="autotune aggregation and grid per model before timing (default: library defaults)")
-    ap.add_argument("--cpu-units", type=int, default=4, help="oracle sample per model")
+                    help="autotune the execution choices per model before timing (default: library defaults)")
+    ap.add_argument("--cpu-units", type=int, default=None, help="columns of the oracle timing sample")
+    ap.add_argument("--cpu-stop-level", type=int, default=None,
+                    help="oracle timing sample: stop after this level (-1: whole columns, checked bit for bit)")
+    ap.add_argument("--cpu-stride", type=int, default=None,
+                    help="oracle timing sample: at the stop level visit every k-th node only")
+    ap.add_argument("--parity-columns", type=int, default=0,
+                    help="columns re-run whole by the oracle and compared bit for bit (beside the timing sample)")
+    ap.add_argument("--exact-units", type=int, default=4,
+                    help="sampled units whose error against the exact FP64 sum is reported")
     ap.add_argument("--cache", default=os.environ.get("AGP_BENCH_CACHE", ""),
                     help="directory to keep the generated graph between runs")
     ap.add_argument("--models", default="katz,tp,hkpr", help="subset of the step to run (profiling)")
     ap.add_argument("--columns", type=int, default=256, help="columns per call (profiling)")
     ap.add_argument("--large-n", type=int, default=111_059_956, help="gnn-ppr-large: nodes")
-    ap.add_argument("--exact-units", type=int, default=None,
-                    help="sampled units whose error against the exact FP64 sum is reported")
+    ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device to device first (reference for HBM counters)")
     args = ap.parse_args()
-    if args.exact_units is None:  # the exact FP64 sum of a 1.7e9-arc graph takes many silent minutes on the host
-        args.exact_units = 0 if args.workload == "gnn-ppr-large" else 1
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         return 2
+    args.host_leg = (not args.no_cpu_baseline) or args.exact_units > 0 or args.parity_columns > 0
 
     import torch
 
@@ -722,6 +810,7 @@ def main() -> int:
     agp.lib()
     dev = torch.device("cuda:0")
     if args.workload == "serve":
+        args.single = 16 if args.single is None else args.single
         print(json.dumps(run_serve(args)), flush=True)
         return 0
     if args.workload == "cluster":
@@ -732,12 +821,25 @@ def main() -> int:
         return 0
     W = WORKLOADS[args.workload](args)
     models, cfg, unit_name, n = W["models"], W["cfg"], W["unit"], W["n"]
+    samp = dict(stop_level=-1, stride=1, units=4)
+    samp.update(W.get("cpu_sample", {}))
+    if args.cpu_units is not None:
+        samp["units"] = args.cpu_units
+    if args.cpu_stop_level is not None:
+        samp["stop_level"] = args.cpu_stop_level
+    if args.cpu_stride is not None:
+        samp["stride"] = args.cpu_stride
+    single = args.single if args.single is not None else W.get("single", 16)
+    copy_gbps = None
     if args.calibrate_copy:
         a_ = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b_ = torch.empty_like(a_)
         b_.copy_(a_)
         torch.cuda.synchronize()
         del a_, b_
+    elif not args.no_copy_probe:
+        copy_gbps = copy_probe_gbps(dev)
+        log(f"copy probe {copy_gbps:.0f} GB/s")
     t = time.time()
     G = W["make_graph"]()
     torch.cuda.synchronize()
@@ -769,11 +871,15 @@ def main() -> int:
             res.append((st, (time.perf_counter() - t0) * 1e3))
         return res
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         step(True)
+        log(f"warmup step {k + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = [step(True) for _ in range(args.steps)]
+    runs = []
+    for k in range(args.steps):
+        runs.append(step(True))
+        log(f"step {k + 1}/{args.steps}: {sum(ms for _, ms in runs[-1]):.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -783,28 +889,22 @@ def main() -> int:
     value = pushes_step / (ms_per_step / 1e3)
     log(f"{ms_per_step:.1f} ms/step, {pushes_step:.3e} pushes/step")
 
-    # roofline of the dominant kernel: the level kernel of levels 1..L
-    # (k_level<float, false, false>, timed together with the k_det_big and
-    # k_samp_big launches that make the level's deferred pushes; level 0
-    # reads the signal and is a separate instantiation)
-    mid_bytes = mid_ms = 0.0
-    launches = 0
+    roofline = level_roofline(runs, models, args, C)
     all_bytes = all_ms = 0.0
     for r in runs:
         for (st, _), m in zip(r, models):
             L = st["levels"]
-            mid_bytes += alg_bytes(st, range(1, L + 1), m["a"] == 0.0)
-            mid_ms += float(st["level_ms"][1:L + 1].sum())
-            launches += L
             all_bytes += alg_bytes(st, range(L + 1), m["a"] == 0.0)
-            all_ms += float(st["level_ms"].sum())
-    achieved = mid_bytes / (mid_ms / 1e3) / 1e9
+            all_ms += float(st["level_total_ms"].sum())
     per_level = []
     for (st, ms), m in zip(runs[0], models):
-        per_level.append({"model": m["name"], "call_ms": round(ms, 3),
+        per_level.append({"model": m["name"], "call_ms": round(ms, 3), "tiles": int(st["tiles"]),
+                          "dense": bool(st["dense"]),
                           "frontier": [int(v) for v in st["frontier"]],
                           "pushes": [int(d + a) for d, a in zip(st["det"], st["acc"])],
-                          "level_ms": [round(float(v), 4) for v in st["level_ms"]]})
+                          "draws": [int(r_ + c_) for r_, c_ in zip(st["runs"], st["cand"])],
+                          "level_ms": [round(float(v), 4) for v in st["level_ms"]],
+                          "level_total_ms": [round(float(v), 4) for v in st["level_total_ms"]]})
 
     # batched vs one unit (query or column) per launch, same eps and keys
     lat_b = []
@@ -813,8 +913,8 @@ def main() -> int:
     lat_b = np.array(lat_b)
     q_per_s_batched = len(models) * C / (ms_per_step / 1e3)
     lat_s = []
-    nq = args.single // max(len(models), 1)
-    one = torch.empty((n, 1), dtype=torch.float32, device=dev)
+    nq = single // max(len(models), 1)
+    one = torch.empty((n, 1), dtype=torch.float32, device=dev) if nq > 0 else None
     single_ok = True
     for m, o, Gm, Xm in zip(models, outs, Gs, Xs):
         for c in range(min(nq, C)):
@@ -824,12 +924,9 @@ def main() -> int:
             agp.propagate(Gm, m["a"], m["b"], m["w"], xc, m["eps"], args.seed, qids=m["qids"][c:c + 1], out=one)
             lat_s.append((time.perf_counter() - ts) * 1e3)
             single_ok &= bool(torch.equal(one[:, 0], o[:, c]))
-    lat_s = np.array(lat_s) if lat_s else np.zeros(1)
-
-    rec = TRAFFIC.get(args.workload)
-    traffic = None
-    if rec and rec["sources"] == kernel_sources_sha() and rec["columns"] == C and not args.tune:
-        traffic = rec["bytes_per_launch"] / (mid_ms / max(launches, 1) / 1e3) / 1e9
+            del xc
+    del one
+    log(f"{len(lat_s)} units one per launch, equal to the batched columns: {single_ok}")
 
     result = {
         "metric": METRIC,
@@ -848,47 +945,60 @@ def main() -> int:
         "tuning": tunings,
         "pushes_per_step": pushes_step,
         "hbm_gbps_algorithmic_all_levels": all_bytes / (all_ms / 1e3) / 1e9,
+        "hbm_copy_probe_gbps": copy_gbps,
         f"{unit_name}_per_s_batched": q_per_s_batched,
         "latency_ms_batched": {"p50": float(np.percentile(lat_b, 50)), "p99": float(np.percentile(lat_b, 99))},
-        f"{unit_name}_per_s_one_per_launch": (1e3 / lat_s.mean()) if lat_s.any() else 0.0,
-        "latency_ms_one_per_launch": {"p50": float(np.percentile(lat_s, 50)),
-                                      "p99": float(np.percentile(lat_s, 99)), "units": int(len(lat_s))},
-        "one_per_launch_equals_batched": single_ok,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_level<float, false, false> + k_det_big<float> + k_samp_big<float> (levels 1..L)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": traffic,
-            "traffic_bytes_per_launch": rec["bytes_per_launch"] if traffic is not None else None,
-            "avg_launch_ms": mid_ms / max(launches, 1),
-            "alg_bytes_per_launch": mid_bytes / max(launches, 1),
-        },
+        "roofline": roofline,
         "per_level": per_level,
     }
+    if lat_s:
+        lat_s = np.array(lat_s)
+        result[f"{unit_name}_per_s_one_per_launch"] = 1e3 / lat_s.mean()
+        result["latency_ms_one_per_launch"] = {"p50": float(np.percentile(lat_s, 50)),
+                                               "p99": float(np.percentile(lat_s, 99)), "units": int(len(lat_s))}
+        result["one_per_launch_equals_batched"] = single_ok
+    print(json.dumps({"partial": True, "value": value, "ms_per_step": ms_per_step, "roofline": roofline}),
+          file=sys.stderr, flush=True)
 
-    if not args.no_cpu_baseline:
-        import oracle
+    if args.host_leg:
+        host_leg(args, W, models, outs, C, samp, unit_name, result)
+    print(json.dumps(result), flush=True)
+    return 0
 
-        k = min(args.cpu_units, C)
-        cols = np.sort(np.random.default_rng(55).choice(C, size=k, replace=False))
-        threads = min(k * len(models), 16, os.cpu_count() or 1)
-        gh, xh = W["oracle_inputs"](cols)
+
+def host_leg(args, W, models, outs, C, samp, unit_name, result) -> None:
+    """The oracle's timing sample, whole-column parity and the error against
+    the exact FP64 sum, on sampled columns of the same inputs."""
+    import torch
+
+    import oracle
+
+    dev = outs[0].device
+    rng = np.random.default_rng(55)
+    want = max(samp["units"] if not args.no_cpu_baseline else 0, args.exact_units, args.parity_columns)
+    cols = np.sort(rng.choice(C, size=min(want, C), replace=False))
+    gh, xh = W["oracle_inputs"](cols)
+    xhs = [W["oracle_signal_of"](xh, m) if "oracle_signal_of" in W else xh for m in models]
+    host_threads = min(16, os.cpu_count() or 1)
+    got = [outs[mi][:, torch.from_numpy(cols).to(dev)].cpu().numpy().astype(np.float64)
+           for mi in range(len(models))]
+    if not args.no_cpu_baseline or args.parity_columns > 0:
         t = time.time()
         if "oracle_graph_of" in W:
             sgs = [W["oracle_graph_of"](gh, m) for m in models]
         else:
-            sg = oracle.degree_sort(gh)
+            sg = oracle.degree_sort(gh, threads=host_threads)
             sgs = [sg for _ in models]
-        xhs = [W["oracle_signal_of"](xh, m) if "oracle_signal_of" in W else xh for m in models]
-        log(f"oracle degree sort {time.time() - t:.1f}s")
+        log(f"oracle degree sort {time.time() - t:.1f}s on {host_threads} threads")
+    if not args.no_cpu_baseline:
+        k = min(samp["units"], cols.size)
+        threads = min(k * len(models), 16, os.cpu_count() or 1)
         results = {}
 
         def run(mi, m):
-            results[mi] = oracle.propagate(sgs[mi], m["a"], m["b"], m["w"], xhs[mi], m["eps"], args.seed,
-                                           qids=m["qids"][cols], threads=max(threads // len(models), 1))
+            results[mi] = oracle.propagate(sgs[mi], m["a"], m["b"], m["w"], xhs[mi][:, :k], m["eps"], args.seed,
+                                           qids=m["qids"][cols[:k]], threads=max(threads // len(models), 1),
+                                           stop_level=samp["stop_level"], sample_stride=samp["stride"])
 
         t = time.time()
         ths = [threading.Thread(target=run, args=(mi, m)) for mi, m in enumerate(models)]
@@ -897,49 +1007,58 @@ def main() -> int:
         for th in ths:
             th.join()
         wall = time.time() - t
-        tot_push = 0
-        parity = True
+        tot_push = sum(int(results[mi][1]["det"].sum() + results[mi][1]["acc"].sum()) for mi in range(len(models)))
+        whole = samp["stop_level"] < 0 and samp["stride"] == 1
+        what = (f"{unit_name} {cols[:k].tolist()} of each model ({', '.join(m['name'] for m in models)})"
+                + ("" if whole else f", level {samp['stop_level']} only"
+                   + ("" if samp["stride"] == 1 else f", nodes with id % {samp['stride']} == 0")))
+        result["cpu_baseline"] = {"value": tot_push / wall, "unit": "edge-pushes/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": f"{what}; same inputs and seeds; {tot_push} pushes in {wall:.1f}s "
+                                            f"wall on {threads} threads (degree sort not counted)"}
+        log(f"oracle sample {wall:.1f}s: {tot_push} pushes")
+        if whole:
+            parity = all(np.array_equal(got[mi][:, :k], results[mi][0]) for mi in range(len(models)))
+            result["parity_full_size"] = {"units_checked": k * len(models), "columns": cols[:k].tolist(),
+                                          "bit_exact": bool(parity)}
+            log(f"parity of the sample: {parity}")
+    if args.parity_columns > 0:
+        k = min(args.parity_columns, cols.size)
+        threads = min(k * len(models), 16, os.cpu_count() or 1)
+        t = time.time()
+        ok = True
         for mi, m in enumerate(models):
-            ref, cnt = results[mi]
-            tot_push += int(cnt["det"].sum() + cnt["acc"].sum())
-            got = outs[mi][:, torch.from_numpy(cols).to(dev)].cpu().numpy().astype(np.float64)
-            parity &= bool(np.array_equal(got, ref))
-        log(f"oracle sample {wall:.1f}s, parity {parity}")
-        per_unit_s = wall * threads / (k * len(models))
-        result["cpu_baseline"] = {
-            "value": tot_push / wall,
-            "unit": "edge-pushes/s",
-            "cores": threads,
-            "kind": "oracle",
-            "sample": f"{unit_name} {cols.tolist()} of each model ({', '.join(m['name'] for m in models)}), "
-                      f"same inputs and seeds, {wall:.1f}s wall on {threads} threads",
-            "seconds_per_unit_one_core": per_unit_s,
-            "step_seconds_extrapolated": per_unit_s * C * len(models) / threads,
-        }
-        result["parity_full_size"] = {"units_checked": k * len(models), "columns": cols.tolist(),
-                                      "bit_exact": parity}
-        # error of the estimate against the exact FP64 sum of Eq. 1 (sparse Horner)
-        if args.exact_units > 0:
-            from oracle import dense
-
-            t = time.time()
-            errs = {}
-            ke = min(args.exact_units, k)
-            for mi, m in enumerate(models):
-                if "exact_of" in W:
-                    exact = W["exact_of"](gh, m, xhs[mi][:, :ke])
-                else:
-                    exact = dense.horner_sparse(gh, m["a"], m["b"], m["w"], xhs[mi][:, :ke])
-                got = outs[mi][:, torch.from_numpy(cols[:ke]).to(dev)].cpu().numpy().astype(np.float64)
-                diff = np.abs(got - exact)
-                errs[m["name"]] = {"columns": cols[:ke].tolist(), "eps": m["eps"], "max_abs": float(diff.max()),
-                                   "rel_l1": float(diff.sum() / max(np.abs(exact).sum(), 1e-300)),
-                                   "max_abs_over_max_exact": float(diff.max() / max(np.abs(exact).max(), 1e-300))}
-            result["error_vs_exact"] = errs
-            log(f"exact sums {time.time() - t:.1f}s: {errs}")
-        del gh
-    print(json.dumps(result), flush=True)
-    return 0
+            ref, _ = oracle.propagate(sgs[mi], m["a"], m["b"], m["w"], xhs[mi][:, :k], m["eps"], args.seed,
+                                      qids=m["qids"][cols[:k]], threads=threads)
+            eq = np.array_equal(got[mi][:, :k], ref)
+            log(f"parity {m['name']} columns {cols[:k].tolist()}: {'bit-exact' if eq else 'DIFFERENT'} "
+                f"({time.time() - t:.0f}s)")
+            ok &= bool(eq)
+        result["parity_full_size"] = {"units_checked": k * len(models), "columns": cols[:k].tolist(),
+                                      "bit_exact": ok, "oracle_seconds": time.time() - t, "threads": threads}
+    if args.exact_units > 0:
+        ke = min(args.exact_units, cols.size)
+        t = time.time()
+        errs = {}
+        for mi, m in enumerate(models):
+            if "exact_of" in W:
+                exact, deg = W["exact_of"](gh, m, xhs[mi][:, :ke])
+            else:
+                exact = oracle.truncated_sum(gh, m["a"], m["b"], m["w"], xhs[mi][:, :ke], threads=host_threads,
+                                             verbose=True)
+                deg = np.diff(gh.row_ptr)
+            diff = np.abs(got[mi][:, :ke] - exact)
+            dn = np.maximum(deg, 1).astype(np.float64)[:, None]
+            errs[m["name"]] = {
+                "columns": cols[:ke].tolist(), "eps": m["eps"],
+                "max_abs": [float(v) for v in diff.max(axis=0)],
+                "max_abs_over_max_exact": [float(v) for v in diff.max(axis=0) / np.maximum(np.abs(exact).max(axis=0),
+                                                                                             1e-300)],
+                "rel_l1": [float(v) for v in diff.sum(axis=0) / np.maximum(np.abs(exact).sum(axis=0), 1e-300)],
+                "max_error_degree_normalized": [float(v) for v in (diff / dn).max(axis=0)],
+            }
+        result["error_vs_exact"] = errs
+        log(f"exact sums {time.time() - t:.1f}s: {errs}")
 
 
 if __name__ == "__main__":

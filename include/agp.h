@@ -77,6 +77,9 @@ typedef struct agp_graph agp_graph_t;
 typedef struct agp_stats {
   int32_t levels;  /* L of the call */
   int32_t columns; /* C of the call */
+  int32_t tiles;   /* column tiles run one after another: each level launches
+                      its level kernel once per tile */
+  int32_t dense;   /* 1: node-major dense levels; 0: (node, column) frontier lists */
   uint64_t frontier[AGP_MAX_LEVELS + 1];
   uint64_t hash[AGP_MAX_LEVELS + 1];
   uint64_t det[AGP_MAX_LEVELS + 1];
@@ -230,8 +233,9 @@ typedef struct agp_tuning {
                            2: records on dense levels, atomics on sparse ones  */
   int32_t level_blocks; /* workgroups of the level kernel (>= 256)               */
   int32_t dense;        /* node-major levels with one lane per column (binary32):
-                           0 never, 1 always, 2 when at least a quarter of the
-                           signal's entries are non-zero and C >= 16           */
+                           0 never (default), 1 always, 2 when at least a
+                           quarter of the signal's entries are non-zero and
+                           C >= 16                                             */
   int32_t tile_columns; /* columns per tile; 0: the widest tile that fits       */
   int32_t big_row;      /* deterministic pushes from which an entry's row is
                            deferred to a grid-wide kernel; 0: 4096              */
@@ -257,7 +261,7 @@ int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int3
                  float* out, void* stream, agp_tuning_t* best);
 
 /* The choice agp_propagate uses for (g, C, a, b): the tuned or set one,
- * else the default (aggregation 2, 4096 workgroups, dense 2, the other
+ * else the default (aggregation 2, 4096 workgroups, dense 0, the other
  * fields at their stated defaults), with the environment overrides below
  * applied. */
 int agp_get_tuning(const agp_graph_t* g, int32_t C, double a, double b, agp_tuning_t* out);

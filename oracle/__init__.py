@@ -45,7 +45,7 @@ def lib():
         u64p = ct.POINTER(ct.c_uint64)
         dp = ct.POINTER(ct.c_double)
         L.orc_sweep.argtypes = [ct.c_int64, i64p, i32p, dp, i32p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
-        L.orc_degree_sort.argtypes = [ct.c_int64, i64p, i32p, i32p, i32p, i32p, i32p]
+        L.orc_degree_sort.argtypes = [ct.c_int64, i64p, i32p, i32p, i32p, i32p, i32p, ct.c_int32]
         L.orc_level_tables.argtypes = [dp, ct.c_int32, ct.c_int32, dp, dp, dp, dp]
         L.orc_theta.argtypes = [dp, ct.c_int64, ct.c_double]
         L.orc_theta.restype = ct.c_double
@@ -58,7 +58,9 @@ def lib():
         L.orc_exact_sum.restype = ct.c_double
         L.orc_propagate_many.argtypes = [ct.c_int64, i64p, i32p, i32p, ct.c_double, ct.c_double,
                                          dp, ct.c_int32, ct.c_int32, dp, ct.c_int32, ct.c_double, ct.c_uint64,
-                                         u32p, ct.c_int32, dp, u64p, ct.c_int32, ct.c_int32]
+                                         u32p, ct.c_int32, dp, u64p, ct.c_int32, ct.c_int32, ct.c_int32]
+        L.orc_exact_sum_horner.argtypes = [ct.c_int64, i64p, i32p, i32p, ct.c_double, ct.c_double, dp,
+                                           ct.c_int32, dp, ct.c_int32, dp, ct.c_int32, ct.c_int32]
         _lib = L
     return _lib
 
@@ -81,7 +83,9 @@ class SortedGraph:
     fdeg: np.ndarray
 
 
-def degree_sort(g, fdeg=None) -> SortedGraph:
+def degree_sort(g, fdeg=None, threads: int | None = None) -> SortedGraph:
+    """Adjacency lists sorted by (neighbour factor degree, id) (Section 4);
+    rows are sorted by `threads` host threads (default: all cores, at most 16)."""
     rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
     col = np.ascontiguousarray(g.col, dtype=np.int32)
     out = np.empty_like(col)
@@ -90,7 +94,8 @@ def degree_sort(g, fdeg=None) -> SortedGraph:
     fin = None if fdeg is None else np.ascontiguousarray(fdeg, dtype=np.int32)
     rc = lib().orc_degree_sort(g.n, _p(rp, ct.c_int64), _p(col, ct.c_int32),
                                None if fin is None else _p(fin, ct.c_int32),
-                               _p(out, ct.c_int32), _p(deg, ct.c_int32), _p(fd, ct.c_int32))
+                               _p(out, ct.c_int32), _p(deg, ct.c_int32), _p(fd, ct.c_int32),
+                               int(threads or min(16, os.cpu_count() or 1)))
     assert rc == 0
     return SortedGraph(g.n, rp, out, deg, fd)
 
@@ -161,7 +166,7 @@ SPLIT_QID_BIT = 1 << 23
 
 def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, *,
               wp: int = 32, qids=None, threads: int | None = None, tail: bool = False,
-              split_signs: bool = False, stop_level: int = -1):
+              split_signs: bool = False, stop_level: int = -1, sample_stride: int = 1):
     """Run Algorithm 2 on every column of x (n x C, or a length-n vector).
 
     Returns (out, counters): out has the shape of x (float64 values that are
@@ -173,7 +178,8 @@ def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, 
 
     stop_level: stop after that level (a bounded timing sample: the output
     then holds the reserves of the levels done, the counters of those
-    levels are complete).
+    levels are complete).  sample_stride: at the stop level, visit only the
+    nodes whose id is a multiple of it (a smaller timing sample).
 
     split_signs: the literal treatment of signed signals (Section 3,
     assumption on the graph signal): x+ (the positive entries) and x- (the
@@ -215,7 +221,7 @@ def propagate(sg: SortedGraph, a: float, b: float, w, x, eps: float, seed: int, 
         sg.n, _p(sg.row_ptr, ct.c_int64), _p(sg.col, ct.c_int32), _p(sg.fdeg, ct.c_int32),
         float(a), float(b), _p(w, ct.c_double), L, int(bool(tail)), _p(xc, ct.c_double), C, float(eps),
         ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), None if q is None else _p(q, ct.c_uint32), wp,
-        _p(out, ct.c_double), _p(cnt, ct.c_uint64), max(1, int(threads)), int(stop_level))
+        _p(out, ct.c_double), _p(cnt, ct.c_uint64), max(1, int(threads)), int(stop_level), int(sample_stride))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     res = out.T
@@ -237,3 +243,27 @@ def sweep(g, pi):
                          ct.byref(size), ct.byref(phi))
     assert rc == 0
     return size.value, phi.value, order
+
+
+def truncated_sum(g, a: float, b: float, w, x, *, fdeg=None, threads: int | None = None,
+                  verbose: bool = False) -> np.ndarray:
+    """Eq. 1 truncated at L in binary64, without sampling or thresholds:
+    sum_{i=0..L} w_i (D^-a A D^-b)^i x by Horner's rule (orc_exact_sum_horner),
+    with row v of g listing the nodes that push into v (the CSR itself for an
+    undirected graph).  x: n x C (C <= 64) or a vector; threads share rows."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    vec = x.ndim == 1
+    X = np.ascontiguousarray(x.reshape(g.n, -1))
+    C = X.shape[1]
+    out = np.empty_like(X)
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    fd = None if fdeg is None else np.ascontiguousarray(fdeg, dtype=np.int32)
+    rc = lib().orc_exact_sum_horner(g.n, _p(rp, ct.c_int64), _p(col, ct.c_int32),
+                                    None if fd is None else _p(fd, ct.c_int32), float(a), float(b),
+                                    _p(w, ct.c_double), w.size - 1, _p(X, ct.c_double), C, _p(out, ct.c_double),
+                                    int(threads or min(16, os.cpu_count() or 1)), int(bool(verbose)))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return out[:, 0].copy() if vec else out

@@ -24,12 +24,18 @@
  *    carry the sign of r (Section 3 splits x into x+ and x-);
  *  - adjacency lists are sorted by (d_v, v), so every correct sort agrees;
  *  - subset sampling (after Algorithm 2): the sampled suffix of N_u is cut
- *    into runs of equal degree group floor(log2 d_v) (only when a > 0) inside
- *    aligned windows of 64 positions.  In a run starting at position s the
- *    scheme draws Bernoulli(p*) per position, p* = p_{v_s} (the largest in the
- *    run), and keeps a drawn position j with probability p_{v_j}/p*.  The
- *    Bernoulli(p*) positions are produced by geometric skips, which has the
- *    same distribution as the paper's Binomial count plus uniform choice;
+ *    into runs inside aligned windows of 64 positions.  In a run starting at
+ *    position s the scheme draws Bernoulli(p*) per position, p* = p_{v_s}
+ *    (the largest in the run), and keeps a drawn position j with probability
+ *    p_{v_j}/p*.  The Bernoulli(p*) positions are produced by geometric skips,
+ *    which has the same distribution as the paper's Binomial count plus
+ *    uniform choice.  With a = 0 a run is the rest of the window.  With
+ *    a > 0 a run ends with the degree group floor(log2 d_v) of its first
+ *    position (so every kept probability is above 1/2), unless p* times the
+ *    positions left in the window is at most ORC_MERGE_CANDIDATES: then the
+ *    run takes the rest of the window (at most that many candidates are
+ *    expected, fewer draws than one run per group).  Every position is still
+ *    kept with probability p_{v_j}, independently;
  *  - randomness: Philox4x32-10 keyed by the 64-bit seed, counter
  *    (t, s, u, (qid << 8) | level), t = draw index in the run;
  *  - the residue of a node at the next level is the exact sum of all
@@ -50,36 +56,77 @@
 
 /* ------------------------------------------------------------ degree sort */
 
-static const int32_t* g_sort_deg; /* degree table used by the comparator */
-
-static int cmp_deg_id(const void* pa, const void* pb) {
+static int cmp_deg_id(const void* pa, const void* pb, void* ctx) {
+  const int32_t* fdeg = (const int32_t*)ctx; /* degree table of the comparison */
   int32_t va = *(const int32_t*)pa, vb = *(const int32_t*)pb;
-  int32_t da = g_sort_deg[va], db = g_sort_deg[vb];
+  int32_t da = fdeg[va], db = fdeg[vb];
   if (da != db) return da < db ? -1 : 1;
   if (va != vb) return va < vb ? -1 : 1;
   return 0;
 }
 
-static pthread_mutex_t g_sort_lock = PTHREAD_MUTEX_INITIALIZER;
+/* Row bounds of nthreads contiguous row ranges with about equal numbers of
+ * arcs: bounds[t] .. bounds[t+1] for thread t. */
+static void split_rows_by_arcs(int64_t n, const int64_t* rp, int nthreads, int64_t* bounds) {
+  bounds[0] = 0;
+  for (int t = 1; t < nthreads; ++t) { /* first row starting at or after the share's end */
+    const int64_t target = rp[n] / nthreads * t;
+    int64_t lo = bounds[t - 1], hi = n;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (rp[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    bounds[t] = lo;
+  }
+  bounds[nthreads] = n;
+}
+
+typedef struct {
+  const int64_t* rp;
+  int32_t* col;
+  const int32_t* fdeg;
+  int64_t lo, hi;
+} sort_job;
+
+static void* sort_rows(void* arg) {
+  sort_job* jb = (sort_job*)arg;
+  for (int64_t u = jb->lo; u < jb->hi; ++u)
+    qsort_r(jb->col + jb->rp[u], (size_t)(jb->rp[u + 1] - jb->rp[u]), sizeof(int32_t), cmp_deg_id,
+            (void*)jb->fdeg);
+  return NULL;
+}
 
 /* Pre-sorting adjacency lists by degree (Section 4): N_u ascending in the
  * degree of the neighbour that enters the factors d^-a, d^-b.  Undirected
  * graphs: that degree is the row length (at least 1).  Directed graphs pass
- * the out-degrees (Section 4, propagation on directed graphs). */
+ * the out-degrees (Section 4, propagation on directed graphs).  Each row is
+ * sorted on its own, so the rows are shared among nthreads threads. */
 int orc_degree_sort(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* fdeg_in,
-                    int32_t* out_col, int32_t* deg, int32_t* fdeg) {
-  if (n < 0) return -1;
+                    int32_t* out_col, int32_t* deg, int32_t* fdeg, int32_t nthreads) {
+  if (n < 0 || nthreads < 1) return -1;
   for (int64_t u = 0; u < n; ++u) {
     deg[u] = (int32_t)(rp[u + 1] - rp[u]);
     const int32_t f = fdeg_in ? fdeg_in[u] : deg[u];
     fdeg[u] = f < 1 ? 1 : f;
   }
   memcpy(out_col, col, (size_t)rp[n] * sizeof(int32_t));
-  pthread_mutex_lock(&g_sort_lock);
-  g_sort_deg = fdeg;
-  for (int64_t u = 0; u < n; ++u)
-    qsort(out_col + rp[u], (size_t)(rp[u + 1] - rp[u]), sizeof(int32_t), cmp_deg_id);
-  pthread_mutex_unlock(&g_sort_lock);
+  if (n < 4096) nthreads = 1;
+  pthread_t* th = malloc(sizeof(pthread_t) * (size_t)nthreads);
+  sort_job* jobs = malloc(sizeof(sort_job) * (size_t)nthreads);
+  int64_t* bounds = malloc(sizeof(int64_t) * ((size_t)nthreads + 1));
+  split_rows_by_arcs(n, rp, nthreads, bounds);
+  for (int t = 0; t < nthreads; ++t) {
+    jobs[t].rp = rp;
+    jobs[t].col = out_col;
+    jobs[t].fdeg = fdeg;
+    jobs[t].lo = bounds[t];
+    jobs[t].hi = bounds[t + 1];
+    pthread_create(&th[t], NULL, sort_rows, &jobs[t]);
+  }
+  for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+  free(th);
+  free(jobs);
+  free(bounds);
   return 0;
 }
 
@@ -345,14 +392,15 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                   const int32_t* deg, double a, double b, const double* w,
                   int32_t L, int32_t tail, const double* x, double eps, uint64_t seed,
                   uint32_t qid, int32_t wp, double* out, orc_counters* cnt) {
-  return orc_propagate_levels(n, rp, col_sorted, deg, a, b, w, L, tail, x, eps, seed, qid, wp, out, cnt, -1);
+  return orc_propagate_levels(n, rp, col_sorted, deg, a, b, w, L, tail, x, eps, seed, qid, wp, out, cnt, -1, 1);
 }
 
 int orc_propagate_levels(int64_t n, const int64_t* rp, const int32_t* col_sorted, const int32_t* deg, double a,
                          double b, const double* w, int32_t L, int32_t tail, const double* x, double eps,
-                         uint64_t seed, uint32_t qid, int32_t wp, double* out, orc_counters* cnt, int32_t stop) {
+                         uint64_t seed, uint32_t qid, int32_t wp, double* out, orc_counters* cnt, int32_t stop,
+                         int32_t stride) {
   if (n < 0 || L < 0 || L > 255 || !(a >= 0.0 && a <= 1.0) || !(b >= 0.0 && b <= 1.0) ||
-      !(eps >= 0.0) || (wp != 32 && wp != 64))
+      !(eps >= 0.0) || (wp != 32 && wp != 64) || stride < 1)
     return -1;
   for (int32_t k = 0; k <= L; ++k)
     if (!(w[k] >= 0.0) || isinf(w[k])) return -1;
@@ -400,6 +448,7 @@ int orc_propagate_levels(int64_t n, const int64_t* rp, const int32_t* col_sorted
     for (int64_t u = 0; u < n; ++u) { /* each u with non-zero residue */
       double ru = r[u];
       if (ru == 0.0) continue;
+      if (i == stop && stride > 1 && u % stride != 0) continue; /* timing sample: every stride-th node */
       ++nf;
       hs += orc_splitmix64((uint64_t)u);
       /* reserve: pi(u) += (w_i / Y_i) r(u), rescaled by S */
@@ -433,6 +482,11 @@ int orc_propagate_levels(int64_t n, const int64_t* rp, const int32_t* col_sorted
         ++nruns;
         const double dstart = da[deg[nb[s]]];
         const double pstar = (c * dstart) / theta;
+        if (a != 0.0) { /* few expected candidates: the run takes the rest of its window */
+          int64_t wend = (s / seg + 1) * seg;
+          if (wend > du) wend = du;
+          if (pstar * (double)(wend - s) <= ORC_MERGE_CANDIDATES) e = wend;
+        }
         int64_t pos = s;
         uint32_t t = 0;
         for (;;) {
@@ -517,6 +571,7 @@ typedef struct many_job {
   double* out;
   uint64_t* counters;
   int32_t stop;
+  int32_t stride;
   int next;
   int status;
   pthread_mutex_t lock;
@@ -545,7 +600,7 @@ static void* many_worker(void* arg) {
     uint32_t qid = jb->qids ? jb->qids[c] : (uint32_t)c;
     int rc = orc_propagate_levels(jb->n, jb->rp, jb->col, jb->deg, jb->a, jb->b, jb->w, jb->L, jb->tail,
                                   jb->x + (size_t)c * (size_t)jb->n, jb->eps, jb->seed, qid, jb->wp,
-                                  jb->out + (size_t)c * (size_t)jb->n, pc, jb->stop);
+                                  jb->out + (size_t)c * (size_t)jb->n, pc, jb->stop, jb->stride);
     if (rc) {
       pthread_mutex_lock(&jb->lock);
       jb->status = rc;
@@ -559,9 +614,10 @@ int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                        const int32_t* deg, double a, double b, const double* w,
                        int32_t L, int32_t tail, const double* x, int32_t C, double eps,
                        uint64_t seed, const uint32_t* qids, int32_t wp,
-                       double* out, uint64_t* counters, int32_t nthreads, int32_t stop) {
+                       double* out, uint64_t* counters, int32_t nthreads, int32_t stop, int32_t stride) {
   if (C < 0 || nthreads < 1) return -1;
-  many_job jb = {n, rp, col_sorted, deg, a, b, w, L, tail, x, C, eps, seed, qids, wp, out, counters, stop, 0, 0};
+  many_job jb = {n, rp, col_sorted, deg, a, b, w, L, tail, x, C, eps, seed, qids, wp, out, counters, stop, stride,
+                 0, 0};
   pthread_mutex_init(&jb.lock, NULL);
   if (nthreads > C) nthreads = C > 0 ? C : 1;
   pthread_t* th = malloc(sizeof(pthread_t) * (size_t)nthreads);
@@ -581,14 +637,17 @@ int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
  * counts the arcs (u, v), u in S, v outside S, of the symmetric CSR (a loop
  * is never cut); vol(S) sums the row lengths; 2m = rp[n]. */
 
-static const double* g_sw_ratio;
-static const int64_t* g_sw_rp;
+typedef struct {
+  const double* ratio;
+  const int64_t* rp;
+} sweep_key;
 
-static int cmp_sweep(const void* pa, const void* pb) {
+static int cmp_sweep(const void* pa, const void* pb, void* ctx) {
+  const sweep_key* k = (const sweep_key*)ctx;
   const int32_t va = *(const int32_t*)pa, vb = *(const int32_t*)pb;
-  const int isoa = g_sw_rp[va + 1] == g_sw_rp[va], isob = g_sw_rp[vb + 1] == g_sw_rp[vb];
+  const int isoa = k->rp[va + 1] == k->rp[va], isob = k->rp[vb + 1] == k->rp[vb];
   if (isoa != isob) return isoa < isob ? -1 : 1;
-  const double ra = g_sw_ratio[va], rb = g_sw_ratio[vb];
+  const double ra = k->ratio[va], rb = k->ratio[vb];
   if (ra != rb) return ra > rb ? -1 : 1;
   return va < vb ? -1 : (va > vb ? 1 : 0);
 }
@@ -605,11 +664,8 @@ int orc_sweep(int64_t n, const int64_t* rp, const int32_t* col, const double* pi
     ratio[v] = r;
     order[v] = (int32_t)v;
   }
-  pthread_mutex_lock(&g_sort_lock);
-  g_sw_ratio = ratio;
-  g_sw_rp = rp;
-  qsort(order, (size_t)n, sizeof(int32_t), cmp_sweep);
-  pthread_mutex_unlock(&g_sort_lock);
+  sweep_key key = {ratio, rp};
+  qsort_r(order, (size_t)n, sizeof(int32_t), cmp_sweep, &key);
   const int64_t two_m = rp[n];
   int64_t cut = 0, vol = 0;
   *best_size = 0;
@@ -638,5 +694,99 @@ int orc_sweep(int64_t n, const int64_t* rp, const int32_t* col, const double* pi
   }
   free(ratio);
   free(in_s);
+  return 0;
+}
+
+/* ---------------------------------------------------------- exact sum */
+/* The quantity the method estimates, Eq. 1 truncated at L:
+ * pi = sum_{i=0..L} w_i P^i x with P = D^-a A D^-b, in binary64 by Horner's
+ * rule: acc = w_L x, then acc = w_i x + P acc for i = L-1 .. 0.  Row v of
+ * (rp, col) lists the u with A[v][u] = 1, so (P y)(v) = d_v^-a sum_u d_u^-b y(u),
+ * summed in row order.  x and out are n x C row-major.  Rows are shared
+ * among nthreads threads; each entry is computed by one thread alone. */
+
+typedef struct {
+  int64_t lo, hi;
+  const int64_t* rp;
+  const int32_t* col;
+  const double *fa, *fb;
+  const double* x;
+  const double* src;
+  double* scaled;
+  double* dst;
+  double wi;
+  int32_t C;
+  int32_t phase;
+} horner_job;
+
+static void* horner_rows(void* arg) {
+  const horner_job* jb = (const horner_job*)arg;
+  const int32_t C = jb->C;
+  if (jb->phase == 0) { /* scaled = D^-b src */
+    for (int64_t u = jb->lo; u < jb->hi; ++u)
+      for (int32_t c = 0; c < C; ++c) jb->scaled[(size_t)u * C + c] = jb->fb[u] * jb->src[(size_t)u * C + c];
+    return NULL;
+  }
+  double sum[64];
+  for (int64_t v = jb->lo; v < jb->hi; ++v) { /* dst = w_i x + D^-a A scaled */
+    for (int32_t c = 0; c < C; ++c) sum[c] = 0.0;
+    for (int64_t k = jb->rp[v]; k < jb->rp[v + 1]; ++k) {
+      const double* y = jb->scaled + (size_t)jb->col[k] * C;
+      for (int32_t c = 0; c < C; ++c) sum[c] += y[c];
+    }
+    for (int32_t c = 0; c < C; ++c)
+      jb->dst[(size_t)v * C + c] = jb->wi * jb->x[(size_t)v * C + c] + jb->fa[v] * sum[c];
+  }
+  return NULL;
+}
+
+int orc_exact_sum_horner(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* fdeg, double a, double b,
+                         const double* w, int32_t L, const double* x, int32_t C, double* out, int32_t nthreads,
+                         int32_t verbose) {
+  if (n < 0 || L < 0 || C < 1 || C > 64 || nthreads < 1) return -1;
+  const size_t cells = (size_t)(n ? n : 1) * (size_t)C;
+  double* fa = malloc(sizeof(double) * (size_t)(n ? n : 1));
+  double* fb = malloc(sizeof(double) * (size_t)(n ? n : 1));
+  double* tmp = malloc(sizeof(double) * cells);
+  double* scaled = malloc(sizeof(double) * cells);
+  for (int64_t v = 0; v < n; ++v) {
+    int32_t d = fdeg ? fdeg[v] : (int32_t)(rp[v + 1] - rp[v]);
+    if (d < 1) d = 1; /* a node without arcs: its factors never meet a non-zero sum */
+    fa[v] = deg_pow(d, a);
+    fb[v] = deg_pow(d, b);
+  }
+  /* acc = w_L x, kept in out; each step writes tmp and swaps */
+  for (size_t k = 0; k < (size_t)n * (size_t)C; ++k) out[k] = w[L] * x[k];
+  double *cur = out, *nxt = tmp;
+  if (n < 4096) nthreads = 1;
+  pthread_t* th = malloc(sizeof(pthread_t) * (size_t)nthreads);
+  horner_job* jobs = malloc(sizeof(horner_job) * (size_t)nthreads);
+  int64_t* bounds = malloc(sizeof(int64_t) * ((size_t)nthreads + 1));
+  split_rows_by_arcs(n, rp, nthreads, bounds);
+  for (int32_t i = L - 1; i >= 0; --i) {
+    for (int32_t phase = 0; phase < 2; ++phase) {
+      for (int t = 0; t < nthreads; ++t) {
+        horner_job jb = {bounds[t], bounds[t + 1], rp, col, fa, fb, x, cur, scaled, nxt, w[i], C, phase};
+        jobs[t] = jb;
+        pthread_create(&th[t], NULL, horner_rows, &jobs[t]);
+      }
+      for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    }
+    double* sw = cur;
+    cur = nxt;
+    nxt = sw;
+    if (verbose) {
+      fprintf(stderr, "[oracle] truncated sum: term %d of %d added\n", (int)(L - i), (int)L);
+      fflush(stderr);
+    }
+  }
+  if (cur != out) memcpy(out, cur, sizeof(double) * (size_t)n * (size_t)C);
+  free(th);
+  free(jobs);
+  free(fa);
+  free(fb);
+  free(tmp);
+  free(scaled);
+  free(bounds);
   return 0;
 }

@@ -24,6 +24,9 @@ extern "C" {
 
 /* Subset sampling splits every sampled suffix at multiples of 2^6 positions. */
 #define ORC_SEG_LOG2 6
+/* A sampling run (a > 0) whose expected candidates over the rest of its
+ * window are at most this many takes the rest of the window. */
+#define ORC_MERGE_CANDIDATES 4.0
 
 /* Per-level counters of one propagation (one column). Arrays have L + 1
  * entries; det/cand/acc/runs use entries 0..L-1, frontier/hash use 0..L. */
@@ -40,9 +43,10 @@ typedef struct orc_counters {
 /* Sort every adjacency list ascending by (factor degree of neighbour, id).
  * rp/col: CSR of the push direction; fdeg_in: factor degrees (out-degrees
  * of a directed graph) or NULL for the row lengths.  out_col gets the sorted
- * lists, deg the row lengths, fdeg the factor degrees clamped to >= 1. */
+ * lists, deg the row lengths, fdeg the factor degrees clamped to >= 1.
+ * The rows are sorted by nthreads host threads. */
 int orc_degree_sort(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* fdeg_in,
-                    int32_t* out_col, int32_t* deg, int32_t* fdeg);
+                    int32_t* out_col, int32_t* deg, int32_t* fdeg, int32_t nthreads);
 
 /* S, Y_0..Y_{L+1}, rho_0..rho_L, kappa_0..kappa_L from w_0..w_L; tail != 0
  * takes the paper-literal infinite tail Y_i = 1 - sum_{k<i} w_k (returns -1
@@ -75,20 +79,23 @@ int orc_propagate(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                   uint32_t qid, int32_t wp, double* out, orc_counters* cnt);
 
 /* orc_propagate that stops after level `stop` (stop < 0: never): out then
- * holds the reserves of levels 0..stop only (a bounded timing sample). */
+ * holds the reserves of levels 0..stop only.  At level `stop` only the nodes
+ * u with u % stride == 0 are visited.  Both serve bounded timing samples;
+ * stop = -1, stride = 1 is orc_propagate. */
 int orc_propagate_levels(int64_t n, const int64_t* rp, const int32_t* col_sorted, const int32_t* deg, double a,
                          double b, const double* w, int32_t L, int32_t tail, const double* x, double eps,
-                         uint64_t seed, uint32_t qid, int32_t wp, double* out, orc_counters* cnt, int32_t stop);
+                         uint64_t seed, uint32_t qid, int32_t wp, double* out, orc_counters* cnt, int32_t stop,
+                         int32_t stride);
 
 /* Columns c = 0..C-1 of column-major x/out (x + c*n), spread over nthreads
  * host threads; qids may be NULL (qid = c).  counters, if not NULL, is a
  * C x 6 x (L+1) uint64 array (frontier, hash, det, cand, acc, runs per
- * column).  stop as in orc_propagate_levels. */
+ * column).  stop and stride as in orc_propagate_levels. */
 int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
                        const int32_t* deg, double a, double b, const double* w,
                        int32_t L, int32_t tail, const double* x, int32_t C, double eps,
                        uint64_t seed, const uint32_t* qids, int32_t wp,
-                       double* out, uint64_t* counters, int32_t nthreads, int32_t stop);
+                       double* out, uint64_t* counters, int32_t nthreads, int32_t stop, int32_t stride);
 
 /* Local clustering sweep of pi (Section 5): order gets the nodes sorted by
  * pi(v)/d_v descending (ties by id, isolated nodes last); best_size is the
@@ -96,6 +103,16 @@ int orc_propagate_many(int64_t n, const int64_t* rp, const int32_t* col_sorted,
  * conductance (best_size 0 and +inf when no prefix has one). */
 int orc_sweep(int64_t n, const int64_t* rp, const int32_t* col, const double* pi, int32_t* order,
               int64_t* best_size, double* best_phi);
+
+/* Eq. 1 truncated at L in binary64 by Horner's rule, without sampling or
+ * thresholds: out = sum_{i=0..L} w_i (D^-a A D^-b)^i x.  Row v of (rp, col)
+ * lists the u with A[v][u] = 1 (the rows that push into v); fdeg: the
+ * degrees in the factors, or NULL for the row lengths.  x and out are n x C
+ * row-major, 1 <= C <= 64; nthreads host threads share the rows; verbose:
+ * a line on stderr after each term (long runs). */
+int orc_exact_sum_horner(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* fdeg, double a, double b,
+                         const double* w, int32_t L, const double* x, int32_t C, double* out, int32_t nthreads,
+                         int32_t verbose);
 
 #ifdef __cplusplus
 }

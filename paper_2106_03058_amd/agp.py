@@ -38,7 +38,7 @@ class AGPError(RuntimeError):
 
 class Stats(ct.Structure):
     _fields_ = [
-        ("levels", ct.c_int32), ("columns", ct.c_int32),
+        ("levels", ct.c_int32), ("columns", ct.c_int32), ("tiles", ct.c_int32), ("dense", ct.c_int32),
         ("frontier", ct.c_uint64 * (MAX_LEVELS + 1)),
         ("hash", ct.c_uint64 * (MAX_LEVELS + 1)),
         ("det", ct.c_uint64 * (MAX_LEVELS + 1)),
@@ -56,6 +56,8 @@ class Stats(ct.Structure):
              for k in ("frontier", "hash", "det", "cand", "acc", "runs")}
         d["levels"] = L
         d["columns"] = self.columns
+        d["tiles"] = self.tiles
+        d["dense"] = bool(self.dense)
         d["device_ms"] = float(self.device_ms)
         d["level_ms"] = np.array(self.level_ms[: L + 1], dtype=np.float64)
         d["level_total_ms"] = np.array(self.level_total_ms[: L + 1], dtype=np.float64)

@@ -15,6 +15,12 @@ namespace agp {
 constexpr int kWave = 64;
 constexpr int kSegLog2 = 6;  // sampled suffixes are cut into 64-position windows
 constexpr int kSeg = 1 << kSegLog2;
+// Sampling runs (a > 0) end with the degree group floor(log2 d) of their
+// first position, except that a run whose rate p* times the positions left in
+// its window is at most this many expected candidates takes the rest of the
+// window: fewer draws than a run per group, every position still kept with
+// probability p_v.
+constexpr double kMergeCandidates = 4.0;
 
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, "Parallel

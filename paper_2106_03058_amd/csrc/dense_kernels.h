@@ -159,9 +159,11 @@ struct WaveLds {
   uint32_t col[kWave];          // the window's neighbour ids
   double da[kWave];             //   their factors d^-a (1 when a = 0)
   uint32_t rs[kWave + 1];       //   run starts (window-relative); rs[R] = window length
-  uint32_t meta[kWave];         // per sampling column, by rank: column | k0 << 8 | jr << 16 | sign << 31
-                                // (k0 its first run, jr its deterministic prefix in the window)
+  uint32_t meta[kWave];         // per sampling column, by rank: column | k0 << 8 | jr << 16 |
+                                // whole << 23 | sign << 31 (k0 its first run, jr its deterministic
+                                // prefix in the window, whole: run k0 takes the rest of the window)
   double cv[kWave];             // per sampling column, by rank: c = rho |r| d_u^-b
+  uint8_t more[kWave];          // ranks of the sampling columns whose run k0 ends with its group
   int nst[kMaxGroups];          // records staged per group
   uint32_t stage[kStageRecs];   // staged records, kStageRecs / ng per group
 };
@@ -463,30 +465,45 @@ __global__ __launch_bounds__(kThreads, 4) void k_dense_level(DenseArgs D) {
         }
         const int R = __popcll(runs);
         // per sampling column: its first run (runs ending at or before its
-        // prefix are deterministic) and its prefix inside the window
+        // prefix are deterministic), its prefix inside the window, and
+        // whether that run takes the rest of the window (few expected
+        // candidates); the run contains position jr, so it starts there
         const uint32_t jr = J > ws ? J - ws : 0u;
+        const uint32_t wlen = we - ws;
         int k0 = 0;
+        bool whole = true;
         if (has) {
           const unsigned long long upto = jr >= 63u ? ~0ull : ((2ull << jr) - 1ull);
           k0 = __popcll(runs & upto & ~1ull);
         }
+        const double da_jr = shfl_f64(daw, static_cast<int>(jr < 63u ? jr : 63u));
+        if (has && !azero && k0 + 1 < R) {
+          const double pr = (cv * da_jr) / s_theta[c];
+          whole = pr * static_cast<double>(wlen - jr) <= kMergeCandidates;
+        }
         const unsigned long long hasm = __ballot(has);
-        const uint32_t total = static_cast<uint32_t>(__popcll(hasm) * R);
-        const uint32_t magic = s_magic[R];
+        const unsigned long long morem = __ballot(has && !whole);
+        // pairs: one per sampling column for its run k0, then (column, run
+        // 1..R-1) for the columns whose run k0 ends with its degree group
+        const uint32_t H = static_cast<uint32_t>(__popcll(hasm));
+        const uint32_t R2 = static_cast<uint32_t>(R > 1 ? R - 1 : 1);
+        const uint32_t total = H + static_cast<uint32_t>(__popcll(morem)) * R2;
+        const uint32_t magic = s_magic[R2];
         wave_sync();  // the previous window's pairs have been read
         W.col[lane] = colw;
         W.da[lane] = daw;
         if ((runs >> lane) & 1ull) W.rs[__popcll(runs & lt_mask)] = static_cast<uint32_t>(lane);
-        if (lane == 0) W.rs[R] = we - ws;
+        if (lane == 0) W.rs[R] = wlen;
         if (has) {
           const int rk = __popcll(hasm & lt_mask);
           W.meta[rk] = static_cast<uint32_t>(c) | (static_cast<uint32_t>(k0) << 8) | (jr << 16) |
-                       (neg ? 0x80000000u : 0u);
+                       (whole ? 0x800000u : 0u) | (neg ? 0x80000000u : 0u);
           W.cv[rk] = cv;
+          if (!whole) W.more[__popcll(morem & lt_mask)] = static_cast<uint8_t>(rk);
         }
         wave_sync();
-        // ---- the window's (column, run) pairs: pair idx = rank * R + run; a
-        // lane takes the next pair as soon as its chain has ended (lane = pair)
+        // ---- the window's pairs; a lane takes the next pair as soon as its
+        // chain has ended (lane = pair)
         uint32_t next = 0;
         bool active = false;
         int pc = 0;
@@ -500,23 +517,48 @@ __global__ __launch_bounds__(kThreads, 4) void k_dense_level(DenseArgs D) {
             const uint32_t idx = next + static_cast<uint32_t>(__popcll(idle & lt_mask));
             next += static_cast<uint32_t>(__popcll(idle));
             if (!active && idx < total) {
-              uint32_t cr = __umulhi(idx, magic);
-              uint32_t k = idx - cr * static_cast<uint32_t>(R);
-              if (k >= static_cast<uint32_t>(R)) {
-                k -= static_cast<uint32_t>(R);
-                ++cr;
+              uint32_t cr = idx, k = 0;
+              const bool first = idx < H;
+              if (!first) {
+                const uint32_t i2 = idx - H;
+                uint32_t r2 = __umulhi(i2, magic);
+                k = i2 - r2 * R2;
+                if (k >= R2) {
+                  k -= R2;
+                  ++r2;
+                }
+                ++k;
+                cr = W.more[r2];
               }
               const uint32_t meta = W.meta[cr];
-              if (k >= ((meta >> 8) & 0xFFu)) {  // runs before k0 lie in the deterministic prefix
+              const uint32_t k0c = (meta >> 8) & 0xFFu;
+              const int q = static_cast<int>(meta & 0xFFu);
+              const double cvr = W.cv[cr];
+              const double thq = s_theta[q];
+              bool live = true;
+              uint32_t s0 = (meta >> 16) & 0x7Fu;  // run k0 starts at the prefix
+              if (first) {
+                k = k0c;
+                e = (meta & 0x800000u) ? wlen : W.rs[k + 1];
+              } else {
+                // runs up to k0 are taken; a run after one that took the rest
+                // of the window is covered by it (p* (wlen - s) does not grow
+                // along the sorted row, and run k0 did not)
+                live = k > k0c;
+                if (live && k > k0c + 1) {
+                  const uint32_t sp = W.rs[k - 1];
+                  const double pp = (cvr * W.da[sp]) / thq;
+                  live = !(pp * static_cast<double>(wlen - sp) <= kMergeCandidates);
+                }
+                if (live) s0 = W.rs[k];
+              }
+              if (live) {
                 ++n_runs;
-                const int q = static_cast<int>(meta & 0xFFu);
-                const uint32_t pjr = (meta >> 16) & 0x7Fu;
-                const uint32_t rs0 = W.rs[k];
-                const uint32_t s0 = rs0 > pjr ? rs0 : pjr;
-                e = W.rs[k + 1];
                 dstart = azero ? 1.0 : W.da[s0];
-                const double num = W.cv[cr] * dstart;
-                tab = make_skip_table(num / s_theta[q]);
+                const double num = cvr * dstart;
+                const double pr = num / thq;
+                if (!first) e = pr * static_cast<double>(wlen - s0) <= kMergeCandidates ? wlen : W.rs[k + 1];
+                tab = make_skip_table(pr);
                 pneg = (meta >> 31) != 0;
                 ctr3 = s_ctr3[q];
                 s_abs = ws + s0;

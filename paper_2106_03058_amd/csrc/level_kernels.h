@@ -377,7 +377,9 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   uint64_t* stage = s_stage[wave];
   int staged = 0;  // wave-uniform
 
-  unsigned long long n_front = 0, n_hash = 0, n_det = 0, n_cand = 0, n_acc = 0, n_runs = 0;
+  // per-lane counts stay far below 2^32 in one launch; the hash wraps mod 2^64
+  uint32_t n_front = 0, n_det = 0, n_cand = 0, n_acc = 0, n_runs = 0;
+  unsigned long long n_hash = 0;
   double mass = 0.0;
 
   // One contribution per lane (or none), in exact units of the next
@@ -439,8 +441,6 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
           if (it_acc) serve_count(A, s_scnt, c, 4, static_cast<unsigned long long>(it_acc));
         }
         if (it_runs) serve_count(A, s_scnt, c, 5, static_cast<unsigned long long>(it_runs));
-      } else {
-        n_runs += it_runs;
       }
     }
     // (b) the queue is empty and a lane is idle: set up the next batch
@@ -666,19 +666,25 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       if (bnext >= nbatch) break;  // queue empty (no idle lane took an item), no batch left
       continue;
     }
-    // (d) a run: the rest of the current window, or (a > 0) of its degree group
+    // (d) a run: the rest of the current window, or (a > 0) of its degree
+    // group unless few candidates are expected over the rest of the window
     if (active && need_run) {
-      ++it_runs;
+      if (kServe)
+        ++it_runs;
+      else
+        ++n_runs;
       const uint32_t wnext = ((s >> kSegLog2) + 1u) << kSegLog2;
       const uint32_t wend = wnext < rend ? wnext : rend;
       run_end = wend;
-      if (!azero) {  // the run also ends with the degree group of position s
-        const uint32_t ds = A.nd[rpu + s];
-        const uint32_t ge = A.gend[rpu + s];
-        dstart = cpp->da[ds];
-        if (ge < wend) run_end = ge;
+      if (!azero) {
+        dstart = cpp->da[A.nd[rpu + s]];
         const double num = cv * dstart;
-        tab = make_skip_table(num / th);
+        const double pr = num / th;
+        if (!(pr * static_cast<double>(wend - s) <= kMergeCandidates)) {
+          const uint32_t ge = A.gend[rpu + s];
+          if (ge < wend) run_end = ge;
+        }
+        tab = make_skip_table(pr);
       }
       pos = s;
       t = 0;
@@ -916,12 +922,14 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
       const uint32_t wend = wnext < rend ? wnext : rend;
       run_end = wend;
       if (!azero) {
-        const uint32_t ds = A.nd[rpu + s];
-        const uint32_t ge = A.gend[rpu + s];
-        dstart = cpp->da[ds];
-        if (ge < wend) run_end = ge;
+        dstart = cpp->da[A.nd[rpu + s]];
         const double num = cv * dstart;
-        tab = make_skip_table(num / th);
+        const double pr = num / th;
+        if (!(pr * static_cast<double>(wend - s) <= kMergeCandidates)) {
+          const uint32_t ge = A.gend[rpu + s];
+          if (ge < wend) run_end = ge;
+        }
+        tab = make_skip_table(pr);
       }
       pos = s;
       t = 0;

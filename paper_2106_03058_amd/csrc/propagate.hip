@@ -181,7 +181,7 @@ agp_tuning_t default_tuning() {
   agp_tuning_t t{};
   t.aggregation = 2;  // records on levels with many pushes, atomics elsewhere
   t.level_blocks = kLevelBlocks;
-  t.dense = 2;
+  t.dense = 0;  // frontier lists: only the active (node, column) entries are visited
   t.tile_columns = 0;
   t.big_row = static_cast<int32_t>(kBigRow);
   t.big_items = static_cast<int32_t>(kBigItems);
@@ -481,6 +481,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     std::vector<unsigned long long> h(static_cast<size_t>(kNumCounters) * (L + 1));
     AGP_HIP(hipMemcpy(h.data(), counters, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     stats->levels = L;
+    stats->tiles += 1;
     for (int32_t i = 0; i <= L; ++i) {
       stats->frontier[i] += h[i * kNumCounters + 0];
       stats->hash[i] += h[i * kNumCounters + 1];
@@ -808,6 +809,8 @@ int propagate_dense_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune,
                                      " (acc " + std::to_string(ha[k]) + ", r " + std::to_string(hr[k]) + ")");
   }
   if (stats) {
+    stats->tiles += 1;
+    stats->dense = 1;
     std::vector<unsigned long long> h(static_cast<size_t>(kNumCounters) * (L + 1));
     AGP_HIP(hipMemcpy(h.data(), counters, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     for (int32_t i = 0; i <= L; ++i) {
@@ -1023,6 +1026,8 @@ void add_stats(agp_stats_t* into, const agp_stats_t& part) {
     into->level_total_ms[i] += part.level_total_ms[i];
   }
   into->device_ms += part.device_ms;
+  into->tiles += part.tiles;
+  into->dense |= part.dense;
 }
 
 // The literal treatment of signed signals (Section 3, assumption on the

@@ -421,6 +421,24 @@ def add_self_loops(n: int, row_ptr: np.ndarray, col: np.ndarray) -> Graph:
     return Graph(n, new_rp, new_col)
 
 
+def add_self_loops_device(n: int, row_ptr, col, chunk: int = 1 << 27):
+    """add_self_loops on device tensors (int64 row_ptr, int32 col): returns
+    the (row_ptr, col) tensors of the CSR with one loop appended to every row."""
+    import torch
+
+    dev = row_ptr.device
+    new_rp = row_ptr + torch.arange(n + 1, device=dev, dtype=torch.int64)
+    new_col = torch.empty(int(new_rp[-1].item()), dtype=torch.int32, device=dev)
+    nnz = col.numel()
+    for lo in range(0, nnz, chunk):  # entry k of row u moves to k + u
+        k = torch.arange(lo, min(lo + chunk, nnz), device=dev, dtype=torch.int64)
+        u = torch.searchsorted(row_ptr, k, right=True) - 1
+        new_col[k + u] = col[lo:lo + k.numel()]
+        del k, u
+    new_col[new_rp[1:] - 1] = torch.arange(n, device=dev, dtype=torch.int32)
+    return new_rp, new_col
+
+
 def features_uniform_device(n: int, C: int, lo: float, hi: float, seed: int, device="cuda:0"):
     """n x C binary32 features, i.i.d. uniform on [lo, hi), generated on the GPU."""
     import torch

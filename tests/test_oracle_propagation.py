@@ -443,3 +443,136 @@ def test_sparse_directed_horner_matches_dense():
                         (0.3, 0.7, inputs.weights_hkpr(2.0, 6))):
             assert np.allclose(dense.horner_sparse_directed(g, a, b, w, x, reverse),
                                dense.horner_directed(g, a, b, w, x, reverse), rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------------ full-size reference pieces
+
+def _transpose(g):
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    dst = np.asarray(g.col, dtype=np.int64)
+    order = np.lexsort((src, dst))
+    rp = np.zeros(g.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(dst, minlength=g.n), out=rp[1:])
+    return type(g)(g.n, rp, src[order].astype(np.int32))
+
+
+def test_threaded_exact_sum_is_the_truncated_sum(orc):
+    """orc_exact_sum_horner (the error reference of the full-size runs)
+    equals the sparse Horner sum, pinned to the dense one, on every model
+    shape, with and without loops; the thread count changes no bit."""
+    for seed, loops in ((3, False), (4, True)):
+        g = inputs.chung_lu(6000, 6, 2.5, seed=seed, self_loops=loops)  # > 4096 rows: rows are shared
+        x = inputs.features_normal(g.n, 5, seed=seed).astype(np.float64)
+        for a, b, w in ((0.0, 1.0, inputs.weights_ppr(0.2, 12)), (0.5, 0.5, inputs.weights_hkpr(4.0, 9)),
+                        (1.0, 0.0, inputs.weights_tp(5)), (0.3, 0.7, inputs.weights_ppr(0.1, 7)),
+                        (0.0, 0.0, inputs.weights_katz(0.02, 6, 0.85))):
+            got = orc.truncated_sum(g, a, b, w, x, threads=8)
+            assert np.allclose(got, dense.horner_sparse(g, a, b, w, x), rtol=1e-12, atol=1e-14)
+            assert np.array_equal(got, orc.truncated_sum(g, a, b, w, x, threads=1))
+            assert np.array_equal(got[:, 2], orc.truncated_sum(g, a, b, w, x[:, 2], threads=3))
+
+
+def test_exact_sum_ppr_closed_form(orc):
+    """PPR = alpha (I - (1 - alpha) A D^-1)^-1 x (Section 2), within the
+    truncation (1 - alpha)^(L+1) at L = 300."""
+    g = inputs.chung_lu(200, 5, 2.5, seed=7)
+    s = int(np.flatnonzero(g.degree > 0)[0])
+    x = inputs.one_hot(g.n, [s]).astype(np.float64)
+    got = orc.truncated_sum(g, 0.0, 1.0, inputs.weights_ppr(0.2, 300), x)
+    assert np.abs(got - dense.ppr_inverse(g, 0.2, x)).max() <= 1e-12
+
+
+def test_exact_sum_directed(orc):
+    """Directed graphs (Section 4): pushes along out-edges read the
+    in-neighbour rows (A~ = A^T), along in-edges the out-neighbour rows
+    (A~ = A); the factors use out-degrees in both cases."""
+    g = inputs.directed_chung_lu(80, 4, 2.4, seed=24)
+    outdeg = np.maximum(np.diff(g.row_ptr), 1).astype(np.int32)
+    x = inputs.features_normal(g.n, 2, seed=3).astype(np.float64)
+    gt = _transpose(g)
+    for a, b, w in ((0.0, 1.0, inputs.weights_ppr(0.2, 10)), (1.0, 0.0, inputs.weights_ppr(0.2, 10)),
+                    (0.3, 0.7, inputs.weights_hkpr(2.0, 6))):
+        fwd = orc.truncated_sum(gt, a, b, w, x, fdeg=outdeg)
+        assert np.allclose(fwd, dense.horner_directed(g, a, b, w, x, False), rtol=1e-12, atol=1e-14)
+        rev = orc.truncated_sum(g, a, b, w, x, fdeg=outdeg)
+        assert np.allclose(rev, dense.horner_directed(g, a, b, w, x, True), rtol=1e-12, atol=1e-14)
+
+
+def test_degree_sort_threads_change_nothing(orc):
+    g = inputs.chung_lu(9000, 8, 2.2, seed=5, self_loops=True)
+    one = orc.degree_sort(g, threads=1)
+    many = orc.degree_sort(g, threads=7)
+    assert np.array_equal(one.col, many.col) and np.array_equal(one.fdeg, many.fdeg)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    key = one.fdeg[one.col].astype(np.int64) * g.n + one.col
+    assert np.all((np.diff(key) > 0) | (np.diff(rows) != 0))  # ascending (degree, id) inside every row
+    assert np.array_equal(np.sort(one.col.astype(np.int64) + rows * g.n), np.sort(g.col + rows * g.n))
+
+
+def test_bounded_timing_samples(orc):
+    """stop_level ends after a level with that level's counters complete;
+    sample_stride visits only every k-th node at the stop level."""
+    g = inputs.chung_lu(3000, 8, 2.3, seed=9, self_loops=True)
+    sg = orc.degree_sort(g)
+    x = inputs.features_uniform(g.n, 2, -1.0, 1.0, seed=4)
+    w = inputs.weights_ppr(0.1, 6)
+    _, full = orc.propagate(sg, 0.5, 0.5, w, x, 1e-4, 3)
+    for stop in (0, 2):
+        _, part = orc.propagate(sg, 0.5, 0.5, w, x, 1e-4, 3, stop_level=stop)
+        for k in full:
+            assert np.array_equal(part[k][:, : stop + 1], full[k][:, : stop + 1])
+            assert not part[k][:, stop + 1:].any()
+    _, samp = orc.propagate(sg, 0.5, 0.5, w, x, 1e-4, 3, stop_level=0, sample_stride=4)
+    assert np.array_equal(samp["frontier"][:, 0], (x[::4] != 0).sum(axis=0))
+    assert 0 < samp["det"][:, 0].sum() + samp["acc"][:, 0].sum() < full["det"][:, 0].sum() + full["acc"][:, 0].sum()
+
+
+def _hub_graph(m=40, step=5):
+    """Node 0 with m neighbours 1..m; neighbour k has degree 1 + step k (its
+    other arcs go to leaves of their own), so the neighbours' degrees span
+    several groups floor(log2 d)."""
+    src, dst = [np.zeros(m, dtype=np.int64)], [np.arange(1, m + 1)]
+    nxt = m + 1
+    for k in range(1, m + 1):
+        extra = step * k
+        src.append(np.full(extra, k))
+        dst.append(np.arange(nxt, nxt + extra))
+        nxt += extra
+    return inputs.csr_from_pairs(nxt, np.concatenate(src), np.concatenate(dst))
+
+
+@pytest.mark.parametrize("theta,merged", [(0.4, True), (0.04, False)])
+def test_subset_sampling_keeps_each_neighbour_independently(orc, theta, merged):
+    """Section 4: after the deterministic prefix every neighbour v of u is
+    pushed to with probability inc_v / theta, independently, whatever the
+    runs and windows the sampler cuts the row into.  With few expected
+    candidates (p* m <= 4) the row is one run; otherwise it starts with
+    runs per degree group."""
+    g = _hub_graph()
+    deg = g.degree
+    a, b, w = 0.5, 0.5, np.array([0.5, 0.5])
+    nb = g.col[g.row_ptr[0]:g.row_ptr[1]]
+    inc = 0.5 * deg[0] ** -b * deg[nb].astype(np.float64) ** -a
+    p = inc / theta
+    assert p.max() < 1.0 and (p.max() * nb.size <= 4.0) == merged
+    R = 20000
+    x = np.zeros((g.n, R))
+    x[0] = 1.0
+    sg = orc.degree_sort(g)
+    out, cnt = orc.propagate(sg, a, b, w, x, theta, seed=9, wp=64, qids=np.arange(R, dtype=np.uint32))
+    hit = out[nb] != 0.0  # L = 1: a neighbour keeps what it received
+    freq = hit.mean(axis=1)
+    assert np.all(np.abs(freq - p) <= 5 * np.sqrt(p * (1 - p) / R))
+    # pairs: 780 standardised differences of joint counts from p_v p_w R
+    joint = (hit[:, None, :] & hit[None, :, :]).sum(axis=2)
+    iu = np.triu_indices(nb.size, 1)
+    pp = np.outer(p, p)[iu]
+    z = (joint[iu] - pp * R) / np.sqrt(pp * (1 - pp) * R)
+    assert 0.8 <= (z ** 2).mean() <= 1.25 and np.abs(z).max() <= 6.5
+    groups = np.unique(np.floor(np.log2(deg[nb])))
+    runs = cnt["runs"][:, 0]
+    assert np.all(runs == runs[0])  # the runs depend on the row and c only
+    if merged:
+        assert runs[0] == 1
+    else:
+        assert 1 < runs[0] <= groups.size

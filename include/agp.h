@@ -191,6 +191,27 @@ int agp_propagate_f64(const agp_graph_t* g, double a, double b, const double* w,
                       const double* x, int32_t C, double eps, uint64_t seed,
                       const uint32_t* qids, double* out, void* stream, agp_stats_t* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * agp_propagate (binary32, same arguments, no stats) that allocates nothing.
+ * Its buffers live in one fixed array of AGP_NOALLOC_SCRATCH_BYTES in the
+ * library's static device memory, one copy per device, held until the
+ * process ends; they take 32 bytes per cell, so n * C is limited to about
+ * 2 million cells (AGP_EINVAL beyond, with the sizes in the message).  The
+ * degree-power tables of (a, b) must already exist on g: any earlier
+ * agp_propagate (or agp_autotune) on g with the same exponents makes them
+ * (AGP_EINVAL otherwise).  It runs frontier lists with atomic aggregation
+ * in one tile, and its result equals agp_propagate's bit for bit.  Every
+ * call on a device shares that device's array, which keeps the last call's
+ * contents (each call clears what must start at zero): calls that overlapped
+ * on one GPU would race, so the library runs them one at a time per device
+ * (each returns only after its work on `stream` has finished).  Errors as
+ * agp_propagate. */
+#define AGP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int agp_propagate_noalloc(const agp_graph_t* g, double a, double b, const double* w, int32_t L,
+                          const float* x, int32_t C, double eps, uint64_t seed, const uint32_t* qids,
+                          float* out, void* stream);
+
 /* Paper-literal variants of the propagation (agp_propagate_variant). */
 #define AGP_VARIANT_INFINITE_TAIL 1u /* Y_i over the infinite weight sequence */
 #define AGP_VARIANT_SPLIT_SIGNS 2u   /* x+ and x- propagated separately     */

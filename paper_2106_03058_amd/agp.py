@@ -25,8 +25,9 @@ EXPORTED = [
     "agp_weights_hkpr", "agp_weights_katz", "agp_weights_tp", "agp_server_create", "agp_submit",
     "agp_poll", "agp_server_destroy", "agp_autotune", "agp_get_tuning", "agp_sweep",
     "agp_propagate_variant", "agp_propagate_variant_f64", "agp_sweep_batch", "agp_graph_groups",
-    "agp_device_philox4x32_10", "agp_device_splitmix64", "agp_set_tuning",
+    "agp_device_philox4x32_10", "agp_device_splitmix64", "agp_set_tuning", "agp_propagate_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 64 << 20
 AGP_VARIANT_INFINITE_TAIL, AGP_VARIANT_SPLIT_SIGNS = 1, 2
 
 
@@ -88,6 +89,7 @@ def lib():
         L.agp_propagate.argtypes = prop
         L.agp_propagate_f64.argtypes = prop
         var = prop[:10] + [ct.c_uint32] + prop[10:]
+        L.agp_propagate_noalloc.argtypes = prop[:-1]
         L.agp_propagate_variant.argtypes = var
         L.agp_propagate_variant_f64.argtypes = var
         L.agp_weights_ppr.argtypes = [ct.c_double, ct.c_int32, dp]
@@ -236,6 +238,40 @@ def propagate(graph: Graph, a: float, b: float, w, x, eps: float, seed: int, *, 
     _check(fn(*args))
     res = o.reshape(-1) if vec else o
     return res, (st.to_dict() if st is not None else None)
+
+
+def propagate_noalloc(graph: Graph, a: float, b: float, w, x, eps: float, seed: int, *, qids=None, out=None,
+                      stream=None):
+    """propagate() through agp_propagate_noalloc: binary32, no stats, no
+    device allocation inside the call (the library's fixed per-device array
+    holds every buffer; at most about 2 million cells n * C).  Pass `out` to
+    keep the call itself free of allocations."""
+    import torch
+
+    if not x.is_cuda or x.dtype != torch.float32:
+        raise ValueError("x must be a float32 device tensor")
+    vec = x.dim() == 1
+    X = x.reshape(graph.n, -1)
+    if not X.is_contiguous():
+        raise ValueError("x must be contiguous")
+    C = X.shape[1]
+    if out is None:
+        out = torch.empty_like(X)
+    o = out.reshape(graph.n, -1)
+    if not o.is_contiguous() or o.dtype != X.dtype or o.shape != X.shape:
+        raise ValueError("out must be a contiguous tensor of x's shape and dtype")
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    q = None
+    if qids is not None:
+        q = np.ascontiguousarray(qids, dtype=np.uint32)
+        if q.size != C:
+            raise ValueError("need one qid per column")
+    _check(lib().agp_propagate_noalloc(graph.handle, float(a), float(b), w.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                       w.size - 1, _dptr(X), C, float(eps),
+                                       ct.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF),
+                                       None if q is None else q.ctypes.data_as(ct.POINTER(ct.c_uint32)), _dptr(o),
+                                       _stream_ptr(stream)))
+    return o.reshape(-1) if vec else o
 
 
 TUNING_FIELDS = ("aggregation", "level_blocks", "dense", "tile_columns", "big_row", "big_items",

@@ -27,6 +27,7 @@ int fail(int code, const std::string& msg);
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;  // a view of memory the library does not own: never freed or grown
   int reserve(size_t want, bool zero, hipStream_t s);
   void release();
   template <typename T>
@@ -96,5 +97,7 @@ struct agp_graph {
 
 namespace agp {
 // Device table of d^-e for d = 0..max_fdeg (0 at d = 0), cached per graph.
-int pow_table(agp_graph* g, double e, const double** out);
+// Device table d^-e for d = 0..max_fdeg, made on first use (may_alloc) and
+// kept with the graph; without may_alloc a missing table is AGP_EINVAL.
+int pow_table(agp_graph* g, double e, const double** out, bool may_alloc = true);
 }  // namespace agp

@@ -16,6 +16,9 @@ int fail(int code, const std::string& msg) {
 
 int DevBuf::reserve(size_t want, bool zero, hipStream_t s) {
   if (want <= bytes && ptr) return AGP_OK;
+  if (borrowed)  // a fixed region: it cannot grow
+    return fail(AGP_ENOMEM, "scratch region of " + std::to_string(bytes) + " bytes, " + std::to_string(want) +
+                                " needed");
   release();
   if (want == 0) want = 8;
   hipError_t e = hipMalloc(&ptr, want);
@@ -31,7 +34,7 @@ int DevBuf::reserve(size_t want, bool zero, hipStream_t s) {
 }
 
 void DevBuf::release() {
-  if (ptr) (void)hipFree(ptr);
+  if (ptr && !borrowed) (void)hipFree(ptr);
   ptr = nullptr;
   bytes = 0;
 }
@@ -79,12 +82,15 @@ static double degree_power(int64_t d, double e) {
   return std::pow(static_cast<double>(d), -e);
 }
 
-int pow_table(agp_graph* g, double e, const double** out) {
+int pow_table(agp_graph* g, double e, const double** out, bool may_alloc) {
   auto it = g->pow_tables.find(e);
   if (it != g->pow_tables.end()) {
     *out = it->second;
     return AGP_OK;
   }
+  if (!may_alloc)
+    return fail(AGP_EINVAL, "no degree-power table for exponent " + std::to_string(e) +
+                                " on this graph yet: an allocating call with it makes one");
   const size_t cnt = static_cast<size_t>(g->max_fdeg) + 1;
   std::vector<double> host(cnt);
   for (size_t d = 0; d < cnt; ++d) host[d] = degree_power(static_cast<int64_t>(d), e);

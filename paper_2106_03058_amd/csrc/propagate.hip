@@ -245,17 +245,16 @@ agp_tuning_t tuning_for(agp_graph* g, int32_t C, double a, double b, const agp_t
 // tile's counters and times are added to it).  The caller holds g->mu and
 // has zeroed out.
 template <typename T>
-int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, double a, double b,
-                   const std::vector<double>& rho, const std::vector<double>& kappa, int32_t L, const T* x,
-                   long long ldc, int32_t C, double eps, uint64_t seed, const uint32_t* qids, uint32_t qid_base,
-                   T* out, hipStream_t s, agp_stats_t* stats) {
+int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, double a, double b, const double* rho,
+                   const double* kappa, int32_t L, const T* x, long long ldc, int32_t C, double eps, uint64_t seed,
+                   const uint32_t* qids, uint32_t qid_base, T* out, hipStream_t s, agp_stats_t* stats, Scratch& sc,
+                   bool may_alloc) {
   using Cell = typename Prec<T>::Cell;
   const int64_t n = g->n;
   const size_t cells = static_cast<size_t>(n) * static_cast<size_t>(C);
   int rc;
   const double *da = nullptr, *db = nullptr;
-  if ((rc = pow_table(g, a, &da)) || (rc = pow_table(g, b, &db))) return rc;
-  Scratch& sc = g->scratch;
+  if ((rc = pow_table(g, a, &da, may_alloc)) || (rc = pow_table(g, b, &db, may_alloc))) return rc;
   const size_t cell_bytes = sizeof(Cell) * (sizeof(T) == 4 ? 1 : 2);
   const int64_t tblocks = (n + kThetaRows - 1) / kThetaRows;
   if ((rc = sc.acc[0].reserve(cells * cell_bytes, true, s)) ||
@@ -366,7 +365,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   unsigned long long* samp_ctr = nullptr;
   BigRow* big_rows = nullptr;
   BigSamp* samp_rows = nullptr;
-  if (big_cap > 0 &&
+  if (big_cap > 0 && (may_alloc || sc.big.bytes > 0) &&
       sc.big.reserve(sizeof(unsigned long long) * 2 * (AGP_MAX_LEVELS + 1) + sizeof(BigRow) * kBigCap +
                          sizeof(BigSamp) * kBigCap,
                      false, s) == AGP_OK) {
@@ -462,9 +461,9 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     if (stats) AGP_HIP(hipEventRecord(ev[4 * i + 3], s));
   }
   AGP_HIP(hipGetLastError());
-  std::vector<double> hmass(static_cast<size_t>(L) + 1);
+  double hmass[AGP_MAX_LEVELS + 1];
   AGP_HIP(hipMemcpyAsync(hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
-  AGP_HIP(hipMemcpyAsync(hmass.data(), mass, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, s));
+  AGP_HIP(hipMemcpyAsync(hmass, mass, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, s));
   AGP_HIP(hipStreamSynchronize(s));
   // no partial sum can wrap while a level's total magnitude stays below the cell range
   const double mass_cap = sizeof(T) == 4 ? 0x1p61 : 0x1p125;
@@ -640,7 +639,7 @@ DensePlan dense_plan(agp_graph* g, int32_t C, const agp_tuning_t& tune, bool bin
 // apart; cpt: the tile's column parameters with theta, units and qids set).
 // The caller holds g->mu.
 int propagate_dense_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, const DensePlan& plan, double a,
-                         double b, const std::vector<double>& rho, const std::vector<double>& kappa, int32_t L,
+                         double b, const double* rho, const double* kappa, int32_t L,
                          const float* x, long long ldc, int32_t Ct, const ColParams* cpt, uint64_t seed, float* out,
                          hipStream_t s, agp_stats_t* stats) {
   using namespace dense;
@@ -786,9 +785,9 @@ int propagate_dense_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune,
   }
   AGP_HIP(hipGetLastError());
   int herr = 0;
-  std::vector<double> hmass(static_cast<size_t>(L) + 1);
+  double hmass[AGP_MAX_LEVELS + 1];
   AGP_HIP(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, s));
-  AGP_HIP(hipMemcpyAsync(hmass.data(), mass, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, s));
+  AGP_HIP(hipMemcpyAsync(hmass, mass, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, s));
   AGP_HIP(hipStreamSynchronize(s));
   for (int32_t i = 0; i <= L; ++i)
     if (!(hmass[i] < 0x1p61)) herr |= 1;
@@ -875,7 +874,7 @@ int all_thresholds(agp_graph* g, const T* x, int32_t C, double eps, const uint32
 constexpr int kNotDense = -1;
 
 int propagate_dense(agp_graph* g, const char* fn, const agp_tuning_t& tune, double a, double b,
-                    const std::vector<double>& rho, const std::vector<double>& kappa, int32_t L, const float* x,
+                    const double* rho, const double* kappa, int32_t L, const float* x,
                     int32_t C, double eps, uint64_t seed, const uint32_t* qids, float* out, hipStream_t s,
                     agp_stats_t* stats) {
   const int64_t n = g->n;
@@ -903,12 +902,15 @@ int propagate_dense(agp_graph* g, const char* fn, const agp_tuning_t& tune, doub
   return AGP_OK;
 }
 
+// borrowed: a fixed scratch region instead of the graph's (nothing is
+// allocated: frontier lists, atomics, one tile of all columns, degree-power
+// tables that already exist); name: the entry point named in errors.
 template <typename T>
 int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L, const T* x,
                    int32_t C, double eps, uint64_t seed, const uint32_t* qids, T* out,
                    hipStream_t s, agp_stats_t* stats, const agp_tuning_t* force = nullptr,
-                   bool tail = false) {
-  const char* fn = sizeof(T) == 4 ? "agp_propagate" : "agp_propagate_f64";
+                   bool tail = false, Scratch* borrowed = nullptr, const char* name = nullptr) {
+  const char* fn = name ? name : (sizeof(T) == 4 ? "agp_propagate" : "agp_propagate_f64");
   if (!g) return fail(AGP_EINVAL, std::string(fn) + ": NULL graph");
   if (!(a >= 0.0 && a <= 1.0) || !(b >= 0.0 && b <= 1.0))
     return fail(AGP_EINVAL, std::string(fn) + ": a and b must lie in [0, 1]");
@@ -945,9 +947,8 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
       return fail(AGP_EINVAL, std::string(fn) + ": the infinite tail needs w_0 + ... + w_L <= 1");
     tail_mass = total < 1.0 ? 1.0 - total : 0.0;
   }
-  std::vector<double> Y(static_cast<size_t>(L) + 2, 0.0), rho(static_cast<size_t>(L) + 1),
-      kappa(static_cast<size_t>(L) + 1);
-  Y[static_cast<size_t>(L) + 1] = tail_mass;
+  double Y[AGP_MAX_LEVELS + 2], rho[AGP_MAX_LEVELS + 1], kappa[AGP_MAX_LEVELS + 1];
+  Y[L + 1] = tail_mass;
   for (int32_t k = L; k >= 0; --k) Y[k] = Y[k + 1] + w[k];
   const double S = Y[0];
   for (int32_t i = 0; i <= L; ++i) {
@@ -956,10 +957,16 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   }
 
   std::lock_guard<std::mutex> lk(g->mu);
-  const agp_tuning_t tune = tuning_for(g, C, a, b, force);
+  agp_tuning_t tune = tuning_for(g, C, a, b, force);
+  Scratch& sc = borrowed ? *borrowed : g->scratch;
+  const bool may_alloc = borrowed == nullptr;
+  if (borrowed) {
+    tune.aggregation = 0;
+    tune.dense = 0;
+  }
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if constexpr (std::is_same<T, float>::value) {
-    if (tune.dense == 1 || (tune.dense == 2 && C >= 16)) {
+    if (may_alloc && (tune.dense == 1 || (tune.dense == 2 && C >= 16))) {
       const int rc = propagate_dense(g, fn, tune, a, b, rho, kappa, L, x, C, eps, seed, qids, out, s, stats);
       if (rc != kNotDense) {
         if (rc == AGP_OK && stats) {
@@ -971,12 +978,13 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
     }
   }
   const bool may_bin = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4;
-  const int32_t tile = column_tile<T>(g, C, may_bin, tune);
+  const int32_t tile = borrowed ? C : column_tile<T>(g, C, may_bin, tune);
   AGP_HIP(hipMemsetAsync(out, 0, cells * sizeof(T), s));
   for (int32_t c0 = 0; c0 < C; c0 += tile) {
     const int32_t ct = std::min(tile, C - c0);
     const int rc = propagate_tile<T>(g, fn, tune, a, b, rho, kappa, L, x + c0, static_cast<long long>(C), ct, eps,
-                                     seed, qids ? qids + c0 : nullptr, static_cast<uint32_t>(c0), out + c0, s, stats);
+                                     seed, qids ? qids + c0 : nullptr, static_cast<uint32_t>(c0), out + c0, s, stats,
+                                     sc, may_alloc);
     if (rc != AGP_OK) return rc;
   }
   if (stats) {
@@ -1111,6 +1119,97 @@ int propagate_variant(const agp_graph_t* g, double a, double b, const double* w,
 }  // namespace
 }  // namespace agp
 
+namespace agp {
+using namespace lvl;
+// ------------------------------------------------ allocation-free calls
+// One fixed scratch array per device (the library's static device memory),
+// for callers that cannot allocate.  In host code `scratch` names a host-side
+// stand-in: only the address hipGetSymbolAddress returns for the current
+// device may reach a kernel or a copy.
+static __device__ __align__(256) unsigned char scratch[AGP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu[kNoAllocDevices];   // one call at a time per device (they share the array)
+void* g_noalloc_base[kNoAllocDevices] = {};  // device address of the array, per device
+
+__global__ void k_zero_words(unsigned long long* p, size_t nwords) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+// Successive 256-byte aligned regions of [base, base + cap) as borrowed buffers.
+struct Carve {
+  char* base;
+  size_t cap;
+  size_t off = 0;
+  bool take(DevBuf& b, size_t bytes) {
+    const size_t at = (off + 255) & ~static_cast<size_t>(255);
+    const size_t len = bytes > 0 ? bytes : 8;
+    if (at > cap || len > cap - at) return false;
+    b.ptr = base + at;
+    b.bytes = len;
+    b.borrowed = true;
+    off = at + len;
+    return true;
+  }
+};
+}  // namespace
+
+int propagate_noalloc(agp_graph* g, double a, double b, const double* w, int32_t L, const float* x, int32_t C,
+                      double eps, uint64_t seed, const uint32_t* qids, float* out, hipStream_t s) {
+  const char* fn = "agp_propagate_noalloc";
+  if (!g) return fail(AGP_EINVAL, std::string(fn) + ": NULL graph");
+  if (C < 1) return fail(AGP_EINVAL, std::string(fn) + ": need C >= 1");
+  int dev = 0;
+  AGP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices) return fail(AGP_EDEVICE, std::string(fn) + ": device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu[dev]);
+  if (!g_noalloc_base[dev]) {  // first call on this device: the array's address here
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return fail(AGP_EDEVICE, std::string(fn) + ": hipGetSymbolAddress of the scratch array failed: " +
+                                   hipGetErrorString(e));
+    }
+    g_noalloc_base[dev] = p;
+  }
+  // the buffers of one tile of all C columns (frontier lists, atomics)
+  using Cell = Prec<float>::Cell;
+  const int64_t n = g->n;
+  const size_t cells = static_cast<size_t>(n) * static_cast<size_t>(C);
+  if (n > 0 && cells / static_cast<size_t>(n) != static_cast<size_t>(C))
+    return fail(AGP_EINVAL, std::string(fn) + ": n * C overflows");
+  const int64_t tblocks = (n + kThetaRows - 1) / kThetaRows;
+  Scratch v;
+  Carve cv{static_cast<char*>(g_noalloc_base[dev]), static_cast<size_t>(AGP_NOALLOC_SCRATCH_BYTES)};
+  const bool fits = cells <= (static_cast<size_t>(AGP_NOALLOC_SCRATCH_BYTES) / sizeof(Cell)) &&
+                    cv.take(v.acc[0], cells * sizeof(Cell)) && cv.take(v.acc[1], cells * sizeof(Cell)) &&
+                    cv.take(v.frontier[0], cells * sizeof(uint64_t)) &&
+                    cv.take(v.frontier[1], cells * sizeof(uint64_t)) &&
+                    cv.take(v.counts, sizeof(unsigned long long) * (AGP_MAX_LEVELS + 2)) &&
+                    cv.take(v.counters, sizeof(unsigned long long) * kNumCounters * (AGP_MAX_LEVELS + 1)) &&
+                    cv.take(v.colparams, sizeof(ColParams) * C + sizeof(uint32_t) * C) &&
+                    cv.take(v.partial, sizeof(double) * static_cast<size_t>(std::max<int64_t>(tblocks, 1)) * C) &&
+                    cv.take(v.flags, sizeof(int) * 4) &&
+                    cv.take(v.levelinfo, (2 * sizeof(double) + sizeof(int)) * (AGP_MAX_LEVELS + 2));
+  if (!fits)
+    return fail(AGP_EINVAL, std::string(fn) + ": n * C = " + std::to_string(cells) + " cells need about " +
+                                std::to_string(cells * 2 * (sizeof(Cell) + sizeof(uint64_t))) +
+                                " bytes of scratch; the fixed array holds " +
+                                std::to_string(static_cast<size_t>(AGP_NOALLOC_SCRATCH_BYTES)));
+  // the residue accumulators start at zero (the array keeps the last call's contents)
+  const size_t words = 2 * cells * sizeof(Cell) / sizeof(unsigned long long);
+  k_zero_words<<<grid_for(static_cast<int64_t>(words > 0 ? words : 1), 256, 4096), 256, 0, s>>>(
+      static_cast<unsigned long long*>(v.acc[0].ptr), cells * sizeof(Cell) / sizeof(unsigned long long));
+  k_zero_words<<<grid_for(static_cast<int64_t>(words > 0 ? words : 1), 256, 4096), 256, 0, s>>>(
+      static_cast<unsigned long long*>(v.acc[1].ptr), cells * sizeof(Cell) / sizeof(unsigned long long));
+  AGP_HIP(hipGetLastError());
+  return propagate_impl<float>(g, a, b, w, L, x, C, eps, seed, qids, out, s, nullptr, nullptr, false, &v, fn);
+}
+}  // namespace agp
+
 extern "C" {
 
 int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int32_t L, const float* x,
@@ -1209,6 +1308,12 @@ int agp_propagate_f64(const agp_graph_t* g, double a, double b, const double* w,
                       double* out, void* stream, agp_stats_t* stats) {
   return agp::propagate_impl<double>(const_cast<agp_graph_t*>(g), a, b, w, L, x, C, eps, seed, qids, out,
                                      (hipStream_t)stream, stats);
+}
+
+int agp_propagate_noalloc(const agp_graph_t* g, double a, double b, const double* w, int32_t L, const float* x,
+                          int32_t C, double eps, uint64_t seed, const uint32_t* qids, float* out, void* stream) {
+  return agp::propagate_noalloc(const_cast<agp_graph_t*>(g), a, b, w, L, x, C, eps, seed, qids, out,
+                                (hipStream_t)stream);
 }
 
 int agp_propagate_variant(const agp_graph_t* g, double a, double b, const double* w, int32_t L, const float* x,

@@ -739,6 +739,8 @@ def level_roofline(runs, models, args, C) -> dict:
                 lvl_ms += float(st["level_ms"][i])
             alg += alg_bytes(st, lv, m["a"] == 0.0)
             launches += len(lv) * max(int(st["tiles"]), 1)
+    if lvl_ms <= 0.0:  # captured level loops are timed as a whole, not per level
+        return None
     avg_s = lvl_ms / 1e3 / max(launches, 1)
     alg_gbps = alg / (lvl_ms / 1e3) / 1e9
     rec = TRAFFIC.get(args.workload)
@@ -795,6 +797,8 @@ def main() -> int:
     ap.add_argument("--columns", type=int, default=256, help="columns per call (profiling)")
     ap.add_argument("--large-n", type=int, default=111_059_956, help="gnn-ppr-large: nodes")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--capture", action="store_true",
+                    help="run every call's level loops as captured hipGraphs (tuning field capture)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device to device first (reference for HBM counters)")
     args = ap.parse_args()
@@ -802,6 +806,8 @@ def main() -> int:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         return 2
     args.host_leg = (not args.no_cpu_baseline) or args.exact_units > 0 or args.parity_columns > 0
+    if args.capture:
+        os.environ["AGP_CAPTURE"] = "1"
 
     import torch
 
@@ -895,7 +901,7 @@ def main() -> int:
         for (st, _), m in zip(r, models):
             L = st["levels"]
             all_bytes += alg_bytes(st, range(L + 1), m["a"] == 0.0)
-            all_ms += float(st["level_total_ms"].sum())
+            all_ms += float(st["level_total_ms"].sum()) or float(st["device_ms"])
     per_level = []
     for (st, ms), m in zip(runs[0], models):
         per_level.append({"model": m["name"], "call_ms": round(ms, 3), "tiles": int(st["tiles"]),
@@ -914,18 +920,20 @@ def main() -> int:
     q_per_s_batched = len(models) * C / (ms_per_step / 1e3)
     lat_s = []
     nq = single // max(len(models), 1)
+    # one input and one output buffer for every single-unit call (a captured
+    # level loop is replayed when the buffers stay the same)
     one = torch.empty((n, 1), dtype=torch.float32, device=dev) if nq > 0 else None
+    one_x = torch.empty((n, 1), dtype=torch.float32, device=dev) if nq > 0 else None
     single_ok = True
     for m, o, Gm, Xm in zip(models, outs, Gs, Xs):
         for c in range(min(nq, C)):
-            xc = Xm[:, c:c + 1].contiguous()
+            one_x.copy_(Xm[:, c:c + 1])
             torch.cuda.synchronize()
             ts = time.perf_counter()
-            agp.propagate(Gm, m["a"], m["b"], m["w"], xc, m["eps"], args.seed, qids=m["qids"][c:c + 1], out=one)
+            agp.propagate(Gm, m["a"], m["b"], m["w"], one_x, m["eps"], args.seed, qids=m["qids"][c:c + 1], out=one)
             lat_s.append((time.perf_counter() - ts) * 1e3)
             single_ok &= bool(torch.equal(one[:, 0], o[:, c]))
-            del xc
-    del one
+    del one, one_x
     log(f"{len(lat_s)} units one per launch, equal to the batched columns: {single_ok}")
 
     result = {
@@ -943,6 +951,7 @@ def main() -> int:
         "data": "synthetic",
         "config": cfg,
         "tuning": tunings,
+        "captured_level_loops": bool(args.capture),
         "pushes_per_step": pushes_step,
         "hbm_gbps_algorithmic_all_levels": all_bytes / (all_ms / 1e3) / 1e9,
         "hbm_copy_probe_gbps": copy_gbps,

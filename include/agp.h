@@ -266,6 +266,11 @@ typedef struct agp_tuning {
                            entries appends first contributions directly; 0: 5 */
   int32_t bin_shift;    /* (aggregation 2) a level whose estimated pushes reach
                            n C / 2^k is binned; 0: 3                            */
+  int32_t capture;      /* 1: the level loop of each column tile (frontier
+                           lists) is captured once into a hipGraph per graph,
+                           column count, level count, buffers and modes, and
+                           replayed by later calls (per-level times are then
+                           not recorded); 0: launched kernel by kernel        */
 } agp_tuning_t;
 
 /* Autotuner: runs the propagation of the arguments (as agp_propagate) once
@@ -296,6 +301,7 @@ int agp_set_tuning(const agp_graph_t* g, int32_t C, double a, double b, const ag
  * tests; none of them changes a result):
  *   AGP_AGGREGATION=atomic|binned|auto   the aggregation of agp_tuning_t;
  *   AGP_DENSE=0|1|auto   the dense field of agp_tuning_t;
+ *   AGP_CAPTURE=0|1      the capture field of agp_tuning_t;
  *   AGP_RECORD_CAP=n     at most n push records per binned level (per record
  *                        group on dense levels; records beyond it are added
  *                        with atomics);

@@ -275,7 +275,7 @@ def propagate_noalloc(graph: Graph, a: float, b: float, w, x, eps: float, seed: 
 
 
 TUNING_FIELDS = ("aggregation", "level_blocks", "dense", "tile_columns", "big_row", "big_items",
-                 "sparse_shift", "bin_shift")
+                 "sparse_shift", "bin_shift", "capture")
 
 
 class Tuning(ct.Structure):

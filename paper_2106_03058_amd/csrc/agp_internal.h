@@ -93,11 +93,15 @@ struct agp_graph {
   std::map<agp_tune_key, agp_tuning_t> tuning;  // autotuned execution choices
   std::mutex mu;
   agp::Scratch scratch;
+  // captured level loops (tuning field `capture`), keyed by everything their
+  // kernels take by value: sizes, pointers, exponents, modes
+  std::map<std::string, hipGraphExec_t> loops;
+  hipStream_t capture_stream = nullptr;  // private stream the loops are captured on
+  void drop_loops();
 };
 
 namespace agp {
-// Device table of d^-e for d = 0..max_fdeg (0 at d = 0), cached per graph.
-// Device table d^-e for d = 0..max_fdeg, made on first use (may_alloc) and
+// Device table d^-e for d = 0..max_fdeg (0 at d = 0), made on first use (may_alloc) and
 // kept with the graph; without may_alloc a missing table is AGP_EINVAL.
 int pow_table(agp_graph* g, double e, const double** out, bool may_alloc = true);
 }  // namespace agp

@@ -108,6 +108,11 @@ int pow_table(agp_graph* g, double e, const double** out, bool may_alloc) {
 
 }  // namespace agp
 
+void agp_graph::drop_loops() {
+  for (auto& kv : loops) (void)hipGraphExecDestroy(kv.second);
+  loops.clear();
+}
+
 extern "C" {
 
 const char* agp_last_error(void) { return agp::t_last_error.c_str(); }

@@ -582,6 +582,8 @@ int agp_graph_destroy(agp_graph_t* g) {
   {
     std::lock_guard<std::mutex> lk(g->mu);
     (void)hipDeviceSynchronize();
+    g->drop_loops();
+    if (g->capture_stream) (void)hipStreamDestroy(g->capture_stream);
     g->scratch.release();
     for (auto& kv : g->pow_tables) (void)hipFree(kv.second);
     (void)hipFree(g->row_ptr);

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <initializer_list>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -155,20 +156,29 @@ __global__ void k_theta_final(const double* __restrict__ partial, int64_t nblock
 }
 
 // Level-dependent parameters of every column of a batched call.
-__global__ void k_set_level(ColParams* __restrict__ cp, int C, int level, double rho, double kappa,
-                            int flags, const double* da, const double* db, uint32_t key0, uint32_t key1,
-                            void* out, long long out_stride, size_t elem) {
+// Per-level values of a call, in device memory so that a captured level
+// loop serves every call with the same buffers.
+struct LevelParams {
+  double rho, kappa;
+  int flags;
+  uint32_t key0, key1;
+  int pad;
+};
+
+__global__ void k_set_level(ColParams* __restrict__ cp, int C, int level, const LevelParams* __restrict__ lp,
+                            const double* da, const double* db, void* out, long long out_stride, size_t elem) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
   ColParams& p = cp[c];
+  const LevelParams q = lp[level];
   p.level = level;
-  p.rho = rho;
-  p.kappa = kappa;
-  p.flags = flags;
+  p.rho = q.rho;
+  p.kappa = q.kappa;
+  p.flags = q.flags;
   p.da = da;
   p.db = db;
-  p.key0 = key0;
-  p.key1 = key1;
+  p.key0 = q.key0;
+  p.key1 = q.key1;
   p.out = static_cast<char*>(out) + static_cast<size_t>(c) * elem;
   p.out_stride = out_stride;
 }
@@ -187,6 +197,7 @@ agp_tuning_t default_tuning() {
   t.big_items = static_cast<int32_t>(kBigItems);
   t.sparse_shift = kSparseShift;
   t.bin_shift = kBinShift;
+  t.capture = 0;
   return t;
 }
 
@@ -203,6 +214,7 @@ agp_tuning_t normalize_tuning(agp_tuning_t t) {
   if (t.big_items <= 0) t.big_items = d.big_items;
   if (t.sparse_shift <= 0 || t.sparse_shift > 30) t.sparse_shift = d.sparse_shift;
   if (t.bin_shift <= 0 || t.bin_shift > 30) t.bin_shift = d.bin_shift;
+  if (t.capture != 1) t.capture = 0;
   return t;
 }
 
@@ -227,6 +239,10 @@ agp_tuning_t tuning_for(agp_graph* g, int32_t C, double a, double b, const agp_t
     if (std::strcmp(e, "0") == 0) t.dense = 0;
     if (std::strcmp(e, "1") == 0) t.dense = 1;
     if (std::strcmp(e, "auto") == 0) t.dense = 2;
+  }
+  if (const char* e = std::getenv("AGP_CAPTURE")) {
+    if (std::strcmp(e, "0") == 0) t.capture = 0;
+    if (std::strcmp(e, "1") == 0) t.capture = 1;
   }
   if (const char* e = std::getenv("AGP_COLUMN_TILE")) {
     const long v = std::strtol(e, nullptr, 10);
@@ -266,7 +282,9 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
       (rc = sc.colparams.reserve(sizeof(ColParams) * C + sizeof(uint32_t) * C, false, s)) ||
       (rc = sc.partial.reserve(sizeof(double) * (size_t)std::max<int64_t>(tblocks, 1) * C, false, s)) ||
       (rc = sc.flags.reserve(sizeof(int) * 4, false, s)) ||
-      (rc = sc.levelinfo.reserve((2 * sizeof(double) + sizeof(int)) * (AGP_MAX_LEVELS + 2), false, s)))
+      (rc = sc.levelinfo.reserve((2 * sizeof(double) + sizeof(int)) * (AGP_MAX_LEVELS + 2) + 256 +
+                                     sizeof(LevelParams) * (AGP_MAX_LEVELS + 1),
+                                 false, s)))
     return rc;
 
   ColParams* cp = sc.colparams.as<ColParams>();
@@ -277,6 +295,8 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   double* mass = sc.levelinfo.as<double>();
   double* est = mass + AGP_MAX_LEVELS + 2;  // estimated pushes per level (auto aggregation)
   int* mode = reinterpret_cast<int*>(est + AGP_MAX_LEVELS + 2);
+  LevelParams* lpd = reinterpret_cast<LevelParams*>(
+      (reinterpret_cast<uintptr_t>(mode + AGP_MAX_LEVELS + 2) + 255) & ~static_cast<uintptr_t>(255));
   AGP_HIP(hipMemsetAsync(sc.levelinfo.ptr, 0, sc.levelinfo.bytes, s));
   AGP_HIP(hipMemsetAsync(counts, 0, sc.counts.bytes, s));
   AGP_HIP(hipMemsetAsync(counters, 0, sc.counters.bytes, s));
@@ -402,63 +422,123 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   A.bucket_shift = shift;
   A.bin_est = nullptr;
   A.bin_pushes = std::ldexp(static_cast<double>(cells), -tune.bin_shift);  // auto: bin levels with n C / 2^k pushes
+  // per-level values of this call (read by k_set_level from device memory)
+  LevelParams lph[AGP_MAX_LEVELS + 1];
   const uint32_t key0 = static_cast<uint32_t>(seed), key1 = static_cast<uint32_t>(seed >> 32);
   for (int32_t i = 0; i <= L; ++i) {
-    const int lflags = (i == L ? kLastLevel : 0) | (a == 0.0 ? kAZero : 0);
-    k_set_level<<<grid_for(C, 64), 64, 0, s>>>(cp, C, i, rho[i], kappa[i], lflags, da, db, key0, key1, out,
-                                              ldc, sizeof(T));
-    A.level = i;
-    A.fin = F[i & 1];
-    A.cnt_in = counts + i;
-    A.fout = F[(i + 1) & 1];
-    A.cnt_out = counts + i + 1;
-    A.mode_out = mode + i + 1;
-    const bool bin_level = binned && i < L;
-    A.rec = bin_level ? sc.rec[0].as<uint32_t>() : nullptr;
-    A.det_bins = bin_level ? det_bins : nullptr;
-    A.big_ctr = (big_ctr != nullptr && i < L) ? big_ctr + i : nullptr;
-    A.samp_ctr = (samp_ctr != nullptr && i < L) ? samp_ctr + i : nullptr;
-    A.big = big_rows;
-    A.samp = samp_rows;
-    A.samp_items = samp_items;
-    A.big_cap = big_cap;
-    A.rec_count = bin_level ? rec_counts + i : nullptr;
-    Cell* cur = acc[i & 1];
-    Cell* nxt = acc[(i + 1) & 1];
-    A.bin_est = nullptr;
-    if (stats) AGP_HIP(hipEventRecord(ev[4 * i], s));
-    if (bin_level && tune.aggregation == 2) {
-      A.bin_est = est + i;
+    lph[i].rho = rho[i];
+    lph[i].kappa = kappa[i];
+    lph[i].flags = (i == L ? kLastLevel : 0) | (a == 0.0 ? kAZero : 0);
+    lph[i].key0 = key0;
+    lph[i].key1 = key1;
+    lph[i].pad = 0;
+  }
+  AGP_HIP(hipMemcpyAsync(lpd, lph, sizeof(LevelParams) * (L + 1), hipMemcpyHostToDevice, s));
+
+  // the level loop: every decision stays on the device, so it can be
+  // captured once and replayed (timed per level only when launched directly)
+  auto levels = [&](hipStream_t s, bool timed) {
+    for (int32_t i = 0; i <= L; ++i) {
+      k_set_level<<<grid_for(C, 64), 64, 0, s>>>(cp, C, i, lpd, da, db, out, ldc, sizeof(T));
+      A.level = i;
+      A.fin = F[i & 1];
+      A.cnt_in = counts + i;
+      A.fout = F[(i + 1) & 1];
+      A.cnt_out = counts + i + 1;
+      A.mode_out = mode + i + 1;
+      const bool bin_level = binned && i < L;
+      A.rec = bin_level ? sc.rec[0].as<uint32_t>() : nullptr;
+      A.det_bins = bin_level ? det_bins : nullptr;
+      A.big_ctr = (big_ctr != nullptr && i < L) ? big_ctr + i : nullptr;
+      A.samp_ctr = (samp_ctr != nullptr && i < L) ? samp_ctr + i : nullptr;
+      A.big = big_rows;
+      A.samp = samp_rows;
+      A.samp_items = samp_items;
+      A.big_cap = big_cap;
+      A.rec_count = bin_level ? rec_counts + i : nullptr;
+      Cell* cur = acc[i & 1];
+      Cell* nxt = acc[(i + 1) & 1];
+      A.bin_est = nullptr;
+      if (timed) (void)hipEventRecord(ev[4 * i], s);
+      if (bin_level && tune.aggregation == 2) {
+        A.bin_est = est + i;
+        if (i == 0)
+          k_estimate<T, true><<<1024, kThreads, 0, s>>>(A, x, cur, est + i);
+        else
+          k_estimate<T, false><<<1024, kThreads, 0, s>>>(A, x, cur, est + i);
+      }
+      if (timed) (void)hipEventRecord(ev[4 * i + 1], s);
       if (i == 0)
-        k_estimate<T, true><<<1024, kThreads, 0, s>>>(A, x, cur, est + i);
+        k_level<T, true, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
       else
-        k_estimate<T, false><<<1024, kThreads, 0, s>>>(A, x, cur, est + i);
+        k_level<T, false, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
+      if (A.big_ctr != nullptr) k_det_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
+      if (A.samp_ctr != nullptr) k_samp_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
+      if (timed) (void)hipEventRecord(ev[4 * i + 2], s);
+      if (bin_level) {
+        uint32_t* r0 = sc.rec[0].as<uint32_t>();
+        uint32_t* r1 = sc.rec[1].as<uint32_t>();
+        k_bins_scan<<<1, kBuckets, 0, s>>>(bucket_count, bucket_off, cursor, rec_counts + i, rec_cap, mode + i + 1);
+        k_apply_overflow<<<2048, kThreads, 0, s>>>(A, reinterpret_cast<long long*>(nxt), mode + i + 1);
+        k_partition<<<1024, kReduceThreads, 0, s>>>(r0, rec_counts + i, cursor, r1, mode + i + 1, shift);
+        k_bin_count<<<2048, kReduceThreads, 0, s>>>(r1, rec_counts + i, bin_count, mode + i + 1, shift);
+        k_bin_scan<<<1, 1024, 0, s>>>(bin_count, nbins, bin_off, bin_cur, mode + i + 1);
+        k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(r1, rec_counts + i, bin_cur, r0, mode + i + 1, shift);
+        k_bin_sum<<<static_cast<unsigned>(nbins), kSumThreads, 0, s>>>(
+            r0, bin_off, cp, (long long)C, 1ll, static_cast<unsigned long long>(cells),
+            reinterpret_cast<long long*>(nxt), F[(i + 1) & 1], counts + i + 1, mode + i + 1, det_bins);
+      }
+      if (i < L)
+        k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, (long long)C, 1ll, F[(i + 1) & 1],
+                                             counts + i + 1, mode + i + 1);
+      if (timed) (void)hipEventRecord(ev[4 * i + 3], s);
     }
-    if (stats) AGP_HIP(hipEventRecord(ev[4 * i + 1], s));
-    if (i == 0)
-      k_level<T, true, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
-    else
-      k_level<T, false, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
-    if (A.big_ctr != nullptr) k_det_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
-    if (A.samp_ctr != nullptr) k_samp_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
-    if (stats) AGP_HIP(hipEventRecord(ev[4 * i + 2], s));
-    if (bin_level) {
-      uint32_t* r0 = sc.rec[0].as<uint32_t>();
-      uint32_t* r1 = sc.rec[1].as<uint32_t>();
-      k_bins_scan<<<1, kBuckets, 0, s>>>(bucket_count, bucket_off, cursor, rec_counts + i, rec_cap, mode + i + 1);
-      k_apply_overflow<<<2048, kThreads, 0, s>>>(A, reinterpret_cast<long long*>(nxt), mode + i + 1);
-      k_partition<<<1024, kReduceThreads, 0, s>>>(r0, rec_counts + i, cursor, r1, mode + i + 1, shift);
-      k_bin_count<<<2048, kReduceThreads, 0, s>>>(r1, rec_counts + i, bin_count, mode + i + 1, shift);
-      k_bin_scan<<<1, 1024, 0, s>>>(bin_count, nbins, bin_off, bin_cur, mode + i + 1);
-      k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(r1, rec_counts + i, bin_cur, r0, mode + i + 1, shift);
-      k_bin_sum<<<static_cast<unsigned>(nbins), kSumThreads, 0, s>>>(
-          r0, bin_off, cp, (long long)C, 1ll, static_cast<unsigned long long>(cells),
-          reinterpret_cast<long long*>(nxt), F[(i + 1) & 1], counts + i + 1, mode + i + 1, det_bins);
+  };
+  if (tune.capture == 1) {
+    // key: everything the captured kernels take by value
+    char key[512];
+    const int kn = std::snprintf(
+        key, sizeof(key), "%lld|%d|%d|%lld|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%llu|%d|%llu|%d|%d|%d|%d|%d|%d",
+        static_cast<long long>(n), C, L, static_cast<long long>(ldc), static_cast<const void*>(x),
+        static_cast<void*>(out), static_cast<void*>(cp), static_cast<void*>(acc[0]), static_cast<void*>(acc[1]),
+        static_cast<void*>(F[0]), static_cast<void*>(F[1]), static_cast<void*>(counts), static_cast<void*>(counters),
+        static_cast<void*>(sc.levelinfo.ptr), static_cast<void*>(flags), static_cast<const void*>(da),
+        static_cast<const void*>(db), static_cast<void*>(sc.rec[0].ptr), static_cast<void*>(sc.bins.ptr),
+        positive ? 1 : 0, binned ? 1 : 0, rec_cap, shift, big_cap, big_ctr != nullptr ? 1 : 0, tune.aggregation,
+        tune.level_blocks, tune.big_row, tune.big_items, (tune.sparse_shift << 8) | tune.bin_shift);
+    std::string k(key, kn > 0 ? static_cast<size_t>(kn) : 0);
+    k.append(reinterpret_cast<const char*>(&big_rows), sizeof(big_rows));
+    k.append(reinterpret_cast<const char*>(&samp_rows), sizeof(samp_rows));
+    k.append(reinterpret_cast<const char*>(&samp_items), sizeof(samp_items));
+    k.append(reinterpret_cast<const char*>(&sc.rec[1].ptr), sizeof(void*));
+    hipGraphExec_t exec = nullptr;
+    auto it = g->loops.find(k);
+    if (it != g->loops.end()) {
+      exec = it->second;
+    } else {
+      if (!g->capture_stream) AGP_HIP(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
+      hipStream_t cs = g->capture_stream;
+      AGP_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      levels(cs, false);
+      hipGraph_t graph = nullptr;
+      const hipError_t le = hipGetLastError();
+      const hipError_t ee = hipStreamEndCapture(cs, &graph);
+      if (le != hipSuccess || ee != hipSuccess || graph == nullptr) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(AGP_EDEVICE, std::string(fn) + ": capturing the level loop failed: " +
+                                     hipGetErrorString(le != hipSuccess ? le : ee));
+      }
+      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) return fail(AGP_EDEVICE, std::string(fn) + ": " + hipGetErrorString(ie));
+      if (g->loops.size() >= 32) g->drop_loops();  // a bounded cache
+      g->loops.emplace(k, exec);
     }
-    if (i < L)
-      k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, (long long)C, 1ll, F[(i + 1) & 1],
-                                           counts + i + 1, mode + i + 1);
-    if (stats) AGP_HIP(hipEventRecord(ev[4 * i + 3], s));
+    if (stats) AGP_HIP(hipEventRecord(ev[0], s));
+    AGP_HIP(hipGraphLaunch(exec, s));
+    if (stats) AGP_HIP(hipEventRecord(ev[4 * L + 3], s));
+  } else {
+    levels(s, stats != nullptr);
   }
   AGP_HIP(hipGetLastError());
   double hmass[AGP_MAX_LEVELS + 1];
@@ -490,7 +570,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
       stats->runs[i] += h[i * kNumCounters + 5];
     }
     float ms = 0.0f;
-    for (int32_t i = 0; i <= L; ++i) {
+    for (int32_t i = 0; i <= L && tune.capture != 1; ++i) {  // a replayed loop is timed as a whole
       AGP_HIP(hipEventElapsedTime(&ms, ev[4 * i + 1], ev[4 * i + 2]));
       stats->level_ms[i] += ms;
       AGP_HIP(hipEventElapsedTime(&ms, ev[4 * i], ev[4 * i + 3]));
@@ -963,6 +1043,7 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
   if (borrowed) {
     tune.aggregation = 0;
     tune.dense = 0;
+    tune.capture = 0;
   }
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if constexpr (std::is_same<T, float>::value) {
@@ -1193,7 +1274,8 @@ int propagate_noalloc(agp_graph* g, double a, double b, const double* w, int32_t
                     cv.take(v.colparams, sizeof(ColParams) * C + sizeof(uint32_t) * C) &&
                     cv.take(v.partial, sizeof(double) * static_cast<size_t>(std::max<int64_t>(tblocks, 1)) * C) &&
                     cv.take(v.flags, sizeof(int) * 4) &&
-                    cv.take(v.levelinfo, (2 * sizeof(double) + sizeof(int)) * (AGP_MAX_LEVELS + 2));
+                    cv.take(v.levelinfo, (2 * sizeof(double) + sizeof(int)) * (AGP_MAX_LEVELS + 2) + 256 +
+                                              sizeof(LevelParams) * (AGP_MAX_LEVELS + 1));
   if (!fits)
     return fail(AGP_EINVAL, std::string(fn) + ": n * C = " + std::to_string(cells) + " cells need about " +
                                 std::to_string(cells * 2 * (sizeof(Cell) + sizeof(uint64_t))) +
@@ -1261,6 +1343,7 @@ int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int3
     field(&agp_tuning_t::big_items, {16, 64, 256});
     field(&agp_tuning_t::sparse_shift, {3, 5, 7});
     if (pick.aggregation == 2) field(&agp_tuning_t::bin_shift, {2, 3, 5});
+    field(&agp_tuning_t::capture, {0, 1});
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -284,7 +284,7 @@ def test_autotune_keeps_results(agp, torch_dev):
     X = torch.from_numpy(x).to(dev)
     before = agp.get_tuning(G, 40, 0.0, 1.0)
     assert before == {"aggregation": "auto", "level_blocks": 4096, "dense": "never", "tile_columns": 0,
-                      "big_row": 4096, "big_items": 64, "sparse_shift": 5, "bin_shift": 3}
+                      "big_row": 4096, "big_items": 64, "sparse_shift": 5, "bin_shift": 3, "capture": 0}
     out = torch.empty_like(X)
     pick = agp.autotune(G, 0.0, 1.0, w, X, 1e-5, 9, out=out)
     assert agp.get_tuning(G, 40, 0.0, 1.0) == pick

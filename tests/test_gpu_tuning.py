@@ -22,6 +22,7 @@ CANDIDATES = {
     "big_items": [1, 16, 256],
     "sparse_shift": [1, 3, 9],
     "bin_shift": [1, 2, 6],
+    "capture": [0, 1],
 }
 
 

@@ -58,16 +58,18 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 VALU_PER_DRAW = 103
 ALU_PEAK_GDRAWS = VALU_LANE_OPS / VALU_PER_DRAW / 1e9
 
-# HBM bytes per launch of the level kernel (levels 1..L), from two rocprofv3
-# --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) with
-# --calibrate-copy; FETCH_SIZE is scaled by the factor that makes the 1 GiB
-# copy read 1 GiB.  Valid only for the kernel sources they were taken from.
+# HBM bytes per launch of the level kernel (levels 1..L with the launches
+# that make its deferred rows and suffixes), from two rocprofv3 --pmc runs
+# of this script (FETCH_SIZE, then WRITE_SIZE) with --calibrate-copy;
+# FETCH_SIZE is scaled by 2.0, the factor that makes the 1 GiB copy read
+# 1 GiB (WRITE_SIZE reads 1 GiB as written).  Valid only for the kernel
+# sources they were taken from and the default tuning.
 TRAFFIC = {
-    "katz-tp": {"sources": "98d1a1fed2a207ce", "columns": 256, "bytes_per_launch": 11014166009.0,
-                "fetch_bytes": 7261762965.0, "write_bytes": 3752403044.0},
+    "gnn-ppr-large": {"sources": "4921aeaf43296b4a", "columns": 128, "bytes_per_launch": 71287683109.0,
+                      "fetch_bytes": 58287955920.0, "write_bytes": 12999727188.0},
 }
 KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
-                  "paper_2106_03058_amd/csrc/dense_kernels.h", "paper_2106_03058_amd/csrc/propagate.hip")
+                  "paper_2106_03058_amd/csrc/bin_kernels.h")
 
 
 def kernel_sources_sha() -> str:
@@ -78,6 +80,8 @@ def kernel_sources_sha() -> str:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
 METRIC = "edge-pushes/s + HBM GB/s; queries/s and p99 latency batched vs per-query at eps"
 
 
@@ -720,13 +724,14 @@ def copy_probe_gbps(dev) -> float:
 def level_roofline(runs, models, args, C) -> dict:
     """Roofline object of the level kernel over the timed steps.
 
-    Node-major dense levels (feature propagation): the kernel is bound by its
-    random draws (runs + candidates), so `achieved` is draws per launch over
-    the launch's HIP-event time against ALU_PEAK_GDRAWS; levels 0..L-1, one
-    launch per level and column tile (level L only converts residues).
-    Frontier-list levels: algorithmic bytes of the launches of levels 1..L
-    against the HBM peak.  Both report the algorithmic HBM rate and, while the
-    kernel sources hash to the profiled ones, the measured traffic."""
+    The launches: frontier-list levels 1..L (the level kernel with the
+    launches that make its deferred rows and suffixes), or node-major dense
+    levels 0..L-1 (level L only converts residues); one launch per level and
+    column tile.  Two floors bound a launch: its random draws (runs +
+    candidates) at ALU_PEAK_GDRAWS, and its algorithmic bytes at the HBM
+    peak.  `bound` is the one with the larger floor (the larger fraction);
+    the other is reported beside it, with the measured HBM traffic while the
+    kernel sources hash to the profiled ones."""
     dense = all(st["dense"] for r in runs for st, _ in r)
     draws = lvl_ms = alg = 0.0
     launches = 0
@@ -743,26 +748,26 @@ def level_roofline(runs, models, args, C) -> dict:
         return None
     avg_s = lvl_ms / 1e3 / max(launches, 1)
     alg_gbps = alg / (lvl_ms / 1e3) / 1e9
+    gdraws = draws / (lvl_ms / 1e3) / 1e9
     rec = TRAFFIC.get(args.workload)
     traffic = None
-    if rec and rec["sources"] == kernel_sources_sha() and rec["columns"] == C and not args.tune:
+    if rec and rec["sources"] == kernel_sources_sha() and rec["columns"] == C and not args.tune and not dense:
         traffic = rec["bytes_per_launch"] / avg_s / 1e9
-    hbm = {"alg_bytes_per_launch": alg / max(launches, 1), "alg_gbps": alg_gbps,
-           "traffic_bytes_per_launch": rec["bytes_per_launch"] if traffic is not None else None,
-           "traffic_gbps": traffic, "traffic_over_alg": (traffic / alg_gbps) if traffic else None}
-    if dense:
-        achieved = draws / max(launches, 1) / avg_s / 1e9
-        return {"bound": "alu", "kernel": "k_dense_level (levels 0..L-1, one launch per level and column tile)",
-                "achieved": achieved, "peak": ALU_PEAK_GDRAWS, "unit": "Gdraw/s", "frac": achieved / ALU_PEAK_GDRAWS,
-                "traffic": traffic, "traffic_unit": "GB/s",
-                "draws_per_launch": draws / max(launches, 1), "avg_launch_ms": avg_s * 1e3, "launches": launches,
-                "peak_derivation": f"{VALU_LANE_OPS:.4g} VALU lane-ops/s / {VALU_PER_DRAW} per draw",
-                "hbm": hbm}
-    return {"bound": "hbm", "kernel": "k_level<float, false, false> + k_det_big<float> + k_samp_big<float> "
-                                      "(levels 1..L)",
-            "achieved": alg_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": alg_gbps / HBM_PEAK_GBPS,
-            "traffic": traffic, "traffic_bytes_per_launch": hbm["traffic_bytes_per_launch"],
-            "avg_launch_ms": avg_s * 1e3, "alg_bytes_per_launch": hbm["alg_bytes_per_launch"], "launches": launches}
+    kernel = ("k_dense_level (levels 0..L-1)" if dense else
+              "k_level<float, false, false> + k_det_big<float> + k_samp_big<float> (levels 1..L)")
+    alu = {"bound": "alu", "achieved": gdraws, "peak": ALU_PEAK_GDRAWS, "unit": "Gdraw/s",
+           "frac": gdraws / ALU_PEAK_GDRAWS,
+           "peak_derivation": f"{VALU_LANE_OPS:.4g} VALU lane-ops/s / {VALU_PER_DRAW} per draw",
+           "draws_per_launch": draws / max(launches, 1)}
+    hbm = {"bound": "hbm", "achieved": alg_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+           "frac": alg_gbps / HBM_PEAK_GBPS, "alg_bytes_per_launch": alg / max(launches, 1)}
+    main_, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
+    out = dict(main_)
+    out.update({"kernel": kernel, "traffic": traffic, "traffic_unit": "GB/s",
+                "traffic_bytes_per_launch": rec["bytes_per_launch"] if traffic is not None else None,
+                "traffic_over_alg_bytes": (traffic / alg_gbps) if traffic else None,
+                "avg_launch_ms": avg_s * 1e3, "launches": launches, "other_bound": other})
+    return out
 
 
 def main() -> int:

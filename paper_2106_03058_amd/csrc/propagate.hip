@@ -1045,34 +1045,46 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
     tune.dense = 0;
     tune.capture = 0;
   }
-  if (stats) std::memset(stats, 0, sizeof(*stats));
-  if constexpr (std::is_same<T, float>::value) {
-    if (may_alloc && (tune.dense == 1 || (tune.dense == 2 && C >= 16))) {
-      const int rc = propagate_dense(g, fn, tune, a, b, rho, kappa, L, x, C, eps, seed, qids, out, s, stats);
-      if (rc != kNotDense) {
-        if (rc == AGP_OK && stats) {
-          stats->levels = L;
-          stats->columns = C;
+  auto run = [&]() -> int {
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if constexpr (std::is_same<T, float>::value) {
+      if (may_alloc && (tune.dense == 1 || (tune.dense == 2 && C >= 16))) {
+        const int rc = propagate_dense(g, fn, tune, a, b, rho, kappa, L, x, C, eps, seed, qids, out, s, stats);
+        if (rc != kNotDense) {
+          if (rc == AGP_OK && stats) {
+            stats->levels = L;
+            stats->columns = C;
+          }
+          return rc;
         }
-        return rc;
       }
     }
+    const bool may_bin = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4;
+    const int32_t tile = borrowed ? C : column_tile<T>(g, C, may_bin, tune);
+    AGP_HIP(hipMemsetAsync(out, 0, cells * sizeof(T), s));
+    for (int32_t c0 = 0; c0 < C; c0 += tile) {
+      const int32_t ct = std::min(tile, C - c0);
+      const int rc = propagate_tile<T>(g, fn, tune, a, b, rho, kappa, L, x + c0, static_cast<long long>(C), ct,
+                                       eps, seed, qids ? qids + c0 : nullptr, static_cast<uint32_t>(c0), out + c0,
+                                       s, stats, sc, may_alloc);
+      if (rc != AGP_OK) return rc;
+    }
+    if (stats) {
+      stats->levels = L;
+      stats->columns = C;
+    }
+    return AGP_OK;
+  };
+  int rc = run();
+  if (rc == AGP_ENOMEM && may_alloc) {
+    // buffers an earlier call shaped differently (another path, tile or
+    // mode) may hold the memory this one needs: release them all, once
+    (void)hipStreamSynchronize(s);
+    g->drop_loops();
+    g->scratch.release();
+    rc = run();
   }
-  const bool may_bin = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4;
-  const int32_t tile = borrowed ? C : column_tile<T>(g, C, may_bin, tune);
-  AGP_HIP(hipMemsetAsync(out, 0, cells * sizeof(T), s));
-  for (int32_t c0 = 0; c0 < C; c0 += tile) {
-    const int32_t ct = std::min(tile, C - c0);
-    const int rc = propagate_tile<T>(g, fn, tune, a, b, rho, kappa, L, x + c0, static_cast<long long>(C), ct, eps,
-                                     seed, qids ? qids + c0 : nullptr, static_cast<uint32_t>(c0), out + c0, s, stats,
-                                     sc, may_alloc);
-    if (rc != AGP_OK) return rc;
-  }
-  if (stats) {
-    stats->levels = L;
-    stats->columns = C;
-  }
-  return AGP_OK;
+  return rc;
 }
 
 // ------------------------------------------------- literal sign split
@@ -1327,7 +1339,9 @@ int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int3
       if (t.*f == v) continue;
       t.*f = v;
       float ms = 0.0f;
-      rc = timed(t, &ms);
+      const int r = timed(t, &ms);
+      if (r == AGP_ENOMEM) continue;  // the candidate does not fit: not a choice here
+      rc = r;
       if (rc == AGP_OK && ms < best_ms) {
         best_ms = ms;
         pick = t;

@@ -367,10 +367,10 @@ def run_serve(args) -> dict:
     # queries re-run by the oracle keep their outputs in buffers of their own
     checked = sorted(np.random.default_rng(77).choice(N, size=min(args.oracle_queries, N), replace=False).tolist())
     held = {i: torch.empty(n, dtype=torch.float32, device=dev) for i in checked if i >= keep}
-    srv = agp.Server(G, max_slots=S, queue_capacity=N + 1)
+    srv = agp.Server(G, max_slots=S, queue_capacity=N + 1, memory_bytes=int(args.serve_memory_gb * 2**30))
     free = list(range(len(pool)))
     outstanding = {}
-    lat, lat_admit, pushes = [], [], 0
+    lat, lat_admit, pushes, restarts = [], [], 0, 0
     submitted = 0
     t0 = time.perf_counter()
     while submitted < N or outstanding:
@@ -391,7 +391,10 @@ def run_serve(args) -> dict:
                 lat.append((t_done - arrivals[i]) * 1e3)
                 lat_admit.append(r["end_ms"] - r["submit_ms"])
                 pushes += r["pushes"]
+                restarts += r["restarts"]
                 done.append(tk)
+                if len(lat) % 128 == 0:
+                    log(f"served {len(lat)}/{N} ({time.perf_counter() - t0:.1f}s)")
                 if slot >= 0:
                     free.append(slot)
         for tk in done:
@@ -457,7 +460,9 @@ def run_serve(args) -> dict:
         "data": "synthetic",
         "config": {"workload": f"served stream of {N} queries (ppr/katz/tp, L 10-40, eps 1e-5..1e-7) "
                                f"at {args.rate:g}/s offered, rmat scale 24",
-                   "graph": {"n": n, "arcs": nnz}, "lambda_1": lam, "slots": S},
+                   "graph": {"n": n, "arcs": nnz}, "lambda_1": lam, "slots": S,
+                   "table_memory_gb": args.serve_memory_gb or "a quarter of the free memory"},
+        "table_restarts": restarts,
         "queries_per_s_served": N / makespan,
         "latency_ms_served": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                               "note": "arrival to completion, including queueing"},
@@ -781,6 +786,8 @@ def main() -> int:
     ap.add_argument("--queries", type=int, default=1024, help="serve: queries in the stream")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: offered arrivals per second")
     ap.add_argument("--slots", type=int, default=112, help="serve: server slots")
+    ap.add_argument("--serve-memory-gb", type=float, default=0.0,
+                    help="serve: device memory of the residue tables (0: a quarter of the free memory)")
     ap.add_argument("--single", type=int, default=None, help="units timed one per launch")
     ap.add_argument("--oracle-queries", type=int, default=0,
                     help="serve: queries of the stream re-run by the oracle (random sample)")

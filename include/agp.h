@@ -345,15 +345,23 @@ typedef struct agp_server_config {
   int32_t queue_capacity; /* submitted but not yet admitted queries (>= 1)      */
   double work_budget;     /* admission cap on the summed Theorem 3.3 push
                              estimates of running queries; 0 = no cap          */
+  int64_t memory_bytes;   /* device memory of the running queries' residue
+                             tables (20 bytes per table entry, two tables of
+                             2^k entries per query); 0 = a quarter of the free
+                             device memory at creation                        */
 } agp_server_config_t;
 
 typedef struct agp_result {
-  int32_t status;     /* AGP_OK, or AGP_ERANGE if the query's residues outgrew
-                         the exact accumulators                                */
+  int32_t status;     /* AGP_OK; AGP_ERANGE if the query's residues outgrew
+                         the exact accumulators; AGP_ENOMEM if its tables
+                         exceed the whole pool                                 */
   int32_t levels;     /* L                                                     */
   uint64_t frontier;  /* sum over levels of the query's frontier sizes         */
   uint64_t pushes;    /* deterministic + accepted sampled pushes               */
   uint64_t candidates;/* sampled candidate positions                           */
+  uint64_t table_entries; /* entries of each of the query's two residue tables  */
+  int32_t restarts;   /* runs ended by a full table (the query then ran again
+                         with tables twice as large)                           */
   double submit_ms;   /* times in ms on the server's clock (steady, from       */
   double start_ms;    /*   server creation): submission, admission, and the    */
   double end_ms;      /*   end of the step that finished the query             */
@@ -368,8 +376,23 @@ typedef struct agp_server agp_server_t;
  * running query by one level per step in one launch; slots may be at
  * different levels with different a, b, L, w and eps.  A query finishes after
  * its level L; its result is independent of what runs beside it.
- * Device memory: about 36 bytes x n x max_slots.  The graph must outlive the
- * server.  Errors: AGP_EINVAL, AGP_ENOMEM, AGP_EDEVICE. */
+ * A query's residues live in two tables (this level's and the next
+ * level's).  With a = 0, b = 1 (column-stochastic P) they are
+ * open-addressing tables of 2^k entries, at least twice the distinct nodes
+ * its busiest level is expected to reach (by Theorem 3.3 the expected
+ * pushes of level i are at most (Y_i / S) / eps for x = e_s, and level 1
+ * reaches at most the neighbours of the signal's nodes), or, when that
+ * would reach n, direct tables of n entries (position = node); with other
+ * exponents the residue mass can grow from level to level and the tables
+ * are direct from the start;
+ * both take one contiguous range of a pool of memory_bytes / 20 entries.  Admission is in submission order, while a
+ * slot is free, the work budget allows and the query's range fits in the
+ * pool: the running queries never hold more than the pool.  A query whose
+ * tables are larger than the whole pool finishes at once with status
+ * AGP_ENOMEM.  A table that fills up (a node finds no free position within
+ * 128 probes) ends that run: the query is queued again at the head with
+ * tables twice as large, and its result is unchanged.  The graph must outlive the server.
+ * Errors: AGP_EINVAL, AGP_ENOMEM, AGP_EDEVICE. */
 int agp_server_create(const agp_graph_t* g, const agp_server_config_t* cfg, agp_server_t** out);
 
 /* Queue a query; *ticket identifies it for agp_poll.  The descriptor and the

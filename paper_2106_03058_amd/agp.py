@@ -443,12 +443,14 @@ class Query(ct.Structure):
 
 
 class ServerConfig(ct.Structure):
-    _fields_ = [("max_slots", ct.c_int32), ("queue_capacity", ct.c_int32), ("work_budget", ct.c_double)]
+    _fields_ = [("max_slots", ct.c_int32), ("queue_capacity", ct.c_int32), ("work_budget", ct.c_double),
+                ("memory_bytes", ct.c_int64)]
 
 
 class Result(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("levels", ct.c_int32), ("frontier", ct.c_uint64),
-                ("pushes", ct.c_uint64), ("candidates", ct.c_uint64), ("submit_ms", ct.c_double),
+                ("pushes", ct.c_uint64), ("candidates", ct.c_uint64), ("table_entries", ct.c_uint64),
+                ("restarts", ct.c_int32), ("submit_ms", ct.c_double),
                 ("start_ms", ct.c_double), ("end_ms", ct.c_double)]
 
     def to_dict(self) -> dict:
@@ -471,10 +473,12 @@ class Server:
     """Continuous-batching server of single-source queries on one graph."""
 
     def __init__(self, graph: Graph, max_slots: int = 64, queue_capacity: int = 4096,
-                 work_budget: float = 0.0):
+                 work_budget: float = 0.0, memory_bytes: int = 0):
+        """memory_bytes: device memory of the running queries' residue tables
+        (0: a quarter of the free device memory)."""
         L = _server_lib()
         self.graph = graph  # keeps the graph alive
-        cfg = ServerConfig(max_slots, queue_capacity, work_budget)
+        cfg = ServerConfig(max_slots, queue_capacity, work_budget, int(memory_bytes))
         h = ct.c_void_p()
         _check(L.agp_server_create(graph.handle, ct.byref(cfg), ct.byref(h)))
         self._h = h

@@ -148,7 +148,55 @@ struct LevelArgs {
   long long samp_items;          // work items from which an entry's sampled suffix is deferred
   // binned levels: deterministic pushes mark their destination bin (nullptr: no marks)
   uint8_t* det_bins;
+  // served queries: each query's residues live in an open-addressing table
+  // of one pool (query c owns positions tab_off[c] .. tab_off[c] + tab_mask[c];
+  // a key is node + 1, 0 when free); frontier entries are (position, c)
+  uint32_t* keys_cur;
+  uint32_t* keys_nxt;
+  const uint32_t* tab_off;   // the next level's tables
+  const uint32_t* tab_mask;
+  const uint32_t* tab_cur;   // this level's tables
 };
+
+// Position of node v in a query's table, claiming it if v is not there yet
+// (*first: v was not there); ~0u when the table is too full.  mask == ~0u:
+// a direct table of n entries (position base + v); else 2^k = mask + 1
+// entries probed linearly from a multiplicative hash of v, at most
+// kMaxProbes of them (a table at most half full needs a few; more means
+// that the query outgrew its table).
+constexpr uint32_t kDirectTable = ~0u;
+// mask == kDirectPlain: a direct table of a query whose residues cannot
+// cancel (a non-negative signal): no keys (the node is the position's
+// offset), plain atomic adds, and the next frontier is formed by a scan of
+// the table's non-zero positions after the level
+constexpr uint32_t kDirectPlain = ~1u;
+constexpr uint32_t kMaxProbes = 128;
+__device__ __forceinline__ uint32_t table_find_or_insert(uint32_t* keys, uint32_t base, uint32_t mask, uint32_t v,
+                                                         bool* first) {
+  // a key changes only once per level (0 -> node + 1), so a coherent read
+  // that already shows v spares the compare-and-swap
+  if (mask == kDirectTable) {
+    const uint32_t pos = base + v;
+    uint32_t old = __hip_atomic_load(keys + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0u) old = atomicCAS(keys + pos, 0u, v + 1u);
+    *first = old == 0u;
+    return pos;
+  }
+  const uint32_t h = static_cast<uint32_t>((static_cast<unsigned long long>(v) * 0x9E3779B97F4A7C15ull) >> 32);
+  const uint32_t probes = mask < kMaxProbes ? mask + 1u : kMaxProbes;
+  for (uint32_t k = 0; k < probes; ++k) {
+    const uint32_t pos = base + ((h + k) & mask);
+    uint32_t old = __hip_atomic_load(keys + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0u) old = atomicCAS(keys + pos, 0u, v + 1u);
+    if (old == 0u || old == v + 1u) {
+      *first = old == 0u;
+      return pos;
+    }
+  }
+  *first = false;
+  return ~0u;
+}
+constexpr int kErrTableFull = 2;  // server: a query's table had no free position
 
 // ----------------------------------------------------- working precision
 template <typename T>
@@ -358,7 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   // cell to the next frontier; dense levels use fire-and-forget atomics and a
   // compaction pass builds the next frontier.
   const bool binned = A.rec != nullptr && (A.bin_est == nullptr || *A.bin_est >= A.bin_pushes);
-  const bool sparse = !binned && A.positive && count < A.dense_cut;
+  const bool sparse = kServe || (!binned && A.positive && count < A.dense_cut);
   if (blockIdx.x == 0 && threadIdx.x == 0)
     *A.mode_out = binned ? kModeBinned : (sparse ? kModeSparse : kModeCompact);
   if (binned) {
@@ -387,8 +435,26 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   // on every level); emit_sampled: a sampled push of -/+ fl(theta) (a
   // 4-byte record on binned levels).
   auto emit_atomic = [&](bool emit, uint32_t v, uint32_t ec, const Delta& delta) {
-    const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(ec) * A.sc;
     bool first = false;
+    if constexpr (kServe) {  // the query's table: first touches go to the next frontier
+      uint32_t pos = 0;
+      if (emit) {
+        const uint32_t mask = A.tab_mask[ec];
+        if (mask == kDirectPlain) {  // the next frontier comes from a scan of the table
+          pos = A.tab_off[ec] + v;
+          P::add(acc_next, pos, delta);
+        } else {
+          pos = table_find_or_insert(A.keys_nxt, A.tab_off[ec], mask, v, &first);
+          if (pos == ~0u)
+            atomicOr(A.err + ec, kErrTableFull);
+          else
+            P::add(acc_next, pos, delta);
+        }
+      }
+      stage_push(stage, staged, (static_cast<uint64_t>(pos) << 32) | ec, first, A.fout, A.cnt_out);
+      return;
+    }
+    const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(ec) * A.sc;
     if (emit) {
       if (sparse)
         first = P::add_ret(acc_next, vcell, delta);
@@ -458,7 +524,16 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         const uint64_t item = A.fin[e0 + lane];
         eu = static_cast<uint32_t>(item >> 32);
         ec = static_cast<uint32_t>(item);
-        const size_t cell = static_cast<size_t>(eu) * A.su + static_cast<size_t>(ec) * A.sc;
+        size_t cell = static_cast<size_t>(eu) * A.su + static_cast<size_t>(ec) * A.sc;
+        if constexpr (kServe) {  // (table position, query): the node is the key (or the offset); free it
+          cell = eu;
+          if (A.tab_mask[ec] == kDirectPlain) {
+            eu = static_cast<uint32_t>(cell) - A.tab_cur[ec];
+          } else {
+            eu = A.keys_cur[cell] - 1u;
+            A.keys_cur[cell] = 0u;
+          }
+        }
         const ColParams& cp = A.cp[ec];
         T r;
         if (kFirst)
@@ -466,7 +541,9 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         else
           r = P::take(acc_cur, cell, cp);
         eneg = r < T(0);
-        if (!(cp.flags & kDrop)) {
+        // (a served query's table also holds nodes whose sum cancelled to zero:
+        // they are not in the frontier)
+        if (!(cp.flags & kDrop) && !(kServe && r == T(0))) {
           if (kServe) {
             serve_count(A, s_scnt, ec, 0, 1ull);
           } else {

@@ -1,6 +1,9 @@
 """Continuous-batching query server: every served result equals the oracle's
 for the same (seed, query_id), alone or in any mix of models, levels and
-thresholds; submission errors stay local to the offending query."""
+thresholds, whatever the size of its residue tables (runs ended by a full
+table start again); admission by table memory never lets the running
+queries hold more than the pool; submission errors stay local to the
+offending query."""
 import time
 
 import numpy as np
@@ -51,8 +54,8 @@ def _oracle_one(g, sg, q):
     return out, {k: v[0] for k, v in cnt.items()}
 
 
-def _serve(torch, agp, G, qs, *, slots, budget=0.0):
-    srv = agp.Server(G, max_slots=slots, queue_capacity=len(qs) + 4, work_budget=budget)
+def _serve(torch, agp, G, qs, *, slots, budget=0.0, memory=256 << 20):
+    srv = agp.Server(G, max_slots=slots, queue_capacity=len(qs) + 4, work_budget=budget, memory_bytes=memory)
     outs = [torch.full((G.n,), float("nan"), dtype=torch.float32, device="cuda:0") for _ in qs]
     tickets = [srv.submit(q["source"], q["a"], q["b"], q["w"], q["eps"], q["seed"], q["qid"], o, x=q.get("x"))
                for q, o in zip(qs, outs)]
@@ -152,21 +155,61 @@ def test_queue_full_is_ebusy(env):
     srv.close()  # finishes the running query, drops the queued ones
 
 
-def test_aggregation_modes_serve_the_same_bits(env, monkeypatch):
-    """Served queries give the oracle's bits whether the server's steps use
-    atomics only, records on every step, or records on heavy steps only."""
+def test_table_sizes_serve_the_same_bits(env, monkeypatch):
+    """Served queries give the oracle's bits with tables sized from their
+    push estimates, and with tables forced so small that runs end on a full
+    table and start again with larger ones."""
     torch, agp, g, G, sg, lam = env
     qs = _mix(g, lam, 9, seed=4)
-    for mode in ("atomic", "binned", None):
-        monkeypatch.delenv("AGP_AGGREGATION", raising=False)
-        if mode:
-            monkeypatch.setenv("AGP_AGGREGATION", mode)
+    for entries in (None, "256", "16"):
+        monkeypatch.delenv("AGP_SERVE_TABLE_ENTRIES", raising=False)
+        if entries:
+            monkeypatch.setenv("AGP_SERVE_TABLE_ENTRIES", entries)
+        print(f"table entries {entries}", flush=True)
         outs, res = _serve(torch, agp, G, qs, slots=4)
         for q, o, r in zip(qs, outs, res):
             ref, cnt = _oracle_one(g, sg, q)
             assert r["status"] == agp.AGP_OK
-            assert np.array_equal(o, ref), f"{mode}: query {q['qid']}"
+            assert np.array_equal(o, ref), f"{entries}: query {q['qid']}"
             assert r["pushes"] == int(cnt["det"].sum() + cnt["acc"].sum())
+            assert r["frontier"] == int(cnt["frontier"].sum())
+        if entries == "16":
+            assert sum(r["restarts"] for r in res) > 0  # some tables did fill up
+            assert all(r["table_entries"] == min(16 << r["restarts"], g.n) for r in res)
+        if entries is None:
+            assert all(r["restarts"] == 0 for r in res)
+
+
+def test_memory_admission(env):
+    """With a pool that holds the tables of only a few queries at once, the
+    queries that run together never hold more than the pool (20 bytes per
+    table entry, two tables each), every result is the oracle's, and a query
+    whose tables exceed the whole pool ends with AGP_ENOMEM."""
+    torch, agp, g, G, sg, lam = env
+    qs = _mix(g, lam, 16, seed=6)
+    pool = 3 * 2 * 5000 * 20 + 1000  # three queries with direct tables (n = 5000 entries each)
+    outs, res = _serve(torch, agp, G, qs, slots=16, memory=pool)
+    for q, o, r in zip(qs, outs, res):
+        ref, _ = _oracle_one(g, sg, q)
+        assert r["status"] == agp.AGP_OK
+        assert np.array_equal(o, ref)
+    events = sorted([(r["start_ms"], 1, 2 * r["table_entries"] * 20) for r in res] +
+                    [(r["end_ms"], 0, -2 * r["table_entries"] * 20) for r in res])  # ends before starts at a tie
+    held = peak = 0
+    for _, _, d in events:
+        held += d
+        peak = max(peak, held)
+    assert 0 < peak <= pool
+    # tables larger than the pool: the query finishes at once with AGP_ENOMEM
+    srv = agp.Server(G, max_slots=2, queue_capacity=4, memory_bytes=2 * 1024 * 20)
+    o = torch.zeros(G.n, dtype=torch.float32, device="cuda:0")
+    t = srv.submit(qs[0]["source"], 0.0, 1.0, inputs.weights_ppr(0.2, 8), 1e-7, 1, 1, o)
+    t0 = time.time()
+    r = None
+    while r is None and time.time() - t0 < 30:
+        r = srv.poll(t)
+    srv.close()
+    assert r is not None and r["status"] == agp.AGP_ENOMEM
 
 
 def _dense(g, q):
@@ -181,8 +224,8 @@ def _dense(g, q):
 def test_sparse_signal_queries(env):
     """Queries with sparse signals (seed sets, signed values) served beside
     single-source ones: each equals the oracle and the batched call on the
-    dense signal with the same (seed, query id); a signed query turns the
-    server's first-touch appends off for the steps it runs in."""
+    dense signal with the same (seed, query id); signed values may cancel to
+    zero inside a table, and such nodes stay out of the frontier."""
     torch, agp, g, G, sg, lam = env
     rng = np.random.default_rng(31)
     qs = _mix(g, lam, 9, seed=5)

@@ -487,6 +487,15 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   const unsigned long long bstride = static_cast<unsigned long long>(gridDim.x) * kWaves;
   unsigned long long bnext = static_cast<unsigned long long>(blockIdx.x) * kWaves + wave;
   long long it_next = 0, it_total = 0;  // wave-uniform: queue of the loaded batch
+  // the frontier items of this wave's next batch, loaded one batch ahead so
+  // that a batch's setup starts from its items
+  auto load_items = [&](unsigned long long b) -> uint64_t {
+    if (b >= nbatch) return 0ull;
+    const unsigned long long e = b * eb;
+    const unsigned long long m = (count - e) < eb ? (count - e) : eb;
+    return static_cast<unsigned long long>(lane) < m ? A.fin[e + lane] : 0ull;
+  };
+  uint64_t next_items = load_items(bnext);
 
   // lane state: the sampled work item in progress
   bool active = false, need_run = false, neg = false, azero = true;
@@ -515,13 +524,15 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       const unsigned long long e0 = bnext * eb;
       bnext += bstride;
       const int ne = static_cast<int>((count - e0) < eb ? (count - e0) : eb);
+      const uint64_t batch_item = next_items;
+      next_items = load_items(bnext);
       long long dwork = 0, iwork = 0;
       uint32_t eu = 0, ec = 0, ed = 0, eJ = 0;
       int64_t erp = 0;
       double ecv = 0.0, ep0 = 0.0;
       bool eneg = false;
       if (lane < ne) {
-        const uint64_t item = A.fin[e0 + lane];
+        const uint64_t item = batch_item;
         eu = static_cast<uint32_t>(item >> 32);
         ec = static_cast<uint32_t>(item);
         size_t cell = static_cast<size_t>(eu) * A.su + static_cast<size_t>(ec) * A.sc;

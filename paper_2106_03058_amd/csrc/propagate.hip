@@ -331,10 +331,11 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   const long long nbins = static_cast<long long>(((cells > 0 ? cells : 1) - 1) >> kBinLog2) + 1;
   unsigned long long rec_cap = 0;
   if (binned) {
-    // room for 4 records per cell, within an eighth of the free memory (two buffers)
+    // room for 4 records per cell (1 when the call runs in several tiles),
+    // within an eighth of the free memory (two buffers)
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
-    rec_cap = std::max<unsigned long long>(1ull << 20, 4ull * cells);
+    rec_cap = std::max<unsigned long long>(1ull << 20, (static_cast<long long>(C) < ldc ? 1ull : 4ull) * cells);
     rec_cap = std::min<unsigned long long>(rec_cap, std::max<unsigned long long>(1ull << 20, free_b / 64));
     if (const char* e = std::getenv("AGP_RECORD_CAP")) {  // smaller record buffer (tuning / tests)
       const unsigned long long v = std::strtoull(e, nullptr, 10);
@@ -590,18 +591,24 @@ template <typename T>
 int32_t column_tile(agp_graph* g, int32_t C, bool binned, const agp_tuning_t& tune) {
   if (tune.tile_columns > 0) return std::min(tune.tile_columns, C);
   const size_t cell_bytes = sizeof(typename Prec<T>::Cell) * (sizeof(T) == 4 ? 1 : 2);
-  // two accumulators and two frontier lists per cell (+ two record buffers of 4 records)
-  const size_t per_cell = 2 * cell_bytes + 2 * sizeof(uint64_t) + (binned ? 2 * 4 * sizeof(uint32_t) : 0);
+  // two accumulators and two frontier lists per cell (+ two record buffers
+  // of 4 records per cell; of 1 when not every column fits: wider tiles,
+  // the records beyond the buffer go to atomics)
+  const size_t base_cell = 2 * cell_bytes + 2 * sizeof(uint64_t);
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return C;
   Scratch& sc = g->scratch;
   const size_t held = sc.acc[0].bytes + sc.acc[1].bytes + sc.frontier[0].bytes + sc.frontier[1].bytes +
                       sc.rec[0].bytes + sc.rec[1].bytes;
   const double budget = 0.85 * static_cast<double>(free_b + held);
-  const double per_col = static_cast<double>(g->n > 0 ? g->n : 1) * static_cast<double>(per_cell);
-  const double fit = budget / per_col;
-  if (fit >= static_cast<double>(C)) return C;
-  return fit < 1.0 ? 1 : static_cast<int32_t>(fit);
+  for (int recs : {4, 1}) {
+    const size_t per_cell = base_cell + (binned ? 2 * static_cast<size_t>(recs) * sizeof(uint32_t) : 0);
+    const double per_col = static_cast<double>(g->n > 0 ? g->n : 1) * static_cast<double>(per_cell);
+    const double fit = budget / per_col;
+    if (fit >= static_cast<double>(C)) return C;
+    if (recs == 1) return fit < 1.0 ? 1 : static_cast<int32_t>(fit);
+  }
+  return 1;
 }
 
 // ------------------------------------------------------------ dense levels

@@ -765,13 +765,12 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
       const uint32_t wend = wnext < rend ? wnext : rend;
       run_end = wend;
       if (!azero) {
+        // the group end is loaded beside the factor degree (one round trip)
+        const uint32_t ge = A.gend[rpu + s];
         dstart = cpp->da[A.nd[rpu + s]];
         const double num = cv * dstart;
         const double pr = num / th;
-        if (!(pr * static_cast<double>(wend - s) <= kMergeCandidates)) {
-          const uint32_t ge = A.gend[rpu + s];
-          if (ge < wend) run_end = ge;
-        }
+        if (!(pr * static_cast<double>(wend - s) <= kMergeCandidates) && ge < wend) run_end = ge;
         tab = make_skip_table(pr);
       }
       pos = s;
@@ -793,6 +792,9 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         ++n_cand;
         ++it_cand;
         const int64_t arc = rpu + cand;
+        // the neighbour is loaded beside its factor degree, before the
+        // acceptance test needs it (one round trip instead of two)
+        const uint32_t va = A.col[arc];
         bool accept = true;  // a = 0: the ratio is 1 and every uniform is below it
         if (!azero) {
           const double ratio = cpp->da[A.nd[arc]] / dstart;
@@ -801,7 +803,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
         if (accept) {
           ++n_acc;
           ++it_acc;
-          v = A.col[arc];
+          v = va;
           emit = true;
           delta = P::theta_units(*cpp, neg);
         }
@@ -1010,13 +1012,12 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
       const uint32_t wend = wnext < rend ? wnext : rend;
       run_end = wend;
       if (!azero) {
+        // the group end is loaded beside the factor degree (one round trip)
+        const uint32_t ge = A.gend[rpu + s];
         dstart = cpp->da[A.nd[rpu + s]];
         const double num = cv * dstart;
         const double pr = num / th;
-        if (!(pr * static_cast<double>(wend - s) <= kMergeCandidates)) {
-          const uint32_t ge = A.gend[rpu + s];
-          if (ge < wend) run_end = ge;
-        }
+        if (!(pr * static_cast<double>(wend - s) <= kMergeCandidates) && ge < wend) run_end = ge;
         tab = make_skip_table(pr);
       }
       pos = s;
@@ -1036,6 +1037,7 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
       } else {
         ++n_cand;
         const int64_t arc = rpu + cand;
+        const uint32_t va = A.col[arc];  // beside the factor degree, as in k_level
         bool accept = true;
         if (!azero) {
           const double ratio = cpp->da[A.nd[arc]] / dstart;
@@ -1043,7 +1045,7 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
         }
         if (accept) {
           ++n_acc;
-          v = A.col[arc];
+          v = va;
           emit = true;
           delta = P::theta_units(*cpp, neg);
         }
@@ -1138,56 +1140,102 @@ __global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __r
 }
 
 // ------------------------------------------------- frontier compaction
-// (u << 32 | c) of every cell whose predicate holds, staged per wave in LDS
-// and appended with one atomic per chunk.  Cells are u * su + c * sc:
-// row-major (su = C, sc = 1) or one n-vector per column (su = 1, sc = n).
+// (u << 32 | c) of every cell u * C + c of a row-major n x C array whose
+// predicate holds.  Every chunk that goes out costs one atomic on the list
+// counter, a round trip to one shared address that all waves contend for,
+// so chunks are made large: a wave takes segments of kCompactSeg
+// consecutive cells, issues kCompactUnroll loads of 64 cells together, and
+// stages the passing cells as 2-byte offsets into its segment (up to
+// kCompactCap of them, 8 KiB of LDS per wave); a chunk goes out when the
+// stage is nearly full and at the end of each segment, in cell order.  Rows
+// and columns of the staged cells are formed when they go out, from one
+// 64-bit division per segment and a float-reciprocal division corrected to
+// the exact quotient per entry.
+constexpr int kCompactUnroll = 16;
+constexpr int kCompactCap = 4096;
+constexpr long long kCompactSeg = 1ll << 16;  // offsets fit in 16 bits
+static_assert(kCompactSeg % (kCompactUnroll * kWave) == 0, "segments hold whole load groups");
+
+// floor(a / C) and a mod C for a < 2^22, from rc = 1 / C rounded to binary32:
+// the product is within one of the quotient, and one correction makes it exact
+__device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t C, float rc, uint32_t* rem) {
+  uint32_t q = static_cast<uint32_t>(static_cast<float>(a) * rc);
+  int32_t r = static_cast<int32_t>(a) - static_cast<int32_t>(q * C);
+  if (r < 0) {
+    --q;
+    r += static_cast<int32_t>(C);
+  } else if (r >= static_cast<int32_t>(C)) {
+    ++q;
+    r -= static_cast<int32_t>(C);
+  }
+  *rem = static_cast<uint32_t>(r);
+  return q;
+}
+
+// The staged offsets of a segment that starts at row u0, column r0: one
+// atomic for the chunk, then the items in staging order.  Wave-uniform.
+__device__ __forceinline__ void compact_flush(const uint16_t* stage, int& staged, long long u0, uint32_t r0,
+                                              uint32_t C, float rc, bool small, uint64_t* __restrict__ F,
+                                              unsigned long long* __restrict__ cnt) {
+  if (staged == 0) return;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(cnt, static_cast<unsigned long long>(staged));
+  base = __shfl(base, 0);
+  for (int i = lane_id(); i < staged; i += kWave) {
+    const uint32_t a = r0 + stage[i];  // < C + kCompactSeg
+    uint32_t c = 0, q = 0;
+    if (small) {
+      q = div_small(a, C, rc, &c);
+    } else {
+      q = a / C;
+      c = a - q * C;
+    }
+    F[base + i] = (static_cast<uint64_t>(u0 + q) << 32) | c;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  staged = 0;
+}
+
 template <typename Pred>
-__global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int C, long long su, long long sc,
-                                                      uint64_t* __restrict__ F,
+__global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int C, uint64_t* __restrict__ F,
                                                       unsigned long long* __restrict__ cnt,
                                                       const int* __restrict__ mode) {
   if (mode && *mode != kModeCompact && *mode != kModeOverflow) return;  // formed elsewhere
-  __shared__ uint64_t s_stage[kThreads / kWave][kStage];
+  constexpr int kWaves = kThreads / kWave;
+  __shared__ uint16_t s_stage[kWaves][kCompactCap];
   const int lane = lane_id();
-  uint64_t* stage = s_stage[threadIdx.x / kWave];
-  int staged = 0;
-  if (su == C && sc == 1 && C >= kWave) {  // row-major, wide rows: a wave per row
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-    for (int64_t u = wave; u < n; u += nwaves) {
-      for (int c0 = 0; c0 < C; c0 += kWave) {
-        const int c = c0 + lane;
-        const bool p = (c < C) && pred(u, c, static_cast<size_t>(u) * C + c);
-        stage_push(stage, staged, (static_cast<uint64_t>(u) << 32) | static_cast<uint32_t>(c), p, F, cnt);
+  uint16_t* stage = s_stage[threadIdx.x / kWave];
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  const long long total = static_cast<long long>(n) * C;
+  const float rc = 1.0f / static_cast<float>(C);
+  const bool small = C <= (1 << 21);  // div_small's range: C + kCompactSeg < 2^22
+  const long long wave = static_cast<long long>(blockIdx.x) * kWaves + threadIdx.x / kWave;
+  const long long nwaves = static_cast<long long>(gridDim.x) * kWaves;
+  for (long long base = wave * kCompactSeg; base < total; base += nwaves * kCompactSeg) {
+    const long long u0 = base / C;
+    const uint32_t r0 = static_cast<uint32_t>(base - u0 * C);
+    int staged = 0;  // wave-uniform
+    for (int j = 0; j < kCompactSeg && base + j < total; j += kCompactUnroll * kWave) {
+      // the index is clamped instead of guarded, so that the loads carry no
+      // branch and go out together
+      bool p[kCompactUnroll];
+#pragma unroll
+      for (int k = 0; k < kCompactUnroll; ++k) {
+        const long long i = base + j + k * kWave + lane;
+        const bool in = i < total;
+        p[k] = pred(0, 0, static_cast<size_t>(in ? i : total - 1)) && in;
+      }
+#pragma unroll
+      for (int k = 0; k < kCompactUnroll; ++k) {
+        const unsigned long long m = __ballot(p[k]);
+        if (p[k]) stage[staged + __popcll(m & lt_mask)] = static_cast<uint16_t>(j + k * kWave + lane);
+        staged += __popcll(m);
+        if (staged > kCompactCap - kWave) compact_flush(stage, staged, u0, r0, C, rc, small, F, cnt);
       }
     }
-  } else {
-    const int64_t total = n * C;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // every lane of a wave runs the same number of iterations
-    const int64_t first = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t iters = (total + stride - 1) / stride;
-    const bool rowmajor = (sc == 1);
-    for (int64_t it = 0; it < iters; ++it) {
-      const int64_t i = first + it * stride;
-      bool p = false;
-      uint64_t item = 0;
-      if (i < total) {
-        int64_t u, c;
-        if (rowmajor) {
-          u = i / C;
-          c = i - u * C;
-        } else {
-          c = i / n;
-          u = i - c * n;
-        }
-        p = pred(u, c, static_cast<size_t>(i));
-        item = (static_cast<uint64_t>(u) << 32) | static_cast<uint32_t>(c);
-      }
-      stage_push(stage, staged, item, p, F, cnt);
-    }
+    compact_flush(stage, staged, u0, r0, C, rc, small, F, cnt);
   }
-  stage_flush(stage, staged, F, cnt);
 }
 
 template <typename T>

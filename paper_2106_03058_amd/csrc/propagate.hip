@@ -40,9 +40,9 @@ using namespace lvl;
 // pass forms the level-0 frontier (the non-zero cells of x, in any order).
 // One wave per (row block, 64 columns); loads are issued 32 rows at a time
 // and summed in row order; the frontier goes out in chunks of up to kCap
-// entries (one atomic each): 2048 when every wave of the launch fits on the
-// chip at once with 16 KiB of LDS each, else 1024.
+// entries (one atomic on the shared list counter each).
 constexpr int kThetaBatch = 32;
+constexpr int kThetaCap = 4096;  // 32 KiB of LDS per wave
 
 template <typename T, int kCap>
 __global__ __launch_bounds__(kWave) void k_theta_partial(const T* __restrict__ x, long long ldx, int64_t n, int C,
@@ -306,12 +306,8 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   // thresholds theta_c = eps ||x_c||_1 and signal checks
   if (tblocks > 0) {
     dim3 grid((unsigned)tblocks, (unsigned)((C + 63) / 64));
-    if (tblocks * static_cast<int64_t>(grid.y) <= 2048)
-      k_theta_partial<T, 2048><<<grid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
-                                                      sc.frontier[0].as<uint64_t>(), counts);
-    else
-      k_theta_partial<T, 1024><<<grid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
-                                                      sc.frontier[0].as<uint64_t>(), counts);
+    k_theta_partial<T, kThetaCap><<<grid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
+                                                         sc.frontier[0].as<uint64_t>(), counts);
   }
   k_theta_final<T><<<grid_for(C, 64), 64, 0, s>>>(sc.partial.as<double>(), tblocks, C, eps,
                                                   qids ? dq : nullptr, qid_base, cp);
@@ -370,7 +366,8 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   if (stats && (rc = sc.ensure_events())) return rc;
   uint64_t* F[2] = {sc.frontier[0].as<uint64_t>(), sc.frontier[1].as<uint64_t>()};
   Cell* acc[2] = {sc.acc[0].as<Cell>(), sc.acc[1].as<Cell>()};
-  const unsigned cgrid = grid_for(n * (int64_t)(C >= kWave ? kWave : C), kThreads, 8192);
+  // compaction: a segment per wave, 32 KiB of LDS per block (five per CU)
+  const unsigned cgrid = grid_for(static_cast<int64_t>((cells + kCompactSeg - 1) / kCompactSeg), kThreads / kWave, 1280);
 
   // rows with long deterministic prefixes, deferred per level to k_det_big
   constexpr unsigned long long kBigCap = 1ull << 16;
@@ -490,8 +487,8 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
             reinterpret_cast<long long*>(nxt), F[(i + 1) & 1], counts + i + 1, mode + i + 1, det_bins);
       }
       if (i < L)
-        k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, (long long)C, 1ll, F[(i + 1) & 1],
-                                             counts + i + 1, mode + i + 1);
+        k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, F[(i + 1) & 1], counts + i + 1,
+                                             mode + i + 1);
       if (timed) (void)hipEventRecord(ev[4 * i + 3], s);
     }
   };

@@ -65,8 +65,8 @@ ALU_PEAK_GDRAWS = VALU_LANE_OPS / VALU_PER_DRAW / 1e9
 # 1 GiB (WRITE_SIZE reads 1 GiB as written).  Valid only for the kernel
 # sources they were taken from and the default tuning.
 TRAFFIC = {
-    "gnn-ppr-large": {"sources": "4921aeaf43296b4a", "columns": 128, "bytes_per_launch": 71287683109.0,
-                      "fetch_bytes": 58287955920.0, "write_bytes": 12999727188.0},
+    "gnn-ppr-large": {"sources": "447708fcd9b24a02", "columns": 128, "bytes_per_launch": 99619992514.0,
+                      "fetch_bytes": 76946709046.0, "write_bytes": 22673283468.0},
 }
 KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
                   "paper_2106_03058_amd/csrc/bin_kernels.h")

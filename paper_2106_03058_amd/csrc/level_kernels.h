@@ -545,16 +545,39 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
             A.keys_cur[cell] = 0u;
           }
         }
+        // The loads that need only the entry go out together (a batched
+        // entry always names a node of the graph and a live column: its row
+        // bounds and factor degree beside its residue and column parameters),
+        // then the ones that need their results (the reserve's old value, the
+        // first neighbour's factor degree, d_u^-b).
+        uint32_t deg_u = 0;
+        int32_t fdeg_u = 0;
+        int64_t rp_u = 0;
+        if (!kServe) {
+          deg_u = static_cast<uint32_t>(A.deg[eu]);
+          fdeg_u = A.fdeg[eu];
+          rp_u = A.rp[eu];
+        }
         const ColParams& cp = A.cp[ec];
         T r;
         if (kFirst)
           r = x[static_cast<size_t>(eu) * static_cast<size_t>(A.xld) + ec];
         else
           r = P::take(acc_cur, cell, cp);
-        eneg = r < T(0);
         // (a served query's table also holds nodes whose sum cancelled to zero:
         // they are not in the frontier)
-        if (!(cp.flags & kDrop) && !(kServe && r == T(0))) {
+        const bool live = !(cp.flags & kDrop) && !(kServe && r == T(0));
+        if (kServe && live) {
+          deg_u = static_cast<uint32_t>(A.deg[eu]);
+          fdeg_u = A.fdeg[eu];
+          rp_u = A.rp[eu];
+        }
+        T* const o = static_cast<T*>(cp.out) + static_cast<size_t>(eu) * static_cast<size_t>(cp.out_stride);
+        const T o_old = (live && cp.kappa != 0.0) ? *o : T(0);
+        const uint32_t nd_first = (live && deg_u > 0) ? A.nd[rp_u] : 0u;
+        const double db_u = live ? cp.db[fdeg_u] : 0.0;
+        eneg = r < T(0);
+        if (live) {
           if (kServe) {
             serve_count(A, s_scnt, ec, 0, 1ull);
           } else {
@@ -563,25 +586,24 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
           }
           // reserve: pi(u) += (S w_i / Y_i) r(u), rounded to the working precision
           if (cp.kappa != 0.0) {
-            T* o = static_cast<T*>(cp.out) + static_cast<size_t>(eu) * static_cast<size_t>(cp.out_stride);
             const T q = to_w(cp.kappa * static_cast<double>(r), T());
-            *o = *o + q;
+            *o = o_old + q;
           }
           if (!(cp.flags & kLastLevel) && cp.rho != 0.0) {
-            ed = static_cast<uint32_t>(A.deg[eu]);
+            ed = deg_u;
             if (ed > 0) {
               const double absr = fabs(static_cast<double>(r));
               const double t0 = cp.rho * absr;
-              ecv = t0 * cp.db[A.fdeg[eu]];
+              ecv = t0 * db_u;
               const double eth = cp.theta;
-              erp = A.rp[eu];
+              erp = rp_u;
               double inc0 = ecv;
               if (cp.flags & kAZero) {
                 eJ = (ecv >= eth) ? ed : 0u;
                 const double num = ecv * 1.0;  // every neighbour's factor d^-0 is 1
                 ep0 = num / eth;
               } else {  // increments fall along the degree-sorted row: binary search
-                inc0 = ecv * cp.da[A.nd[erp]];
+                inc0 = ecv * cp.da[nd_first];
                 uint32_t lo = 0, hi = ed;
                 if (!(inc0 >= eth))
                   hi = 0;  // no deterministic push

@@ -368,6 +368,28 @@ struct BatchLds {
   uint32_t u[kBatch], c[kBatch], d[kBatch], J[kBatch], neg[kBatch];
 };
 
+// floor(a / C) and a mod C for a < 2^22, from rc = 1 / C rounded to binary32:
+// the product is within one of the quotient, and one correction makes it exact
+__device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t C, float rc, uint32_t* rem) {
+  uint32_t q = static_cast<uint32_t>(static_cast<float>(a) * rc);
+  int32_t r = static_cast<int32_t>(a) - static_cast<int32_t>(q * C);
+  if (r < 0) {
+    --q;
+    r += static_cast<int32_t>(C);
+  } else if (r >= static_cast<int32_t>(C)) {
+    ++q;
+    r -= static_cast<int32_t>(C);
+  }
+  *rem = static_cast<uint32_t>(r);
+  return q;
+}
+
+// Level 0 of a batched call whose signal is mostly non-zero: the frontier is
+// every cell in order, entry e = (e / C, e mod C), and no list is formed
+// (A.fin == nullptr; C = A.su <= kVirtualMaxC); its zero cells are skipped
+// by the level kernel as if they were not listed.
+constexpr long long kVirtualMaxC = 1 << 21;
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -493,7 +515,16 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
     if (b >= nbatch) return 0ull;
     const unsigned long long e = b * eb;
     const unsigned long long m = (count - e) < eb ? (count - e) : eb;
-    return static_cast<unsigned long long>(lane) < m ? A.fin[e + lane] : 0ull;
+    if (static_cast<unsigned long long>(lane) >= m) return 0ull;
+    if (kFirst && A.fin == nullptr) {  // every cell: (e / C, e mod C)
+      const uint32_t C = static_cast<uint32_t>(A.su);
+      const unsigned long long u0 = e / C;
+      uint32_t c = 0;
+      const uint32_t q = div_small(static_cast<uint32_t>(e - u0 * C) + static_cast<uint32_t>(lane), C,
+                                   1.0f / static_cast<float>(C), &c);
+      return ((u0 + q) << 32) | c;
+    }
+    return A.fin[e + lane];
   };
   uint64_t next_items = load_items(bnext);
 
@@ -564,9 +595,10 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
           r = x[static_cast<size_t>(eu) * static_cast<size_t>(A.xld) + ec];
         else
           r = P::take(acc_cur, cell, cp);
-        // (a served query's table also holds nodes whose sum cancelled to zero:
-        // they are not in the frontier)
-        const bool live = !(cp.flags & kDrop) && !(kServe && r == T(0));
+        // (a served query's table also holds nodes whose sum cancelled to zero,
+        // and level 0 over every cell holds the zero cells of x: they are not
+        // in the frontier)
+        const bool live = !(cp.flags & kDrop) && !((kServe || (kFirst && A.fin == nullptr)) && r == T(0));
         if (kServe && live) {
           deg_u = static_cast<uint32_t>(A.deg[eu]);
           fdeg_u = A.fdeg[eu];
@@ -1130,9 +1162,16 @@ __global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __r
   double sum = 0.0;
   for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; j * stride < count;
        j += (unsigned long long)gridDim.x * blockDim.x) {
-    const uint64_t item = A.fin[j * stride];
-    const uint32_t u = static_cast<uint32_t>(item >> 32);
-    const uint32_t c = static_cast<uint32_t>(item);
+    uint32_t u, c;
+    if (kFirst && A.fin == nullptr) {  // every cell (see kVirtualMaxC)
+      const unsigned long long e = j * stride;
+      u = static_cast<uint32_t>(e / static_cast<unsigned long long>(A.su));
+      c = static_cast<uint32_t>(e - static_cast<unsigned long long>(u) * static_cast<unsigned long long>(A.su));
+    } else {
+      const uint64_t item = A.fin[j * stride];
+      u = static_cast<uint32_t>(item >> 32);
+      c = static_cast<uint32_t>(item);
+    }
     const ColParams& cp = A.cp[c];
     if ((cp.flags & (kDrop | kLastLevel)) || cp.rho == 0.0) continue;
     const uint32_t d = static_cast<uint32_t>(A.deg[u]);
@@ -1177,22 +1216,6 @@ constexpr int kCompactUnroll = 16;
 constexpr int kCompactCap = 4096;
 constexpr long long kCompactSeg = 1ll << 16;  // offsets fit in 16 bits
 static_assert(kCompactSeg % (kCompactUnroll * kWave) == 0, "segments hold whole load groups");
-
-// floor(a / C) and a mod C for a < 2^22, from rc = 1 / C rounded to binary32:
-// the product is within one of the quotient, and one correction makes it exact
-__device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t C, float rc, uint32_t* rem) {
-  uint32_t q = static_cast<uint32_t>(static_cast<float>(a) * rc);
-  int32_t r = static_cast<int32_t>(a) - static_cast<int32_t>(q * C);
-  if (r < 0) {
-    --q;
-    r += static_cast<int32_t>(C);
-  } else if (r >= static_cast<int32_t>(C)) {
-    ++q;
-    r -= static_cast<int32_t>(C);
-  }
-  *rem = static_cast<uint32_t>(r);
-  return q;
-}
 
 // The staged offsets of a segment that starts at row u0, column r0: one
 // atomic for the chunk, then the items in staging order.  Wave-uniform.

@@ -44,11 +44,15 @@ using namespace lvl;
 constexpr int kThetaBatch = 32;
 constexpr int kThetaCap = 4096;  // 32 KiB of LDS per wave
 
-template <typename T, int kCap>
+__global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
+
+// kList: append the non-zero cells to F (the level-0 frontier); else only
+// count them in *cnt (a mostly non-zero signal needs no list).
+template <typename T, int kCap, bool kList>
 __global__ __launch_bounds__(kWave) void k_theta_partial(const T* __restrict__ x, long long ldx, int64_t n, int C,
                                                          double* __restrict__ partial, int* __restrict__ flags,
                                                          uint64_t* __restrict__ F, unsigned long long* __restrict__ cnt) {
-  __shared__ uint64_t s_stage[kCap];
+  __shared__ uint64_t s_stage[kList ? kCap : 1];
   const int c = blockIdx.y * blockDim.x + threadIdx.x;
   const bool live = c < C;
   const int64_t lo = (int64_t)blockIdx.x * kThetaRows;
@@ -63,15 +67,21 @@ __global__ __launch_bounds__(kWave) void k_theta_partial(const T* __restrict__ x
       v[k] = (live && i0 + k < hi) ? x[static_cast<size_t>(i0 + k) * static_cast<size_t>(ldx) + c] : T(0);
 #pragma unroll
     for (int k = 0; k < kThetaBatch; ++k) {
-      if (i0 + k >= hi) break;  // wave-uniform
+      if (i0 + k >= hi) continue;  // wave-uniform
       if (!isfinite(static_cast<double>(v[k]))) f |= 1;
       if (v[k] < T(0)) f |= 2;
       sum = sum + fabs(static_cast<double>(v[k]));
-      stage_push<kCap>(s_stage, staged, (static_cast<uint64_t>(i0 + k) << 32) | static_cast<uint32_t>(c),
-                              v[k] != T(0), F, cnt);
+      if constexpr (kList)
+        stage_push<kCap>(s_stage, staged, (static_cast<uint64_t>(i0 + k) << 32) | static_cast<uint32_t>(c),
+                         v[k] != T(0), F, cnt);
+      else
+        staged += __popcll(__ballot(v[k] != T(0)));
     }
   }
-  stage_flush(s_stage, staged, F, cnt);
+  if constexpr (kList)
+    stage_flush(s_stage, staged, F, cnt);
+  else if (staged > 0 && lane_id() == 0)
+    atomicAdd(cnt, static_cast<unsigned long long>(staged));
   if (live) partial[(size_t)blockIdx.x * C + c] = sum;
   if (f) atomicOr(flags, f);
 }
@@ -109,10 +119,15 @@ __global__ __launch_bounds__(kWave) void k_theta_scan(const T* __restrict__ x, l
   if (lane_id() == 0 && tot) atomicAdd(nnz, tot);
 }
 
+// nnz_out (if not null) receives *nnz_in, so that one copy to the host
+// brings the signal flags and the count of non-zero cells together.
 template <typename T>
 __global__ void k_theta_final(const double* __restrict__ partial, int64_t nblocks, int C, double eps,
-                              const uint32_t* __restrict__ qids, uint32_t qid_base, ColParams* __restrict__ cp) {
+                              const uint32_t* __restrict__ qids, uint32_t qid_base, ColParams* __restrict__ cp,
+                              const unsigned long long* __restrict__ nnz_in = nullptr,
+                              unsigned long long* __restrict__ nnz_out = nullptr) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0 && nnz_out != nullptr) *nnz_out = *nnz_in;
   if (c >= C) return;
   double total = 0.0;
   constexpr int kInFlight = 16;  // loads issued together, added in block order
@@ -303,19 +318,35 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   AGP_HIP(hipMemsetAsync(flags, 0, sc.flags.bytes, s));
   if (qids) AGP_HIP(hipMemcpyAsync(dq, qids, sizeof(uint32_t) * C, hipMemcpyHostToDevice, s));
 
-  // thresholds theta_c = eps ||x_c||_1 and signal checks
-  if (tblocks > 0) {
-    dim3 grid((unsigned)tblocks, (unsigned)((C + 63) / 64));
-    k_theta_partial<T, kThetaCap><<<grid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
-                                                         sc.frontier[0].as<uint64_t>(), counts);
-  }
+  // thresholds theta_c = eps ||x_c||_1 and signal checks, counting the
+  // non-zero cells of x; when at least half of the cells are non-zero,
+  // level 0 visits every cell in order (skipping the zeros), else a second
+  // pass lists the non-zero cells
+  const dim3 tgrid((unsigned)std::max<int64_t>(tblocks, 1), (unsigned)((C + 63) / 64));
+  if (tblocks > 0)
+    k_theta_partial<T, kThetaCap, false><<<tgrid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
+                                                                 nullptr, counts);
+  // flags[2..3]: the count of non-zero cells of x
   k_theta_final<T><<<grid_for(C, 64), 64, 0, s>>>(sc.partial.as<double>(), tblocks, C, eps,
-                                                  qids ? dq : nullptr, qid_base, cp);
+                                                  qids ? dq : nullptr, qid_base, cp, counts,
+                                                  reinterpret_cast<unsigned long long*>(flags + 2));
   AGP_HIP(hipGetLastError());
   int hflags[4] = {0, 0, 0, 0};
   AGP_HIP(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
   AGP_HIP(hipStreamSynchronize(s));
+  unsigned long long nnz_x = 0;
+  std::memcpy(&nnz_x, hflags + 2, sizeof(nnz_x));
   if (hflags[1] & 1) return fail(AGP_EINVAL, std::string(fn) + ": x holds a non-finite value");
+  const bool virtual0 = nnz_x > 0 && 2 * nnz_x >= static_cast<unsigned long long>(cells) &&
+                        static_cast<long long>(C) <= kVirtualMaxC;
+  if (virtual0) {
+    k_set_u64<<<1, 1, 0, s>>>(counts, static_cast<unsigned long long>(cells));  // the level-0 entries
+  } else if (tblocks > 0) {
+    AGP_HIP(hipMemsetAsync(counts, 0, sizeof(unsigned long long), s));
+    k_theta_partial<T, kThetaCap, true><<<tgrid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
+                                                                sc.frontier[0].as<uint64_t>(), counts);
+    AGP_HIP(hipGetLastError());
+  }
   const bool positive = sizeof(T) == 4 && !(hflags[1] & 2);
 
   // binned aggregation: binary32, cells addressable in 32 bits, LDS scale table
@@ -439,7 +470,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     for (int32_t i = 0; i <= L; ++i) {
       k_set_level<<<grid_for(C, 64), 64, 0, s>>>(cp, C, i, lpd, da, db, out, ldc, sizeof(T));
       A.level = i;
-      A.fin = F[i & 1];
+      A.fin = (i == 0 && virtual0) ? nullptr : F[i & 1];
       A.cnt_in = counts + i;
       A.fout = F[(i + 1) & 1];
       A.cnt_out = counts + i + 1;
@@ -505,6 +536,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
         positive ? 1 : 0, binned ? 1 : 0, rec_cap, shift, big_cap, big_ctr != nullptr ? 1 : 0, tune.aggregation,
         tune.level_blocks, tune.big_row, tune.big_items, (tune.sparse_shift << 8) | tune.bin_shift);
     std::string k(key, kn > 0 ? static_cast<size_t>(kn) : 0);
+    k.push_back(virtual0 ? 'v' : 'l');  // level 0 over every cell or over the listed ones
     k.append(reinterpret_cast<const char*>(&big_rows), sizeof(big_rows));
     k.append(reinterpret_cast<const char*>(&samp_rows), sizeof(samp_rows));
     k.append(reinterpret_cast<const char*>(&samp_items), sizeof(samp_items));

@@ -150,6 +150,25 @@ def test_propagate_parity_fp32(agp, torch_dev, name, C):
     assert st["pushes"] > 0
 
 
+@pytest.mark.parametrize("zero_share", [0.1, 0.49, 0.51, 0.9])
+@pytest.mark.parametrize("wp", [32, 64])
+def test_signals_with_zero_cells(agp, torch_dev, zero_share, wp):
+    """Level 0 visits every cell of a mostly non-zero signal and skips its
+    zeros, and lists the non-zero cells of a mostly zero one: either way the
+    frontier, the counters and the estimates are the oracle's."""
+    g = inputs.chung_lu(3000, 10, 2.5, seed=23, self_loops=True)
+    x = inputs.features_uniform(g.n, 6, -1.0, 1.0, seed=24)
+    rng = np.random.default_rng(25)
+    x[rng.random(x.shape) < zero_share] = 0.0
+    x[5, :] = 0.0  # a node with no signal at all
+    x = x.astype(np.float32 if wp == 32 else np.float64)
+    w = inputs.weights_ppr(0.1, 8)
+    got, st = _run(agp, torch_dev, g, 0.5, 0.5, w, x, 1e-4, 31, wp=wp)
+    ref, cnt = _oracle(g, 0.5, 0.5, w, x, 1e-4, 31, wp=wp)
+    _assert_parity(got, st, ref, cnt, 8)
+    assert st["frontier"][0] == np.count_nonzero(x)
+
+
 def test_parity_fp64_c1_shape(agp, torch_dev):
     """PPR from node 0 (the top-weight hub) on a Chung-Lu graph, binary64."""
     g = inputs.chung_lu(10000, 10, 2.5, seed=1)

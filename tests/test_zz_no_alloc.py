@@ -6,6 +6,8 @@ row (the second smaller, so it starts from the first one's leftovers), it
 must not change the device's free memory, and it must refuse sizes beyond
 the array with AGP_EINVAL.
 """
+import gc
+
 import numpy as np
 import pytest
 
@@ -54,11 +56,20 @@ def test_noalloc_equals_propagate_two_calls_in_a_row(env):
         print(f"case {k}: a={a} b={b} C={C} {kind}", flush=True)
         ref, _ = agp.propagate(G, a, b, w, X, eps, 77 + k, qids=qids)  # makes the tables of (a, b)
         out = torch.full_like(X, float("nan"))
+        # objects of earlier tests that the collector frees (graphs, servers)
+        # return their memory: collect them first and keep the collector off
+        # while the call is measured
+        gc.collect()
         torch.cuda.synchronize()
-        free0 = torch.cuda.mem_get_info()[0]
-        agp.propagate_noalloc(G, a, b, w, X, eps, 77 + k, qids=qids, out=out)
-        torch.cuda.synchronize()
-        assert torch.cuda.mem_get_info()[0] == free0, "the call changed the device's free memory"
+        gc.disable()
+        try:
+            free0 = torch.cuda.mem_get_info()[0]
+            agp.propagate_noalloc(G, a, b, w, X, eps, 77 + k, qids=qids, out=out)
+            torch.cuda.synchronize()
+            free1 = torch.cuda.mem_get_info()[0]
+        finally:
+            gc.enable()
+        assert free1 == free0, "the call changed the device's free memory"
         assert torch.equal(out, ref), f"case {k}: max diff {(out - ref).abs().max().item()}"
 
 

@@ -65,8 +65,8 @@ ALU_PEAK_GDRAWS = VALU_LANE_OPS / VALU_PER_DRAW / 1e9
 # 1 GiB (WRITE_SIZE reads 1 GiB as written).  Valid only for the kernel
 # sources they were taken from and the default tuning.
 TRAFFIC = {
-    "gnn-ppr-large": {"sources": "447708fcd9b24a02", "columns": 128, "bytes_per_launch": 99619992514.0,
-                      "fetch_bytes": 76946709046.0, "write_bytes": 22673283468.0},
+    "gnn-ppr-large": {"sources": "4093d28bbd13f766", "columns": 128, "bytes_per_launch": 101868420000.0,
+                      "fetch_bytes": 79198660000.0, "write_bytes": 22669760000.0},
 }
 KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
                   "paper_2106_03058_amd/csrc/bin_kernels.h")

@@ -303,8 +303,12 @@ int agp_set_tuning(const agp_graph_t* g, int32_t C, double a, double b, const ag
  *   AGP_DENSE=0|1|auto   the dense field of agp_tuning_t;
  *   AGP_CAPTURE=0|1      the capture field of agp_tuning_t;
  *   AGP_RECORD_CAP=n     at most n push records per binned level (per record
- *                        group on dense levels; records beyond it are added
+ *                        group on dense levels, split between the two groups
+ *                        of frontier-list levels; records beyond it are added
  *                        with atomics);
+ *   AGP_RECORD_GROUPS=2  frontier-list levels keep their records in two
+ *                        column groups even when n C < 2^31 (they always do
+ *                        from n C >= 2^31 on: record cells are 31-bit);
  *   AGP_COLUMN_TILE=n    at most n columns per tile of a call;
  *   AGP_BIG_ROWS=n       at most n entries per level in each list of deferred
  *                        work (0: every entry keeps its pushes in its wave);

@@ -23,21 +23,28 @@ namespace {
 constexpr int kMaxBinnedC = 1024;
 constexpr int kReduceThreads = 512;
 
-__global__ __launch_bounds__(1024) void k_bins_scan(unsigned int* __restrict__ bucket_count,
+// One block per column group of records: the group's nbk bucket counts at
+// g * nbk (cleared), its offsets and cursors at g * (kBuckets + 1) and
+// g * kBuckets; a group whose records outgrew its buffer switches the level
+// to the atomic fallback.
+__global__ __launch_bounds__(1024) void k_bins_scan(unsigned int* __restrict__ bucket_count, int nbk,
                                                     unsigned long long* __restrict__ bucket_off,
                                                     unsigned long long* __restrict__ cursor,
                                                     const unsigned long long* __restrict__ rec_count,
                                                     unsigned long long cap, int* __restrict__ mode) {
   __shared__ unsigned long long s[kBuckets];
+  const int g = blockIdx.x;
   const int t = threadIdx.x;
-  const int m = *mode;
-  if (m != kModeBinned) return;
-  const unsigned long long v = bucket_count[t];
-  bucket_count[t] = 0;  // ready for the next level
-  if (*rec_count > cap) {
-    if (t == 0) *mode = kModeOverflow;
+  unsigned int* bc = bucket_count + static_cast<size_t>(g) * nbk;
+  const unsigned long long v = t < nbk ? bc[t] : 0ull;
+  if (t < nbk) bc[t] = 0;  // ready for the next level (zero unless this one was binned)
+  if (*mode != kModeBinned) return;  // (or another group overflowed)
+  if (rec_count[g] > cap) {
+    if (t == 0) atomicExch(mode, kModeOverflow);
     return;
   }
+  bucket_off += static_cast<size_t>(g) * (kBuckets + 1);
+  cursor += static_cast<size_t>(g) * kBuckets;
   s[t] = v;
   __syncthreads();
   for (int off = 1; off < kBuckets; off <<= 1) {
@@ -55,10 +62,14 @@ __global__ __launch_bounds__(1024) void k_bins_scan(unsigned int* __restrict__ b
 __global__ __launch_bounds__(kThreads) void k_apply_overflow(LevelArgs A, long long* __restrict__ acc,
                                                              const int* __restrict__ mode) {
   if (*mode != kModeOverflow) return;
-  const unsigned long long n = *A.rec_count < A.rec_cap ? *A.rec_count : A.rec_cap;
-  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < n;
-       i += (unsigned long long)gridDim.x * blockDim.x)
-    apply_record(A, acc, A.rec[i]);
+  const int ng = A.rec_groups > 1 ? A.rec_groups : 1;
+  for (int g = 0; g < ng; ++g) {
+    const unsigned long long n = A.rec_count[g] < A.rec_cap ? A.rec_count[g] : A.rec_cap;
+    const uint32_t* rec = A.rec + static_cast<size_t>(g) * A.rec_cap;
+    for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x)
+      apply_record<0>(A, acc, rec[i], static_cast<uint32_t>(g));
+  }
 }
 
 constexpr int kBatchLoads = 8;  // records per thread per load batch (memory-level parallelism)
@@ -327,7 +338,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_bin_scatter(const uint32_t* 
 // One block per bin: signed record counts in LDS, then each cell's new value
 // acc += count * fl(theta_c) (its deterministic pushes are already in acc);
 // the bin's non-zero cells are gathered in LDS and appended to the next
-// frontier with one atomic per bin.  With det non-null (a flag per bin that
+// frontier with one atomic per bin.  ldacc > 0: the cells are those of a
+// column group (local cell u * su + l, l < wg valid, for the accumulator
+// cell u * ldacc + c0 + l of column c0 + l; row-major, sc = 1).  With det non-null (a flag per bin that
 // the level's deterministic pushes set), a bin whose flag is clear holds
 // only zeros before its records: it is not read, and without records it has
 // nothing to do.  A set flag is cleared for the next level; a stale set flag
@@ -339,7 +352,8 @@ __global__ __launch_bounds__(kSumThreads) void k_bin_sum(const uint32_t* __restr
                                                          const ColParams* __restrict__ cp, long long su, long long sc,
                                                          unsigned long long cells, long long* __restrict__ acc,
                                                          uint64_t* __restrict__ F, unsigned long long* __restrict__ cnt,
-                                                         const int* __restrict__ mode, uint8_t* __restrict__ det) {
+                                                         const int* __restrict__ mode, uint8_t* __restrict__ det,
+                                                         long long ldacc = 0, int c0 = 0, int wg = 0) {
   if (*mode != kModeBinned) return;
   constexpr int kBin = 1 << kBinLog2;
   __shared__ int s_cnt[kBin];
@@ -368,25 +382,51 @@ __global__ __launch_bounds__(kSumThreads) void k_bin_sum(const uint32_t* __restr
   }
   __syncthreads();
   constexpr int kCellsPer = kBin / kSumThreads;
+  // column groups: the bin's first cell as (row u0, local column l0); cells
+  // of the bin are u0 + (l0 + j) / su, (l0 + j) mod su (su + kBin < 2^22)
+  const bool grouped = ldacc > 0;
+  const unsigned long long u0 = grouped ? cell0 / static_cast<unsigned long long>(su) : 0ull;
+  const uint32_t l0 = grouped ? static_cast<uint32_t>(cell0 - u0 * static_cast<unsigned long long>(su)) : 0u;
+  const float rsu = grouped ? 1.0f / static_cast<float>(su) : 0.0f;
+  // accumulator cell of bin cell j and, for a group, its column (false: not
+  // a cell of the call)
+  auto locate = [&](int j, size_t* at, uint32_t* c) -> bool {
+    const unsigned long long cell = cell0 + static_cast<unsigned long long>(j);
+    *c = 0u;
+    if (cell >= cells) return false;
+    if (!grouped) {
+      *at = cell;
+      return true;
+    }
+    uint32_t l = 0;
+    const uint32_t q = div_small(l0 + static_cast<uint32_t>(j), static_cast<uint32_t>(su), rsu, &l);
+    if (l >= static_cast<uint32_t>(wg)) return false;
+    *c = static_cast<uint32_t>(c0) + l;
+    *at = static_cast<size_t>(u0 + q) * static_cast<size_t>(ldacc) + *c;
+    return true;
+  };
   for (int k0 = 0; k0 < kCellsPer; k0 += 8) {
     long long vv[8];
+    size_t at[8];
+    uint32_t col[8];
+    bool ok[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const unsigned long long cell = cell0 + static_cast<unsigned long long>((k0 + k) * kSumThreads + threadIdx.x);
-      vv[k] = (read_acc && cell < cells) ? acc[cell] : 0ll;
+      ok[k] = locate((k0 + k) * kSumThreads + threadIdx.x, &at[k], &col[k]);
+      vv[k] = (read_acc && ok[k]) ? acc[at[k]] : 0ll;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int j = (k0 + k) * kSumThreads + threadIdx.x;
-      const unsigned long long cell = cell0 + static_cast<unsigned long long>(j);
       long long v = vv[k];
-      if (cell < cells) {
+      if (ok[k]) {
         const int kc = s_cnt[j];
         if (kc != 0) {
-          const uint32_t c = sc == 1 ? static_cast<uint32_t>(cell % static_cast<unsigned long long>(su))
-                                     : static_cast<uint32_t>(cell / static_cast<unsigned long long>(sc));
+          const uint32_t c = grouped ? col[k]
+                             : sc == 1 ? static_cast<uint32_t>(at[k] % static_cast<unsigned long long>(su))
+                                       : static_cast<uint32_t>(at[k] / static_cast<unsigned long long>(sc));
           v += static_cast<long long>(kc) * cp[c].dtheta;
-          acc[cell] = v;
+          acc[at[k]] = v;
         }
       }
       const unsigned long long m = __ballot(v != 0);
@@ -404,7 +444,11 @@ __global__ __launch_bounds__(kSumThreads) void k_bin_sum(const uint32_t* __restr
   for (unsigned int i = threadIdx.x; i < total; i += blockDim.x) {
     const unsigned long long cell = cell0 + s_nz[i];
     uint32_t u, c;
-    if (sc == 1) {  // row-major: cell = u * C + c
+    if (grouped) {
+      uint32_t l = 0;
+      u = static_cast<uint32_t>(u0) + div_small(l0 + static_cast<uint32_t>(s_nz[i]), static_cast<uint32_t>(su), rsu, &l);
+      c = static_cast<uint32_t>(c0) + l;
+    } else if (sc == 1) {  // row-major: cell = u * C + c
       u = static_cast<uint32_t>(cell / static_cast<unsigned long long>(su));
       c = static_cast<uint32_t>(cell - static_cast<unsigned long long>(u) * su);
     } else {  // one n-vector per column: cell = c * n + u

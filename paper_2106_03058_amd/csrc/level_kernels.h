@@ -130,11 +130,15 @@ struct LevelArgs {
   int positive;                  // non-negative signals: sparse levels allowed
   unsigned long long dense_cut;  // frontier size from which a level is dense
   int* mode_out;                 // how the next frontier is formed (kMode*)
-  // binned aggregation (binary32 batched calls; rec == nullptr: disabled)
+  // binned aggregation (binary32 batched calls; rec == nullptr: disabled);
+  // records are kept per column group (rec_groups groups of rec_gw columns,
+  // 1 group: the whole row), group g's at rec + g * rec_cap
   uint32_t* rec;
-  unsigned long long* rec_count;
-  unsigned long long rec_cap;
-  unsigned int* bucket_count;    // records per bucket of this level
+  unsigned long long* rec_count;  // this level's record count of each group
+  unsigned long long rec_cap;     // records per group
+  int rec_groups;
+  uint32_t rec_gw;
+  unsigned int* bucket_count;    // records per bucket of this level (kBuckets per group)
   int bucket_shift;              // cells per bucket = 2^bucket_shift
   const double* bin_est;         // non-null: bin only if *bin_est >= bin_pushes (estimated pushes)
   double bin_pushes;
@@ -146,8 +150,10 @@ struct LevelArgs {
   unsigned long long* samp_ctr;  // the same for deferred sampled suffixes (entries << 40 | items)
   BigSamp* samp;
   long long samp_items;          // work items from which an entry's sampled suffix is deferred
-  // binned levels: deterministic pushes mark their destination bin (nullptr: no marks)
+  // binned levels: deterministic pushes mark their destination bin (nullptr:
+  // no marks); group g's bins at det_bins + g * det_bins_g
   uint8_t* det_bins;
+  unsigned long long det_bins_g;
   // served queries: each query's residues live in an open-addressing table
   // of one pool (query c owns positions tab_off[c] .. tab_off[c] + tab_mask[c];
   // a key is node + 1, 0 when free); frontier entries are (position, c)
@@ -287,51 +293,151 @@ __device__ __forceinline__ double to_w(double v, double) { return v; }
 // ------------------------------------------------- record staging
 // On binned levels a sampled push becomes a 4-byte record, cell | sign << 31
 // (its value is -/+ fl(theta_c) of the cell's column c); deterministic pushes
-// still use atomics.  Records go to A.rec in chunks (one atomic per chunk).
-// Records beyond the buffer capacity are added to the accumulator directly;
-// the level then ends in kModeOverflow (the buffered records are applied
-// with atomics too).
-constexpr int kRecStage = 2 * kStage;  // 4-byte records per wave stage
+// still use atomics.  Records go to their group's buffer in chunks (one
+// atomic per chunk).  Records beyond the buffer capacity are added to the
+// accumulator directly; the level then ends in kModeOverflow (the buffered
+// records are applied with atomics too).
+//
+// The cell of a record is local to a column group, so that it stays below
+// 2^31 when n C does not: with one group it is u * su + c * sc; with two
+// (row-major cells only) group g = [c >= rec_gw] holds the columns from
+// g rec_gw on and the local cell is u * rec_gw + (c - g rec_gw).
+constexpr int kRecStage = 2 * kStage;  // 4-byte records per wave stage (both groups)
 constexpr uint32_t kRecCellMask = 0x7FFFFFFFu;
+constexpr int kMaxRecGroups = 2;
 
-template <typename Cell>
-__device__ __forceinline__ void apply_record(const LevelArgs& A, Cell* acc, uint32_t rec);
-
-template <>
-__device__ __forceinline__ void apply_record<long long>(const LevelArgs& A, long long* acc, uint32_t rec) {
-  const uint32_t cell = rec & kRecCellMask;
-  const uint32_t c = A.sc == 1 ? cell % static_cast<uint32_t>(A.su) : cell / static_cast<uint32_t>(A.sc);
-  const long long d = (rec >> 31) ? -A.cp[c].dtheta : A.cp[c].dtheta;
-  atomic_add_relaxed(reinterpret_cast<unsigned long long*>(acc + cell), static_cast<unsigned long long>(d));
+// kG: the groups of the launch (A.rec_groups of a binned level), a template
+// argument so that one-group levels keep the plain single-group code.
+struct RecCell {
+  uint32_t g, cell;
+};
+template <int kG>
+__device__ __forceinline__ RecCell rec_cell(const LevelArgs& A, uint32_t u, uint32_t c) {
+  if constexpr (kG > 1) {
+    const uint32_t g = c >= A.rec_gw ? 1u : 0u;
+    return RecCell{g, u * A.rec_gw + (c - g * A.rec_gw)};
+  } else {
+    return RecCell{0u, u * static_cast<uint32_t>(A.su) + c * static_cast<uint32_t>(A.sc)};
+  }
 }
 
-template <>
-__device__ __forceinline__ void apply_record<unsigned long long>(const LevelArgs&, unsigned long long*, uint32_t) {}
+// (kG = 0: the groups of A at run time)
+template <int kG>
+__device__ __forceinline__ void apply_record(const LevelArgs& A, long long* acc, uint32_t rec, uint32_t g) {
+  const uint32_t cell = rec & kRecCellMask;
+  uint32_t c;
+  size_t at = cell;
+  if (kG > 1 || (kG == 0 && A.rec_groups > 1)) {
+    const uint32_t u = cell / A.rec_gw;
+    c = g * A.rec_gw + (cell - u * A.rec_gw);
+    at = static_cast<size_t>(u) * static_cast<size_t>(A.su) + c;
+  } else {
+    c = A.sc == 1 ? cell % static_cast<uint32_t>(A.su) : cell / static_cast<uint32_t>(A.sc);
+  }
+  const long long d = (rec >> 31) ? -A.cp[c].dtheta : A.cp[c].dtheta;
+  atomic_add_relaxed(reinterpret_cast<unsigned long long*>(acc + at), static_cast<unsigned long long>(d));
+}
 
-template <typename Cell>
+template <int kG>
+__device__ __forceinline__ void apply_record(const LevelArgs&, unsigned long long*, uint32_t, uint32_t) {}
+
+// Staged record counts of a wave: the count (one group), or group 0's in the
+// low 16 bits and group 1's in the high 16 bits of one wave-uniform int.
+//
+// The staged records out: group 0's from the front of the stage, group 1's
+// from its back (one atomic on each group's count; records beyond a group's
+// buffer are added with atomics).  Wave-uniform.
+template <int kG, typename Cell>
 __device__ __forceinline__ void stage_flush_records(uint32_t* stage, int& staged, const LevelArgs& A, Cell* acc) {
-  if (staged == 0) return;
+  if constexpr (kG == 1) {
+    if (staged == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(A.rec_count, static_cast<unsigned long long>(staged));
+    base = __shfl(base, 0);
+    for (int i = lane_id(); i < staged; i += kWave) {
+      if (base + i < A.rec_cap)
+        A.rec[base + i] = stage[i];
+      else
+        apply_record<kG>(A, acc, stage[i], 0u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    staged = 0;
+    return;
+  }
+  const int n0 = staged & 0xFFFF, n1 = staged >> 16;
+  const int total = n0 + n1;
+  if (total == 0) return;
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const int lane = lane_id();
   unsigned long long base = 0;
-  if (lane_id() == 0) base = atomicAdd(A.rec_count, static_cast<unsigned long long>(staged));
-  base = __shfl(base, 0);
-  for (int i = lane_id(); i < staged; i += kWave) {
-    if (base + i < A.rec_cap)
-      A.rec[base + i] = stage[i];
+  if (lane < 2) {
+    const int k = lane == 0 ? n0 : n1;
+    if (k > 0) base = atomicAdd(A.rec_count + lane, static_cast<unsigned long long>(k));
+  }
+  const unsigned long long base0 = __shfl(base, 0), base1 = __shfl(base, 1);
+  for (int i = lane; i < total; i += kWave) {
+    const uint32_t g = i < n0 ? 0u : 1u;
+    const int j = i - (g ? n0 : 0);
+    const uint32_t r = g ? stage[kRecStage - 1 - j] : stage[j];
+    const unsigned long long at = (g ? base1 : base0) + static_cast<unsigned long long>(j);
+    if (at < A.rec_cap)
+      A.rec[static_cast<size_t>(g) * A.rec_cap + at] = r;
     else
-      apply_record(A, acc, stage[i]);
+      apply_record<kG>(A, acc, r, g);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   staged = 0;
 }
 
-template <typename Cell>
-__device__ __forceinline__ void stage_push_records(uint32_t* stage, int& staged, uint32_t rec, bool pred,
-                                                   const LevelArgs& A, Cell* acc) {
-  const unsigned long long mask = __ballot(pred);
-  if (pred) stage[staged + __popcll(mask & ((1ull << lane_id()) - 1ull))] = rec;
-  staged += __popcll(mask);
-  if (staged > kRecStage - kWave) stage_flush_records(stage, staged, A, acc);
+// One sampled push of every lane that emits (a wave-uniform call) as a
+// record of its group: its bucket counted in s_hist (kBuckets buckets, or
+// kBuckets / 2 per group with two groups), the record staged (group 0 from
+// the front of the stage, group 1 from its back); the stage goes out when it
+// is nearly full.
+template <int kG, typename Cell>
+__device__ __forceinline__ void emit_record(const LevelArgs& A, unsigned int* s_hist, uint32_t* stage, int& staged,
+                                            bool emit, uint32_t v, uint32_t c, bool neg, Cell* acc) {
+  uint32_t rec = 0, g = 0;
+  if (emit) {
+    const RecCell rc = rec_cell<kG>(A, v, c);
+    g = rc.g;
+    rec = rc.cell | (neg ? 0x80000000u : 0u);
+    atomicAdd(&s_hist[g * (kBuckets / kMaxRecGroups) + (rc.cell >> A.bucket_shift)], 1u);
+  }
+  const unsigned long long lt = (1ull << lane_id()) - 1ull;
+  if constexpr (kG > 1) {
+    const int n0 = staged & 0xFFFF, n1 = staged >> 16;
+    const unsigned long long m1 = __ballot(emit && g != 0);
+    const unsigned long long m0 = __ballot(emit) & ~m1;
+    if (emit) stage[g ? kRecStage - 1 - (n1 + __popcll(m1 & lt)) : n0 + __popcll(m0 & lt)] = rec;
+    const int k0 = n0 + __popcll(m0), k1 = n1 + __popcll(m1);
+    staged = k0 | (k1 << 16);
+    if (k0 + k1 > kRecStage - kWave) stage_flush_records<kG>(stage, staged, A, acc);
+  } else {
+    const unsigned long long m0 = __ballot(emit);
+    if (emit) stage[staged + __popcll(m0 & lt)] = rec;
+    staged += __popcll(m0);
+    if (staged > kRecStage - kWave) stage_flush_records<kG>(stage, staged, A, acc);
+  }
+}
+
+// The end of a binned launch: the staged records out, then (after a block
+// barrier) the block's bucket counts added to the level's.
+template <int kG, typename Cell>
+__device__ __forceinline__ void finish_records(const LevelArgs& A, unsigned int* s_hist, uint32_t* stage, int& staged,
+                                               Cell* acc) {
+  stage_flush_records<kG>(stage, staged, A, acc);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
+    if (s_hist[i]) atomicAdd(A.bucket_count + i, s_hist[i]);
+}
+
+// a deterministic push's mark on its destination bin (binned levels)
+template <int kG>
+__device__ __forceinline__ void mark_det_bin(const LevelArgs& A, uint8_t* det_bins, uint32_t v, uint32_t c) {
+  const RecCell rc = rec_cell<kG>(A, v, c);
+  det_bins[rc.g * A.det_bins_g + (rc.cell >> kBinLog2)] = 1;
 }
 
 // Server counters: LDS sums for the first kServeLdsSlots columns, global
@@ -407,8 +513,9 @@ __device__ __forceinline__ int batch_find(const long long* off, long long k) {
 
 // kFirst: the residues are the signal x (level 0 of a batched call).
 // kServe: counters and overflow mass are kept per column instead of per level.
-template <typename T, bool kFirst, bool kServe>
-__global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __restrict__ x,
+// kG: column groups of the records on binned levels (1 or 2).
+template <typename T, bool kFirst, bool kServe, int kG = 1>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1 ? 4 : 1, 8))) void k_level(LevelArgs A, const T* __restrict__ x,
                                                     typename Prec<T>::Cell* __restrict__ acc_cur,
                                                     typename Prec<T>::Cell* __restrict__ acc_next) {
   using P = Prec<T>;
@@ -488,13 +595,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
   };
   auto emit_sampled = [&](bool emit, uint32_t v, uint32_t ec, const Delta& delta, bool eneg) {
     if (binned) {
-      uint32_t rec = 0;
-      if (emit) {
-        const uint32_t vcell = v * static_cast<uint32_t>(A.su) + ec * static_cast<uint32_t>(A.sc);
-        rec = vcell | (eneg ? 0x80000000u : 0u);
-        atomicAdd(&s_hist[vcell >> A.bucket_shift], 1u);
-      }
-      stage_push_records(reinterpret_cast<uint32_t*>(stage), staged, rec, emit, A, acc_next);
+      emit_record<kG>(A, s_hist, reinterpret_cast<uint32_t*>(stage), staged, emit, v, ec, eneg, acc_next);
     } else {
       emit_atomic(emit, v, ec, delta);
     }
@@ -760,8 +861,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
           if (B.neg[e]) val = -val;
           emit = P::to_units(val, *cpd, &delta);
           if (!emit) atomicOr(A.err + (kServe ? vc : 0u), 1);
-          if (binned && A.det_bins != nullptr)
-            A.det_bins[(static_cast<size_t>(v) * A.su + static_cast<size_t>(vc) * A.sc) >> kBinLog2] = 1;
+          if (binned && A.det_bins != nullptr) mark_det_bin<kG>(A, A.det_bins, v, vc);
         }
         emit_atomic(emit, v, vc, delta);
       }
@@ -868,12 +968,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
     emit_sampled(emit, v, c, delta, neg);
   }
   if (sparse) stage_flush(stage, staged, A.fout, A.cnt_out);
-  if (binned) {
-    stage_flush_records(reinterpret_cast<uint32_t*>(stage), staged, A, acc_next);
-    __syncthreads();
-    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
-      if (s_hist[i]) atomicAdd(A.bucket_count + i, s_hist[i]);
-  }
+  if (binned) finish_records<kG>(A, s_hist, reinterpret_cast<uint32_t*>(stage), staged, acc_next);
   if (kServe) {  // flush the block's per-column sums
     __syncthreads();
     for (int i = threadIdx.x; i < kServeLdsSlots * kNumCounters; i += blockDim.x) {
@@ -913,7 +1008,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs A, const T* __rest
 // the rows' offsets and moves to the next row when it crosses its end.  The
 // pushes are computed and accumulated as in k_level (first contributions of
 // a sparse level appended to the next frontier).
-template <typename T>
+template <typename T, int kG = 1>
 __global__ __launch_bounds__(kThreads) void k_det_big(LevelArgs A, typename Prec<T>::Cell* __restrict__ acc_next) {
   using P = Prec<T>;
   using Delta = typename P::Delta;
@@ -967,7 +1062,7 @@ __global__ __launch_bounds__(kThreads) void k_det_big(LevelArgs A, typename Prec
         if (!emit) atomicOr(A.err, 1);
       }
       const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(vc) * A.sc;
-      if (emit && det_bins != nullptr) det_bins[vcell >> kBinLog2] = 1;
+      if (emit && det_bins != nullptr) mark_det_bin<kG>(A, det_bins, v, vc);
       bool first = false;
       if (emit) {
         if (sparse)
@@ -989,7 +1084,7 @@ __global__ __launch_bounds__(kThreads) void k_det_big(LevelArgs A, typename Prec
 // are emitted as in k_level's mode for the level (records, first-touch
 // appends or plain atomics), and the level's candidate and acceptance
 // counters get this kernel's counts.
-template <typename T>
+template <typename T, int kG = 1>
 __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Prec<T>::Cell* __restrict__ acc_next) {
   using P = Prec<T>;
   using Delta = typename P::Delta;
@@ -1108,13 +1203,7 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
       }
     }
     if (binned) {
-      uint32_t rec = 0;
-      if (emit) {
-        const uint32_t vcell = v * static_cast<uint32_t>(A.su) + c * static_cast<uint32_t>(A.sc);
-        rec = vcell | (neg ? 0x80000000u : 0u);
-        atomicAdd(&s_hist[vcell >> A.bucket_shift], 1u);
-      }
-      stage_push_records(reinterpret_cast<uint32_t*>(stage), staged, rec, emit, A, acc_next);
+      emit_record<kG>(A, s_hist, reinterpret_cast<uint32_t*>(stage), staged, emit, v, c, neg, acc_next);
     } else {
       const size_t vcell = static_cast<size_t>(v) * A.su + static_cast<size_t>(c) * A.sc;
       bool first = false;
@@ -1128,12 +1217,7 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
     }
   }
   if (sparse) stage_flush(stage, staged, A.fout, A.cnt_out);
-  if (binned) {
-    stage_flush_records(reinterpret_cast<uint32_t*>(stage), staged, A, acc_next);
-    __syncthreads();
-    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
-      if (s_hist[i]) atomicAdd(A.bucket_count + i, s_hist[i]);
-  }
+  if (binned) finish_records<kG>(A, s_hist, reinterpret_cast<uint32_t*>(stage), staged, acc_next);
   unsigned long long* cnt = A.counters + static_cast<size_t>(A.level) * kNumCounters;
   const unsigned long long v3 = wave_sum_u64(n_cand);
   const unsigned long long v4 = wave_sum_u64(n_acc);

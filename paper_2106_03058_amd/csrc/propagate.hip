@@ -349,48 +349,65 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   }
   const bool positive = sizeof(T) == 4 && !(hflags[1] & 2);
 
-  // binned aggregation: binary32, cells addressable in 32 bits, LDS scale table
-  bool binned = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4 && cells < (1ull << 31) &&
+  // binned aggregation: binary32, LDS scale table, record cells in 31 bits:
+  // one group of all C columns when n C < 2^31, else two column groups of
+  // ceil(C / 2) columns (cells local to a group) when n ceil(C / 2) < 2^31
+  int ng = static_cast<unsigned long long>(cells) < (1ull << 31) ? 1 : kMaxRecGroups;
+  if (const char* e = std::getenv("AGP_RECORD_GROUPS"))  // column groups at any size (tests)
+    if (std::strcmp(e, "2") == 0 && C >= 2) ng = kMaxRecGroups;
+  const long long gw = ng == 1 ? C : (C + 1) / 2;
+  const unsigned long long gcells = static_cast<unsigned long long>(n) * static_cast<unsigned long long>(gw);
+  bool binned = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4 && gcells < (1ull << 31) &&
                 C <= kMaxBinnedC && cells > 0;
-  // buckets of 2^shift cells: at most 1024 buckets, bins of 8192 cells
+  // buckets of 2^shift group cells: at most 1024 buckets (512 per group with
+  // two groups, which share the level kernel's histogram), bins of 8192 cells
+  const unsigned long long nbk = static_cast<unsigned long long>(kBuckets / ng);
   int shift = kBinLog2;
-  while (shift < 32 && (static_cast<unsigned long long>(cells) - 1ull) >> shift >= (unsigned long long)kBuckets) ++shift;
-  const long long nbins = static_cast<long long>(((cells > 0 ? cells : 1) - 1) >> kBinLog2) + 1;
-  unsigned long long rec_cap = 0;
+  while (shift < 32 && (gcells > 0 ? gcells - 1ull : 0ull) >> shift >= nbk) ++shift;
+  const long long nbins = static_cast<long long>(((gcells > 0 ? gcells : 1) - 1) >> kBinLog2) + 1;  // per group
+  unsigned long long rec_cap = 0;  // per group
   if (binned) {
-    // room for 4 records per cell (1 when the call runs in several tiles),
-    // within an eighth of the free memory (two buffers)
+    // room for 4 records per cell (1 when the call runs in several tiles,
+    // whose width left room for that), within 80% of the free memory (two
+    // buffers)
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
-    rec_cap = std::max<unsigned long long>(1ull << 20, (static_cast<long long>(C) < ldc ? 1ull : 4ull) * cells);
-    rec_cap = std::min<unsigned long long>(rec_cap, std::max<unsigned long long>(1ull << 20, free_b / 64));
+    const size_t held = sc.rec[0].bytes + sc.rec[1].bytes;
+    unsigned long long cap = std::max<unsigned long long>(1ull << 20, (static_cast<long long>(C) < ldc ? 1ull : 4ull) * cells);
+    cap = std::min<unsigned long long>(cap, std::max<unsigned long long>(1ull << 20, (free_b + held) / 10));
     if (const char* e = std::getenv("AGP_RECORD_CAP")) {  // smaller record buffer (tuning / tests)
       const unsigned long long v = std::strtoull(e, nullptr, 10);
-      if (v > 0 && v < rec_cap) rec_cap = v;
+      if (v > 0 && v < cap) cap = v;
     }
-    if (sc.rec[0].reserve(rec_cap * sizeof(uint32_t), false, s) ||
-        sc.rec[1].reserve(rec_cap * sizeof(uint32_t), false, s) ||
-        sc.bins.reserve(sizeof(unsigned int) * kBuckets + sizeof(unsigned long long) * (2 * kBuckets + 1) +
-                            sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1) +
-                            sizeof(unsigned long long) * (3 * nbins + 1) + static_cast<size_t>(nbins), true, s)) {
+    rec_cap = (cap + ng - 1) / ng;
+    if (sc.rec[0].reserve(rec_cap * ng * sizeof(uint32_t), false, s) ||
+        sc.rec[1].reserve(rec_cap * ng * sizeof(uint32_t), false, s) ||
+        sc.bins.reserve(ng * (sizeof(unsigned int) * kBuckets + sizeof(unsigned long long) * (2 * kBuckets + 1) +
+                              sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1) + static_cast<size_t>(nbins)) +
+                            sizeof(unsigned long long) * (3 * nbins + 1),
+                        true, s)) {
       sc.rec[0].release();  // not enough memory for the record buffers: atomics instead
       sc.rec[1].release();
       binned = false;
       (void)hipGetLastError();
     }
   }
+  // bucket counts (group g's kBuckets / ng at g * kBuckets / ng); per group:
+  // bucket offsets, partition cursors (kBuckets + 1 and kBuckets), per-level
+  // record counts (level i, group g at i * ng + g), deterministic-push flags
+  // per bin; shared by the groups in turn: bin counts, offsets, cursors
   unsigned int* bucket_count = binned ? sc.bins.as<unsigned int>() : nullptr;
-  unsigned long long* bucket_off = binned ? reinterpret_cast<unsigned long long*>(bucket_count + kBuckets) : nullptr;
-  unsigned long long* cursor = binned ? bucket_off + kBuckets + 1 : nullptr;
-  unsigned long long* rec_counts = binned ? cursor + kBuckets : nullptr;
-  unsigned long long* bin_count = binned ? rec_counts + AGP_MAX_LEVELS + 1 : nullptr;
+  unsigned long long* bucket_off = binned ? reinterpret_cast<unsigned long long*>(bucket_count + kBuckets * ng) : nullptr;
+  unsigned long long* cursor = binned ? bucket_off + (kBuckets + 1) * ng : nullptr;
+  unsigned long long* rec_counts = binned ? cursor + kBuckets * ng : nullptr;
+  unsigned long long* bin_count = binned ? rec_counts + (AGP_MAX_LEVELS + 1) * ng : nullptr;
   unsigned long long* bin_off = binned ? bin_count + nbins : nullptr;
   unsigned long long* bin_cur = binned ? bin_off + nbins + 1 : nullptr;
   uint8_t* det_bins = binned ? reinterpret_cast<uint8_t*>(bin_cur + nbins) : nullptr;  // any stale value is safe
   if (binned) {
-    AGP_HIP(hipMemsetAsync(rec_counts, 0, sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1), s));
+    AGP_HIP(hipMemsetAsync(rec_counts, 0, sizeof(unsigned long long) * (AGP_MAX_LEVELS + 1) * ng, s));
     AGP_HIP(hipMemsetAsync(bin_count, 0, sizeof(unsigned long long) * nbins, s));
-    AGP_HIP(hipMemsetAsync(bucket_count, 0, sizeof(unsigned int) * kBuckets, s));  // the dense path shares the buffer
+    AGP_HIP(hipMemsetAsync(bucket_count, 0, sizeof(unsigned int) * kBuckets * ng, s));  // the dense path shares the buffer
   }
 
   hipEvent_t* ev = sc.events;
@@ -447,10 +464,16 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   A.rec = nullptr;
   A.rec_count = nullptr;
   A.rec_cap = rec_cap;
+  A.rec_groups = ng;
+  A.rec_gw = static_cast<uint32_t>(gw);
+  A.det_bins_g = static_cast<unsigned long long>(nbins);
   A.bucket_count = bucket_count;
   A.bucket_shift = shift;
   A.bin_est = nullptr;
-  A.bin_pushes = std::ldexp(static_cast<double>(cells), -tune.bin_shift);  // auto: bin levels with n C / 2^k pushes
+  // auto: bin levels with n C / 2^k estimated pushes; with two column groups
+  // from twice that (on 32-column tiles of a 111M-node graph the record
+  // passes cost more than the atomics they replace below about n C / 4)
+  A.bin_pushes = std::ldexp(static_cast<double>(cells), -(ng > 1 ? std::max(tune.bin_shift - 1, 1) : tune.bin_shift));
   // per-level values of this call (read by k_set_level from device memory)
   LevelParams lph[AGP_MAX_LEVELS + 1];
   const uint32_t key0 = static_cast<uint32_t>(seed), key1 = static_cast<uint32_t>(seed >> 32);
@@ -484,7 +507,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
       A.samp = samp_rows;
       A.samp_items = samp_items;
       A.big_cap = big_cap;
-      A.rec_count = bin_level ? rec_counts + i : nullptr;
+      A.rec_count = bin_level ? rec_counts + static_cast<size_t>(i) * ng : nullptr;
       Cell* cur = acc[i & 1];
       Cell* nxt = acc[(i + 1) & 1];
       A.bin_est = nullptr;
@@ -497,25 +520,52 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
           k_estimate<T, false><<<1024, kThreads, 0, s>>>(A, x, cur, est + i);
       }
       if (timed) (void)hipEventRecord(ev[4 * i + 1], s);
-      if (i == 0)
-        k_level<T, true, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
-      else
-        k_level<T, false, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
-      if (A.big_ctr != nullptr) k_det_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
-      if (A.samp_ctr != nullptr) k_samp_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
+      bool grouped = false;  // records in two column groups (binary32 only)
+      if constexpr (sizeof(T) == 4) {
+        grouped = bin_level && ng > 1;
+        if (grouped) {
+          if (i == 0)
+            k_level<T, true, false, 2><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
+          else
+            k_level<T, false, false, 2><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
+          if (A.big_ctr != nullptr) k_det_big<T, 2><<<1024, kThreads, 0, s>>>(A, nxt);
+          if (A.samp_ctr != nullptr) k_samp_big<T, 2><<<1024, kThreads, 0, s>>>(A, nxt);
+        }
+      }
+      if (!grouped) {
+        if (i == 0)
+          k_level<T, true, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
+        else
+          k_level<T, false, false><<<tune.level_blocks, kThreads, 0, s>>>(A, x, cur, nxt);
+        if (A.big_ctr != nullptr) k_det_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
+        if (A.samp_ctr != nullptr) k_samp_big<T><<<1024, kThreads, 0, s>>>(A, nxt);
+      }
       if (timed) (void)hipEventRecord(ev[4 * i + 2], s);
       if (bin_level) {
         uint32_t* r0 = sc.rec[0].as<uint32_t>();
         uint32_t* r1 = sc.rec[1].as<uint32_t>();
-        k_bins_scan<<<1, kBuckets, 0, s>>>(bucket_count, bucket_off, cursor, rec_counts + i, rec_cap, mode + i + 1);
+        unsigned long long* rc = rec_counts + static_cast<size_t>(i) * ng;
+        k_bins_scan<<<ng, kBuckets, 0, s>>>(bucket_count, static_cast<int>(nbk), bucket_off, cursor, rc, rec_cap,
+                                            mode + i + 1);
         k_apply_overflow<<<2048, kThreads, 0, s>>>(A, reinterpret_cast<long long*>(nxt), mode + i + 1);
-        k_partition<<<1024, kReduceThreads, 0, s>>>(r0, rec_counts + i, cursor, r1, mode + i + 1, shift);
-        k_bin_count<<<2048, kReduceThreads, 0, s>>>(r1, rec_counts + i, bin_count, mode + i + 1, shift);
-        k_bin_scan<<<1, 1024, 0, s>>>(bin_count, nbins, bin_off, bin_cur, mode + i + 1);
-        k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(r1, rec_counts + i, bin_cur, r0, mode + i + 1, shift);
-        k_bin_sum<<<static_cast<unsigned>(nbins), kSumThreads, 0, s>>>(
-            r0, bin_off, cp, (long long)C, 1ll, static_cast<unsigned long long>(cells),
-            reinterpret_cast<long long*>(nxt), F[(i + 1) & 1], counts + i + 1, mode + i + 1, det_bins);
+        for (int gi = 0; gi < ng; ++gi) {  // each group's records in turn
+          uint32_t* g0 = r0 + static_cast<size_t>(gi) * rec_cap;
+          uint32_t* g1 = r1 + static_cast<size_t>(gi) * rec_cap;
+          k_partition<<<1024, kReduceThreads, 0, s>>>(g0, rc + gi, cursor + static_cast<size_t>(gi) * kBuckets, g1,
+                                                      mode + i + 1, shift);
+          k_bin_count<<<2048, kReduceThreads, 0, s>>>(g1, rc + gi, bin_count, mode + i + 1, shift);
+          k_bin_scan<<<1, 1024, 0, s>>>(bin_count, nbins, bin_off, bin_cur, mode + i + 1);
+          k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(g1, rc + gi, bin_cur, g0, mode + i + 1, shift);
+          if (ng == 1)
+            k_bin_sum<<<static_cast<unsigned>(nbins), kSumThreads, 0, s>>>(
+                g0, bin_off, cp, (long long)C, 1ll, static_cast<unsigned long long>(cells),
+                reinterpret_cast<long long*>(nxt), F[(i + 1) & 1], counts + i + 1, mode + i + 1, det_bins);
+          else
+            k_bin_sum<<<static_cast<unsigned>(nbins), kSumThreads, 0, s>>>(
+                g0, bin_off, cp, gw, 1ll, gcells, reinterpret_cast<long long*>(nxt), F[(i + 1) & 1], counts + i + 1,
+                mode + i + 1, det_bins + static_cast<size_t>(gi) * nbins, (long long)C, static_cast<int>(gi * gw),
+                static_cast<int>(std::min<long long>(gw, C - gi * gw)));
+        }
       }
       if (i < L)
         k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, F[(i + 1) & 1], counts + i + 1,
@@ -533,7 +583,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
         static_cast<void*>(F[0]), static_cast<void*>(F[1]), static_cast<void*>(counts), static_cast<void*>(counters),
         static_cast<void*>(sc.levelinfo.ptr), static_cast<void*>(flags), static_cast<const void*>(da),
         static_cast<const void*>(db), static_cast<void*>(sc.rec[0].ptr), static_cast<void*>(sc.bins.ptr),
-        positive ? 1 : 0, binned ? 1 : 0, rec_cap, shift, big_cap, big_ctr != nullptr ? 1 : 0, tune.aggregation,
+        positive ? 1 : 0, binned ? ng : 0, rec_cap, shift, big_cap, big_ctr != nullptr ? 1 : 0, tune.aggregation,
         tune.level_blocks, tune.big_row, tune.big_items, (tune.sparse_shift << 8) | tune.bin_shift);
     std::string k(key, kn > 0 ? static_cast<size_t>(kn) : 0);
     k.push_back(virtual0 ? 'v' : 'l');  // level 0 over every cell or over the listed ones

@@ -274,7 +274,10 @@ def test_error_paths(agp, torch_dev):
 @pytest.mark.parametrize("name", ["ppr", "tp", "gdc_signed", "general_ab"])
 def test_aggregation_modes_are_bit_identical(agp, torch_dev, name, monkeypatch):
     """Binned LDS aggregation, its record-overflow fallback and plain atomics
-    give the same bits (exact integer sums), equal to the oracle's."""
+    give the same bits (exact integer sums), equal to the oracle's; so do
+    records kept in two column groups (cells local to a group, as when n C
+    reaches 2^31; 33 columns: groups of 17 and 16), with and without
+    overflow."""
     a, b, w, eps, kind = CASES[name]
     g = inputs.chung_lu(6000, 12, 2.5, seed=31, self_loops=kind != "onehot")
     x = _signal(g, kind, 33, seed=4)
@@ -282,9 +285,12 @@ def test_aggregation_modes_are_bit_identical(agp, torch_dev, name, monkeypatch):
     ref, cnt = _oracle(g, a, b, w, x, eps, 5)
     results = []
     for env in ({}, {"AGP_AGGREGATION": "atomic"}, {"AGP_AGGREGATION": "binned"}, {"AGP_AGGREGATION": "auto"},
-                {"AGP_AGGREGATION": "binned", "AGP_RECORD_CAP": "5000"}):
-        monkeypatch.delenv("AGP_AGGREGATION", raising=False)
-        monkeypatch.delenv("AGP_RECORD_CAP", raising=False)
+                {"AGP_AGGREGATION": "binned", "AGP_RECORD_CAP": "5000"},
+                {"AGP_AGGREGATION": "binned", "AGP_RECORD_GROUPS": "2"},
+                {"AGP_AGGREGATION": "auto", "AGP_RECORD_GROUPS": "2"},
+                {"AGP_AGGREGATION": "binned", "AGP_RECORD_GROUPS": "2", "AGP_RECORD_CAP": "5000"}):
+        for k in ("AGP_AGGREGATION", "AGP_RECORD_CAP", "AGP_RECORD_GROUPS"):
+            monkeypatch.delenv(k, raising=False)
         for k, v in env.items():
             monkeypatch.setenv(k, v)
         got, st = _run(agp, torch_dev, g, a, b, w, x, eps, seed=5, G=G)

@@ -65,8 +65,8 @@ ALU_PEAK_GDRAWS = VALU_LANE_OPS / VALU_PER_DRAW / 1e9
 # 1 GiB (WRITE_SIZE reads 1 GiB as written).  Valid only for the kernel
 # sources they were taken from and the default tuning.
 TRAFFIC = {
-    "gnn-ppr-large": {"sources": "4093d28bbd13f766", "columns": 128, "bytes_per_launch": 101868420000.0,
-                      "fetch_bytes": 79198660000.0, "write_bytes": 22669760000.0},
+    "gnn-ppr-large": {"sources": "3eaf853071fb3798", "columns": 128, "bytes_per_launch": 122883380000.0,
+                      "fetch_bytes": 106039300000.0, "write_bytes": 16844080000.0},
 }
 KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
                   "paper_2106_03058_amd/csrc/bin_kernels.h")
@@ -759,7 +759,8 @@ def level_roofline(runs, models, args, C) -> dict:
     if rec and rec["sources"] == kernel_sources_sha() and rec["columns"] == C and not args.tune and not dense:
         traffic = rec["bytes_per_launch"] / avg_s / 1e9
     kernel = ("k_dense_level (levels 0..L-1)" if dense else
-              "k_level<float, false, false> + k_det_big<float> + k_samp_big<float> (levels 1..L)")
+              "k_level<float, false, false, G> + k_det_big<float, G> + k_samp_big<float, G> (levels 1..L; "
+              "G = 2 record column groups on binned levels of tiles with n C >= 2^31, else 1)")
     alu = {"bound": "alu", "achieved": gdraws, "peak": ALU_PEAK_GDRAWS, "unit": "Gdraw/s",
            "frac": gdraws / ALU_PEAK_GDRAWS,
            "peak_derivation": f"{VALU_LANE_OPS:.4g} VALU lane-ops/s / {VALU_PER_DRAW} per draw",

@@ -1288,17 +1288,19 @@ __global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __r
 // (u << 32 | c) of every cell u * C + c of a row-major n x C array whose
 // predicate holds.  Every chunk that goes out costs one atomic on the list
 // counter, a round trip to one shared address that all waves contend for,
-// so chunks are made large: a wave takes segments of kCompactSeg
-// consecutive cells, issues kCompactUnroll loads of 64 cells together, and
-// stages the passing cells as 2-byte offsets into its segment (up to
-// kCompactCap of them, 8 KiB of LDS per wave); a chunk goes out when the
-// stage is nearly full and at the end of each segment, in cell order.  Rows
+// so chunks are made large: a wave takes segments of seg consecutive cells
+// (a multiple of kCompactUnroll x 64, at most kCompactSeg: large arrays take
+// the largest, small ones smaller segments so that every CU has waves),
+// issues kCompactUnroll loads of 64 cells together, and stages the passing
+// cells as 2-byte offsets into its segment (up to kCompactCap of them, 8 KiB
+// of LDS per wave); a chunk goes out when the stage is nearly full and at the
+// end of each segment, in cell order.  Rows
 // and columns of the staged cells are formed when they go out, from one
 // 64-bit division per segment and a float-reciprocal division corrected to
 // the exact quotient per entry.
 constexpr int kCompactUnroll = 16;
 constexpr int kCompactCap = 4096;
-constexpr long long kCompactSeg = 1ll << 16;  // offsets fit in 16 bits
+constexpr long long kCompactSeg = 1ll << 16;  // the largest segment: offsets fit in 16 bits
 static_assert(kCompactSeg % (kCompactUnroll * kWave) == 0, "segments hold whole load groups");
 
 // The staged offsets of a segment that starts at row u0, column r0: one
@@ -1327,8 +1329,8 @@ __device__ __forceinline__ void compact_flush(const uint16_t* stage, int& staged
 }
 
 template <typename Pred>
-__global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int C, uint64_t* __restrict__ F,
-                                                      unsigned long long* __restrict__ cnt,
+__global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int C, long long seg,
+                                                      uint64_t* __restrict__ F, unsigned long long* __restrict__ cnt,
                                                       const int* __restrict__ mode) {
   if (mode && *mode != kModeCompact && *mode != kModeOverflow) return;  // formed elsewhere
   constexpr int kWaves = kThreads / kWave;
@@ -1341,11 +1343,11 @@ __global__ __launch_bounds__(kThreads) void k_compact(Pred pred, int64_t n, int 
   const bool small = C <= (1 << 21);  // div_small's range: C + kCompactSeg < 2^22
   const long long wave = static_cast<long long>(blockIdx.x) * kWaves + threadIdx.x / kWave;
   const long long nwaves = static_cast<long long>(gridDim.x) * kWaves;
-  for (long long base = wave * kCompactSeg; base < total; base += nwaves * kCompactSeg) {
+  for (long long base = wave * seg; base < total; base += nwaves * seg) {
     const long long u0 = base / C;
     const uint32_t r0 = static_cast<uint32_t>(base - u0 * C);
     int staged = 0;  // wave-uniform
-    for (int j = 0; j < kCompactSeg && base + j < total; j += kCompactUnroll * kWave) {
+    for (int j = 0; j < seg && base + j < total; j += kCompactUnroll * kWave) {
       // the index is clamped instead of guarded, so that the loads carry no
       // branch and go out together
       bool p[kCompactUnroll];

@@ -414,8 +414,11 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   if (stats && (rc = sc.ensure_events())) return rc;
   uint64_t* F[2] = {sc.frontier[0].as<uint64_t>(), sc.frontier[1].as<uint64_t>()};
   Cell* acc[2] = {sc.acc[0].as<Cell>(), sc.acc[1].as<Cell>()};
-  // compaction: a segment per wave, 32 KiB of LDS per block (five per CU)
-  const unsigned cgrid = grid_for(static_cast<int64_t>((cells + kCompactSeg - 1) / kCompactSeg), kThreads / kWave, 1280);
+  // compaction: 32 KiB of LDS per block (five per CU); segments of 2^10 to
+  // 2^16 cells per wave, as large as leaves about 4096 of them
+  long long cseg = kCompactUnroll * kWave;
+  while (cseg < kCompactSeg && cseg * 4096 < static_cast<long long>(cells)) cseg <<= 1;
+  const unsigned cgrid = grid_for(static_cast<int64_t>((cells + cseg - 1) / cseg), kThreads / kWave, 1280);
 
   // rows with long deterministic prefixes, deferred per level to k_det_big
   constexpr unsigned long long kBigCap = 1ull << 16;
@@ -568,7 +571,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
         }
       }
       if (i < L)
-        k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, F[(i + 1) & 1], counts + i + 1,
+        k_compact<<<cgrid, kThreads, 0, s>>>(NonZeroCell<T>{nxt}, n, C, cseg, F[(i + 1) & 1], counts + i + 1,
                                              mode + i + 1);
       if (timed) (void)hipEventRecord(ev[4 * i + 3], s);
     }

@@ -707,7 +707,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
         }
         T* const o = static_cast<T*>(cp.out) + static_cast<size_t>(eu) * static_cast<size_t>(cp.out_stride);
         const T o_old = (live && cp.kappa != 0.0) ? *o : T(0);
-        const uint32_t nd_first = (live && deg_u > 0) ? A.nd[rp_u] : 0u;
+        // (a = 0: every factor d^-a is 1, no degree is read)
+        const uint32_t nd_first = (live && deg_u > 0 && !(cp.flags & kAZero)) ? A.nd[rp_u] : 0u;
         const double db_u = live ? cp.db[fdeg_u] : 0.0;
         eneg = r < T(0);
         if (live) {

@@ -287,9 +287,9 @@ int agp_autotune(const agp_graph_t* g, double a, double b, const double* w, int3
                  float* out, void* stream, agp_tuning_t* best);
 
 /* The choice agp_propagate uses for (g, C, a, b): the tuned or set one,
- * else the default (aggregation 2, 4096 workgroups, dense 0, the other
- * fields at their stated defaults), with the environment overrides below
- * applied. */
+ * else the default (aggregation 2, 4096 workgroups (8192 when n C >= 2^31),
+ * dense 0, the other fields at their stated defaults), with the environment
+ * overrides below applied. */
 int agp_get_tuning(const agp_graph_t* g, int32_t C, double a, double b, agp_tuning_t* out);
 
 /* Pin the choice for later calls on g with C columns and exponents (a, b),

@@ -65,8 +65,8 @@ ALU_PEAK_GDRAWS = VALU_LANE_OPS / VALU_PER_DRAW / 1e9
 # 1 GiB (WRITE_SIZE reads 1 GiB as written).  Valid only for the kernel
 # sources they were taken from and the default tuning.
 TRAFFIC = {
-    "gnn-ppr-large": {"sources": "3eaf853071fb3798", "columns": 128, "bytes_per_launch": 122883380000.0,
-                      "fetch_bytes": 106039300000.0, "write_bytes": 16844080000.0},
+    "gnn-ppr-large": {"sources": "cdabc941bb085e46", "columns": 128, "bytes_per_launch": 120436240000.0,
+                      "fetch_bytes": 103580600000.0, "write_bytes": 16855640000.0},
 }
 KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
                   "paper_2106_03058_amd/csrc/bin_kernels.h")

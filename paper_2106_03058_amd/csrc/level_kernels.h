@@ -8,13 +8,15 @@
 // advance together in one launch.
 //
 // Cells: the residue of node u in column c lives at cell u * su + c * sc
-// (row-major n x C for agp_propagate, one contiguous n-vector per slot for
-// the server).  Next-level residues are exact integers of a per-column unit
+// (row-major n x C for agp_propagate; a served query's residues live at
+// positions of its own table instead).  Next-level residues are exact
+// integers of a per-column unit
 // (int64 cells for binary32, 128-bit cells for binary64), so the integer
 // atomics that add contributions commute and the result does not depend on
 // the order in which pushes land.
 //
-// A wave takes batches of up to 64 frontier entries (u, c): each lane
+// A wave takes batches of up to 64 frontier entries (u, c) (from a list, or,
+// at level 0 of a mostly non-zero signal, every cell in order): each lane
 // converts one entry's residue, updates the reserve (pi(u) += kappa_i r(u)),
 // finds the deterministic prefix J of the degree-sorted row (increment >=
 // theta, by binary search) and counts the work items of its sampled suffix;
@@ -138,7 +140,7 @@ struct LevelArgs {
   unsigned long long rec_cap;     // records per group
   int rec_groups;
   uint32_t rec_gw;
-  unsigned int* bucket_count;    // records per bucket of this level (kBuckets per group)
+  unsigned int* bucket_count;    // records per bucket of this level (kBuckets, kBuckets / 2 per group with two)
   int bucket_shift;              // cells per bucket = 2^bucket_shift
   const double* bin_est;         // non-null: bin only if *bin_est >= bin_pushes (estimated pushes)
   double bin_pushes;
@@ -1295,10 +1297,9 @@ __global__ __launch_bounds__(kThreads) void k_estimate(LevelArgs A, const T* __r
 // issues kCompactUnroll loads of 64 cells together, and stages the passing
 // cells as 2-byte offsets into its segment (up to kCompactCap of them, 8 KiB
 // of LDS per wave); a chunk goes out when the stage is nearly full and at the
-// end of each segment, in cell order.  Rows
-// and columns of the staged cells are formed when they go out, from one
-// 64-bit division per segment and a float-reciprocal division corrected to
-// the exact quotient per entry.
+// end of each segment, in cell order.  Rows and columns of the staged cells
+// are formed when they go out, from one 64-bit division per segment and a
+// float-reciprocal division corrected to the exact quotient per entry.
 constexpr int kCompactUnroll = 16;
 constexpr int kCompactCap = 4096;
 constexpr long long kCompactSeg = 1ll << 16;  // the largest segment: offsets fit in 16 bits

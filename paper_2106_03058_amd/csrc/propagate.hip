@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <initializer_list>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -86,6 +87,110 @@ __global__ __launch_bounds__(kWave) void k_theta_partial(const T* __restrict__ x
   if (f) atomicOr(flags, f);
 }
 
+// Adds the 64 lanes' values of v to sum in lane order (wave-uniform sum).
+__device__ __forceinline__ double add_lanes_in_order(double sum, double v) {
+  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
+  const uint32_t lo = static_cast<uint32_t>(b), hi = static_cast<uint32_t>(b >> 32);
+#pragma unroll 16
+  for (int j = 0; j < kWave; ++j) {
+    const uint64_t bj = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(hi, j))) << 32) |
+                        static_cast<uint32_t>(__builtin_amdgcn_readlane(lo, j));
+    sum = sum + __longlong_as_double(static_cast<long long>(bj));
+  }
+  return sum;
+}
+
+// Exponent of the lowest set bit of a finite a > 0: a is an integer multiple
+// of 2^low_exp(a).
+__device__ __forceinline__ int low_exp(double a) {
+  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(a));
+  const int e = static_cast<int>(b >> 52) & 0x7ff;
+  uint64_t m = b & ((1ull << 52) - 1);
+  if (e) m |= 1ull << 52;
+  return (e ? e : 1) - 1075 + __builtin_ctzll(m);
+}
+
+// Sum of non-negative values spread over the wave (lane partial sums s, each
+// lane's smallest low_exp m, INT_MAX for none), if it is exact.  When every
+// value is an integer multiple of 2^m and the exact total is below 2^(m+53),
+// every partial sum, in any order, is such a multiple below 2^(m+53) and so a
+// binary64 number: each addition is exact and every order of additions, the
+// sequential one included, gives the exact total.  An inexact addition would
+// round up to at least 2^(m+53), and the additions after it keep the total
+// there, so a computed total below that bound proves exactness.  Returns false
+// (and the caller adds in order) otherwise, also for non-finite values.
+__device__ __forceinline__ bool wave_exact_sum(double s, int m, double& total) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    s = s + __shfl_xor(s, off);
+    const int mo = __shfl_xor(m, off);
+    m = mo < m ? mo : m;
+  }
+  const uint64_t sb = static_cast<uint64_t>(__double_as_longlong(s));
+  const uint64_t ub = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(
+                           static_cast<uint32_t>(sb >> 32)))) << 32) |
+                      static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(sb)));
+  total = __longlong_as_double(static_cast<long long>(ub));
+  m = __builtin_amdgcn_readfirstlane(m);
+  if (m == INT_MAX) return total == 0.0;
+  return total < ldexp(1.0, m + 53);
+}
+
+// k_theta_partial for one column (C = 1): the lanes load all 4096 rows of the
+// block at once (row lo + 64 k + lane in v[k]); the block's sum is the exact
+// one when wave_exact_sum proves it, else the wave adds the rows one by one in
+// row order.  Either way it is the sequential sum of k_theta_partial; the
+// frontier entries are the same (u << 32).
+template <typename T, bool kList>
+__global__ __launch_bounds__(kWave) void k_theta_partial_c1(const T* __restrict__ x, long long ldx, int64_t n,
+                                                            double* __restrict__ partial, int* __restrict__ flags,
+                                                            uint64_t* __restrict__ F,
+                                                            unsigned long long* __restrict__ cnt) {
+  __shared__ uint64_t s_stage[kList ? kThetaCap : 1];
+  constexpr int kLoads = kThetaRows / kWave;
+  const int lane = lane_id();
+  const int64_t lo = (int64_t)blockIdx.x * kThetaRows;
+  const int64_t hi = (lo + kThetaRows) < n ? lo + kThetaRows : n;
+  T v[kLoads];
+#pragma unroll
+  for (int k = 0; k < kLoads; ++k) {
+    const int64_t i = lo + k * kWave + lane;
+    v[k] = i < hi ? x[static_cast<size_t>(i) * static_cast<size_t>(ldx)] : T(0);  // +0 past the end
+  }
+  double s = 0.0;
+  int m = INT_MAX;
+  int f = 0;
+  int staged = 0;  // wave-uniform
+#pragma unroll
+  for (int k = 0; k < kLoads; ++k) {
+    if (!isfinite(static_cast<double>(v[k]))) f |= 1;
+    if (v[k] < T(0)) f |= 2;
+    const double a = fabs(static_cast<double>(v[k]));
+    s = s + a;
+    if (a != 0.0) {
+      const int e = low_exp(a);
+      m = e < m ? e : m;
+    }
+    if constexpr (kList)
+      stage_push<kThetaCap>(s_stage, staged, static_cast<uint64_t>(lo + k * kWave + lane) << 32, v[k] != T(0), F,
+                            cnt);
+    else
+      staged += __popcll(__ballot(v[k] != T(0)));
+  }
+  double sum;
+  if (!wave_exact_sum(s, m, sum)) {
+    sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) sum = add_lanes_in_order(sum, fabs(static_cast<double>(v[k])));
+  }
+  if constexpr (kList)
+    stage_flush(s_stage, staged, F, cnt);
+  else if (staged > 0 && lane == 0)
+    atomicAdd(cnt, static_cast<unsigned long long>(staged));
+  if (lane == 0) partial[blockIdx.x] = sum;
+  if (f) atomicOr(flags, f);
+}
+
 // The same sums as k_theta_partial without forming a frontier; counts the
 // non-zero entries of x instead (their share decides the dense path).
 template <typename T>
@@ -122,24 +227,60 @@ __global__ __launch_bounds__(kWave) void k_theta_scan(const T* __restrict__ x, l
 // nnz_out (if not null) receives *nnz_in, so that one copy to the host
 // brings the signal flags and the count of non-zero cells together.
 template <typename T>
-__global__ void k_theta_final(const double* __restrict__ partial, int64_t nblocks, int C, double eps,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_theta_final(const double* __restrict__ partial, int64_t nblocks, int C, double eps,
                               const uint32_t* __restrict__ qids, uint32_t qid_base, ColParams* __restrict__ cp,
                               const unsigned long long* __restrict__ nnz_in = nullptr,
                               unsigned long long* __restrict__ nnz_out = nullptr) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c == 0 && nnz_out != nullptr) *nnz_out = *nnz_in;
-  if (c >= C) return;
   double total = 0.0;
-  constexpr int kInFlight = 16;  // loads issued together, added in block order
-  int64_t b = 0;
-  for (; b + kInFlight <= nblocks; b += kInFlight) {
-    double v[kInFlight];
+  if (C == 1) {  // one wave: lane l loads block b0 + 64 k + l
+    constexpr int kInFlight = 16;
+    double s = 0.0;
+    int m = INT_MAX;
+    for (int64_t b0 = 0; b0 < nblocks; b0 += kInFlight * kWave) {
+      double v[kInFlight];
 #pragma unroll
-    for (int k = 0; k < kInFlight; ++k) v[k] = partial[(size_t)(b + k) * C + c];
+      for (int k = 0; k < kInFlight; ++k) {
+        const int64_t b = b0 + k * kWave + threadIdx.x;
+        v[k] = b < nblocks ? partial[b] : 0.0;
+      }
 #pragma unroll
-    for (int k = 0; k < kInFlight; ++k) total = total + v[k];
+      for (int k = 0; k < kInFlight; ++k) {
+        s = s + v[k];
+        if (v[k] != 0.0) {
+          const int e = low_exp(v[k]);
+          m = e < m ? e : m;
+        }
+      }
+    }
+    if (!wave_exact_sum(s, m, total)) {  // add in block order
+      total = 0.0;
+      for (int64_t b0 = 0; b0 < nblocks; b0 += kInFlight * kWave) {
+        double v[kInFlight];
+#pragma unroll
+        for (int k = 0; k < kInFlight; ++k) {
+          const int64_t b = b0 + k * kWave + threadIdx.x;
+          v[k] = b < nblocks ? partial[b] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kInFlight; ++k) total = add_lanes_in_order(total, v[k]);
+      }
+    }
   }
-  for (; b < nblocks; ++b) total = total + partial[(size_t)b * C + c];
+  if (c >= C) return;
+  if (C > 1) {  // one lane per column, in block order
+    constexpr int kInFlight = 64;  // loads issued together
+    int64_t b = 0;
+    for (; b + kInFlight <= nblocks; b += kInFlight) {
+      double v[kInFlight];
+#pragma unroll
+      for (int k = 0; k < kInFlight; ++k) v[k] = partial[(size_t)(b + k) * C + c];
+#pragma unroll
+      for (int k = 0; k < kInFlight; ++k) total = total + v[k];
+    }
+    for (; b < nblocks; ++b) total = total + partial[(size_t)b * C + c];
+  }
   ColParams p = cp[c];
   p.theta = eps * total;
   p.qid = qids ? qids[c] : qid_base + static_cast<uint32_t>(c);
@@ -329,7 +470,10 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   // level 0 visits every cell in order (skipping the zeros), else a second
   // pass lists the non-zero cells
   const dim3 tgrid((unsigned)std::max<int64_t>(tblocks, 1), (unsigned)((C + 63) / 64));
-  if (tblocks > 0)
+  if (tblocks > 0 && C == 1)
+    k_theta_partial_c1<T, false><<<tgrid, kWave, 0, s>>>(x, ldc, n, sc.partial.as<double>(), flags + 1, nullptr,
+                                                         counts);
+  else if (tblocks > 0)
     k_theta_partial<T, kThetaCap, false><<<tgrid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
                                                                  nullptr, counts);
   // flags[2..3]: the count of non-zero cells of x
@@ -349,8 +493,12 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     k_set_u64<<<1, 1, 0, s>>>(counts, static_cast<unsigned long long>(cells));  // the level-0 entries
   } else if (tblocks > 0) {
     AGP_HIP(hipMemsetAsync(counts, 0, sizeof(unsigned long long), s));
-    k_theta_partial<T, kThetaCap, true><<<tgrid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
-                                                                sc.frontier[0].as<uint64_t>(), counts);
+    if (C == 1)
+      k_theta_partial_c1<T, true><<<tgrid, kWave, 0, s>>>(x, ldc, n, sc.partial.as<double>(), flags + 1,
+                                                          sc.frontier[0].as<uint64_t>(), counts);
+    else
+      k_theta_partial<T, kThetaCap, true><<<tgrid, kWave, 0, s>>>(x, ldc, n, C, sc.partial.as<double>(), flags + 1,
+                                                                  sc.frontier[0].as<uint64_t>(), counts);
     AGP_HIP(hipGetLastError());
   }
   const bool positive = sizeof(T) == 4 && !(hflags[1] & 2);

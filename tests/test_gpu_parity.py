@@ -169,6 +169,38 @@ def test_signals_with_zero_cells(agp, torch_dev, zero_share, wp):
     assert st["frontier"][0] == np.count_nonzero(x)
 
 
+@pytest.mark.parametrize("kind", ["normal", "sparse", "onehot", "tiny"])
+@pytest.mark.parametrize("wp", [32, 64])
+def test_one_column_signals(agp, torch_dev, kind, wp):
+    """One column over several 4096-row threshold blocks with a ragged tail:
+    the one-column threshold pass gives the sum in row order (exact sums of
+    binary32 blocks taken in any order; one entry of 1e-30, or binary64
+    entries, make the block sums inexact and the wave adds in row order), so
+    theta, the level-0 frontier and the estimates are the oracle's; a
+    non-finite entry in the last block is rejected."""
+    torch, dev = torch_dev
+    g = inputs.chung_lu(10000, 8, 2.5, seed=41, self_loops=kind != "onehot")
+    if kind == "onehot":
+        x = inputs.one_hot(g.n, [9999])
+    else:
+        x = inputs.features_normal(g.n, 1, seed=42)
+        if kind == "sparse":
+            x[np.random.default_rng(43).random(x.shape) < 0.9] = 0.0
+        if kind == "tiny":
+            x[7000, 0] = 1e-30
+    x = x.astype(np.float32 if wp == 32 else np.float64)
+    w = inputs.weights_ppr(0.2, 8)
+    got, st = _run(agp, torch_dev, g, 0.5, 0.5, w, x, 1e-5, 44, wp=wp)
+    ref, cnt = _oracle(g, 0.5, 0.5, w, x, 1e-5, 44, wp=wp)
+    _assert_parity(got, st, ref, cnt, 8)
+    assert st["frontier"][0] == np.count_nonzero(x)
+    xn = torch.from_numpy(x.copy()).to(dev)
+    xn[9000, 0] = float("inf")
+    with pytest.raises(agp.AGPError) as e:
+        agp.propagate(agp.Graph.from_inputs(g), 0.5, 0.5, w, xn, 1e-5, 44)
+    assert e.value.code == agp.AGP_EINVAL
+
+
 def test_parity_fp64_c1_shape(agp, torch_dev):
     """PPR from node 0 (the top-weight hub) on a Chung-Lu graph, binary64."""
     g = inputs.chung_lu(10000, 10, 2.5, seed=1)

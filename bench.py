@@ -63,13 +63,13 @@ ALU_PEAK_GDRAWS = VALU_LANE_OPS / VALU_PER_DRAW / 1e9
 # of this script (FETCH_SIZE, then WRITE_SIZE) with --calibrate-copy;
 # FETCH_SIZE is scaled by 2.0, the factor that makes the 1 GiB copy read
 # 1 GiB (WRITE_SIZE reads 1 GiB as written).  Valid only for the kernel
-# sources they were taken from and the default tuning.
+# sources they were taken from (the files that define k_level, k_det_big and
+# k_samp_big, code without comments) and the default tuning.
 TRAFFIC = {
-    "gnn-ppr-large": {"sources": "5a515d49385f0758", "columns": 128, "bytes_per_launch": 120436240000.0,
+    "gnn-ppr-large": {"sources": "0dfe30de78f97b6b", "columns": 128, "bytes_per_launch": 120436240000.0,
                       "fetch_bytes": 103580600000.0, "write_bytes": 16855640000.0},
 }
-KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h",
-                  "paper_2106_03058_amd/csrc/bin_kernels.h")
+KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h")
 
 
 def _code_only(text: str) -> str:

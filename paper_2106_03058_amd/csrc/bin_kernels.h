@@ -222,44 +222,104 @@ __global__ __launch_bounds__(kReduceThreads) void k_bin_count(const uint32_t* __
   }
 }
 
-// Exclusive scan of the bin counts (one block); clears the counts for the
-// next level and sets the scatter cursors.
-__global__ __launch_bounds__(1024) void k_bin_scan(unsigned long long* __restrict__ bin_count, long long nbins,
+// Exclusive scan of the bin counts: block b takes bins [16384 b, 16384 (b +
+// 1)), adds up every count before them itself (coalesced; at most a few
+// hundred thousand bins, so the repeated prefix reads stay small), scans its
+// own (each k-th load of the 1024 threads is a contiguous run of bins: wave
+// scans, then one scan of the 16 x 16 wave totals in LDS) and sets offsets and
+// scatter cursors.  Launch nbins / 16384 + 1 blocks: the last one also writes
+// bin_off[nbins].  The counts are cleared later, by k_bin_scatter.
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = 1024 * kScanPer;
+
+__global__ __launch_bounds__(1024) void k_bin_scan(const unsigned long long* __restrict__ bin_count, long long nbins,
                                                    unsigned long long* __restrict__ bin_off,
                                                    unsigned long long* __restrict__ bin_cur,
                                                    const int* __restrict__ mode) {
   if (*mode != kModeBinned) return;
-  __shared__ unsigned long long s[1024];
-  const long long per = (nbins + 1023) / 1024;
-  const long long b0 = threadIdx.x * per;
-  const long long b1 = b0 + per < nbins ? b0 + per : nbins;
-  unsigned long long run = 0;
-  for (long long b = b0; b < b1; ++b) run += bin_count[b];
-  s[threadIdx.x] = run;
+  constexpr int kWaves = 1024 / kWave;
+  __shared__ unsigned long long s_pre[kWaves + 1];  // each wave's share of the prefix, then the chunk total
+  __shared__ unsigned long long s_w[kScanPer * kWaves];  // (k, wave) totals, then their exclusive prefixes
+  const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+  const long long c0 = static_cast<long long>(blockIdx.x) * kScanChunk;
+  unsigned long long pre = 0;
+  for (long long b = t; b < c0; b += 1024ll * 8) {  // c0 is a multiple of 8 * 1024
+    unsigned long long p[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[k] = bin_count[b + 1024ll * k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) pre += p[k];
+  }
+  pre = wave_sum_u64(pre);
+  if (lane == 0) s_pre[wave] = pre;
+  unsigned long long v[kScanPer], incl[kScanPer];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const long long i = c0 + 1024ll * k + t;
+    v[k] = i < nbins ? bin_count[i] : 0ull;
+  }
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    incl[k] = v[k];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const unsigned long long u = __shfl_up(incl[k], off);
+      if (lane >= off) incl[k] += u;
+    }
+    if (lane == kWave - 1) s_w[k * kWaves + wave] = incl[k];
+  }
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const unsigned long long add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0ull;
-    __syncthreads();
-    s[threadIdx.x] += add;
-    __syncthreads();
+  if (wave == 0) {  // exclusive scan of the 256 totals in (k, wave) order, 4 per lane
+    constexpr int kPer = kScanPer * kWaves / kWave;
+    unsigned long long x[kPer], run = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      x[j] = s_w[lane * kPer + j];
+      run += x[j];
+    }
+    unsigned long long sc = run;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const unsigned long long u = __shfl_up(sc, off);
+      if (lane >= off) sc += u;
+    }
+    sc -= run;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      s_w[lane * kPer + j] = sc;
+      sc += x[j];
+    }
+    if (lane == kWave - 1) s_pre[kWaves] = sc;  // the chunk's total
   }
-  unsigned long long acc = s[threadIdx.x] - run;
-  for (long long b = b0; b < b1; ++b) {
-    const unsigned long long v = bin_count[b];
-    bin_off[b] = acc;
-    bin_cur[b] = acc;
-    bin_count[b] = 0;
-    acc += v;
+  __syncthreads();
+  unsigned long long base = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) base += s_pre[w];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const long long i = c0 + 1024ll * k + t;
+    if (i < nbins) {
+      const unsigned long long o = base + s_w[k * kWaves + wave] + incl[k] - v[k];
+      bin_off[i] = o;
+      bin_cur[i] = o;
+    }
   }
-  if (threadIdx.x == 1023) bin_off[nbins] = s[1023];
+  if (t == 0 && nbins >= c0 && nbins < c0 + kScanChunk) bin_off[nbins] = base + s_pre[kWaves];
 }
 
+// Also clears the nbins bin counts for the next k_bin_count (k_bin_scan has
+// read them).
 __global__ __launch_bounds__(kReduceThreads) void k_bin_scatter(const uint32_t* __restrict__ part,
                                                                 const unsigned long long* __restrict__ rec_count,
                                                                 unsigned long long* __restrict__ bin_cur,
                                                                 uint32_t* __restrict__ out,
-                                                                const int* __restrict__ mode, int shift) {
+                                                                const int* __restrict__ mode, int shift,
+                                                                unsigned long long* __restrict__ bin_count,
+                                                                long long nbins) {
   if (*mode != kModeBinned) return;
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < nbins;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    bin_count[i] = 0;
   __shared__ uint32_t s_rec[kBinTile];
   __shared__ unsigned int s_h[kBinWindow];
   __shared__ unsigned int s_loc[kBinWindow];

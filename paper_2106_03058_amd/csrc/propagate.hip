@@ -711,8 +711,10 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
           k_partition<<<1024, kReduceThreads, 0, s>>>(g0, rc + gi, cursor + static_cast<size_t>(gi) * kBuckets, g1,
                                                       mode + i + 1, shift);
           k_bin_count<<<2048, kReduceThreads, 0, s>>>(g1, rc + gi, bin_count, mode + i + 1, shift);
-          k_bin_scan<<<1, 1024, 0, s>>>(bin_count, nbins, bin_off, bin_cur, mode + i + 1);
-          k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(g1, rc + gi, bin_cur, g0, mode + i + 1, shift);
+          k_bin_scan<<<static_cast<unsigned>(nbins / kScanChunk + 1), 1024, 0, s>>>(bin_count, nbins, bin_off,
+                                                                                 bin_cur, mode + i + 1);
+          k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(g1, rc + gi, bin_cur, g0, mode + i + 1, shift, bin_count,
+                                                        nbins);
           if (ng == 1)
             k_bin_sum<<<static_cast<unsigned>(nbins), kSumThreads, 0, s>>>(
                 g0, bin_off, cp, (long long)C, 1ll, static_cast<unsigned long long>(cells),
@@ -1093,8 +1095,9 @@ int propagate_dense_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune,
           k_partition<<<1024, kReduceThreads, 0, s>>>(r0, rc_g, cursor + static_cast<size_t>(gi) * kBuckets, r1, md,
                                                       shift);
           k_bin_count<<<2048, kReduceThreads, 0, s>>>(r1, rc_g, bin_count, md, shift);
-          k_bin_scan<<<1, 1024, 0, s>>>(bin_count, nbins, bin_off, bin_cur, md);
-          k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(r1, rc_g, bin_cur, r0, md, shift);
+          k_bin_scan<<<static_cast<unsigned>(nbins / kScanChunk + 1), 1024, 0, s>>>(bin_count, nbins, bin_off,
+                                                                                 bin_cur, md);
+          k_bin_scatter<<<2048, kReduceThreads, 0, s>>>(r1, rc_g, bin_cur, r0, md, shift, bin_count, nbins);
           k_dense_bin_sum<<<static_cast<unsigned>(nbins), dense::kSumThreads, 0, s>>>(
               r0, bin_off, cpt, Ct, gi * gw, wgi, gcells, acc, r, fnext, md, det_bins + static_cast<size_t>(gi) * nbins_g);
         }

@@ -473,8 +473,16 @@ struct BatchLds {
   double p0[kBatch];           // a = 0: sampling probability of every run of the entry
   long long doff[kBatch + 1];  // deterministic pushes before each entry (exclusive scan)
   long long ioff[kBatch + 1];  // sampled work items before each entry
-  uint32_t u[kBatch], c[kBatch], d[kBatch], J[kBatch], neg[kBatch];
+  // the entry's column parameters that its work items need (theta, the
+  // random stream's counter word and key), so that taking an item reads LDS
+  double th[kBatch];
+  uint32_t ctr3[kBatch], key0[kBatch], key1[kBatch];
+  // c: column | kBatchNeg (negative residue) | kBatchAZero (a = 0)
+  uint32_t u[kBatch], c[kBatch], d[kBatch], J[kBatch];
 };
+constexpr uint32_t kBatchNeg = 1u << 31, kBatchAZero = 1u << 30, kBatchCol = kBatchAZero - 1u;
+// columns of one level launch at most (the column index leaves those two bits free)
+constexpr int32_t kMaxTileColumns = static_cast<int32_t>(kBatchCol);
 
 // floor(a / C) and a mod C for a < 2^22, from rc = 1 / C rounded to binary32:
 // the product is within one of the quotient, and one correction makes it exact
@@ -661,7 +669,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
       const uint64_t batch_item = next_items;
       next_items = load_items(bnext);
       long long dwork = 0, iwork = 0;
-      uint32_t eu = 0, ec = 0, ed = 0, eJ = 0;
+      uint32_t eu = 0, ec = 0, ed = 0, eJ = 0, ecw = 0;
       int64_t erp = 0;
       double ecv = 0.0, ep0 = 0.0;
       bool eneg = false;
@@ -713,6 +721,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
         const uint32_t nd_first = (live && deg_u > 0 && !(cp.flags & kAZero)) ? A.nd[rp_u] : 0u;
         const double db_u = live ? cp.db[fdeg_u] : 0.0;
         eneg = r < T(0);
+        ecw = ec | (eneg ? kBatchNeg : 0u) | ((cp.flags & kAZero) ? kBatchAZero : 0u);
+        // (the previous batch is no longer read: these slots are free; the
+        // entries past ne get no work items)
+        B.th[lane] = cp.theta;
+        B.ctr3[lane] = (cp.qid << 8) | static_cast<uint32_t>(cp.level);
+        B.key0[lane] = cp.key0;
+        B.key1[lane] = cp.key1;
         if (live) {
           if (kServe) {
             serve_count(A, s_scnt, ec, 0, 1ull);
@@ -840,10 +855,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
         B.ioff[kBatch] = iinc;
       }
       B.u[lane] = eu;
-      B.c[lane] = ec;
+      B.c[lane] = ecw;
       B.d[lane] = ed;
       B.J[lane] = eJ;
-      B.neg[lane] = eneg ? 1u : 0u;
       wave_sync();
       // deterministic pushes of the batch: the increment reaches theta
       const long long dtot = B.doff[kBatch];
@@ -855,13 +869,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
         if (k < dtot) {
           const int e = batch_find(B.doff, k);
           const int64_t arc = B.rp[e] + (k - B.doff[e]);
-          vc = B.c[e];
+          const uint32_t cw = B.c[e];
+          vc = cw & kBatchCol;
           const ColParams* cpd = A.cp + vc;
           v = A.col[arc];
           double inc = B.cv[e];
           if (!(cpd->flags & kAZero)) inc = inc * cpd->da[A.nd[arc]];
           T val = to_w(inc, T());
-          if (B.neg[e]) val = -val;
+          if (cw & kBatchNeg) val = -val;
           emit = P::to_units(val, *cpd, &delta);
           if (!emit) atomicOr(A.err + (kServe ? vc : 0u), 1);
           if (binned && A.det_bins != nullptr) mark_det_bin<kG>(A, A.det_bins, v, vc);
@@ -880,17 +895,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
           const int e = batch_find(B.ioff, it);
           const uint32_t il = static_cast<uint32_t>(it - B.ioff[e]);
           u = B.u[e];
-          c = B.c[e];
+          const uint32_t cw = B.c[e];
+          c = cw & kBatchCol;
           rpu = B.rp[e];
           cv = B.cv[e];
-          neg = B.neg[e] != 0;
+          neg = (cw & kBatchNeg) != 0;
           const uint32_t J = B.J[e], d = B.d[e];
           cpp = A.cp + c;
-          azero = (cpp->flags & kAZero) != 0;
-          th = cpp->theta;
-          ctr3 = (cpp->qid << 8) | static_cast<uint32_t>(cpp->level);
-          key0 = cpp->key0;
-          key1 = cpp->key1;
+          azero = (cw & kBatchAZero) != 0;
+          th = B.th[e];
+          ctr3 = B.ctr3[e];
+          key0 = B.key0[e];
+          key1 = B.key1[e];
           const uint32_t nwin = ((d - 1) >> kSegLog2) - (J >> kSegLog2) + 1;
           const uint32_t w0 = il * kWinPerItem;
           const uint32_t w1 = (w0 + kWinPerItem) < nwin ? w0 + kWinPerItem : nwin;

@@ -1306,7 +1306,7 @@ int propagate_impl(agp_graph* g, double a, double b, const double* w, int32_t L,
       }
     }
     const bool may_bin = (tune.aggregation == 1 || tune.aggregation == 2) && sizeof(T) == 4;
-    const int32_t tile = borrowed ? C : column_tile<T>(g, C, may_bin, tune);
+    const int32_t tile = std::min(borrowed ? C : column_tile<T>(g, C, may_bin, tune), kMaxTileColumns);
     AGP_HIP(hipMemsetAsync(out, 0, cells * sizeof(T), s));
     for (int32_t c0 = 0; c0 < C; c0 += tile) {
       const int32_t ct = std::min(tile, C - c0);

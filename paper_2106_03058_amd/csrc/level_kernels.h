@@ -466,6 +466,7 @@ __device__ __forceinline__ void serve_count(const LevelArgs& A, unsigned long lo
 // lockstep per wave so that staging can use wave-wide ballots.
 constexpr int kBatch = kWave;
 constexpr int kWinPerItem = 16;
+constexpr int kItemMap = 128;
 
 struct BatchLds {
   int64_t rp[kBatch];
@@ -479,6 +480,7 @@ struct BatchLds {
   uint32_t ctr3[kBatch], key0[kBatch], key1[kBatch];
   // c: column | kBatchNeg (negative residue) | kBatchAZero (a = 0)
   uint32_t u[kBatch], c[kBatch], d[kBatch], J[kBatch];
+  uint8_t item_entry[kItemMap];  // the entry of each of the batch's first kItemMap work items
 };
 constexpr uint32_t kBatchNeg = 1u << 31, kBatchAZero = 1u << 30, kBatchCol = kBatchAZero - 1u;
 // columns of one level launch at most (the column index leaves those two bits free)
@@ -525,7 +527,7 @@ __device__ __forceinline__ int batch_find(const long long* off, long long k) {
 // kServe: counters and overflow mass are kept per column instead of per level.
 // kG: column groups of the records on binned levels (1 or 2).
 template <typename T, bool kFirst, bool kServe, int kG = 1>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1 ? 4 : 1, 8))) void k_level(LevelArgs A, const T* __restrict__ x,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_level(LevelArgs A, const T* __restrict__ x,
                                                     typename Prec<T>::Cell* __restrict__ acc_cur,
                                                     typename Prec<T>::Cell* __restrict__ acc_next) {
   using P = Prec<T>;
@@ -565,7 +567,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
   int staged = 0;  // wave-uniform
 
   // per-lane counts stay far below 2^32 in one launch; the hash wraps mod 2^64
-  uint32_t n_front = 0, n_det = 0, n_cand = 0, n_acc = 0, n_runs = 0;
+  uint32_t n_det = 0;
+  uint32_t w_front = 0, w_cand = 0, w_acc = 0, w_runs = 0;  // wave-uniform (ballot counts)
   unsigned long long n_hash = 0;
   double mass = 0.0;
 
@@ -673,6 +676,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
       int64_t erp = 0;
       double ecv = 0.0, ep0 = 0.0;
       bool eneg = false;
+      bool front_live = false;
       if (lane < ne) {
         const uint64_t item = batch_item;
         eu = static_cast<uint32_t>(item >> 32);
@@ -732,7 +736,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
           if (kServe) {
             serve_count(A, s_scnt, ec, 0, 1ull);
           } else {
-            ++n_front;
+            front_live = true;
             n_hash += splitmix64(eu);
           }
           // reserve: pi(u) += (S w_i / Y_i) r(u), rounded to the working precision
@@ -835,6 +839,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
           }
         }
       }
+      if (!kServe) w_front += static_cast<uint32_t>(__popcll(__ballot(front_live)));
       long long dinc = dwork, iinc = iwork;
 #pragma unroll
       for (int off = 1; off < kWave; off <<= 1) {
@@ -850,6 +855,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
       B.p0[lane] = ep0;
       B.doff[lane] = dinc - dwork;
       B.ioff[lane] = iinc - iwork;
+      {
+        const int j1 = static_cast<int>(iinc < kItemMap ? iinc : kItemMap);
+        for (int j = static_cast<int>(iinc - iwork < kItemMap ? iinc - iwork : kItemMap); j < j1; ++j)
+          B.item_entry[j] = static_cast<uint8_t>(lane);
+      }
       if (lane == kWave - 1) {
         B.doff[kBatch] = dinc;
         B.ioff[kBatch] = iinc;
@@ -892,7 +902,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
       if (!active) {
         const long long it = it_next + __popcll(idle & lt_mask);
         if (it < it_total) {
-          const int e = batch_find(B.ioff, it);
+          const int e = it < kItemMap ? B.item_entry[it] : batch_find(B.ioff, it);
           const uint32_t il = static_cast<uint32_t>(it - B.ioff[e]);
           u = B.u[e];
           const uint32_t cw = B.c[e];
@@ -929,11 +939,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
     }
     // (d) a run: the rest of the current window, or (a > 0) of its degree
     // group unless few candidates are expected over the rest of the window
+    if (!kServe) w_runs += static_cast<uint32_t>(__popcll(__ballot(active && need_run)));
     if (active && need_run) {
-      if (kServe)
-        ++it_runs;
-      else
-        ++n_runs;
+      if (kServe) ++it_runs;
       const uint32_t wnext = ((s >> kSegLog2) + 1u) << kSegLog2;
       const uint32_t wend = wnext < rend ? wnext : rend;
       run_end = wend;
@@ -951,7 +959,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
       need_run = false;
     }
     // (e) one draw of the run's chain
-    bool emit = false;
+    bool emit = false, cand_hit = false;
     uint32_t v = 0;
     Delta delta{};
     if (active && !need_run) {
@@ -962,8 +970,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
         s = run_end;
         need_run = true;
       } else {
-        ++n_cand;
-        ++it_cand;
+        cand_hit = true;
+        if (kServe) ++it_cand;
         const int64_t arc = rpu + cand;
         // the neighbour is loaded beside its factor degree, before the
         // acceptance test needs it (one round trip instead of two)
@@ -974,8 +982,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
           accept = unit_double(o.z, o.w) < ratio;
         }
         if (accept) {
-          ++n_acc;
-          ++it_acc;
+          if (kServe) ++it_acc;
           v = va;
           emit = true;
           delta = P::theta_units(*cpp, neg);
@@ -983,6 +990,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
         pos = cand + 1;
         ++t;
       }
+    }
+    if (!kServe) {
+      w_cand += static_cast<uint32_t>(__popcll(__ballot(cand_hit)));
+      w_acc += static_cast<uint32_t>(__popcll(__ballot(emit)));
     }
     emit_sampled(emit, v, c, delta, neg);
   }
@@ -999,12 +1010,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kG > 1
   }
   if (!kServe) {  // per-level counters: one atomic per wave
     unsigned long long* cnt = A.counters + static_cast<size_t>(A.level) * kNumCounters;
-    const unsigned long long v0 = wave_sum_u64(n_front);
+    const unsigned long long v0 = w_front;
     const unsigned long long v1 = wave_sum_u64(n_hash);
     const unsigned long long v2 = wave_sum_u64(n_det);
-    const unsigned long long v3 = wave_sum_u64(n_cand);
-    const unsigned long long v4 = wave_sum_u64(n_acc);
-    const unsigned long long v5 = wave_sum_u64(n_runs);
+    const unsigned long long v3 = w_cand;
+    const unsigned long long v4 = w_acc;
+    const unsigned long long v5 = w_runs;
     double m = mass;
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) m += __shfl_down(m, off);

@@ -758,7 +758,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                 const double num = ecv * 1.0;  // every neighbour's factor d^-0 is 1
                 ep0 = num / eth;
               } else {  // increments fall along the degree-sorted row: binary search
-                inc0 = ecv * cp.da[nd_first];
+                const double da0 = cp.da[nd_first];
+                inc0 = ecv * da0;
                 uint32_t lo = 0, hi = ed;
                 if (!(inc0 >= eth))
                   hi = 0;  // no deterministic push
@@ -773,6 +774,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                     hi = mid;
                 }
                 eJ = lo;
+                // without deterministic pushes the first sampled run starts at
+                // the row's first arc: its factor goes with the entry
+                ep0 = eJ == 0 ? da0 : 0.0;
               }
               const long long windows =
                   (eJ < ed) ? static_cast<long long>(((ed - 1) >> kSegLog2) - (eJ >> kSegLog2) + 1) : 0;
@@ -924,7 +928,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
           const uint32_t we = ((J >> kSegLog2) + w1) << kSegLog2;
           s = ws > J ? ws : J;
           rend = we < d ? we : d;
-          if (azero) tab = make_skip_table(B.p0[e]);
+          if (azero)
+            tab = make_skip_table(B.p0[e]);
+          else  // the first run's factor when the entry's setup has it (else 0)
+            dstart = il == 0 ? B.p0[e] : 0.0;
+          run_end = 0;  // (the item has no run yet)
           active = true;
           need_run = true;
           it_cand = it_acc = it_runs = 0;
@@ -944,14 +952,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
       if (kServe) ++it_runs;
       const uint32_t wnext = ((s >> kSegLog2) + 1u) << kSegLog2;
       const uint32_t wend = wnext < rend ? wnext : rend;
+      const bool first = run_end == 0;
       run_end = wend;
       if (!azero) {
-        // the group end is loaded beside the factor degree (one round trip)
-        const uint32_t ge = A.gend[rpu + s];
-        dstart = cpp->da[A.nd[rpu + s]];
+        // the factor of the run's first arc (for an item's first run at the
+        // row start, from the entry's setup); the group end only when the
+        // run stops there
+        if (!(first && dstart > 0.0)) dstart = cpp->da[A.nd[rpu + s]];
         const double num = cv * dstart;
         const double pr = num / th;
-        if (!(pr * static_cast<double>(wend - s) <= kMergeCandidates) && ge < wend) run_end = ge;
+        if (!(pr * static_cast<double>(wend - s) <= kMergeCandidates)) {
+          const uint32_t ge = A.gend[rpu + s];
+          if (ge < wend) run_end = ge;
+        }
         tab = make_skip_table(pr);
       }
       pos = s;

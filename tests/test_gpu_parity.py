@@ -241,6 +241,21 @@ def test_hubs_and_many_windows(agp, torch_dev):
     _assert_parity(got, st, ref, cnt, 5)
 
 
+@pytest.mark.parametrize("a, b", [(0.0, 1.0), (0.5, 0.5)])
+def test_batches_with_many_work_items(agp, torch_dev, a, b):
+    """Sixteen leaf sources of a 20000-leaf star: at level 1 the hub holds
+    a residue in all 16 columns, each a work item per 16 sampling windows
+    (20 items), so a batch holds more work items than the level kernel maps
+    to their entries in LDS and the rest are found by search."""
+    g = inputs.star_graph(20000)
+    x = inputs.one_hot(g.n, list(range(1, 17)))
+    w = inputs.weights_ppr(0.2, 4)
+    got, st = _run(agp, torch_dev, g, a, b, w, x, 1e-3, seed=8)
+    ref, cnt = _oracle(g, a, b, w, x, 1e-3, 8)
+    _assert_parity(got, st, ref, cnt, 4)
+    assert st["cand"][1] > 16 * 100  # the hub's columns were sampled, not pushed deterministically
+
+
 def test_edge_cases(agp, torch_dev):
     g = inputs.chung_lu(1500, 6, 2.5, seed=8)
     deg = g.degree

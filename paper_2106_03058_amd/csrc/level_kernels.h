@@ -471,7 +471,9 @@ constexpr int kItemMap = 128;
 struct BatchLds {
   int64_t rp[kBatch];
   double cv[kBatch];
-  double p0[kBatch];           // a = 0: sampling probability of every run of the entry
+  double p0[kBatch];           // a = 0: sampling probability of every run of the entry;
+                               // a > 0: the first arc's factor when the entry has no
+                               // deterministic push (its first run starts there), else 0
   long long doff[kBatch + 1];  // deterministic pushes before each entry (exclusive scan)
   long long ioff[kBatch + 1];  // sampled work items before each entry
   // the entry's column parameters that its work items need (theta, the
@@ -566,7 +568,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
   uint64_t* stage = s_stage[wave];
   int staged = 0;  // wave-uniform
 
-  // per-lane counts stay far below 2^32 in one launch; the hash wraps mod 2^64
+  // per-lane and per-wave counts stay far below 2^32 in one launch (at least
+  // 1024 waves share at most one candidate per arc and column of the level);
+  // the hash wraps mod 2^64
   uint32_t n_det = 0;
   uint32_t w_front = 0, w_cand = 0, w_acc = 0, w_runs = 0;  // wave-uniform (ballot counts)
   unsigned long long n_hash = 0;

@@ -62,6 +62,8 @@ void Scratch::release() {
   rec[0].release();
   rec[1].release();
   big.release();
+  nodefac.release();
+  nodefac_a = nodefac_b = -1.0;
   sweep.release();
   sweep_items.release();
   sweep_nitems = -1;

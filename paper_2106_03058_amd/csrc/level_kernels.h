@@ -119,6 +119,10 @@ struct LevelArgs {
   const int32_t* deg;   // row lengths (neighbours to push to)
   const int32_t* fdeg;  // degrees in the factors d^-a, d^-b
   const ColParams* cp;
+  // batched calls (one a and b for every column): per node u, d_u^-b and the
+  // d^-a of its first neighbour (2 doubles; 0 for a node without arcs), or
+  // null (the setup then reads them through the degree tables)
+  const double* nodefac;
   long long su, sc;  // cell = u * su + c * sc
   long long xld;     // level 0 of a batched call: x[u * xld + c]
   int level;         // batched calls: counter row
@@ -703,9 +707,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
         uint32_t deg_u = 0;
         int32_t fdeg_u = 0;
         int64_t rp_u = 0;
+        const bool pre = !kServe && A.nodefac != nullptr;  // the node's two factors in one load
+        double2 nf = make_double2(0.0, 0.0);
         if (!kServe) {
           deg_u = static_cast<uint32_t>(A.deg[eu]);
-          fdeg_u = A.fdeg[eu];
+          if (pre)
+            nf = reinterpret_cast<const double2*>(A.nodefac)[eu];
+          else
+            fdeg_u = A.fdeg[eu];
           rp_u = A.rp[eu];
         }
         const ColParams& cp = A.cp[ec];
@@ -726,8 +735,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
         T* const o = static_cast<T*>(cp.out) + static_cast<size_t>(eu) * static_cast<size_t>(cp.out_stride);
         const T o_old = (live && cp.kappa != 0.0) ? *o : T(0);
         // (a = 0: every factor d^-a is 1, no degree is read)
-        const uint32_t nd_first = (live && deg_u > 0 && !(cp.flags & kAZero)) ? A.nd[rp_u] : 0u;
-        const double db_u = live ? cp.db[fdeg_u] : 0.0;
+        const uint32_t nd_first = (!pre && live && deg_u > 0 && !(cp.flags & kAZero)) ? A.nd[rp_u] : 0u;
+        const double db_u = live ? (pre ? nf.x : cp.db[fdeg_u]) : 0.0;
         eneg = r < T(0);
         ecw = ec | (eneg ? kBatchNeg : 0u) | ((cp.flags & kAZero) ? kBatchAZero : 0u);
         // (the previous batch is no longer read: these slots are free; the
@@ -762,7 +771,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                 const double num = ecv * 1.0;  // every neighbour's factor d^-0 is 1
                 ep0 = num / eth;
               } else {  // increments fall along the degree-sorted row: binary search
-                const double da0 = cp.da[nd_first];
+                const double da0 = pre ? nf.y : cp.da[nd_first];
                 inc0 = ecv * da0;
                 uint32_t lo = 0, hi = ed;
                 if (!(inc0 >= eth))

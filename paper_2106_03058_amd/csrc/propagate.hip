@@ -339,6 +339,17 @@ __global__ void k_set_level(ColParams* __restrict__ cp, int C, int level, const 
   p.out_stride = out_stride;
 }
 
+// Per node u: d_u^-b (its factor degree's entry) and the d^-a of its first
+// neighbour in the degree-sorted row (0 for a node without arcs).
+__global__ void k_node_factors(const int64_t* __restrict__ rp, const int32_t* __restrict__ deg,
+                               const int32_t* __restrict__ fdeg, const uint32_t* __restrict__ nd,
+                               const double* __restrict__ da, const double* __restrict__ db, int64_t n,
+                               double2* __restrict__ out) {
+  for (int64_t u = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; u < n;
+       u += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    out[u] = make_double2(db[fdeg[u]], deg[u] > 0 ? da[nd[rp[u]]] : 0.0);
+}
+
 // ------------------------------------------------------------ driver
 constexpr int kSparseShift = 5;  // sparse levels: frontier below n C / 32
 constexpr int kBinShift = 3;     // binned levels: estimated pushes reach n C / 8
@@ -631,6 +642,24 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   // from twice that (on 32-column tiles of a 111M-node graph the record
   // passes cost more than the atomics they replace below about n C / 4)
   A.bin_pushes = std::ldexp(static_cast<double>(cells), -(ng > 1 ? std::max(tune.bin_shift - 1, 1) : tune.bin_shift));
+  // per node: d_u^-b and the first neighbour's d^-a, so that a batch setup
+  // loads both with the row bounds (kept for later calls with the same a, b)
+  A.nodefac = nullptr;
+  if (may_alloc && n > 0) {
+    const void* before = sc.nodefac.ptr;
+    if (sc.nodefac.reserve(static_cast<size_t>(n) * sizeof(double2), false, s) == AGP_OK) {
+      if (sc.nodefac.ptr != before || sc.nodefac_a != a || sc.nodefac_b != b) {
+        k_node_factors<<<grid_for(n, 256), 256, 0, s>>>(g->row_ptr, g->degree, g->fdeg, g->ndeg, da, db, n,
+                                                        sc.nodefac.as<double2>());
+        sc.nodefac_a = a;
+        sc.nodefac_b = b;
+      }
+      A.nodefac = sc.nodefac.as<double>();
+    } else {
+      (void)hipGetLastError();  // no room: the setup reads the factors through the degree tables
+      sc.nodefac_a = sc.nodefac_b = -1.0;
+    }
+  }
   // per-level values of this call (read by k_set_level from device memory)
   LevelParams lph[AGP_MAX_LEVELS + 1];
   const uint32_t key0 = static_cast<uint32_t>(seed), key1 = static_cast<uint32_t>(seed >> 32);
@@ -750,6 +779,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     k.append(reinterpret_cast<const char*>(&samp_rows), sizeof(samp_rows));
     k.append(reinterpret_cast<const char*>(&samp_items), sizeof(samp_items));
     k.append(reinterpret_cast<const char*>(&sc.rec[1].ptr), sizeof(void*));
+    k.append(reinterpret_cast<const char*>(&A.nodefac), sizeof(void*));
     hipGraphExec_t exec = nullptr;
     auto it = g->loops.find(k);
     if (it != g->loops.end()) {
@@ -837,7 +867,7 @@ int32_t column_tile(agp_graph* g, int32_t C, bool binned, const agp_tuning_t& tu
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return C;
   Scratch& sc = g->scratch;
   const size_t held = sc.acc[0].bytes + sc.acc[1].bytes + sc.frontier[0].bytes + sc.frontier[1].bytes +
-                      sc.rec[0].bytes + sc.rec[1].bytes;
+                      sc.rec[0].bytes + sc.rec[1].bytes + sc.nodefac.bytes;
   const double budget = 0.85 * static_cast<double>(free_b + held);
   for (int recs : {4, 1}) {
     const size_t per_cell = base_cell + (binned ? 2 * static_cast<size_t>(recs) * sizeof(uint32_t) : 0);
@@ -922,7 +952,7 @@ DensePlan dense_plan(agp_graph* g, int32_t C, const agp_tuning_t& tune, bool bin
   (void)hipMemGetInfo(&free_b, &total_b);
   Scratch& sc = g->scratch;
   const size_t held = sc.acc[0].bytes + sc.acc[1].bytes + sc.frontier[0].bytes + sc.frontier[1].bytes +
-                      sc.rec[0].bytes + sc.rec[1].bytes;
+                      sc.rec[0].bytes + sc.rec[1].bytes + sc.nodefac.bytes;
   const double budget = 0.9 * static_cast<double>(free_b + held);
   // 8 B exact sum + 4 B residue per cell, 2 flag bytes per node; records
   // (two buffers of 4 B) take at least a quarter record per cell

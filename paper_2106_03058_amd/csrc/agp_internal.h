@@ -52,6 +52,8 @@ struct Scratch {
   DevBuf big;        // deferred long deterministic rows: per-level counters, then the row list
   DevBuf nodefac;    // batched calls: per node d_u^-b and the d^-a of its first neighbour
   double nodefac_a = -1.0, nodefac_b = -1.0;  // the exponents it holds (-1: none)
+  DevBuf arcfac;     // batched calls: d^-a of every arc's neighbour (arc order)
+  double arcfac_a = -1.0;                      // the exponent it holds (-1: none)
   DevBuf sweep;      // clustering sweep: keys, order, ranks, prefix sums, sort space
   DevBuf sweep_items;        // clustering sweep: arc-balanced work items of the graph
   int64_t sweep_nitems = -1; // their number (-1: not built yet)

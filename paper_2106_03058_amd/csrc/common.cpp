@@ -64,6 +64,8 @@ void Scratch::release() {
   big.release();
   nodefac.release();
   nodefac_a = nodefac_b = -1.0;
+  arcfac.release();
+  arcfac_a = -1.0;
   sweep.release();
   sweep_items.release();
   sweep_nitems = -1;

@@ -123,6 +123,8 @@ struct LevelArgs {
   // d^-a of its first neighbour (2 doubles; 0 for a node without arcs), or
   // null (the setup then reads them through the degree tables)
   const double* nodefac;
+  // batched calls: d^-a of every arc's neighbour (arc order), or null
+  const double* arcfac;
   long long su, sc;  // cell = u * su + c * sc
   long long xld;     // level 0 of a batched call: x[u * xld + c]
   int level;         // batched calls: counter row
@@ -708,6 +710,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
         int32_t fdeg_u = 0;
         int64_t rp_u = 0;
         const bool pre = !kServe && A.nodefac != nullptr;  // the node's two factors in one load
+        const bool pre_arc = !kServe && A.arcfac != nullptr;  // each arc's neighbour factor in one load
         double2 nf = make_double2(0.0, 0.0);
         if (!kServe) {
           deg_u = static_cast<uint32_t>(A.deg[eu]);
@@ -776,11 +779,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                 uint32_t lo = 0, hi = ed;
                 if (!(inc0 >= eth))
                   hi = 0;  // no deterministic push
-                else if (ecv * cp.da[A.nd[erp + ed - 1]] >= eth)
+                else if (ecv * (pre_arc ? A.arcfac[erp + ed - 1] : cp.da[A.nd[erp + ed - 1]]) >= eth)
                   lo = ed;  // every push is deterministic
                 while (lo < hi) {
                   const uint32_t mid = (lo + hi) >> 1;
-                  const double inc = ecv * cp.da[A.nd[erp + mid]];
+                  const double inc = ecv * (pre_arc ? A.arcfac[erp + mid] : cp.da[A.nd[erp + mid]]);
                   if (inc >= eth)
                     lo = mid + 1;
                   else
@@ -901,7 +904,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
           const ColParams* cpd = A.cp + vc;
           v = A.col[arc];
           double inc = B.cv[e];
-          if (!(cpd->flags & kAZero)) inc = inc * cpd->da[A.nd[arc]];
+          if (!(cpd->flags & kAZero)) inc = inc * (A.arcfac != nullptr ? A.arcfac[arc] : cpd->da[A.nd[arc]]);
           T val = to_w(inc, T());
           if (cw & kBatchNeg) val = -val;
           emit = P::to_units(val, *cpd, &delta);
@@ -971,7 +974,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
         // the factor of the run's first arc (for an item's first run at the
         // row start, from the entry's setup); the group end only when the
         // run stops there
-        if (!(first && dstart > 0.0)) dstart = cpp->da[A.nd[rpu + s]];
+        if (!(first && dstart > 0.0))
+          dstart = A.arcfac != nullptr ? A.arcfac[rpu + s] : cpp->da[A.nd[rpu + s]];
         const double num = cv * dstart;
         const double pr = num / th;
         if (!(pr * static_cast<double>(wend - s) <= kMergeCandidates)) {
@@ -1004,7 +1008,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
         const uint32_t va = A.col[arc];
         bool accept = true;  // a = 0: the ratio is 1 and every uniform is below it
         if (!azero) {
-          const double ratio = cpp->da[A.nd[arc]] / dstart;
+          const double ratio = (A.arcfac != nullptr ? A.arcfac[arc] : cpp->da[A.nd[arc]]) / dstart;
           accept = unit_double(o.z, o.w) < ratio;
         }
         if (accept) {

@@ -350,6 +350,14 @@ __global__ void k_node_factors(const int64_t* __restrict__ rp, const int32_t* __
     out[u] = make_double2(db[fdeg[u]], deg[u] > 0 ? da[nd[rp[u]]] : 0.0);
 }
 
+// Per arc j: d^-a of its neighbour (the factor degree nd[j]).
+__global__ void k_arc_factors(const uint32_t* __restrict__ nd, const double* __restrict__ da, int64_t nnz,
+                              double* __restrict__ out) {
+  for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < nnz;
+       j += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    out[j] = da[nd[j]];
+}
+
 // ------------------------------------------------------------ driver
 constexpr int kSparseShift = 5;  // sparse levels: frontier below n C / 32
 constexpr int kBinShift = 3;     // binned levels: estimated pushes reach n C / 8
@@ -660,6 +668,27 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
       sc.nodefac_a = sc.nodefac_b = -1.0;
     }
   }
+  // per arc: its neighbour's d^-a (a > 0), so that an acceptance test or a
+  // run start loads it beside the neighbour id (kept for later calls with
+  // the same a); only when it fits beside the tile's scratch
+  A.arcfac = nullptr;
+  if (may_alloc && a != 0.0 && g->nnz > 0) {
+    const void* before = sc.arcfac.ptr;
+    const size_t want = static_cast<size_t>(g->nnz) * sizeof(double);
+    size_t free_b = 0, total_b = 0;
+    const bool room = sc.arcfac.bytes >= want ||
+                      (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > want + (want >> 2) + (1ull << 30));
+    if (room && sc.arcfac.reserve(want, false, s) == AGP_OK) {
+      if (sc.arcfac.ptr != before || sc.arcfac_a != a) {
+        k_arc_factors<<<grid_for(g->nnz, 256), 256, 0, s>>>(g->ndeg, da, g->nnz, sc.arcfac.as<double>());
+        sc.arcfac_a = a;
+      }
+      A.arcfac = sc.arcfac.as<double>();
+    } else {
+      (void)hipGetLastError();
+      sc.arcfac_a = -1.0;
+    }
+  }
   // per-level values of this call (read by k_set_level from device memory)
   LevelParams lph[AGP_MAX_LEVELS + 1];
   const uint32_t key0 = static_cast<uint32_t>(seed), key1 = static_cast<uint32_t>(seed >> 32);
@@ -780,6 +809,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
     k.append(reinterpret_cast<const char*>(&samp_items), sizeof(samp_items));
     k.append(reinterpret_cast<const char*>(&sc.rec[1].ptr), sizeof(void*));
     k.append(reinterpret_cast<const char*>(&A.nodefac), sizeof(void*));
+    k.append(reinterpret_cast<const char*>(&A.arcfac), sizeof(void*));
     hipGraphExec_t exec = nullptr;
     auto it = g->loops.find(k);
     if (it != g->loops.end()) {
@@ -867,7 +897,7 @@ int32_t column_tile(agp_graph* g, int32_t C, bool binned, const agp_tuning_t& tu
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return C;
   Scratch& sc = g->scratch;
   const size_t held = sc.acc[0].bytes + sc.acc[1].bytes + sc.frontier[0].bytes + sc.frontier[1].bytes +
-                      sc.rec[0].bytes + sc.rec[1].bytes + sc.nodefac.bytes;
+                      sc.rec[0].bytes + sc.rec[1].bytes + sc.nodefac.bytes + sc.arcfac.bytes;
   const double budget = 0.85 * static_cast<double>(free_b + held);
   for (int recs : {4, 1}) {
     const size_t per_cell = base_cell + (binned ? 2 * static_cast<size_t>(recs) * sizeof(uint32_t) : 0);
@@ -952,7 +982,7 @@ DensePlan dense_plan(agp_graph* g, int32_t C, const agp_tuning_t& tune, bool bin
   (void)hipMemGetInfo(&free_b, &total_b);
   Scratch& sc = g->scratch;
   const size_t held = sc.acc[0].bytes + sc.acc[1].bytes + sc.frontier[0].bytes + sc.frontier[1].bytes +
-                      sc.rec[0].bytes + sc.rec[1].bytes + sc.nodefac.bytes;
+                      sc.rec[0].bytes + sc.rec[1].bytes + sc.nodefac.bytes + sc.arcfac.bytes;
   const double budget = 0.9 * static_cast<double>(free_b + held);
   // 8 B exact sum + 4 B residue per cell, 2 flag bytes per node; records
   // (two buffers of 4 B) take at least a quarter record per cell

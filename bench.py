@@ -66,8 +66,8 @@ ALU_PEAK_GDRAWS = VALU_LANE_OPS / VALU_PER_DRAW / 1e9
 # sources they were taken from (the files that define k_level, k_det_big and
 # k_samp_big, code without comments) and the default tuning.
 TRAFFIC = {
-    "gnn-ppr-large": {"sources": "8dfe1b0a1bd5b121", "columns": 128, "bytes_per_launch": 98756900000.0,
-                      "fetch_bytes": 81887190000.0, "write_bytes": 16869710000.0},
+    "gnn-ppr-large": {"sources": "0fd3ed3950369b42", "columns": 128, "bytes_per_launch": 102346960000.0,
+                      "fetch_bytes": 85478380000.0, "write_bytes": 16868580000.0},
 }
 KERNEL_SOURCES = ("paper_2106_03058_amd/csrc/level_kernels.h", "paper_2106_03058_amd/csrc/agp_device.h")
 

@@ -1115,7 +1115,7 @@ __global__ __launch_bounds__(kThreads) void k_det_big(LevelArgs A, typename Prec
         const int64_t arc = br.rp + static_cast<int64_t>(k - off);
         v = A.col[arc];
         double inc = br.cv;
-        if (!(cpd->flags & kAZero)) inc = inc * cpd->da[A.nd[arc]];
+        if (!(cpd->flags & kAZero)) inc = inc * (A.arcfac != nullptr ? A.arcfac[arc] : cpd->da[A.nd[arc]]);
         T val = to_w(inc, T());
         if (br.neg) val = -val;
         emit = P::to_units(val, *cpd, &delta);
@@ -1223,7 +1223,7 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
       if (!azero) {
         // the group end is loaded beside the factor degree (one round trip)
         const uint32_t ge = A.gend[rpu + s];
-        dstart = cpp->da[A.nd[rpu + s]];
+        dstart = A.arcfac != nullptr ? A.arcfac[rpu + s] : cpp->da[A.nd[rpu + s]];
         const double num = cv * dstart;
         const double pr = num / th;
         if (!(pr * static_cast<double>(wend - s) <= kMergeCandidates) && ge < wend) run_end = ge;
@@ -1249,7 +1249,7 @@ __global__ __launch_bounds__(kThreads) void k_samp_big(LevelArgs A, typename Pre
         const uint32_t va = A.col[arc];  // beside the factor degree, as in k_level
         bool accept = true;
         if (!azero) {
-          const double ratio = cpp->da[A.nd[arc]] / dstart;
+          const double ratio = (A.arcfac != nullptr ? A.arcfac[arc] : cpp->da[A.nd[arc]]) / dstart;
           accept = unit_double(o.z, o.w) < ratio;
         }
         if (accept) {

@@ -177,6 +177,10 @@ int agp_graph_destroy(agp_graph_t* g);
  * (Section 3).  Signed signals are pushed in one pass (decisions on |r|,
  * contributions carry the sign of r).  Each next-level residue is the exact
  * sum of what a node receives in the level, rounded once to binary32.
+ * Working memory is kept with the graph for later calls: the column tiles'
+ * accumulators, frontier lists and record buffers (within 85% of the free
+ * memory), 16 bytes per node of per-call factors and, for a > 0 and when it
+ * fits beside them, 8 bytes per arc (reused while a and b stay the same).
  * Errors: AGP_EINVAL (bad sizes/ranges, non-finite x), AGP_ERANGE (a
  * residue outgrew the exact accumulators: contributions larger than about
  * 2^39 theta), AGP_ENOMEM, AGP_EDEVICE.  On AGP_EINVAL nothing is written; on

@@ -317,6 +317,9 @@ int agp_set_tuning(const agp_graph_t* g, int32_t C, double a, double b, const ag
  *   AGP_BIG_ROWS=n       at most n entries per level in each list of deferred
  *                        work (0: every entry keeps its pushes in its wave);
  *   AGP_BIG_ITEMS=n      the big_items field;
+ *   AGP_FACTOR_VECTORS=0 batched calls read the degree factors through the
+ *                        per-exponent tables instead of the per-call node and
+ *                        arc factor vectors (and allocate neither);
  *   AGP_DENSE_GROUP_SHIFT=k  dense levels: records grouped by 2^k columns;
  *   AGP_CHECK_ZERO=1     dense levels: after each tile, check on the host
  *                        that the scratch sums and residues are all-zero

@@ -653,7 +653,9 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   // per node: d_u^-b and the first neighbour's d^-a, so that a batch setup
   // loads both with the row bounds (kept for later calls with the same a, b)
   A.nodefac = nullptr;
-  if (may_alloc && n > 0) {
+  const char* fv = std::getenv("AGP_FACTOR_VECTORS");  // "0": read the factors through the tables (tests)
+  const bool factors = may_alloc && !(fv && std::strcmp(fv, "0") == 0);
+  if (factors && n > 0) {
     const void* before = sc.nodefac.ptr;
     if (sc.nodefac.reserve(static_cast<size_t>(n) * sizeof(double2), false, s) == AGP_OK) {
       if (sc.nodefac.ptr != before || sc.nodefac_a != a || sc.nodefac_b != b) {
@@ -672,7 +674,7 @@ int propagate_tile(agp_graph* g, const char* fn, const agp_tuning_t& tune, doubl
   // run start loads it beside the neighbour id (kept for later calls with
   // the same a); only when it fits beside the tile's scratch
   A.arcfac = nullptr;
-  if (may_alloc && a != 0.0 && g->nnz > 0) {
+  if (factors && a != 0.0 && g->nnz > 0) {
     const void* before = sc.arcfac.ptr;
     const size_t want = static_cast<size_t>(g->nnz) * sizeof(double);
     size_t free_b = 0, total_b = 0;

@@ -318,6 +318,22 @@ def test_error_paths(agp, torch_dev):
     _assert_parity(got, st, ref, cnt, 5)
 
 
+@pytest.mark.parametrize("name", ["gdc_signed", "general_ab", "single_target"])
+def test_factor_vectors_are_bit_identical(agp, torch_dev, name, monkeypatch):
+    """The per-call node and arc factor vectors give the results and counters
+    of reading the factors through the degree tables (and the oracle's)."""
+    a, b, w, eps, kind = CASES[name]
+    g = inputs.chung_lu(3000, 10, 2.5, seed=29, self_loops=kind != "onehot")
+    x = _signal(g, kind, 24, seed=30)
+    ref, cnt = _oracle(g, a, b, w, x, eps, 31)
+    monkeypatch.setenv("AGP_FACTOR_VECTORS", "0")
+    got0, st0 = _run(agp, torch_dev, g, a, b, w, x, eps, seed=31)
+    monkeypatch.delenv("AGP_FACTOR_VECTORS")
+    got1, st1 = _run(agp, torch_dev, g, a, b, w, x, eps, seed=31)
+    _assert_parity(got0, st0, ref, cnt, len(w) - 1)
+    _assert_parity(got1, st1, ref, cnt, len(w) - 1)
+
+
 @pytest.mark.parametrize("name", ["ppr", "tp", "gdc_signed", "general_ab"])
 def test_aggregation_modes_are_bit_identical(agp, torch_dev, name, monkeypatch):
     """Binned LDS aggregation, its record-overflow fallback and plain atomics
